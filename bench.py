@@ -1,0 +1,165 @@
+"""Throughput of the batched likelihood evaluation on one MI355X.
+
+Workload: the Fabry-Perot-like galaxy, 128 x 128 spatial x 48 channels of
+16 km/s, exponential disc r0 = 20 px, exponential-rise rotation curve,
+PSF FWHM 3 px, LSF FWHM 30 km/s, noise 3 km/s, flux mask at 1% of the peak.
+One step = one batched evaluation (model cube -> PSF/LSF -> moments ->
+masked chi-square) of 400 parameter rows, the live-point batch of the nested
+sampler, drawn from the workload's generative ranges; every step uses a
+different batch, all resident in device memory before timing starts.
+
+Prints one JSON line: evals/s, the roofline of the dominant kernel (timed
+live with HIP events on the launch stream) and the CPU oracle baseline.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "model evals/s (cube+PSF+moments+χ²); fits/hour, surrogate vs plain"
+BATCH = 400
+
+# MI355X: 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz = 3.93e13 VALU lane-ops/s;
+# one FP64 FMA per lane-op slot = 78.6 TFLOP/s (packed FP32 is not used).
+LANE_OPS_PER_S = 256 * 64 * 2.4e9
+PEAK_TFLOPS = 2 * LANE_OPS_PER_S / 1e12
+# VALU lane-op slots per line-support voxel of k_line_sums: e += sqrt(kappa),
+# e*e, f64->f32, exp2, f32->f64, 3 FMA (exp2 counted as TRANS_SLOTS slots)
+TRANS_SLOTS = 1
+SLOTS_PER_VOXEL = 7 + TRANS_SLOTS
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-rows-per-thread", type=int, default=12)
+    return ap.parse_args()
+
+
+def cpu_baseline(grid, rows, obs, rows_per_thread):
+    """The FP64 oracle (untuned) on a bounded sample of the same workload."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    from oracle import oracle as O
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from parity import oracle_desc
+    O.lib()
+    d = oracle_desc(O, grid.as_dict())
+    threads = max(1, min(16, os.cpu_count() or 1))
+    n = threads * rows_per_thread
+    sample = rows[:n]
+
+    def one(r):
+        return O.eval_chi2(d, r, obs.vel, obs.sig, obs.evel, obs.esig, obs.mask, obs.W)[0]
+
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(threads) as ex:
+        res = list(ex.map(one, sample))
+    dt = time.perf_counter() - t0
+    return {"value": n / dt, "unit": "evals/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n} rows of the first batch ({rows_per_thread} per thread), "
+                      f"FP64 literal cube pipeline, {dt:.2f} s wall",
+            "chi2_first": res[0]}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); "
+              "this build has no multi-GPU path", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_1510_01815_amd import gbk
+    from paper_1510_01815_amd import inputs as I
+    if not os.path.exists(gbk.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    dev = torch.device("cuda:0")
+
+    grid = I.c2_grid()
+    model = gbk.Model.from_grid(grid, device=0)
+    truth = I.c2_draw(I.rng_for(2, 0, 0), 1)
+    truth_maps = model.evaluate(torch.tensor(truth, device=dev)).cpu().numpy()[0]
+    obs = I.make_observation(truth_maps, 3.0, I.rng_for(2, 0, 1))
+    model.set_obs(obs)
+
+    K, W = args.steps, args.warmup
+    rng = I.rng_for(2, 0, 2)
+    batches = torch.tensor(I.c2_draw(rng, (K + W) * BATCH).reshape(K + W, BATCH, I.NPAR),
+                           device=dev)
+    chi2 = torch.empty((K + W, BATCH), dtype=torch.float64, device=dev)
+    nval = torch.empty((K + W, BATCH), dtype=torch.int64, device=dev)
+    stream = torch.cuda.current_stream()
+
+    for k in range(W):
+        model.chi2(batches[k], out=chi2[k], n_valid=nval[k], stream=stream)
+    torch.cuda.synchronize()
+
+    # timed region: K steps, kernel launches bracketed by HIP events on `stream`
+    model.set_profiling(gbk.GK_PROF_TIMING)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(W, W + K):
+        model.chi2(batches[k], out=chi2[k], n_valid=nval[k], stream=stream)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = model.read_profile()
+    model.set_profiling(0)
+
+    # untimed pass over the same batches: count the line-support voxels
+    model.set_profiling(gbk.GK_PROF_COUNT)
+    for k in range(W, W + K):
+        model.chi2(batches[k], stream=stream)
+    torch.cuda.synchronize()
+    cnt = model.read_profile()
+    model.set_profiling(0)
+
+    assert torch.isfinite(chi2[W:]).all().item(), "non-finite chi-square in the timed steps"
+    evals = K * BATCH
+    value = evals / dt
+
+    k_ms = prof["kernel_ms"]["k_line_sums"] / max(prof["launches"]["k_line_sums"], 1)
+    vox_per_launch = cnt["support_voxels"] / K
+    flop_per_launch = vox_per_launch * SLOTS_PER_VOXEL * 2
+    achieved = flop_per_launch / (k_ms * 1e-3) / 1e12
+    roofline = {"bound": "alu", "kernel": "k_line_sums", "achieved": round(achieved, 3),
+                "peak": round(PEAK_TFLOPS, 1), "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK_TFLOPS, 4), "traffic": None,
+                "kernel_ms_avg": round(k_ms, 5),
+                "support_voxels_per_launch": int(vox_per_launch),
+                "flop_per_voxel": SLOTS_PER_VOXEL * 2}
+    per_kernel_ms = {n: round(prof["kernel_ms"][n] / max(prof["launches"][n], 1), 5)
+                     for n in gbk.KERNEL_NAMES}
+
+    out = {"metric": METRIC, "value": round(value, 1), "unit": "evals/s", "n_gpus": 1,
+           "steps": K, "warmup": W, "ms_per_step": round(1e3 * dt / K, 4),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32 exp / f64 sums", "data": "synthetic",
+           "config": {"workload": "Fabry-Perot-like 128x128x48 cube, 16 km/s channels, "
+                                  "400 nested-sampling proposals per launch",
+                      "nx": 128, "ny": 128, "nz": 48, "batch": BATCH,
+                      "psf_fwhm_pix": grid.psf_fwhm, "lsf_sigma_kms": round(grid.lsf_sigma, 4),
+                      "rotation_curve": "exponential rise", "parallelism": "single GPU"},
+           "roofline": roofline, "kernel_ms_per_launch": per_kernel_ms}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(grid, batches[W].cpu().numpy(), obs,
+                                           args.cpu_rows_per_thread)
+        gpu_first = float(chi2[W, 0].item())
+        cb = out["cpu_baseline"].pop("chi2_first")
+        out["cpu_baseline"]["chi2_rel_diff_first_row"] = abs(gpu_first - cb) / abs(cb)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

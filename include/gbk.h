@@ -1,0 +1,166 @@
+/*
+ * gbk.h -- C ABI of the MI355X (gfx950) library libgbk.so: batched likelihood
+ * evaluation of the thin-disc intensity-cube model of Bekiaris, Glazebrook,
+ * Fluke & Abraham (2016), "Kinematic modelling of disc galaxies using
+ * graphics processing units", and the optimisers that call it.
+ *
+ * One evaluation = model cube (Sec. 2.1 eqs. 1-8, Sec. 2.2.2) -> convolution
+ * with the PSF and LSF (eq. 9, Sec. 2.2.3) -> down-sampling by the
+ * upsampling factor (Sec. 2.2.4) -> moment maps (Sec. 2.2.5) -> masked
+ * goodness of fit (eq. 11, Sec. 2.2.6).
+ *
+ * Conventions (fixed for every entry point):
+ *  - angles in degrees, lengths in data pixels, velocities in km/s;
+ *  - data pixel (i, j) is centred at (x, y) = (i, j), x along the fastest
+ *    axis of every map; maps are row-major [ny][nx];
+ *  - data channel k has velocity v0_kms + (k - crpix) * dv_kms; with
+ *    upsampling u the model grid is u times finer along x, y and velocity,
+ *    fine pixel m sitting at (m + 1/2)/u - 1/2 in data units;
+ *  - the PSF is a circular Gaussian of the given FWHM (data pixels), the LSF
+ *    a Gaussian of the given sigma (km/s); each axis is sampled at integer
+ *    fine-grid offsets -h..h, h = ceil(R * sigma), and normalised to unit
+ *    sum; 0 switches an axis off;
+ *  - the model is evaluated on the data window plus a halo of h fine pixels
+ *    (channels) on each side and every convolution is "valid";
+ *  - line profile: I(r) times a unit-area Gaussian of width sigma_model
+ *    sampled at channel centres, I(r) = I0 exp(-min(r/r0, 60));
+ *  - m0 = dv * sum C, m1 = sum C v / sum C, m2 = sqrt(sum C (v - m1)^2 / sum C)
+ *    over the data channels; sum C == 0 gives (0, Vsys, 0);
+ *  - chi2 = sum over mask != 0 of (m1 - v_obs)^2 / E_v^2 + W (m2 - s_obs)^2 / E_s^2.
+ *
+ * Parameter rows are 12 doubles (GK_NP), in the slot order of the enum below.
+ * A row outside the model's domain (non-finite value, inclination outside
+ * (0, 90), sigma <= 0, r0 <= 0, rt <= 0, I0 <= 0, or for the Epinat curve
+ * g <= 0 or a < 0) evaluates to NaN maps and chi2 = +inf.
+ *
+ * Memory: `params` may be host or device memory (told apart with
+ * hipPointerGetAttributes); outputs named "device" must be device memory
+ * owned by the caller.  Observations are copied into library-owned device
+ * memory.  Work is enqueued on the caller's HIP stream (NULL = the null
+ * stream) and the call returns without waiting, except where stated.
+ * Calls on one model from several host threads, or overlapping calls on
+ * different streams, race on the model's scratch memory: serialise them.
+ * No C++ exception crosses this interface; on failure the entry points
+ * return a negative gk_status and gk_last_error() describes it.
+ */
+#ifndef GBK_H
+#define GBK_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gk_model gk_model; /* opaque, created and freed by the library */
+
+typedef enum {
+    GK_OK = 0,
+    GK_PARTIAL = 1,     /* some host-given rows are out of domain (their chi2 = +inf, maps NaN) */
+    GK_EINVAL = -1,     /* invalid argument: descriptor, observation, pointer kind, size */
+    GK_ENOMEM = -2,     /* device or host allocation failed */
+    GK_EDEVICE = -3,    /* HIP runtime error */
+    GK_ENOTCONV = -4,   /* an optimiser stopped at its iteration cap */
+    GK_ESTATE = -5      /* call out of order (e.g. chi2 before an observation is set) */
+} gk_status;
+
+/* Parameter slots (Sec. 2.1): kinematic centre, position angle, inclination,
+ * systemic velocity, rotation-curve velocity and turn-over radius, intrinsic
+ * dispersion (Sec. 2.1.4), exponential-disc scale length and central
+ * brightness (eq. 5), Epinat outer and inner slopes a, g (eq. 7). */
+enum { GK_XO = 0, GK_YO, GK_PA, GK_INC, GK_VSYS, GK_VT, GK_RT, GK_SIG, GK_R0, GK_I0, GK_A, GK_G,
+       GK_NP };
+
+/* Rotation curves: arctan (eq. 6), Epinat (eq. 7), exponential rise
+ * Vt (1 - exp(-r/rt)). */
+enum { GK_RC_ARCTAN = 0, GK_RC_EPINAT = 1, GK_RC_BOISSIER = 2 };
+
+typedef struct {
+    int32_t nx, ny, nz;          /* data grid, each >= 1 */
+    int32_t upsample;            /* u >= 1 (Sec. 2.2.2, eq. 10) */
+    double dv_kms;               /* channel width, > 0 */
+    double v0_kms, crpix;        /* v_k = v0 + (k - crpix) dv */
+    double psf_fwhm_pix;         /* >= 0; 0 = no PSF */
+    double lsf_sigma_kms;        /* >= 0; 0 = no LSF */
+    double kernel_radius_sigma;  /* R > 0 (4 is the usual choice) */
+    int32_t rc;                  /* GK_RC_* */
+    int32_t reserved;            /* must be 0 */
+} gk_model_desc;
+
+/* Creates a model for one instrument grid on HIP device `device`.
+ * Errors: GK_EINVAL (bad descriptor), GK_ENOMEM, GK_EDEVICE. */
+gk_status gk_create_model(const gk_model_desc *desc, int device, gk_model **out);
+
+/* Frees the model and its device memory; waits for its pending work.  NULL is a no-op. */
+gk_status gk_destroy_model(gk_model *model);
+
+/* Sets the observed maps (Sec. 2.2, Sec. 2.2.6): velocity, dispersion and
+ * their errors, [ny][nx] float host arrays, a [ny][nx] byte mask (nonzero =
+ * use the pixel) and the dispersion weight W >= 0 of eq. 11.  The data are
+ * copied; the call blocks until the copy is done.  `sig`/`esig` may be NULL
+ * only when W == 0.  Errors: GK_EINVAL if an unmasked pixel has a non-finite
+ * value or an error <= 0 (E_s only checked when W > 0). */
+gk_status gk_set_observation(gk_model *model, const float *vel, const float *sig,
+                             const float *evel, const float *esig, const uint8_t *mask,
+                             double W);
+
+/* Number of unmasked pixels of the current observation (host value). */
+gk_status gk_observation_count(const gk_model *model, int64_t *n_valid);
+
+/* Evaluates B parameter rows `params` [B][GK_NP] (host or device) into the
+ * device array `maps` [B][3][ny][nx] float: m0, m1, m2 of each row
+ * (Sec. 2.2.2-2.2.5).  Returns GK_PARTIAL when host-given rows are out of
+ * domain; rows given in device memory are checked on the device only (their
+ * maps become NaN, the status stays GK_OK).  B == 0 is a no-op. */
+gk_status gk_evaluate_batch(gk_model *model, const double *params, int32_t B, float *maps,
+                            void *hip_stream);
+
+/* Masked chi-square (eq. 11) of B rows against the current observation:
+ * chi2 [B] double and, if not NULL, n_valid [B] int64 (unmasked pixels
+ * counted; 0 for an out-of-domain row), both device arrays.  The sums are
+ * double precision and reduced in a fixed order, so repeated calls give
+ * bit-identical results.  Errors: GK_ESTATE without an observation. */
+gk_status gk_chi2_batch(gk_model *model, const double *params, int32_t B, double *chi2,
+                        int64_t *n_valid, void *hip_stream);
+
+/* Weighted residual maps for least squares (Sec. 2.3.1): resid [B][2][ny][nx]
+ * double device array, (m1 - v_obs)/E_v and sqrt(W) (m2 - s_obs)/E_s on
+ * unmasked pixels and 0 elsewhere; the sum of squares of a row is its chi2.
+ * Out-of-domain rows are filled with NaN.  Errors: GK_ESTATE without an
+ * observation. */
+gk_status gk_residual_batch(gk_model *model, const double *params, int32_t B, double *resid,
+                            void *hip_stream);
+
+/* Measurement hooks for the benchmark (not needed for correct results).
+ * flags: GK_PROF_TIMING brackets every kernel launch of the following calls
+ * with HIP events on the caller's stream; GK_PROF_COUNT makes the line-profile
+ * kernel count, per row, the fine voxels inside each spaxel's line support
+ * (channels within sqrt(64 / kappa) of the line centre, i.e. where the
+ * Gaussian of Sec. 2.2.2 exceeds 2^-64 of its peak), which is the work the
+ * evaluation has to do.  Counting adds atomics, so it is meant for an
+ * untimed pass.  gk_read_profile waits for the recorded work, returns the
+ * totals since the last read and clears them.  Kernel index: 0 = per-row
+ * constants, 1 = line profiles, 2 = PSF passes + moments + chi-square terms,
+ * 3 = chi-square reduction. */
+enum { GK_PROF_TIMING = 1, GK_PROF_COUNT = 2 };
+typedef struct {
+    double kernel_ms[4];        /* summed kernel durations */
+    int64_t launches[4];        /* launches timed */
+    int64_t support_voxels;     /* counted line-support voxels (GK_PROF_COUNT) */
+    int64_t rows;               /* rows evaluated while profiling */
+} gk_profile_stats;
+gk_status gk_set_profiling(gk_model *model, int flags);
+gk_status gk_read_profile(gk_model *model, gk_profile_stats *out);
+
+/* Shape of the fine model cube with its halo and the halos themselves:
+ * dims = {nx_ext, ny_ext, nz_ext, h_psf, h_lsf}. */
+gk_status gk_model_dims(const gk_model *model, int32_t dims[5]);
+
+/* Message of the last failed call on this host thread ("" if none). */
+const char *gk_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GBK_H */

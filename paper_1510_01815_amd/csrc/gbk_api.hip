@@ -1,0 +1,574 @@
+// gbk_api.hip -- host runtime and C ABI of libgbk.so (declared in gbk.h).
+//
+// Owns the per-model device state: PSF taps, the three per-channel moment
+// weight tables W_j (LSF + spectral down-sampling + moment weights, see
+// gbk_kernels.hip), the observation, and growable scratch for the per-row
+// constants, the T_j planes and the chi-square tile partials.  Batches larger
+// than the scratch budget are processed in chunks on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "gbk.h"
+#include "gbk_internal.h"
+
+using namespace gbk;
+
+namespace {
+
+thread_local std::string g_err;
+
+gk_status fail(gk_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+#define HIP_TRY(expr)                                                                   \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            return fail(e_ == hipErrorOutOfMemory ? GK_ENOMEM : GK_EDEVICE, "%s: %s (%s:%d)", \
+                        #expr, hipGetErrorString(e_), __FILE__, __LINE__);              \
+    } while (0)
+
+// Restores the caller's current device on scope exit.
+struct DeviceGuard {
+    int prev = -1;
+    hipError_t err = hipSuccess;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        err = hipSetDevice(dev);
+    }
+    ~DeviceGuard()
+    {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+// Scratch budget for the T_j planes of one chunk of rows.
+constexpr size_t kScratchBudget = size_t(1) << 30;
+constexpr size_t kMaxLds = 64 * 1024;
+
+double fwhm_to_sigma(double f) { return f / (2.0 * std::sqrt(2.0 * std::log(2.0))); }
+
+// Unit-sum Gaussian taps at integer offsets -h..h, h = ceil(R sigma); a zero
+// width gives the single tap 1 (eq. 9, one axis).
+std::vector<double> gaussian_taps(double sigma, double R)
+{
+    if (!(sigma > 0.0)) return {1.0};
+    int h = (int)std::ceil(R * sigma);
+    std::vector<double> t(2 * h + 1);
+    double s = 0.0;
+    for (int k = -h; k <= h; ++k) s += (t[k + h] = std::exp(-0.5 * (double)k * k / (sigma * sigma)));
+    for (double &v : t) v /= s;
+    return t;
+}
+
+enum PtrKind { PTR_HOST, PTR_DEVICE, PTR_BAD };
+
+PtrKind pointer_kind(const void *p)
+{
+    hipPointerAttribute_t at;
+    std::memset(&at, 0, sizeof at);
+    hipError_t e = hipPointerGetAttributes(&at, p);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return PTR_HOST;  // unregistered host memory
+    }
+    switch (at.type) {
+    case hipMemoryTypeDevice:
+    case hipMemoryTypeManaged:
+        return PTR_DEVICE;
+    case hipMemoryTypeHost:
+    case hipMemoryTypeUnregistered:
+        return PTR_HOST;
+    default:
+        return PTR_BAD;
+    }
+}
+
+bool row_valid(const double *p, int rc)
+{
+    for (int k = 0; k < NPAR; ++k)
+        if (!std::isfinite(p[k])) return false;
+    if (!(p[P_INC] > 0.0 && p[P_INC] < 90.0)) return false;
+    if (!(p[P_SIG] > 0.0 && p[P_R0] > 0.0 && p[P_RT] > 0.0 && p[P_I0] > 0.0)) return false;
+    if (rc == RC_EPINAT && !(p[P_G] > 0.0 && p[P_A] >= 0.0)) return false;
+    return true;
+}
+
+template <class T> hipError_t dev_alloc(T **p, size_t n)
+{
+    return hipMalloc((void **)p, std::max<size_t>(n, 1) * sizeof(T));
+}
+
+}  // namespace
+
+struct gk_model {
+    gk_model_desc d{};
+    int device = 0;
+    int hp = 0, hl = 0, NX = 0, NY = 0, NZ = 0, EX = 0, EY = 0, NZE = 0;
+    double vf0 = 0, dvf = 0, inv_dvf = 0, vref = 0;
+    int TXd = 0, TYd = 0, ntx = 0, nty = 0, ntiles = 0;
+    size_t lds_bytes = 0;
+    double *d_kp = nullptr, *d_wz = nullptr;
+    // observation
+    bool has_obs = false;
+    int64_t nvalid = 0;
+    float *d_vo = nullptr, *d_so = nullptr;
+    double *d_iev = nullptr, *d_ies = nullptr;
+    uint8_t *d_mask = nullptr;
+    // scratch, sized for `cap` rows
+    int cap = 0;
+    double *d_params = nullptr, *d_consts = nullptr, *d_T = nullptr, *d_partial = nullptr;
+    // pinned staging of host-given rows; ev_staged marks when its last copy is done
+    double *h_params = nullptr;
+    hipEvent_t ev_staged = nullptr;
+    // measurement hooks (gk_set_profiling)
+    int prof_flags = 0;
+    std::vector<std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>>> prof_events;
+    unsigned long long *d_count = nullptr;
+    int64_t prof_rows = 0;
+
+    int chunk_rows() const
+    {
+        size_t per = (size_t)3 * EX * EY * sizeof(double);
+        size_t n = std::max<size_t>(1, kScratchBudget / per);
+        return (int)std::min<size_t>(n, 65535);
+    }
+
+    hipError_t reserve(int rows)
+    {
+        if (rows <= cap) return hipSuccess;
+        (void)hipFree(d_params);
+        (void)hipFree(d_consts);
+        (void)hipFree(d_T);
+        (void)hipFree(d_partial);
+        if (h_params) {
+            if (ev_staged) (void)hipEventSynchronize(ev_staged);
+            (void)hipHostFree(h_params);
+        }
+        d_params = d_consts = d_T = d_partial = h_params = nullptr;
+        cap = 0;
+        hipError_t e;
+        if (!ev_staged && (e = hipEventCreateWithFlags(&ev_staged, hipEventDisableTiming)) != hipSuccess)
+            return e;
+        if ((e = hipHostMalloc((void **)&h_params, sizeof(double) * NPAR * rows, 0)) != hipSuccess)
+            return e;
+        if ((e = dev_alloc(&d_params, (size_t)rows * NPAR)) != hipSuccess) return e;
+        if ((e = dev_alloc(&d_consts, (size_t)rows * NCONST)) != hipSuccess) return e;
+        if ((e = dev_alloc(&d_T, (size_t)rows * 3 * EX * EY)) != hipSuccess) return e;
+        if ((e = dev_alloc(&d_partial, (size_t)rows * ntiles)) != hipSuccess) return e;
+        cap = rows;
+        return hipSuccess;
+    }
+
+    void release()
+    {
+        (void)hipFree(d_kp);
+        (void)hipFree(d_wz);
+        (void)hipFree(d_vo);
+        (void)hipFree(d_so);
+        (void)hipFree(d_iev);
+        (void)hipFree(d_ies);
+        (void)hipFree(d_mask);
+        (void)hipFree(d_params);
+        (void)hipFree(d_consts);
+        (void)hipFree(d_T);
+        (void)hipFree(d_partial);
+        if (h_params) (void)hipHostFree(h_params);
+        if (ev_staged) (void)hipEventDestroy(ev_staged);
+        (void)hipFree(d_count);
+        for (auto &call : prof_events)
+            for (auto &k : call) {
+                (void)hipEventDestroy(k.second.first);
+                (void)hipEventDestroy(k.second.second);
+            }
+    }
+};
+
+namespace {
+
+size_t psf_lds_bytes(int TXd, int TYd, int u, int hp)
+{
+    size_t TX = (size_t)u * TXd, TY = (size_t)u * TYd, LX = TX + 2 * hp, LY = TY + 2 * hp;
+    return sizeof(double) * (LY * LX + LY * TX + (size_t)(2 * hp + 1));
+}
+
+// Picks the data-pixel tile of k_psf_moments: as large as the thread budget
+// and the LDS limit allow, no wider than the image.
+void choose_tile(gk_model *m)
+{
+    int tx = 32, ty = 16;
+    while (tx > 1 && tx >= 2 * m->d.nx) tx /= 2;
+    while (ty > 1 && ty >= 2 * m->d.ny) ty /= 2;
+    while (psf_lds_bytes(tx, ty, m->d.upsample, m->hp) > kMaxLds && (tx > 1 || ty > 1)) {
+        if (tx >= ty && tx > 1) tx /= 2;
+        else ty /= 2;
+    }
+    m->TXd = tx;
+    m->TYd = ty;
+    m->ntx = (m->d.nx + tx - 1) / tx;
+    m->nty = (m->d.ny + ty - 1) / ty;
+    m->ntiles = m->ntx * m->nty;
+    m->lds_bytes = psf_lds_bytes(tx, ty, m->d.upsample, m->hp);
+}
+
+gk_status run_batch(gk_model *m, const double *params, int32_t B, float *maps, double *resid,
+                    double *chi2, int64_t *nvalid, void *stream)
+{
+    if (!m) return fail(GK_EINVAL, "model is NULL");
+    if (B < 0) return fail(GK_EINVAL, "negative batch size %d", B);
+    if (B == 0) return GK_OK;
+    if (!params) return fail(GK_EINVAL, "params is NULL");
+    if ((resid || chi2) && !m->has_obs) return fail(GK_ESTATE, "no observation set");
+    DeviceGuard g(m->device);
+    HIP_TRY(g.err);
+    hipStream_t s = (hipStream_t)stream;
+
+    for (const void *out : {(const void *)maps, (const void *)resid, (const void *)chi2,
+                            (const void *)nvalid}) {
+        if (out && pointer_kind(out) != PTR_DEVICE)
+            return fail(GK_EINVAL, "output arrays must be device memory");
+    }
+    PtrKind pk = pointer_kind(params);
+    if (pk == PTR_BAD) return fail(GK_EINVAL, "params pointer of unknown kind");
+    int n_bad = 0;
+    if (pk == PTR_HOST)
+        for (int b = 0; b < B; ++b) n_bad += !row_valid(params + (size_t)b * NPAR, m->d.rc);
+
+    const int chunk = std::min<int>(B, m->chunk_rows());
+    HIP_TRY(m->reserve(chunk));
+    const bool timing = m->prof_flags & GK_PROF_TIMING;
+    unsigned long long *counter = (m->prof_flags & GK_PROF_COUNT) ? m->d_count : nullptr;
+    if (timing) m->prof_events.emplace_back();
+    // launches kernel `k` through `fn`, bracketed by events when timing
+    auto timed = [&](int k, auto fn) -> hipError_t {
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (timing) {
+            hipError_t e = hipEventCreate(&e0);
+            if (e == hipSuccess) e = hipEventCreate(&e1);
+            if (e == hipSuccess) e = hipEventRecord(e0, s);
+            if (e != hipSuccess) return e;
+        }
+        hipError_t e = fn();
+        if (timing) {
+            if (e == hipSuccess) e = hipEventRecord(e1, s);
+            m->prof_events.back().push_back({k, {e0, e1}});
+        }
+        return e;
+    };
+    if (m->prof_flags) m->prof_rows += B;
+    const size_t npix = (size_t)m->d.nx * m->d.ny;
+    for (int b0 = 0; b0 < B; b0 += chunk) {
+        const int nb = std::min(chunk, B - b0);
+        const double *prow = params + (size_t)b0 * NPAR;
+        if (pk == PTR_HOST) {
+            // the staging buffer is reused: wait for its previous copy only
+            HIP_TRY(hipEventSynchronize(m->ev_staged));
+            std::memcpy(m->h_params, prow, sizeof(double) * NPAR * nb);
+            HIP_TRY(hipMemcpyAsync(m->d_params, m->h_params, sizeof(double) * NPAR * nb,
+                                   hipMemcpyHostToDevice, s));
+            HIP_TRY(hipEventRecord(m->ev_staged, s));
+            prow = m->d_params;
+        }
+        HIP_TRY(timed(0, [&] { return launch_prep(prow, nb, m->d.rc, m->dvf, m->d_consts, s); }));
+        HIP_TRY(timed(1, [&] {
+            return launch_line_sums(m->d_consts, m->d_wz, m->NZE, m->EX, m->EY, m->hp,
+                                    m->d.upsample, m->d.rc, m->vf0, m->inv_dvf, m->d_T, counter,
+                                    nb, s);
+        }));
+        PsfArgs a{};
+        a.T = m->d_T;
+        a.consts = m->d_consts;
+        a.kp = m->d_kp;
+        a.hp = m->hp;
+        a.u = m->d.upsample;
+        a.nx = m->d.nx;
+        a.ny = m->d.ny;
+        a.EX = m->EX;
+        a.EY = m->EY;
+        a.TXd = m->TXd;
+        a.TYd = m->TYd;
+        a.ntx = m->ntx;
+        a.ntiles = m->ntiles;
+        a.dv = m->d.dv_kms;
+        a.vref = m->vref;
+        if (resid || chi2) {
+            a.mask = m->d_mask;
+            a.vo = m->d_vo;
+            a.so = m->d_so;
+            a.iev = m->d_iev;
+            a.ies = m->d_ies;
+        }
+        a.maps = maps ? maps + (size_t)b0 * 3 * npix : nullptr;
+        a.resid = resid ? resid + (size_t)b0 * 2 * npix : nullptr;
+        a.partial = chi2 ? m->d_partial : nullptr;
+        HIP_TRY(timed(2, [&] { return launch_psf_moments(a, nb, m->lds_bytes, s); }));
+        if (chi2)
+            HIP_TRY(timed(3, [&] {
+                return launch_reduce_chi2(m->d_partial, m->ntiles, m->d_consts, m->nvalid,
+                                          chi2 + b0, nvalid ? nvalid + b0 : nullptr, nb, s);
+            }));
+    }
+    return n_bad ? GK_PARTIAL : GK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *gk_last_error(void) { return g_err.c_str(); }
+
+gk_status gk_create_model(const gk_model_desc *desc, int device, gk_model **out)
+{
+    if (!desc || !out) return fail(GK_EINVAL, "desc and out must not be NULL");
+    *out = nullptr;
+    const gk_model_desc &d = *desc;
+    if (d.nx < 1 || d.ny < 1 || d.nz < 1) return fail(GK_EINVAL, "grid sizes must be >= 1");
+    if (d.upsample < 1 || d.upsample > 8) return fail(GK_EINVAL, "upsample must be in 1..8");
+    if (!(d.dv_kms > 0.0) || !std::isfinite(d.dv_kms)) return fail(GK_EINVAL, "dv must be > 0");
+    if (!std::isfinite(d.v0_kms) || !std::isfinite(d.crpix))
+        return fail(GK_EINVAL, "v0 and crpix must be finite");
+    if (!(d.psf_fwhm_pix >= 0.0) || !std::isfinite(d.psf_fwhm_pix) || !(d.lsf_sigma_kms >= 0.0) ||
+        !std::isfinite(d.lsf_sigma_kms))
+        return fail(GK_EINVAL, "PSF FWHM and LSF sigma must be finite and >= 0");
+    if (!(d.kernel_radius_sigma > 0.0) || d.kernel_radius_sigma > 16.0)
+        return fail(GK_EINVAL, "kernel radius must be in (0, 16]");
+    if (d.rc < GK_RC_ARCTAN || d.rc > GK_RC_BOISSIER) return fail(GK_EINVAL, "unknown rotation curve");
+    if (d.reserved != 0) return fail(GK_EINVAL, "reserved field must be 0");
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
+        return fail(GK_EINVAL, "no HIP device %d", device);
+
+    gk_model *m = new (std::nothrow) gk_model();
+    if (!m) return fail(GK_ENOMEM, "host allocation failed");
+    m->d = d;
+    m->device = device;
+    const int u = d.upsample;
+    const double sp = d.psf_fwhm_pix > 0 ? u * fwhm_to_sigma(d.psf_fwhm_pix) : 0.0;
+    const double sl = d.lsf_sigma_kms > 0 ? u * d.lsf_sigma_kms / d.dv_kms : 0.0;
+    std::vector<double> kp = gaussian_taps(sp, d.kernel_radius_sigma);
+    std::vector<double> kl = gaussian_taps(sl, d.kernel_radius_sigma);
+    m->hp = (int)(kp.size() / 2);
+    m->hl = (int)(kl.size() / 2);
+    m->NX = u * d.nx;
+    m->NY = u * d.ny;
+    m->NZ = u * d.nz;
+    m->EX = m->NX + 2 * m->hp;
+    m->EY = m->NY + 2 * m->hp;
+    m->NZE = m->NZ + 2 * m->hl;
+    if ((double)m->EX * m->EY >= 2.0e9 || m->NZE > (1 << 20)) {
+        delete m;
+        return fail(GK_EINVAL, "model grid too large");
+    }
+    m->dvf = d.dv_kms / u;
+    m->inv_dvf = u / d.dv_kms;
+    m->vf0 = d.v0_kms + ((0 - m->hl + 0.5) / u - 0.5 - d.crpix) * d.dv_kms;
+    // reference velocity of the moment sums: the centre of the data band
+    m->vref = d.v0_kms + (0.5 * (d.nz - 1) - d.crpix) * d.dv_kms;
+
+    // W_j(z') = (1/u) sum_{m in [0, NZ)} vrel(m/u)^j K_z[m + 2 hl - z']
+    std::vector<double> wz((size_t)4 * m->NZE, 0.0);  // [NZE][4] = {W0, W1, W2, 0}
+    for (int zp = 0; zp < m->NZE; ++zp) {
+        double w0 = 0, w1 = 0, w2 = 0;
+        for (int t = 0; t <= 2 * m->hl; ++t) {
+            int mm = zp + t - 2 * m->hl;  // fine window channel reached by tap t
+            if (mm < 0 || mm >= m->NZ) continue;
+            double vr = (mm / u - 0.5 * (d.nz - 1)) * d.dv_kms;
+            double k = kl[t];
+            w0 += k;
+            w1 += k * vr;
+            w2 += k * vr * vr;
+        }
+        wz[4 * (size_t)zp + 0] = w0 / u;
+        wz[4 * (size_t)zp + 1] = w1 / u;
+        wz[4 * (size_t)zp + 2] = w2 / u;
+    }
+    choose_tile(m);
+    if (m->lds_bytes > kMaxLds) {
+        delete m;
+        return fail(GK_EINVAL, "PSF too wide for the direct convolution path");
+    }
+
+    DeviceGuard g(device);
+    hipError_t e = g.err;
+    if (e == hipSuccess) e = dev_alloc(&m->d_kp, kp.size());
+    if (e == hipSuccess) e = dev_alloc(&m->d_wz, wz.size());
+    if (e == hipSuccess)
+        e = hipMemcpy(m->d_kp, kp.data(), kp.size() * sizeof(double), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(m->d_wz, wz.data(), wz.size() * sizeof(double), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        m->release();
+        delete m;
+        return fail(e == hipErrorOutOfMemory ? GK_ENOMEM : GK_EDEVICE, "create_model: %s",
+                    hipGetErrorString(e));
+    }
+    *out = m;
+    return GK_OK;
+}
+
+gk_status gk_destroy_model(gk_model *m)
+{
+    if (!m) return GK_OK;
+    {
+        DeviceGuard g(m->device);
+        (void)hipDeviceSynchronize();
+        m->release();
+    }
+    delete m;
+    return GK_OK;
+}
+
+gk_status gk_set_profiling(gk_model *m, int flags)
+{
+    if (!m) return fail(GK_EINVAL, "model is NULL");
+    if (flags & ~(GK_PROF_TIMING | GK_PROF_COUNT)) return fail(GK_EINVAL, "unknown profiling flag");
+    DeviceGuard g(m->device);
+    HIP_TRY(g.err);
+    if ((flags & GK_PROF_COUNT) && !m->d_count) {
+        HIP_TRY(hipMalloc((void **)&m->d_count, sizeof(unsigned long long)));
+        HIP_TRY(hipMemset(m->d_count, 0, sizeof(unsigned long long)));
+    }
+    m->prof_flags = flags;
+    return GK_OK;
+}
+
+gk_status gk_read_profile(gk_model *m, gk_profile_stats *out)
+{
+    if (!m || !out) return fail(GK_EINVAL, "NULL argument");
+    DeviceGuard g(m->device);
+    HIP_TRY(g.err);
+    std::memset(out, 0, sizeof *out);
+    hipError_t err = hipSuccess;
+    for (auto &call : m->prof_events)
+        for (auto &k : call) {
+            float ms = 0.0f;
+            hipError_t e = hipEventSynchronize(k.second.second);
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, k.second.first, k.second.second);
+            if (e == hipSuccess) {
+                out->kernel_ms[k.first] += ms;
+                out->launches[k.first] += 1;
+            } else if (err == hipSuccess) {
+                err = e;
+            }
+            (void)hipEventDestroy(k.second.first);
+            (void)hipEventDestroy(k.second.second);
+        }
+    m->prof_events.clear();
+    if (m->d_count) {
+        unsigned long long c = 0;
+        HIP_TRY(hipDeviceSynchronize());
+        HIP_TRY(hipMemcpy(&c, m->d_count, sizeof c, hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemset(m->d_count, 0, sizeof c));
+        out->support_voxels = (int64_t)c;
+    }
+    out->rows = m->prof_rows;
+    m->prof_rows = 0;
+    HIP_TRY(err);
+    return GK_OK;
+}
+
+gk_status gk_model_dims(const gk_model *m, int32_t dims[5])
+{
+    if (!m || !dims) return fail(GK_EINVAL, "NULL argument");
+    dims[0] = m->EX;
+    dims[1] = m->EY;
+    dims[2] = m->NZE;
+    dims[3] = m->hp;
+    dims[4] = m->hl;
+    return GK_OK;
+}
+
+gk_status gk_set_observation(gk_model *m, const float *vel, const float *sig, const float *evel,
+                             const float *esig, const uint8_t *mask, double W)
+{
+    if (!m || !vel || !evel || !mask) return fail(GK_EINVAL, "NULL observation array");
+    if (!(W >= 0.0) || !std::isfinite(W)) return fail(GK_EINVAL, "W must be finite and >= 0");
+    if (W > 0.0 && (!sig || !esig)) return fail(GK_EINVAL, "dispersion maps needed when W > 0");
+    const size_t n = (size_t)m->d.nx * m->d.ny;
+    std::vector<float> vo(n), so(n, 0.0f);
+    std::vector<double> iev(n, 0.0), ies(n, 0.0);
+    std::vector<uint8_t> mk(n);
+    int64_t nv = 0;
+    const double sw = std::sqrt(W);
+    for (size_t i = 0; i < n; ++i) {
+        mk[i] = mask[i] ? 1 : 0;
+        vo[i] = vel[i];
+        if (sig) so[i] = sig[i];
+        if (!mk[i]) continue;
+        if (!std::isfinite(vel[i]) || !std::isfinite(evel[i]) || !(evel[i] > 0.0f))
+            return fail(GK_EINVAL, "pixel %zu: velocity or its error invalid", i);
+        iev[i] = 1.0 / (double)evel[i];
+        if (W > 0.0) {
+            if (!std::isfinite(sig[i]) || !std::isfinite(esig[i]) || !(esig[i] > 0.0f))
+                return fail(GK_EINVAL, "pixel %zu: dispersion or its error invalid", i);
+            ies[i] = sw / (double)esig[i];
+        }
+        ++nv;
+    }
+    DeviceGuard g(m->device);
+    HIP_TRY(g.err);
+    if (!m->d_vo) {
+        HIP_TRY(dev_alloc(&m->d_vo, n));
+        HIP_TRY(dev_alloc(&m->d_so, n));
+        HIP_TRY(dev_alloc(&m->d_iev, n));
+        HIP_TRY(dev_alloc(&m->d_ies, n));
+        HIP_TRY(dev_alloc(&m->d_mask, n));
+    }
+    HIP_TRY(hipDeviceSynchronize());  // no pending kernel may still read the old observation
+    HIP_TRY(hipMemcpy(m->d_vo, vo.data(), n * sizeof(float), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(m->d_so, so.data(), n * sizeof(float), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(m->d_iev, iev.data(), n * sizeof(double), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(m->d_ies, ies.data(), n * sizeof(double), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(m->d_mask, mk.data(), n, hipMemcpyHostToDevice));
+    m->nvalid = nv;
+    m->has_obs = true;
+    return GK_OK;
+}
+
+gk_status gk_observation_count(const gk_model *m, int64_t *n_valid)
+{
+    if (!m || !n_valid) return fail(GK_EINVAL, "NULL argument");
+    if (!m->has_obs) return fail(GK_ESTATE, "no observation set");
+    *n_valid = m->nvalid;
+    return GK_OK;
+}
+
+gk_status gk_evaluate_batch(gk_model *m, const double *params, int32_t B, float *maps,
+                            void *stream)
+{
+    if (!maps && B > 0) return fail(GK_EINVAL, "maps is NULL");
+    return run_batch(m, params, B, maps, nullptr, nullptr, nullptr, stream);
+}
+
+gk_status gk_chi2_batch(gk_model *m, const double *params, int32_t B, double *chi2,
+                        int64_t *n_valid, void *stream)
+{
+    if (!chi2 && B > 0) return fail(GK_EINVAL, "chi2 is NULL");
+    return run_batch(m, params, B, nullptr, nullptr, chi2, n_valid, stream);
+}
+
+gk_status gk_residual_batch(gk_model *m, const double *params, int32_t B, double *resid,
+                            void *stream)
+{
+    if (!resid && B > 0) return fail(GK_EINVAL, "resid is NULL");
+    return run_batch(m, params, B, nullptr, resid, nullptr, nullptr, stream);
+}
+
+}  // extern "C"

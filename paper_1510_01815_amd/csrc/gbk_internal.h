@@ -1,0 +1,53 @@
+// gbk_internal.h -- private declarations shared by the kernels and the
+// runtime of libgbk.so (not part of the C ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gbk {
+
+// parameter slots of a row (same order as the public enum)
+enum { P_XO = 0, P_YO, P_PA, P_INC, P_VSYS, P_VT, P_RT, P_SIG, P_R0, P_I0, P_A, P_G, NPAR };
+enum { RC_ARCTAN = 0, RC_EPINAT = 1, RC_BOISSIER = 2 };
+
+// per-row constants written by k_prep (FP64)
+enum {
+    C_XO = 0, C_YO, C_SPA, C_CPA, C_SECI, C_SINI, C_VSYS, C_VT, C_IRT, C_IR0, C_AMP, C_KAPPA,
+    C_A, C_G, C_VALID, C_ZSPAN, C_SQK, NCONST
+};
+
+// A fine channel further than sqrt(kZSpanLog2 / kappa) from the line centre
+// carries less than 2^-kZSpanLog2 of the line peak and is skipped.
+constexpr double kZSpanLog2 = 64.0;
+
+// data pixels handled by one thread of k_psf_moments (tile <= 256 * this)
+constexpr int kMaxPixPerThread = 4;
+
+struct PsfArgs {
+    const double *T;       // [B][3][EY][EX]
+    const double *consts;  // [B][NCONST]
+    const double *kp;      // PSF taps, 2hp+1
+    int hp, u, nx, ny, EX, EY;
+    int TXd, TYd, ntx, ntiles;
+    double dv, vref;
+    // observation (mask == nullptr: no observation, no chi2 or residuals)
+    const uint8_t *mask;
+    const float *vo, *so;
+    const double *iev, *ies;
+    // outputs (nullable)
+    float *maps;      // [B][3][ny][nx]
+    double *resid;    // [B][2][ny][nx]
+    double *partial;  // [B][ntiles]
+};
+
+hipError_t launch_prep(const double *params, int B, int rc, double dvf, double *consts,
+                       hipStream_t s);
+hipError_t launch_line_sums(const double *consts, const double *wz, int NZE, int EX, int EY,
+                            int hp, int u, int rc, double vf0, double inv_dvf, double *T,
+                            unsigned long long *support_count, int B, hipStream_t s);
+hipError_t launch_psf_moments(const PsfArgs &a, int B, size_t lds_bytes, hipStream_t s);
+hipError_t launch_reduce_chi2(const double *partial, int ntiles, const double *consts,
+                              int64_t nvalid_obs, double *chi2, int64_t *nvalid, int B,
+                              hipStream_t s);
+
+}  // namespace gbk

@@ -1,0 +1,213 @@
+"""ctypes binding of libgbk.so (C ABI in include/gbk.h).
+
+Argument marshalling only: every step of the evaluation runs in the HIP
+library.  PyTorch provides device memory and streams (``data_ptr()`` and
+``torch.cuda.current_stream().cuda_stream``).  Importing this module does not
+need a GPU; loading the library does, and a missing library raises at once
+(there is no CPU fallback).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libgbk.so")
+
+GK_OK, GK_PARTIAL, GK_EINVAL, GK_ENOMEM, GK_EDEVICE, GK_ENOTCONV, GK_ESTATE = 0, 1, -1, -2, -3, -4, -5
+NPAR = 12
+RC = {"arctan": 0, "epinat": 1, "boissier": 2}
+
+# exported symbols, kept in step with include/gbk.h
+SYMBOLS = (
+    "gk_create_model", "gk_destroy_model", "gk_set_observation", "gk_observation_count",
+    "gk_evaluate_batch", "gk_chi2_batch", "gk_residual_batch", "gk_model_dims", "gk_last_error",
+    "gk_set_profiling", "gk_read_profile",
+)
+GK_PROF_TIMING, GK_PROF_COUNT = 1, 2
+
+
+class GkError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"gbk status {status}: {msg}")
+        self.status = status
+
+
+class ModelDesc(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("upsample", ctypes.c_int32), ("dv_kms", ctypes.c_double),
+                ("v0_kms", ctypes.c_double), ("crpix", ctypes.c_double),
+                ("psf_fwhm_pix", ctypes.c_double), ("lsf_sigma_kms", ctypes.c_double),
+                ("kernel_radius_sigma", ctypes.c_double), ("rc", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class ProfileStats(ctypes.Structure):
+    _fields_ = [("kernel_ms", ctypes.c_double * 4), ("launches", ctypes.c_int64 * 4),
+                ("support_voxels", ctypes.c_int64), ("rows", ctypes.c_int64)]
+
+
+KERNEL_NAMES = ("k_prep", "k_line_sums", "k_psf_moments", "k_reduce_chi2")
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Loads libgbk.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise FileNotFoundError(f"{path} is missing: build it with __graft_entry__.build() "
+                                "(hipcc --offload-arch=gfx950)")
+    L = ctypes.CDLL(path)
+    vp, i32, i64p, dp = ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64), ctypes.c_double
+    L.gk_create_model.argtypes = [ctypes.POINTER(ModelDesc), ctypes.c_int, ctypes.POINTER(vp)]
+    L.gk_destroy_model.argtypes = [vp]
+    L.gk_set_observation.argtypes = [vp, vp, vp, vp, vp, vp, dp]
+    L.gk_observation_count.argtypes = [vp, i64p]
+    L.gk_evaluate_batch.argtypes = [vp, vp, i32, vp, vp]
+    L.gk_chi2_batch.argtypes = [vp, vp, i32, vp, vp, vp]
+    L.gk_residual_batch.argtypes = [vp, vp, i32, vp, vp]
+    L.gk_model_dims.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
+    L.gk_set_profiling.argtypes = [vp, ctypes.c_int]
+    L.gk_read_profile.argtypes = [vp, ctypes.POINTER(ProfileStats)]
+    L.gk_last_error.restype = ctypes.c_char_p
+    for name in SYMBOLS:
+        if name != "gk_last_error":
+            getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(st: int, allow_partial: bool = True) -> int:
+    if st < 0:
+        raise GkError(st, load().gk_last_error().decode())
+    if st == GK_PARTIAL and not allow_partial:
+        raise GkError(st, "rows out of domain")
+    return st
+
+
+def _stream_ptr(stream=None) -> int:
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return s.cuda_stream
+
+
+def _params_arg(params):
+    """(pointer, B, keepalive) for a [B][12] float64 host array or CUDA tensor."""
+    try:
+        import torch
+        if isinstance(params, torch.Tensor):
+            if params.dtype != torch.float64 or params.dim() != 2 or params.shape[1] != NPAR:
+                raise ValueError("params must be a [B][12] float64 tensor")
+            params = params.contiguous()
+            return params.data_ptr(), params.shape[0], params
+    except ImportError:
+        pass
+    a = np.ascontiguousarray(params, dtype=np.float64).reshape(-1, NPAR)
+    return a.ctypes.data, a.shape[0], a
+
+
+class Model:
+    """One instrument grid on one device; see gk_create_model."""
+
+    def __init__(self, nx, ny, nz, dv, psf_fwhm=0.0, lsf_sigma=0.0, u=1, v0=0.0, crpix=None,
+                 R=4.0, rc=0, device=0):
+        L = load()
+        if isinstance(rc, str):
+            rc = RC[rc]
+        self.desc = ModelDesc(nx, ny, nz, u, dv, v0, nz / 2.0 if crpix is None else crpix,
+                              psf_fwhm, lsf_sigma, R, rc, 0)
+        self.nx, self.ny, self.nz, self.device = nx, ny, nz, device
+        h = ctypes.c_void_p()
+        _check(L.gk_create_model(ctypes.byref(self.desc), device, ctypes.byref(h)))
+        self._h = h
+
+    @classmethod
+    def from_grid(cls, grid, device=0):
+        d = grid.as_dict() if hasattr(grid, "as_dict") else dict(grid)
+        return cls(d["nx"], d["ny"], d["nz"], d["dv"], d["psf_fwhm"], d["lsf_sigma"], d["u"],
+                   d["v0"], d["crpix"], d["R"], d["rc"], device)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().gk_destroy_model(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def dims(self):
+        d = (ctypes.c_int32 * 5)()
+        _check(load().gk_model_dims(self._h, d))
+        return tuple(d)
+
+    def set_observation(self, vel, sig, evel, esig, mask, W=1.0):
+        f = lambda a: np.ascontiguousarray(a, dtype=np.float32)
+        vel, evel = f(vel), f(evel)
+        sig = None if sig is None else f(sig)
+        esig = None if esig is None else f(esig)
+        mask = np.ascontiguousarray(mask, dtype=np.uint8)
+        self._obs = (vel, sig, evel, esig, mask)
+        ptr = lambda a: None if a is None else a.ctypes.data
+        _check(load().gk_set_observation(self._h, ptr(vel), ptr(sig), ptr(evel), ptr(esig),
+                                         ptr(mask), float(W)))
+
+    def set_obs(self, obs):
+        self.set_observation(obs.vel, obs.sig, obs.evel, obs.esig, obs.mask, obs.W)
+
+    def n_valid(self) -> int:
+        n = ctypes.c_int64()
+        _check(load().gk_observation_count(self._h, ctypes.byref(n)))
+        return n.value
+
+    def evaluate(self, params, out=None, stream=None):
+        """maps [B][3][ny][nx] float32 CUDA tensor (m0, m1, m2)."""
+        import torch
+        p, B, keep = _params_arg(params)
+        if out is None:
+            out = torch.empty((B, 3, self.ny, self.nx), dtype=torch.float32,
+                              device=f"cuda:{self.device}")
+        self.last_status = _check(load().gk_evaluate_batch(self._h, p, B, out.data_ptr(),
+                                                           _stream_ptr(stream)))
+        return out
+
+    def chi2(self, params, out=None, n_valid=None, stream=None):
+        """(chi2 [B] float64, n_valid [B] int64) CUDA tensors."""
+        import torch
+        p, B, keep = _params_arg(params)
+        dev = f"cuda:{self.device}"
+        if out is None:
+            out = torch.empty(B, dtype=torch.float64, device=dev)
+        if n_valid is None:
+            n_valid = torch.empty(B, dtype=torch.int64, device=dev)
+        self.last_status = _check(load().gk_chi2_batch(self._h, p, B, out.data_ptr(),
+                                                       n_valid.data_ptr(), _stream_ptr(stream)))
+        return out, n_valid
+
+    def set_profiling(self, flags: int):
+        _check(load().gk_set_profiling(self._h, flags))
+
+    def read_profile(self) -> dict:
+        st = ProfileStats()
+        _check(load().gk_read_profile(self._h, ctypes.byref(st)))
+        return {"kernel_ms": dict(zip(KERNEL_NAMES, st.kernel_ms)),
+                "launches": dict(zip(KERNEL_NAMES, st.launches)),
+                "support_voxels": st.support_voxels, "rows": st.rows}
+
+    def residuals(self, params, out=None, stream=None):
+        """resid [B][2][ny][nx] float64 CUDA tensor."""
+        import torch
+        p, B, keep = _params_arg(params)
+        if out is None:
+            out = torch.empty((B, 2, self.ny, self.nx), dtype=torch.float64,
+                              device=f"cuda:{self.device}")
+        self.last_status = _check(load().gk_residual_batch(self._h, p, B, out.data_ptr(),
+                                                           _stream_ptr(stream)))
+        return out
