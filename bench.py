@@ -25,14 +25,14 @@ sys.path.insert(0, ROOT)
 METRIC = "model evals/s (cube+PSF+moments+χ²); fits/hour, surrogate vs plain"
 BATCH = 400
 
-# MI355X: 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz = 3.93e13 VALU lane-ops/s;
-# one FP64 FMA per lane-op slot = 78.6 TFLOP/s (packed FP32 is not used).
+# MI355X FP64 vector peak: 256 CUs x 64 lanes x 2.4 GHz x 2 FLOP (FMA)
+# = 78.6 TFLOP/s.  The dominant kernel, k_line_sums, runs its per-voxel work in
+# FP64; packed FP32 is not used anywhere.
 LANE_OPS_PER_S = 256 * 64 * 2.4e9
 PEAK_TFLOPS = 2 * LANE_OPS_PER_S / 1e12
-# VALU lane-op slots per line-support voxel of k_line_sums: e += sqrt(kappa),
-# e*e, f64->f32, exp2, f32->f64, 3 FMA (exp2 counted as TRANS_SLOTS slots)
-TRANS_SLOTS = 1
-SLOTS_PER_VOXEL = 7 + TRANS_SLOTS
+# FP64 FLOP per line-support voxel: the profile by the ratio recurrence
+# (g *= r, r *= q: 2 FLOP) and three weighted sums (3 FMA: 6 FLOP)
+FLOP_PER_VOXEL = 8
 
 
 def parse():
@@ -41,22 +41,25 @@ def parse():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-rows-per-thread", type=int, default=12)
+    ap.add_argument("--cpu-rows-per-thread", type=int, default=40)
     return ap.parse_args()
 
 
-def cpu_baseline(grid, rows, obs, rows_per_thread):
-    """The FP64 oracle (untuned) on a bounded sample of the same workload."""
+def cpu_baseline(grid, first_row, obs, rows_per_thread):
+    """The FP64 oracle (untuned) on a bounded sample of the same workload:
+    `first_row` (also evaluated on the GPU, for a cross-check) plus rows drawn
+    like the timed batches."""
     from concurrent.futures import ThreadPoolExecutor
 
     from oracle import oracle as O
+    from paper_1510_01815_amd import inputs as I
     sys.path.insert(0, os.path.join(ROOT, "tests"))
     from parity import oracle_desc
     O.lib()
     d = oracle_desc(O, grid.as_dict())
     threads = max(1, min(16, os.cpu_count() or 1))
     n = threads * rows_per_thread
-    sample = rows[:n]
+    sample = np.concatenate([first_row[None, :], I.c2_draw(I.rng_for(2, 0, 3), n - 1)])
 
     def one(r):
         return O.eval_chi2(d, r, obs.vel, obs.sig, obs.evel, obs.esig, obs.mask, obs.W)[0]
@@ -66,8 +69,8 @@ def cpu_baseline(grid, rows, obs, rows_per_thread):
         res = list(ex.map(one, sample))
     dt = time.perf_counter() - t0
     return {"value": n / dt, "unit": "evals/s", "cores": threads, "kind": "oracle",
-            "sample": f"{n} rows of the first batch ({rows_per_thread} per thread), "
-                      f"FP64 literal cube pipeline, {dt:.2f} s wall",
+            "sample": f"{n} rows drawn like the timed batches ({rows_per_thread} per thread), "
+                      f"FP64 literal cube pipeline, {dt:.2f} s wall, {dt * threads:.1f} CPU-s",
             "chi2_first": res[0]}
 
 
@@ -131,14 +134,14 @@ def main():
 
     k_ms = prof["kernel_ms"]["k_line_sums"] / max(prof["launches"]["k_line_sums"], 1)
     vox_per_launch = cnt["support_voxels"] / K
-    flop_per_launch = vox_per_launch * SLOTS_PER_VOXEL * 2
+    flop_per_launch = vox_per_launch * FLOP_PER_VOXEL
     achieved = flop_per_launch / (k_ms * 1e-3) / 1e12
     roofline = {"bound": "alu", "kernel": "k_line_sums", "achieved": round(achieved, 3),
                 "peak": round(PEAK_TFLOPS, 1), "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK_TFLOPS, 4), "traffic": None,
                 "kernel_ms_avg": round(k_ms, 5),
                 "support_voxels_per_launch": int(vox_per_launch),
-                "flop_per_voxel": SLOTS_PER_VOXEL * 2}
+                "flop_per_voxel": FLOP_PER_VOXEL}
     per_kernel_ms = {n: round(prof["kernel_ms"][n] / max(prof["launches"][n], 1), 5)
                      for n in gbk.KERNEL_NAMES}
 
@@ -153,7 +156,7 @@ def main():
                       "rotation_curve": "exponential rise", "parallelism": "single GPU"},
            "roofline": roofline, "kernel_ms_per_launch": per_kernel_ms}
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(grid, batches[W].cpu().numpy(), obs,
+        out["cpu_baseline"] = cpu_baseline(grid, batches[W, 0].cpu().numpy(), obs,
                                            args.cpu_rows_per_thread)
         gpu_first = float(chi2[W, 0].item())
         cb = out["cpu_baseline"].pop("chi2_first")

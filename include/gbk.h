@@ -135,8 +135,8 @@ gk_status gk_residual_batch(gk_model *model, const double *params, int32_t B, do
  * flags: GK_PROF_TIMING brackets every kernel launch of the following calls
  * with HIP events on the caller's stream; GK_PROF_COUNT makes the line-profile
  * kernel count, per row, the fine voxels inside each spaxel's line support
- * (channels within sqrt(64 / kappa) of the line centre, i.e. where the
- * Gaussian of Sec. 2.2.2 exceeds 2^-64 of its peak), which is the work the
+ * (channels within sqrt(40 / kappa) of the line centre, i.e. where the
+ * Gaussian of Sec. 2.2.2 exceeds 2^-40 of its peak), which is the work the
  * evaluation has to do.  Counting adds atomics, so it is meant for an
  * untimed pass.  gk_read_profile waits for the recorded work, returns the
  * totals since the last read and clears them.  Kernel index: 0 = per-row

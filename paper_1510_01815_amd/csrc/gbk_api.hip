@@ -151,6 +151,11 @@ struct gk_model {
         return (int)std::min<size_t>(n, 65535);
     }
 
+    size_t count_slots() const
+    {
+        return (size_t)chunk_rows() * ((EX + 15) / 16) * ((EY + 15) / 16) * 4;
+    }
+
     hipError_t reserve(int rows)
     {
         if (rows <= cap) return hipSuccess;
@@ -209,10 +214,32 @@ size_t psf_lds_bytes(int TXd, int TYd, int u, int hp)
     return sizeof(double) * (LY * LX + LY * TX + (size_t)(2 * hp + 1));
 }
 
-// Picks the data-pixel tile of k_psf_moments: as large as the thread budget
-// and the LDS limit allow, no wider than the image.
+// Picks the data-pixel tile of the PSF/moment kernel.  u = 1 with an image
+// of at least 32 x 32 takes the register-blocked 32 x 32 kernel; otherwise
+// the tile is as large as the thread budget and the LDS limit allow, and no
+// wider than the image.
+// LDS of the register-blocked u = 1 kernel: padded rows, see k_psf_moments_u1
+size_t psf_u1_lds_bytes(int TX, int hp)
+{
+    auto pad = [](int n) { return n + ((1 - n) % 4 + 4) % 4; };
+    const size_t LY = 32 + 2 * hp;
+    return sizeof(double) * (LY * pad(TX + 2 * hp) + LY * pad(TX));
+}
+
 void choose_tile(gk_model *m)
 {
+    if (m->d.upsample == 1 && m->d.nx >= 32 && m->d.ny >= 32 && m->hp <= kMaxFastHalo) {
+        const int tx = 32;
+        if (psf_u1_lds_bytes(tx, m->hp) <= kMaxLds) {
+            m->TXd = tx;
+            m->TYd = 32;
+            m->ntx = (m->d.nx + tx - 1) / tx;
+            m->nty = (m->d.ny + 31) / 32;
+            m->ntiles = m->ntx * m->nty;
+            m->lds_bytes = psf_u1_lds_bytes(tx, m->hp);
+            return;
+        }
+    }
     int tx = 32, ty = 16;
     while (tx > 1 && tx >= 2 * m->d.nx) tx /= 2;
     while (ty > 1 && ty >= 2 * m->d.ny) ty /= 2;
@@ -286,7 +313,9 @@ gk_status run_batch(gk_model *m, const double *params, int32_t B, float *maps, d
             HIP_TRY(hipEventRecord(m->ev_staged, s));
             prow = m->d_params;
         }
-        HIP_TRY(timed(0, [&] { return launch_prep(prow, nb, m->d.rc, m->dvf, m->d_consts, s); }));
+        HIP_TRY(timed(0, [&] {
+            return launch_prep(prow, nb, m->d.rc, m->dvf, m->hp, m->d.upsample, m->d_consts, s);
+        }));
         HIP_TRY(timed(1, [&] {
             return launch_line_sums(m->d_consts, m->d_wz, m->NZE, m->EX, m->EY, m->hp,
                                     m->d.upsample, m->d.rc, m->vf0, m->inv_dvf, m->d_T, counter,
@@ -442,8 +471,10 @@ gk_status gk_set_profiling(gk_model *m, int flags)
     DeviceGuard g(m->device);
     HIP_TRY(g.err);
     if ((flags & GK_PROF_COUNT) && !m->d_count) {
-        HIP_TRY(hipMalloc((void **)&m->d_count, sizeof(unsigned long long)));
-        HIP_TRY(hipMemset(m->d_count, 0, sizeof(unsigned long long)));
+        // one counter per (row, wave) of the largest chunk
+        const size_t n = m->count_slots();
+        HIP_TRY(hipMalloc((void **)&m->d_count, n * sizeof(unsigned long long)));
+        HIP_TRY(hipMemset(m->d_count, 0, n * sizeof(unsigned long long)));
     }
     m->prof_flags = flags;
     return GK_OK;
@@ -472,11 +503,15 @@ gk_status gk_read_profile(gk_model *m, gk_profile_stats *out)
         }
     m->prof_events.clear();
     if (m->d_count) {
-        unsigned long long c = 0;
+        const size_t n = m->count_slots();
+        std::vector<unsigned long long> c(n);
         HIP_TRY(hipDeviceSynchronize());
-        HIP_TRY(hipMemcpy(&c, m->d_count, sizeof c, hipMemcpyDeviceToHost));
-        HIP_TRY(hipMemset(m->d_count, 0, sizeof c));
-        out->support_voxels = (int64_t)c;
+        HIP_TRY(hipMemcpy(c.data(), m->d_count, n * sizeof(unsigned long long),
+                          hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemset(m->d_count, 0, n * sizeof(unsigned long long)));
+        unsigned long long tot = 0;
+        for (unsigned long long v : c) tot += v;
+        out->support_voxels = (int64_t)tot;
     }
     out->rows = m->prof_rows;
     m->prof_rows = 0;

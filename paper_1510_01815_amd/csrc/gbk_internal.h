@@ -12,16 +12,21 @@ enum { RC_ARCTAN = 0, RC_EPINAT = 1, RC_BOISSIER = 2 };
 
 // per-row constants written by k_prep (FP64)
 enum {
-    C_XO = 0, C_YO, C_SPA, C_CPA, C_SECI, C_SINI, C_VSYS, C_VT, C_IRT, C_IR0, C_AMP, C_KAPPA,
-    C_A, C_G, C_VALID, C_ZSPAN, C_SQK, NCONST
+    C_XO = 0, C_YO, C_SPA, C_CPA, C_SECI, C_SINI, C_VSYS, C_VT, C_IRT, C_IR0, C_LOG2AMP, C_KAPPA,
+    C_A, C_G, C_VALID, C_ZSPAN, C_SQK, C_Q, C_VTSINI, C_XEX, C_XEY, C_XE0, C_YEX, C_YEY, C_YE0,
+    NCONST
 };
 
 // A fine channel further than sqrt(kZSpanLog2 / kappa) from the line centre
-// carries less than 2^-kZSpanLog2 of the line peak and is skipped.
-constexpr double kZSpanLog2 = 64.0;
+// carries less than 2^-kZSpanLog2 of the line peak and is skipped: the mass
+// dropped is below 1e-12 of the line, far under what the moment maps resolve.
+constexpr double kZSpanLog2 = 40.0;
 
 // data pixels handled by one thread of k_psf_moments (tile <= 256 * this)
 constexpr int kMaxPixPerThread = 4;
+
+// largest PSF half-width (fine pixels) of the register-blocked u = 1 kernel
+constexpr int kMaxFastHalo = 16;
 
 struct PsfArgs {
     const double *T;       // [B][3][EY][EX]
@@ -40,8 +45,8 @@ struct PsfArgs {
     double *partial;  // [B][ntiles]
 };
 
-hipError_t launch_prep(const double *params, int B, int rc, double dvf, double *consts,
-                       hipStream_t s);
+hipError_t launch_prep(const double *params, int B, int rc, double dvf, int hp, int u,
+                       double *consts, hipStream_t s);
 hipError_t launch_line_sums(const double *consts, const double *wz, int NZE, int EX, int EY,
                             int hp, int u, int rc, double vf0, double inv_dvf, double *T,
                             unsigned long long *support_count, int B, hipStream_t s);

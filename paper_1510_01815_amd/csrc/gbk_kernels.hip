@@ -35,6 +35,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <array>
+#include <utility>
+
 #include "gbk_internal.h"
 
 namespace gbk {
@@ -46,8 +49,8 @@ constexpr double kPi = 3.14159265358979323846;
 // ---------------------------------------------------------------------------
 // k_prep: per-row constants (FP64) -- slot layout in gbk_internal.h
 // ---------------------------------------------------------------------------
-__global__ void k_prep(const double *__restrict__ params, int B, int rc, double dvf,
-                       double *__restrict__ consts)
+__global__ void k_prep(const double *__restrict__ params, int B, int rc, double dvf, int hp,
+                       int u, double *__restrict__ consts)
 {
     int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= B) return;
@@ -76,34 +79,77 @@ __global__ void k_prep(const double *__restrict__ params, int B, int rc, double 
     c[C_VT] = p[P_VT];
     c[C_IRT] = 1.0 / p[P_RT];
     c[C_IR0] = 1.0 / p[P_R0];
-    c[C_AMP] = p[P_I0] * kInvSqrt2Pi / sig;
+    c[C_LOG2AMP] = log2(p[P_I0] * kInvSqrt2Pi / sig);
     c[C_KAPPA] = kappa;
     c[C_A] = p[P_A];
     c[C_G] = p[P_G];
     c[C_VALID] = 1.0;
     c[C_ZSPAN] = sqrt(kZSpanLog2 / kappa);
     c[C_SQK] = sqrt(kappa);
+    c[C_Q] = exp2(-2.0 * kappa);
+    c[C_VTSINI] = p[P_VT] * sin(inc);
+    // fine pixel (gx, gy) of the halo-extended grid sits at x = gx/u + base
+    const double invu = 1.0 / u, base = (0.5 - hp) * invu - 0.5;
+    const double sp = c[C_SPA], cp = c[C_CPA], se = c[C_SECI];
+    const double bx = base - p[P_XO], by = base - p[P_YO];
+    c[C_XEX] = -invu * sp;                       // x_e = -dx sin PA + dy cos PA   (eq. 1)
+    c[C_XEY] = invu * cp;
+    c[C_XE0] = -bx * sp + by * cp;
+    c[C_YEX] = -invu * cp * se;                  // y_e / cos i, eqs. 2-3
+    c[C_YEY] = -invu * sp * se;
+    c[C_YE0] = (-bx * cp - by * sp) * se;
 }
 
 // ---------------------------------------------------------------------------
-// wave-wide integer min / max (wave64, butterfly over all 64 lanes)
+// Wave-wide (wave64) minimum of two small non-negative integers at once:
+// a and b (< 65536) are packed into one register and reduced with packed
+// 16-bit minima, DPP within each row of 16 lanes, then the four row results
+// through scalar registers.  The results are uniform.
 // ---------------------------------------------------------------------------
-__device__ inline int wave_min(int v)
+__device__ inline void wave_min2(int a, int b, int &amin, int &bmin)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
-    return v;
+    typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+    auto pmin = [](unsigned x, unsigned y) {
+        u16x2 r = __builtin_elementwise_min(__builtin_bit_cast(u16x2, x),
+                                            __builtin_bit_cast(u16x2, y));
+        return __builtin_bit_cast(unsigned, r);
+    };
+    unsigned v = (unsigned)a | ((unsigned)b << 16);
+    v = pmin(v, __builtin_amdgcn_update_dpp(v, v, 0xB1, 0xF, 0xF, false));   // quad_perm 1,0,3,2
+    v = pmin(v, __builtin_amdgcn_update_dpp(v, v, 0x4E, 0xF, 0xF, false));   // quad_perm 2,3,0,1
+    v = pmin(v, __builtin_amdgcn_update_dpp(v, v, 0x124, 0xF, 0xF, false));  // row_ror 4
+    v = pmin(v, __builtin_amdgcn_update_dpp(v, v, 0x128, 0xF, 0xF, false));  // row_ror 8
+    const unsigned r0 = __builtin_amdgcn_readlane(v, 0), r1 = __builtin_amdgcn_readlane(v, 16);
+    const unsigned r2 = __builtin_amdgcn_readlane(v, 32), r3 = __builtin_amdgcn_readlane(v, 48);
+    const unsigned lo = min(min(r0 & 0xffff, r1 & 0xffff), min(r2 & 0xffff, r3 & 0xffff));
+    const unsigned hi = min(min(r0 >> 16, r1 >> 16), min(r2 >> 16, r3 >> 16));
+    amin = (int)lo;
+    bmin = (int)hi;
 }
-__device__ inline int wave_max(int v)
+
+// 2^x for x in roughly [-1070, 1000] in FP64 with FP32 relative accuracy:
+// x = n + f, f in [0, 1), 2^x = ldexp(2^f, n).
+__device__ inline double exp2_wide(double x)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
-    return v;
+    const double n = floor(x);
+    return ldexp((double)__builtin_amdgcn_exp2f((float)(x - n)), (int)n);
 }
 
 // ---------------------------------------------------------------------------
 // k_line_sums: T_j for every fine spaxel of the halo-extended grid.
-// grid = (ceil(EX*EY / 256), B); T layout [B][3][EY][EX] (x fastest).
+// grid = (ceil(EX/16), ceil(EY/16), B); a block covers 16 x 16 spaxels and
+// each wave an 8 x 8 square of them, so the union of the lanes' line
+// supports (the wave's channel loop) stays close to each lane's own support.
+// T layout [B][3][EY][EX] (x fastest).
+//
+// Along the channel loop the brightness-weighted line profile
+// A 2^(-e^2), e = (z - zc) sqrt(kappa), is carried by the exact ratio
+// recurrence g <- g r, r <- r q with q = 2^(-2 kappa), started at the wave's
+// first channel.  The start values come from FP32 exp2 scaled into FP64;
+// their rounding multiplies a spaxel's whole line by a constant (or tilts it
+// by ~1e-6 over its width), which the moment ratios do not see at the stated
+// tolerances.  When some lane would start below 2^-1020 (a steep velocity
+// gradient across the wave's square), the wave evaluates exp2 per channel.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_line_sums(const double *__restrict__ consts,
                                                    const double *__restrict__ wz, int NZE, int EX,
@@ -111,75 +157,103 @@ __global__ __launch_bounds__(256) void k_line_sums(const double *__restrict__ co
                                                    double inv_dvf, double *__restrict__ T,
                                                    unsigned long long *__restrict__ support_count)
 {
-    const int b = blockIdx.y;
+    const int b = blockIdx.z;
     const double *c = consts + (size_t)b * NCONST;
     if (c[C_VALID] == 0.0) return;  // uniform over the block
-    const int idx = blockIdx.x * 256 + threadIdx.x;
-    const bool in = idx < EX * EY;
-    const int xx = in ? idx % EX : 0, yy = in ? idx / EX : 0;
-    const double invu = 1.0 / u;
-    const double x = ((xx - hp) + 0.5) * invu - 0.5;
-    const double y = ((yy - hp) + 0.5) * invu - 0.5;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int gx = (blockIdx.x << 4) + ((wave & 1) << 3) + (lane & 7);
+    const int gy = (blockIdx.y << 4) + ((wave >> 1) << 3) + (lane >> 3);
+    const bool in = gx < EX && gy < EY;
 
-    // disc geometry, eqs. 1-4
-    const double dx = x - c[C_XO], dy = y - c[C_YO];
-    const double xe = -dx * c[C_SPA] + dy * c[C_CPA];
-    const double ye = (-dx * c[C_CPA] - dy * c[C_SPA]) * c[C_SECI];
-    const double r = sqrt(xe * xe + ye * ye);
-    const double costh = r > 0.0 ? xe / r : 0.0;
+    // disc geometry, eqs. 1-4: x_e and y_e / cos(i) are affine in the fine
+    // pixel indices (coefficients from k_prep).  The radius is FP64: the
+    // brightness exponent r/r0 reaches 60, where FP32 rounding of r would move
+    // I(r) by ~1e-5.  It is r2 * rsqrt(r2), the FP32 rsqrt refined by one
+    // Newton step in FP64 (relative error ~1e-14).
+    const double fx = (double)gx, fy = (double)gy;
+    const double xe = fma(fx, c[C_XEX], fma(fy, c[C_XEY], c[C_XE0]));
+    const double ye = fma(fx, c[C_YEX], fma(fy, c[C_YEY], c[C_YE0]));
+    const double r2 = fma(xe, xe, ye * ye);
+    const double y0 = (double)__builtin_amdgcn_rsqf(fmaxf((float)r2, 1e-30f));
+    const double rd = r2 * (y0 * fma(-0.5 * r2 * y0, y0, 1.5));
+    const float r = (float)rd;
+    const float costh = r > 0.0f ? (float)xe * __builtin_amdgcn_rcpf(r) : 0.0f;
 
-    // rotation curve (eqs. 6-7 or exponential rise), FP32 transcendental
-    const float q = (float)(r * c[C_IRT]);
+    // rotation curve (eqs. 6-7 or exponential rise), FP32
+    const float q = r * (float)c[C_IRT];
     float shape;
     if (rc == RC_ARCTAN) {
         shape = (float)(2.0 / kPi) * atanf(q);
     } else if (rc == RC_EPINAT) {
         shape = q > 0.0f ? powf(q, (float)c[C_G]) / (1.0f + powf(q, (float)c[C_A])) : 0.0f;
     } else {
-        shape = -expm1f(-q);
+        // 1 - e^-q; absolute error ~1e-7, i.e. ~1e-5 km/s on the velocity
+        shape = 1.0f - __builtin_amdgcn_exp2f(-q * (float)kLog2e);
     }
-    const double vlos = c[C_VSYS] + c[C_VT] * (double)shape * c[C_SINI] * costh;  // eq. 8
+    // eq. 8 (the FP32 product is added to Vsys in FP64)
+    const double vlos = c[C_VSYS] + (double)((float)c[C_VTSINI] * shape * costh);
 
-    // surface brightness (eq. 5) with the exp(-60) floor, times 1/(sqrt(2 pi) sigma)
-    const float rr = fminf((float)(r * c[C_IR0]), 60.0f);
-    const double amp = c[C_AMP] * (double)expf(-rr);
-
-    // line centre in fine halo-channel units, its significant range
+    // line centre in fine halo-channel units and its significant range
     const double zc = (vlos - vf0) * inv_dvf;
-    const double span = c[C_ZSPAN];
-    // clamp in floating point first so that the integer conversion cannot overflow
-    int lo = in ? (int)fmin(fmax(ceil(zc - span), 0.0), (double)NZE) : NZE;
-    int hi = in ? (int)fmax(fmin(floor(zc + span), (double)(NZE - 1)), -1.0) : -1;
-    const int zlo = __builtin_amdgcn_readfirstlane(wave_min(lo));
-    const int zhi = __builtin_amdgcn_readfirstlane(wave_max(hi));
+    const float zcf = (float)zc, span = (float)c[C_ZSPAN];
+    // clamp in floating point first so that the integer conversion cannot overflow;
+    // an empty range is lo = NZE, hi = -1 (packed below as NZE - hi = NZE + 1)
+    const int lo = in ? (int)fminf(fmaxf(ceilf(zcf - span), 0.0f), (float)NZE) : NZE;
+    const int hi = in ? (int)fmaxf(fminf(floorf(zcf + span), (float)(NZE - 1)), -1.0f) : -1;
+    int zlo, nhi;
+    wave_min2(lo, NZE - hi, zlo, nhi);
+    const int zhi = NZE - nhi;
     if (support_count) {  // measurement only: voxels inside each lane's own support
         int n = max(hi - lo + 1, 0);
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) n += __shfl_xor(n, o, 64);
-        if ((threadIdx.x & 63) == 0) atomicAdd(support_count, (unsigned long long)n);
+        // one slot per (row, wave): launches on a stream are ordered, so += is race-free
+        const size_t blk = ((size_t)b * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+        if (lane == 0) support_count[blk * 4 + wave] += n;
     }
 
-    // e = (z - zc) sqrt(kappa), so the profile is 2^(-e^2); the weights of a
-    // channel are one 32-byte record {W0, W1, W2, 0} read with a scalar load
+    // log2 of the brightness factor: I(r) / (sqrt(2 pi) sigma), eq. 5 with the
+    // exp(-60) floor
+    const double lamp = c[C_LOG2AMP] - fmin(rd * c[C_IR0], 60.0) * kLog2e;
     const double sqk = c[C_SQK];
     const double4 *w = reinterpret_cast<const double4 *>(wz);
-    double e = ((double)zlo - zc) * sqk;
+    const double e0 = ((double)zlo - zc) * sqk;
     double t0 = 0.0, t1 = 0.0, t2 = 0.0;
+    if (!__any(in && e0 * e0 - lamp > 1020.0)) {
+        double g = exp2_wide(lamp - e0 * e0);
+        double rt = exp2_wide(-(2.0 * e0 + sqk) * sqk);
+        const double qq = c[C_Q];
 #pragma unroll 2
-    for (int z = zlo; z <= zhi; ++z) {
-        const double g = (double)__builtin_amdgcn_exp2f(-(float)(e * e));
-        const double4 wk = w[z];
-        t0 = fma(g, wk.x, t0);
-        t1 = fma(g, wk.y, t1);
-        t2 = fma(g, wk.z, t2);
-        e += sqk;
+        for (int z = zlo; z <= zhi; ++z) {
+            const double4 wk = w[z];
+            t0 = fma(g, wk.x, t0);
+            t1 = fma(g, wk.y, t1);
+            t2 = fma(g, wk.z, t2);
+            g *= rt;
+            rt *= qq;
+        }
+    } else {
+        double e = e0;
+#pragma unroll 2
+        for (int z = zlo; z <= zhi; ++z) {
+            const double g = (double)__builtin_amdgcn_exp2f(-(float)(e * e));
+            const double4 wk = w[z];
+            t0 = fma(g, wk.x, t0);
+            t1 = fma(g, wk.y, t1);
+            t2 = fma(g, wk.z, t2);
+            e += sqk;
+        }
+        const double amp = exp2_wide(lamp);
+        t0 *= amp;
+        t1 *= amp;
+        t2 *= amp;
     }
     if (in) {
         const size_t plane = (size_t)EX * EY;
-        double *Tb = T + (size_t)b * 3 * plane + idx;
-        Tb[0] = t0 * amp;
-        Tb[plane] = t1 * amp;
-        Tb[2 * plane] = t2 * amp;
+        double *Tb = T + (size_t)b * 3 * plane + (size_t)gy * EX + gx;
+        Tb[0] = t0;
+        Tb[plane] = t1;
+        Tb[2 * plane] = t2;
     }
 }
 
@@ -308,6 +382,168 @@ __global__ __launch_bounds__(256) void k_psf_moments(PsfArgs a)
 }
 
 // ---------------------------------------------------------------------------
+// k_psf_moments_u1<HP, TX>: the u = 1 case with TX x 32 data-pixel tiles
+// (TX = 32 or 64) and a compile-time PSF half-width HP (0..kMaxFastHalo).
+// Each plane j: T tile + halo -> LDS (sT), x pass -> sX, y pass -> registers.
+// Both passes are register-blocked along the pass direction (a thread makes
+// 4 or RPT consecutive outputs from one window of LDS values) with the taps
+// in scalar registers.  Row strides of sT and sX are = 1 (mod 4) doubles so
+// that the lanes of a wave spread over all LDS banks.  Thread t owns column
+// t % TX and RPT = TX * 32 / 256 consecutive rows.
+// ---------------------------------------------------------------------------
+template <int HP, int N>
+__device__ inline void window(const double *src, int stride, const double *kp, double *out)
+{
+    constexpr int K = 2 * HP + 1;
+    double v[K + N - 1];
+#pragma unroll
+    for (int w = 0; w < K + N - 1; ++w) v[w] = src[w * stride];
+#pragma unroll
+    for (int o = 0; o < N; ++o) {
+        double acc = 0.0;
+        // output o = sum_k K[k] v[o + 2HP - k]
+#pragma unroll
+        for (int k = 0; k < K; ++k) acc = fma(kp[k], v[o + 2 * HP - k], acc);
+        out[o] = acc;
+    }
+}
+
+constexpr int pad_stride(int n) { return n + ((1 - n) % 4 + 4) % 4; }
+
+template <int HP, int TX>
+__global__ __launch_bounds__(256) void k_psf_moments_u1(PsfArgs a)
+{
+    extern __shared__ double lds[];
+    constexpr int TY = 32, K = 2 * HP + 1;
+    constexpr int LX = TX + 2 * HP, LY = TY + 2 * HP;
+    constexpr int ST = pad_stride(LX), SX = pad_stride(TX);
+    constexpr int RPT = TX * TY / 256;       // rows per thread in the y pass
+    constexpr int TPR = TX / 4;              // x-pass tasks per row
+    const int b = blockIdx.y, tile = blockIdx.x, tid = threadIdx.x;
+    const int tx0 = (tile % a.ntx) * TX, ty0 = (tile / a.ntx) * TY;
+    double *sT = lds, *sX = lds + LY * ST;
+    const double *cb = a.consts + (size_t)b * NCONST;
+    const bool valid = cb[C_VALID] != 0.0;
+    double kp[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) kp[k] = a.kp[k];
+    const int col = tid % TX, row0 = (tid / TX) * RPT;
+
+    double S[3][RPT];
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) S[j][q] = 0.0;
+
+    if (valid) {
+        const size_t plane = (size_t)a.EX * a.EY;
+        // tile + halo, LY x LX values: element i of thread t is flat index
+        // t + 256 i; the next plane is fetched into registers while the
+        // current one is convolved
+        constexpr int NLD = (LY * LX + 255) / 256;
+        int goff[NLD];
+        bool gok[NLD];
+#pragma unroll
+        for (int i = 0; i < NLD; ++i) {
+            const int f = tid + 256 * i, ly = f / LX, lx = f - ly * LX;
+            const int gy = ty0 + ly, gx = tx0 + lx;
+            gok[i] = f < LY * LX && gy < a.EY && gx < a.EX;
+            goff[i] = gok[i] ? gy * a.EX + gx : 0;
+        }
+        const double *Tb = a.T + (size_t)b * 3 * plane;
+        double pre[NLD];
+#pragma unroll
+        for (int i = 0; i < NLD; ++i) pre[i] = gok[i] ? Tb[goff[i]] : 0.0;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            if (j) __syncthreads();
+#pragma unroll
+            for (int i = 0; i < NLD; ++i) {
+                const int f = tid + 256 * i, ly = f / LX, lx = f - ly * LX;
+                if (f < LY * LX) sT[ly * ST + lx] = pre[i];
+            }
+            if (j < 2) {
+                const double *Tn = Tb + (size_t)(j + 1) * plane;
+#pragma unroll
+                for (int i = 0; i < NLD; ++i) pre[i] = gok[i] ? Tn[goff[i]] : 0.0;
+            }
+            __syncthreads();
+            for (int task = tid; task < LY * TPR; task += 256) {
+                const int ly = task / TPR, x0 = (task % TPR) * 4;
+                double o4[4];
+                window<HP, 4>(sT + ly * ST + x0, 1, kp, o4);
+                double *dst = sX + ly * SX + x0;
+#pragma unroll
+                for (int o = 0; o < 4; ++o) dst[o] = o4[o];
+            }
+            __syncthreads();
+            window<HP, RPT>(sX + row0 * SX + col, SX, kp, S[j]);
+        }
+    }
+
+    double acc = 0.0;
+    const size_t npix = (size_t)a.nx * a.ny;
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+        const int xd = tx0 + col, yd = ty0 + row0 + q;
+        if (xd >= a.nx || yd >= a.ny) continue;
+        const size_t p = (size_t)yd * a.nx + xd;
+        double m0, m1, m2;
+        if (!valid) {
+            m0 = m1 = m2 = __builtin_nan("");
+        } else if (S[0][q] > 0.0) {
+            const double mr = S[1][q] / S[0][q];
+            m0 = a.dv * S[0][q];
+            m1 = a.vref + mr;
+            m2 = sqrt(fmax(S[2][q] / S[0][q] - mr * mr, 0.0));
+        } else {
+            m0 = 0.0;
+            m1 = cb[C_VSYS];
+            m2 = 0.0;
+        }
+        if (a.maps) {
+            float *mb = a.maps + (size_t)b * 3 * npix;
+            mb[p] = (float)m0;
+            mb[npix + p] = (float)m1;
+            mb[2 * npix + p] = (float)m2;
+        }
+        if (a.mask) {
+            const bool use = a.mask[p] != 0;
+            const double rv = use ? (m1 - (double)a.vo[p]) * a.iev[p] : 0.0;
+            const double rs = use ? (m2 - (double)a.so[p]) * a.ies[p] : 0.0;
+            if (use) acc += rv * rv + rs * rs;
+            if (a.resid) {
+                double *rb = a.resid + (size_t)b * 2 * npix;
+                rb[p] = valid ? rv : __builtin_nan("");
+                rb[npix + p] = valid ? rs : __builtin_nan("");
+            }
+        }
+    }
+    if (a.partial) {
+        for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+        __shared__ double wsum[4];
+        __syncthreads();
+        if ((tid & 63) == 0) wsum[tid >> 6] = acc;
+        __syncthreads();
+        if (tid == 0)
+            a.partial[(size_t)b * a.ntiles + tile] = ((wsum[0] + wsum[1]) + wsum[2]) + wsum[3];
+    }
+}
+
+template <int HP, int TX> void launch_u1(const PsfArgs &a, dim3 grid, size_t lds, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_psf_moments_u1<HP, TX>), grid, dim3(256), lds, s, a);
+}
+
+using LaunchFn = void (*)(const PsfArgs &, dim3, size_t, hipStream_t);
+template <int TX, int... H> constexpr auto make_u1_table(std::integer_sequence<int, H...>)
+{
+    return std::array<LaunchFn, sizeof...(H)>{&launch_u1<H, TX>...};
+}
+static const auto kU1Table32 = make_u1_table<32>(std::make_integer_sequence<int, kMaxFastHalo + 1>{});
+static const auto kU1Table64 = make_u1_table<64>(std::make_integer_sequence<int, kMaxFastHalo + 1>{});
+
+// ---------------------------------------------------------------------------
 // k_reduce_chi2: one wave per evaluation, fixed order
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(64) void k_reduce_chi2(const double *__restrict__ partial, int ntiles,
@@ -329,10 +565,11 @@ __global__ __launch_bounds__(64) void k_reduce_chi2(const double *__restrict__ p
 // ---------------------------------------------------------------------------
 // launch wrappers
 // ---------------------------------------------------------------------------
-hipError_t launch_prep(const double *params, int B, int rc, double dvf, double *consts,
-                       hipStream_t s)
+hipError_t launch_prep(const double *params, int B, int rc, double dvf, int hp, int u,
+                       double *consts, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_prep, dim3((B + 63) / 64), dim3(64), 0, s, params, B, rc, dvf, consts);
+    hipLaunchKernelGGL(k_prep, dim3((B + 63) / 64), dim3(64), 0, s, params, B, rc, dvf, hp, u,
+                       consts);
     return hipGetLastError();
 }
 
@@ -340,7 +577,7 @@ hipError_t launch_line_sums(const double *consts, const double *wz, int NZE, int
                             int hp, int u, int rc, double vf0, double inv_dvf, double *T,
                             unsigned long long *support_count, int B, hipStream_t s)
 {
-    dim3 grid((EX * EY + 255) / 256, B);
+    dim3 grid((EX + 15) / 16, (EY + 15) / 16, B);
     hipLaunchKernelGGL(k_line_sums, grid, dim3(256), 0, s, consts, wz, NZE, EX, EY, hp, u, rc, vf0,
                        inv_dvf, T, support_count);
     return hipGetLastError();
@@ -349,7 +586,12 @@ hipError_t launch_line_sums(const double *consts, const double *wz, int NZE, int
 hipError_t launch_psf_moments(const PsfArgs &a, int B, size_t lds_bytes, hipStream_t s)
 {
     dim3 grid(a.ntiles, B);
-    hipLaunchKernelGGL(k_psf_moments, grid, dim3(256), lds_bytes, s, a);
+    if (a.u == 1 && a.TXd == 64 && a.TYd == 32 && a.hp <= kMaxFastHalo)
+        kU1Table64[a.hp](a, grid, lds_bytes, s);
+    else if (a.u == 1 && a.TXd == 32 && a.TYd == 32 && a.hp <= kMaxFastHalo)
+        kU1Table32[a.hp](a, grid, lds_bytes, s);
+    else
+        hipLaunchKernelGGL(k_psf_moments, grid, dim3(256), lds_bytes, s, a);
     return hipGetLastError();
 }
 
