@@ -33,6 +33,38 @@ PEAK_TFLOPS = 2 * LANE_OPS_PER_S / 1e12
 # FP64 FLOP per line-support voxel: the profile by the ratio recurrence
 # (g *= r, r *= q: 2 FLOP) and three weighted sums (3 FMA: 6 FLOP)
 FLOP_PER_VOXEL = 8
+PEAK_HBM_GBS = 8000.0
+
+# HBM traffic per launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
+# passes; reported only while the kernel sources still hash to the profiled ones
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_c2_128x128x48.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1510_01815_amd", "csrc", f)
+                  for f in ("gbk_kernels.hip", "gbk_internal.h")]
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic() -> dict:
+    """{kernel: HBM bytes per launch} from the committed counter summary, or {}."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return {}
+    if t.get("source_sha256") != kernel_source_hash():
+        return {}
+    out = {}
+    for k, v in t["kernels"].items():
+        out[k] = round(v["FETCH_SIZE_KiB"] * 1024 * t["fetch_factor"] +
+                       v["WRITE_SIZE_KiB"] * 1024 * t["write_factor"])
+    return out
 
 
 def parse():
@@ -132,18 +164,37 @@ def main():
     evals = K * BATCH
     value = evals / dt
 
-    k_ms = prof["kernel_ms"]["k_line_sums"] / max(prof["launches"]["k_line_sums"], 1)
-    vox_per_launch = cnt["support_voxels"] / K
-    flop_per_launch = vox_per_launch * FLOP_PER_VOXEL
-    achieved = flop_per_launch / (k_ms * 1e-3) / 1e12
-    roofline = {"bound": "alu", "kernel": "k_line_sums", "achieved": round(achieved, 3),
-                "peak": round(PEAK_TFLOPS, 1), "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_TFLOPS, 4), "traffic": None,
-                "kernel_ms_avg": round(k_ms, 5),
-                "support_voxels_per_launch": int(vox_per_launch),
-                "flop_per_voxel": FLOP_PER_VOXEL}
-    per_kernel_ms = {n: round(prof["kernel_ms"][n] / max(prof["launches"][n], 1), 5)
+    per_kernel_ms = {n: prof["kernel_ms"][n] / max(prof["launches"][n], 1)
                      for n in gbk.KERNEL_NAMES}
+    traffic = measured_traffic()
+    nxe, nye, _, _, _ = model.dims()
+    # k_line_sums: FP64 FLOP of the line-support voxels (counted per launch)
+    ls_ms = per_kernel_ms["k_line_sums"]
+    vox_per_launch = cnt["support_voxels"] / K
+    ls_tflops = vox_per_launch * FLOP_PER_VOXEL / (ls_ms * 1e-3) / 1e12
+    # k_psf_moments: algorithmic HBM bytes = the three T planes of every row
+    # read once, plus the observation and the tile partials
+    ps_ms = per_kernel_ms["k_psf_moments"]
+    ps_bytes = BATCH * 3 * nxe * nye * 8 + 128 * 128 * 25 + BATCH * 32 * 8
+    ps_gbs = ps_bytes / (ps_ms * 1e-3) / 1e9
+    rooflines = {
+        "k_line_sums": {"bound": "alu", "kernel": "k_line_sums", "achieved": round(ls_tflops, 3),
+                        "peak": round(PEAK_TFLOPS, 1), "unit": "TFLOP/s",
+                        "frac": round(ls_tflops / PEAK_TFLOPS, 4),
+                        "traffic": traffic.get("k_line_sums"),
+                        "kernel_ms_avg": round(ls_ms, 5),
+                        "support_voxels_per_launch": int(vox_per_launch),
+                        "flop_per_voxel": FLOP_PER_VOXEL},
+        "k_psf_moments": {"bound": "hbm", "kernel": "k_psf_moments", "achieved": round(ps_gbs, 1),
+                          "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                          "frac": round(ps_gbs / PEAK_HBM_GBS, 4),
+                          "traffic": traffic.get("k_psf_moments"),
+                          "kernel_ms_avg": round(ps_ms, 5),
+                          "algorithmic_bytes_per_launch": ps_bytes},
+    }
+    dominant = max(("k_line_sums", "k_psf_moments"), key=lambda n: per_kernel_ms[n])
+    roofline = rooflines[dominant]
+    per_kernel_ms = {n: round(v, 5) for n, v in per_kernel_ms.items()}
 
     out = {"metric": METRIC, "value": round(value, 1), "unit": "evals/s", "n_gpus": 1,
            "steps": K, "warmup": W, "ms_per_step": round(1e3 * dt / K, 4),
@@ -154,7 +205,7 @@ def main():
                       "nx": 128, "ny": 128, "nz": 48, "batch": BATCH,
                       "psf_fwhm_pix": grid.psf_fwhm, "lsf_sigma_kms": round(grid.lsf_sigma, 4),
                       "rotation_curve": "exponential rise", "parallelism": "single GPU"},
-           "roofline": roofline, "kernel_ms_per_launch": per_kernel_ms}
+           "roofline": roofline, "rooflines": rooflines, "kernel_ms_per_launch": per_kernel_ms}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(grid, batches[W, 0].cpu().numpy(), obs,
                                            args.cpu_rows_per_thread)
