@@ -152,6 +152,49 @@ typedef struct {
 gk_status gk_set_profiling(gk_model *model, int flags);
 gk_status gk_read_profile(gk_model *model, gk_profile_stats *out);
 
+/* ---- Levenberg-Marquardt (Sec. 2.3.1) ----------------------------------
+ * Damped Gauss-Newton on the residuals of gk_residual_batch with box
+ * constraints.  Jacobian column a of a free slot: (r(p+) - r(p-)) / (p+ - p-),
+ * p+- = p_a +- fd_step clipped to [lo_a, hi_a] (the paper uses an absolute
+ * step of about 0.1, Sec. 4).  A = J^T J and g = J^T r are formed on the
+ * device in FP64; the step (A + lambda diag A) d = -g is solved on the host by
+ * Cholesky in FP64, trial = clip(p + d).  A trial that lowers chi2 is accepted
+ * (lambda /= 10), otherwise lambda *= 10.  Free slots whose Jacobian column is
+ * identically zero (e.g. I0, which only scales the cube) are frozen.  Each
+ * iteration is one batched launch of 1 + 2 n_free rows: the trial point and
+ * the Jacobian rows around it (used if the trial is accepted). */
+typedef struct {
+    int32_t max_iter;   /* trials; default 200 */
+    int32_t reserved;   /* must be 0 */
+    double fd_step;     /* absolute finite-difference step in ABI units; default 0.1 */
+    double lambda0;     /* initial damping; default 1e-3 */
+    double ftol;        /* stop when the relative chi2 decrease <= ftol; default 1e-10 */
+    double xtol;        /* stop when max |d_a| / (|p_a| + 1e-10) <= xtol; default 1e-10 */
+} gk_lm_opts;
+
+enum { GK_LM_FTOL = 1, GK_LM_XTOL = 2, GK_LM_LAMBDA = 3, GK_LM_MAXITER = 4 };
+
+typedef struct {
+    double chi2;              /* at the returned parameters */
+    int64_t n_valid;          /* unmasked pixels */
+    int32_t iterations;       /* trials made */
+    int32_t reason;           /* GK_LM_* */
+    int64_t n_evals;          /* parameter rows evaluated */
+    double errors[GK_NP];     /* sqrt(diag((J^T J)^-1)) of free slots, 0 elsewhere */
+} gk_lm_result;
+
+/* Fills opts with the defaults above. */
+gk_status gk_lm_default_opts(gk_lm_opts *opts);
+
+/* Fits p_inout [GK_NP] (host, start values in, optimum out) with the slots
+ * where free_mask[k] != 0 free inside [lo_k, hi_k] (host arrays; NULL bounds
+ * mean unbounded).  Blocks until done; runs on a stream of the model's own.
+ * Needs an observation (GK_ESTATE otherwise).  Returns GK_OK, or GK_ENOTCONV
+ * when max_iter was reached (the result is still filled), or an error; a
+ * start outside the model's domain is GK_EINVAL.  opts may be NULL. */
+gk_status gk_fit_lm(gk_model *model, double *p_inout, const uint8_t *free_mask, const double *lo,
+                    const double *hi, const gk_lm_opts *opts, gk_lm_result *result);
+
 /* Shape of the fine model cube with its halo and the halos themselves:
  * dims = {nx_ext, ny_ext, nz_ext, h_psf, h_lsf}. */
 gk_status gk_model_dims(const gk_model *model, int32_t dims[5]);

@@ -1,0 +1,146 @@
+"""Reference optimisers of the oracle (Sec. 2.3), plain FP64 numpy.
+
+TEST INFRASTRUCTURE ONLY (see oracle.py): used by tests/ to check the GPU
+library's fitters.  Each follows the step-by-step specification shared with
+the library (written out in the design doc); the paper names the algorithms but
+uses third-party implementations (mpfit, MultiNest), so the details below are
+this project's reading.
+
+levenberg_marquardt: Sec. 2.3.1 -- gradient/curvature local optimiser with box
+constraints and a finite-difference Jacobian of absolute step ~0.1 (Sec. 4).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import oracle as O
+
+
+@dataclass
+class LMResult:
+    p: np.ndarray
+    chi2: float
+    iterations: int
+    n_evals: int
+    errors: np.ndarray
+    reason: str
+    history: list = field(default_factory=list)
+
+
+def _cholesky_solve(M: np.ndarray, rhs: np.ndarray) -> np.ndarray:
+    """Solves M x = rhs for symmetric positive definite M by an explicit
+    Cholesky factorisation M = L L^T (no library solver)."""
+    n = M.shape[0]
+    L = np.zeros_like(M)
+    for i in range(n):
+        for j in range(i + 1):
+            s = M[i, j] - sum(L[i, k] * L[j, k] for k in range(j))
+            if i == j:
+                if s <= 0.0:
+                    raise np.linalg.LinAlgError("matrix not positive definite")
+                L[i, i] = math.sqrt(s)
+            else:
+                L[i, j] = s / L[j, j]
+    y = np.zeros(n)
+    for i in range(n):
+        y[i] = (rhs[i] - sum(L[i, k] * y[k] for k in range(i))) / L[i, i]
+    x = np.zeros(n)
+    for i in reversed(range(n)):
+        x[i] = (y[i] - sum(L[k, i] * x[k] for k in range(i + 1, n))) / L[i, i]
+    return x
+
+
+def levenberg_marquardt(resid, p0, free, lo, hi, h=0.1, lam0=1e-3, max_iter=200,
+                        ftol=1e-10, xtol=1e-10) -> LMResult:
+    """Damped Gauss-Newton with box constraints.
+
+    resid(p) -> residual vector r(p); chi2 = r.r.
+    Jacobian column a (free slots): (r(p+) - r(p-)) / (p+ - p-), with
+    p+- = p_a +- h clipped to the box.  A = J^T J, g = J^T r; free slots whose
+    column is identically zero are frozen.  Step: (A + lam diag A) d = -g,
+    trial = clip(p + d).  A trial that lowers chi2 is accepted (lam /= 10),
+    otherwise lam *= 10.  Stops after an accepted step when the relative
+    chi2 decrease <= ftol or max |d_a| / (|p_a| + 1e-10) <= xtol, or when
+    lam > 1e10 or after max_iter trials.  Errors: sqrt(diag(A^-1)) at the end.
+    """
+    p = np.clip(np.asarray(p0, dtype=np.float64).copy(), lo, hi)
+    free = [a for a in range(len(p)) if free[a] and hi[a] > lo[a]]
+    n_evals = 0
+
+    def jac(pc):
+        nonlocal n_evals
+        r0 = resid(pc)
+        n_evals += 1
+        cols = []
+        for a in free:
+            pp, pm = pc.copy(), pc.copy()
+            pp[a] = min(pc[a] + h, hi[a])
+            pm[a] = max(pc[a] - h, lo[a])
+            cols.append((resid(pp) - resid(pm)) / (pp[a] - pm[a]))
+            n_evals += 2
+        J = np.stack(cols, axis=1) if cols else np.zeros((len(r0), 0))
+        return r0, J
+
+    r, J = jac(p)
+    chi2 = float(r @ r)
+    A, g = J.T @ J, J.T @ r
+    lam, it, reason, hist = lam0, 0, "maxiter", []
+    while it < max_iter:
+        it += 1
+        act = [k for k in range(len(free)) if A[k, k] > 0.0]
+        d = np.zeros(len(free))
+        if act:
+            M = A[np.ix_(act, act)].copy()
+            M[np.diag_indices_from(M)] *= (1.0 + lam)
+            d[act] = _cholesky_solve(M, -g[act])
+        pt = p.copy()
+        for k, a in enumerate(free):
+            pt[a] = min(max(p[a] + d[k], lo[a]), hi[a])
+        rt, Jt = jac(pt)
+        chi2t = float(rt @ rt)
+        if chi2t < chi2:
+            step = max((abs(pt[a] - p[a]) / (abs(p[a]) + 1e-10) for a in free), default=0.0)
+            dec = (chi2 - chi2t) / chi2 if chi2 > 0 else 0.0
+            p, r, J, chi2 = pt, rt, Jt, chi2t
+            A, g = J.T @ J, J.T @ r
+            lam = lam / 10.0
+            hist.append(chi2)
+            if chi2 == 0.0 or dec <= ftol:
+                reason = "ftol"
+                break
+            if step <= xtol:
+                reason = "xtol"
+                break
+        else:
+            lam *= 10.0
+            if lam > 1e10:
+                reason = "lambda"
+                break
+    err = np.zeros(len(p))
+    act = [k for k in range(len(free)) if A[k, k] > 0.0]
+    if act:
+        Ainv = np.linalg.inv(A[np.ix_(act, act)])
+        for j, k in enumerate(act):
+            err[free[k]] = math.sqrt(max(Ainv[j, j], 0.0))
+    return LMResult(p, chi2, it, n_evals, err, reason, hist)
+
+
+def model_residuals(d: "O.Desc", obs):
+    """r(p) of the oracle model against an observation: (m1 - v_obs)/E_v then
+    sqrt(W) (m2 - s_obs)/E_s over unmasked pixels (the terms of eq. 11)."""
+    mk = np.asarray(obs.mask).astype(bool).ravel()
+    vo = np.asarray(obs.vel, dtype=np.float64).ravel()[mk]
+    so = np.asarray(obs.sig, dtype=np.float64).ravel()[mk]
+    ev = np.asarray(obs.evel, dtype=np.float64).ravel()[mk]
+    es = np.asarray(obs.esig, dtype=np.float64).ravel()[mk]
+    sw = math.sqrt(obs.W)
+
+    def resid(p):
+        m = O.evaluate(d, p)
+        rv = (m[1].ravel()[mk] - vo) / ev
+        rs = sw * (m[2].ravel()[mk] - so) / es if obs.W > 0 else np.zeros_like(rv)
+        return np.concatenate([rv, rs])
+    return resid

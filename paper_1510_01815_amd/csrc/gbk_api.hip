@@ -16,14 +16,13 @@
 #include <string>
 #include <vector>
 
-#include "gbk.h"
-#include "gbk_internal.h"
+#include "gbk_model.h"
 
 using namespace gbk;
 
-namespace {
-
 thread_local std::string g_err;
+
+namespace gbk {
 
 gk_status fail(gk_status st, const char *fmt, ...)
 {
@@ -36,38 +35,14 @@ gk_status fail(gk_status st, const char *fmt, ...)
     return st;
 }
 
-#define HIP_TRY(expr)                                                                   \
-    do {                                                                                \
-        hipError_t e_ = (expr);                                                         \
-        if (e_ != hipSuccess)                                                           \
-            return fail(e_ == hipErrorOutOfMemory ? GK_ENOMEM : GK_EDEVICE, "%s: %s (%s:%d)", \
-                        #expr, hipGetErrorString(e_), __FILE__, __LINE__);              \
-    } while (0)
 
-// Restores the caller's current device on scope exit.
-struct DeviceGuard {
-    int prev = -1;
-    hipError_t err = hipSuccess;
-    explicit DeviceGuard(int dev)
-    {
-        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-        err = hipSetDevice(dev);
-    }
-    ~DeviceGuard()
-    {
-        if (prev >= 0) (void)hipSetDevice(prev);
-    }
-};
 
-// Scratch budget for the T_j planes of one chunk of rows.
-constexpr size_t kScratchBudget = size_t(1) << 30;
-constexpr size_t kMaxLds = 64 * 1024;
 
-double fwhm_to_sigma(double f) { return f / (2.0 * std::sqrt(2.0 * std::log(2.0))); }
+static double fwhm_to_sigma(double f) { return f / (2.0 * std::sqrt(2.0 * std::log(2.0))); }
 
 // Unit-sum Gaussian taps at integer offsets -h..h, h = ceil(R sigma); a zero
 // width gives the single tap 1 (eq. 9, one axis).
-std::vector<double> gaussian_taps(double sigma, double R)
+static std::vector<double> gaussian_taps(double sigma, double R)
 {
     if (!(sigma > 0.0)) return {1.0};
     int h = (int)std::ceil(R * sigma);
@@ -78,7 +53,6 @@ std::vector<double> gaussian_taps(double sigma, double R)
     return t;
 }
 
-enum PtrKind { PTR_HOST, PTR_DEVICE, PTR_BAD };
 
 PtrKind pointer_kind(const void *p)
 {
@@ -111,100 +85,9 @@ bool row_valid(const double *p, int rc)
     return true;
 }
 
-template <class T> hipError_t dev_alloc(T **p, size_t n)
-{
-    return hipMalloc((void **)p, std::max<size_t>(n, 1) * sizeof(T));
-}
 
-}  // namespace
+}  // namespace gbk
 
-struct gk_model {
-    gk_model_desc d{};
-    int device = 0;
-    int hp = 0, hl = 0, NX = 0, NY = 0, NZ = 0, EX = 0, EY = 0, NZE = 0;
-    double vf0 = 0, dvf = 0, inv_dvf = 0, vref = 0;
-    int TXd = 0, TYd = 0, ntx = 0, nty = 0, ntiles = 0;
-    size_t lds_bytes = 0;
-    double *d_kp = nullptr, *d_wz = nullptr;
-    // observation
-    bool has_obs = false;
-    int64_t nvalid = 0;
-    float *d_vo = nullptr, *d_so = nullptr;
-    double *d_iev = nullptr, *d_ies = nullptr;
-    uint8_t *d_mask = nullptr;
-    // scratch, sized for `cap` rows
-    int cap = 0;
-    double *d_params = nullptr, *d_consts = nullptr, *d_T = nullptr, *d_partial = nullptr;
-    // pinned staging of host-given rows; ev_staged marks when its last copy is done
-    double *h_params = nullptr;
-    hipEvent_t ev_staged = nullptr;
-    // measurement hooks (gk_set_profiling)
-    int prof_flags = 0;
-    std::vector<std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>>> prof_events;
-    unsigned long long *d_count = nullptr;
-    int64_t prof_rows = 0;
-
-    int chunk_rows() const
-    {
-        size_t per = (size_t)3 * EX * EY * sizeof(double);
-        size_t n = std::max<size_t>(1, kScratchBudget / per);
-        return (int)std::min<size_t>(n, 65535);
-    }
-
-    size_t count_slots() const
-    {
-        return (size_t)chunk_rows() * ((EX + 15) / 16) * ((EY + 15) / 16) * 4;
-    }
-
-    hipError_t reserve(int rows)
-    {
-        if (rows <= cap) return hipSuccess;
-        (void)hipFree(d_params);
-        (void)hipFree(d_consts);
-        (void)hipFree(d_T);
-        (void)hipFree(d_partial);
-        if (h_params) {
-            if (ev_staged) (void)hipEventSynchronize(ev_staged);
-            (void)hipHostFree(h_params);
-        }
-        d_params = d_consts = d_T = d_partial = h_params = nullptr;
-        cap = 0;
-        hipError_t e;
-        if (!ev_staged && (e = hipEventCreateWithFlags(&ev_staged, hipEventDisableTiming)) != hipSuccess)
-            return e;
-        if ((e = hipHostMalloc((void **)&h_params, sizeof(double) * NPAR * rows, 0)) != hipSuccess)
-            return e;
-        if ((e = dev_alloc(&d_params, (size_t)rows * NPAR)) != hipSuccess) return e;
-        if ((e = dev_alloc(&d_consts, (size_t)rows * NCONST)) != hipSuccess) return e;
-        if ((e = dev_alloc(&d_T, (size_t)rows * 3 * EX * EY)) != hipSuccess) return e;
-        if ((e = dev_alloc(&d_partial, (size_t)rows * ntiles)) != hipSuccess) return e;
-        cap = rows;
-        return hipSuccess;
-    }
-
-    void release()
-    {
-        (void)hipFree(d_kp);
-        (void)hipFree(d_wz);
-        (void)hipFree(d_vo);
-        (void)hipFree(d_so);
-        (void)hipFree(d_iev);
-        (void)hipFree(d_ies);
-        (void)hipFree(d_mask);
-        (void)hipFree(d_params);
-        (void)hipFree(d_consts);
-        (void)hipFree(d_T);
-        (void)hipFree(d_partial);
-        if (h_params) (void)hipHostFree(h_params);
-        if (ev_staged) (void)hipEventDestroy(ev_staged);
-        (void)hipFree(d_count);
-        for (auto &call : prof_events)
-            for (auto &k : call) {
-                (void)hipEventDestroy(k.second.first);
-                (void)hipEventDestroy(k.second.second);
-            }
-    }
-};
 
 namespace {
 
@@ -255,8 +138,10 @@ void choose_tile(gk_model *m)
     m->lds_bytes = psf_lds_bytes(tx, ty, m->d.upsample, m->hp);
 }
 
-gk_status run_batch(gk_model *m, const double *params, int32_t B, float *maps, double *resid,
-                    double *chi2, int64_t *nvalid, void *stream)
+}  // namespace
+
+gk_status gbk::run_batch(gk_model *m, const double *params, int32_t B, float *maps,
+                          double *resid, double *chi2, int64_t *nvalid, void *stream)
 {
     if (!m) return fail(GK_EINVAL, "model is NULL");
     if (B < 0) return fail(GK_EINVAL, "negative batch size %d", B);
@@ -357,7 +242,6 @@ gk_status run_batch(gk_model *m, const double *params, int32_t B, float *maps, d
     return n_bad ? GK_PARTIAL : GK_OK;
 }
 
-}  // namespace
 
 extern "C" {
 

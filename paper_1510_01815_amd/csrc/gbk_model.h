@@ -1,0 +1,170 @@
+// gbk_model.h -- private: the model object behind the opaque gk_model handle,
+// error helpers and the batch runner shared by the evaluation entry points
+// and the fitters.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "gbk.h"
+#include "gbk_internal.h"
+
+namespace gbk {
+
+// Sets the thread's last-error message and returns `st`.
+gk_status fail(gk_status st, const char *fmt, ...);
+
+#define HIP_TRY(expr)                                                                        \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return ::gbk::fail(e_ == hipErrorOutOfMemory ? GK_ENOMEM : GK_EDEVICE,           \
+                               "%s: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__,     \
+                               __LINE__);                                                    \
+    } while (0)
+
+#define GK_TRY(expr)                                                                         \
+    do {                                                                                     \
+        gk_status s_ = (expr);                                                               \
+        if (s_ < 0) return s_;                                                               \
+    } while (0)
+
+// Restores the caller's current device on scope exit.
+struct DeviceGuard {
+    int prev = -1;
+    hipError_t err = hipSuccess;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        err = hipSetDevice(dev);
+    }
+    ~DeviceGuard()
+    {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+// Scratch budget for the T_j planes of one chunk of rows.
+constexpr size_t kScratchBudget = size_t(1) << 30;
+constexpr size_t kMaxLds = 64 * 1024;
+
+enum PtrKind { PTR_HOST, PTR_DEVICE, PTR_BAD };
+PtrKind pointer_kind(const void *p);
+bool row_valid(const double *p, int rc);
+
+template <class T> hipError_t dev_alloc(T **p, size_t n)
+{
+    return hipMalloc((void **)p, std::max<size_t>(n, 1) * sizeof(T));
+}
+
+struct FitWork;
+void fit_release(FitWork *w);
+
+}  // namespace gbk
+
+struct gk_model {
+    // see gbk_api.hip for the meaning of each field
+    gk_model_desc d{};
+    int device = 0;
+    int hp = 0, hl = 0, NX = 0, NY = 0, NZ = 0, EX = 0, EY = 0, NZE = 0;
+    double vf0 = 0, dvf = 0, inv_dvf = 0, vref = 0;
+    int TXd = 0, TYd = 0, ntx = 0, nty = 0, ntiles = 0;
+    size_t lds_bytes = 0;
+    double *d_kp = nullptr, *d_wz = nullptr;
+    // observation
+    bool has_obs = false;
+    int64_t nvalid = 0;
+    float *d_vo = nullptr, *d_so = nullptr;
+    double *d_iev = nullptr, *d_ies = nullptr;
+    uint8_t *d_mask = nullptr;
+    // scratch, sized for `cap` rows
+    int cap = 0;
+    double *d_params = nullptr, *d_consts = nullptr, *d_T = nullptr, *d_partial = nullptr;
+    // pinned staging of host-given rows; ev_staged marks when its last copy is done
+    double *h_params = nullptr;
+    hipEvent_t ev_staged = nullptr;
+    // measurement hooks (gk_set_profiling)
+    int prof_flags = 0;
+    std::vector<std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>>> prof_events;
+    unsigned long long *d_count = nullptr;
+    int64_t prof_rows = 0;
+    // fitter workspace (gbk_fit.hip), created on first use
+    gbk::FitWork *fit = nullptr;
+
+    int chunk_rows() const
+    {
+        size_t per = (size_t)3 * EX * EY * sizeof(double);
+        size_t n = std::max<size_t>(1, gbk::kScratchBudget / per);
+        return (int)std::min<size_t>(n, 65535);
+    }
+
+    size_t count_slots() const
+    {
+        return (size_t)chunk_rows() * ((EX + 15) / 16) * ((EY + 15) / 16) * 4;
+    }
+
+    hipError_t reserve(int rows)
+    {
+        if (rows <= cap) return hipSuccess;
+        (void)hipFree(d_params);
+        (void)hipFree(d_consts);
+        (void)hipFree(d_T);
+        (void)hipFree(d_partial);
+        if (h_params) {
+            if (ev_staged) (void)hipEventSynchronize(ev_staged);
+            (void)hipHostFree(h_params);
+        }
+        d_params = d_consts = d_T = d_partial = h_params = nullptr;
+        cap = 0;
+        hipError_t e;
+        if (!ev_staged && (e = hipEventCreateWithFlags(&ev_staged, hipEventDisableTiming)) != hipSuccess)
+            return e;
+        if ((e = hipHostMalloc((void **)&h_params, sizeof(double) * gbk::NPAR * rows, 0)) != hipSuccess)
+            return e;
+        if ((e = gbk::dev_alloc(&d_params, (size_t)rows * gbk::NPAR)) != hipSuccess) return e;
+        if ((e = gbk::dev_alloc(&d_consts, (size_t)rows * gbk::NCONST)) != hipSuccess) return e;
+        if ((e = gbk::dev_alloc(&d_T, (size_t)rows * 3 * EX * EY)) != hipSuccess) return e;
+        if ((e = gbk::dev_alloc(&d_partial, (size_t)rows * ntiles)) != hipSuccess) return e;
+        cap = rows;
+        return hipSuccess;
+    }
+
+    void release()
+    {
+        (void)hipFree(d_kp);
+        (void)hipFree(d_wz);
+        (void)hipFree(d_vo);
+        (void)hipFree(d_so);
+        (void)hipFree(d_iev);
+        (void)hipFree(d_ies);
+        (void)hipFree(d_mask);
+        (void)hipFree(d_params);
+        (void)hipFree(d_consts);
+        (void)hipFree(d_T);
+        (void)hipFree(d_partial);
+        gbk::fit_release(fit);
+        fit = nullptr;
+        if (h_params) (void)hipHostFree(h_params);
+        if (ev_staged) (void)hipEventDestroy(ev_staged);
+        (void)hipFree(d_count);
+        for (auto &call : prof_events)
+            for (auto &k : call) {
+                (void)hipEventDestroy(k.second.first);
+                (void)hipEventDestroy(k.second.second);
+            }
+    }
+};
+
+namespace gbk {
+
+// Evaluates B rows (host or device) on `stream`: any of maps [B][3][ny][nx]
+// float, resid [B][2][ny][nx] double, chi2 [B] / nvalid [B] (device).
+gk_status run_batch(gk_model *m, const double *params, int32_t B, float *maps, double *resid,
+                    double *chi2, int64_t *nvalid, void *stream);
+
+}  // namespace gbk

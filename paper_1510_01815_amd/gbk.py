@@ -24,8 +24,9 @@ RC = {"arctan": 0, "epinat": 1, "boissier": 2}
 SYMBOLS = (
     "gk_create_model", "gk_destroy_model", "gk_set_observation", "gk_observation_count",
     "gk_evaluate_batch", "gk_chi2_batch", "gk_residual_batch", "gk_model_dims", "gk_last_error",
-    "gk_set_profiling", "gk_read_profile",
+    "gk_set_profiling", "gk_read_profile", "gk_lm_default_opts", "gk_fit_lm",
 )
+LM_REASONS = {1: "ftol", 2: "xtol", 3: "lambda", 4: "maxiter"}
 GK_PROF_TIMING, GK_PROF_COUNT = 1, 2
 
 
@@ -47,6 +48,18 @@ class ModelDesc(ctypes.Structure):
 class ProfileStats(ctypes.Structure):
     _fields_ = [("kernel_ms", ctypes.c_double * 4), ("launches", ctypes.c_int64 * 4),
                 ("support_voxels", ctypes.c_int64), ("rows", ctypes.c_int64)]
+
+
+class LMOpts(ctypes.Structure):
+    _fields_ = [("max_iter", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("fd_step", ctypes.c_double), ("lambda0", ctypes.c_double),
+                ("ftol", ctypes.c_double), ("xtol", ctypes.c_double)]
+
+
+class LMResult(ctypes.Structure):
+    _fields_ = [("chi2", ctypes.c_double), ("n_valid", ctypes.c_int64),
+                ("iterations", ctypes.c_int32), ("reason", ctypes.c_int32),
+                ("n_evals", ctypes.c_int64), ("errors", ctypes.c_double * NPAR)]
 
 
 KERNEL_NAMES = ("k_prep", "k_line_sums", "k_psf_moments", "k_reduce_chi2")
@@ -74,6 +87,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.gk_model_dims.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
     L.gk_set_profiling.argtypes = [vp, ctypes.c_int]
     L.gk_read_profile.argtypes = [vp, ctypes.POINTER(ProfileStats)]
+    L.gk_lm_default_opts.argtypes = [ctypes.POINTER(LMOpts)]
+    L.gk_fit_lm.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(LMOpts), ctypes.POINTER(LMResult)]
     L.gk_last_error.restype = ctypes.c_char_p
     for name in SYMBOLS:
         if name != "gk_last_error":
@@ -200,6 +215,27 @@ class Model:
         return {"kernel_ms": dict(zip(KERNEL_NAMES, st.kernel_ms)),
                 "launches": dict(zip(KERNEL_NAMES, st.launches)),
                 "support_voxels": st.support_voxels, "rows": st.rows}
+
+    def fit_lm(self, p0, free, lo=None, hi=None, **opts) -> dict:
+        """Levenberg-Marquardt fit (gk_fit_lm); returns the fitted row and diagnostics."""
+        L = load()
+        o = LMOpts()
+        _check(L.gk_lm_default_opts(ctypes.byref(o)))
+        for k, v in opts.items():
+            setattr(o, k, v)
+        p = np.ascontiguousarray(p0, dtype=np.float64).copy()
+        fm = np.ascontiguousarray(free, dtype=np.uint8)
+        lo_a = None if lo is None else np.ascontiguousarray(lo, dtype=np.float64)
+        hi_a = None if hi is None else np.ascontiguousarray(hi, dtype=np.float64)
+        r = LMResult()
+        st = L.gk_fit_lm(self._h, p.ctypes.data, fm.ctypes.data,
+                         None if lo_a is None else lo_a.ctypes.data,
+                         None if hi_a is None else hi_a.ctypes.data, ctypes.byref(o), ctypes.byref(r))
+        if st < 0 and st != GK_ENOTCONV:
+            _check(st)
+        return {"p": p, "chi2": r.chi2, "n_valid": r.n_valid, "iterations": r.iterations,
+                "reason": LM_REASONS.get(r.reason, str(r.reason)), "n_evals": r.n_evals,
+                "errors": np.array(r.errors[:]), "status": st}
 
     def residuals(self, params, out=None, stream=None):
         """resid [B][2][ny][nx] float64 CUDA tensor."""
