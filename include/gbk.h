@@ -195,6 +195,64 @@ gk_status gk_lm_default_opts(gk_lm_opts *opts);
 gk_status gk_fit_lm(gk_model *model, double *p_inout, const uint8_t *free_mask, const double *lo,
                     const double *hi, const gk_lm_opts *opts, gk_lm_result *result);
 
+/* ---- Nested sampling (Sec. 2.3.2) -----------------------------------------
+ * Single-ellipsoid nested sampling (Skilling 2004; ellipsoidal bound as in
+ * Mukherjee et al. 2006) over a uniform prior box.  N live points; L =
+ * exp(-chi2/2).  Each round fits the bounding ellipsoid of the live points
+ * (covariance scaled to enclose them all, volume enlarged by `enlarge`),
+ * draws `batch` candidates uniformly inside it and inside the box, evaluates
+ * them in one launch, and consumes them in draw order: a candidate whose L
+ * exceeds the current lowest live L replaces that point, which is retired with
+ * prior-volume weight X_{k-1} - X_k, X_k = exp(-k/N).  Stops when
+ * log(Z + L_max X_k) - log Z < tol, then adds the live points with weight X_k/N.
+ * Random numbers: Philox4x32-10 (Salmon et al. 2011) keyed by `seed`. */
+typedef struct {
+    int32_t n_live;      /* default 400 */
+    int32_t batch;       /* candidates per launch; default n_live */
+    int64_t max_iter;    /* retired points; default 1e6 */
+    double enlarge;      /* ellipsoid volume factor; default 1.25 (= 1/e with e = 0.8) */
+    double tol;          /* evidence tolerance; default 0.5 */
+    uint64_t seed;       /* default 1 */
+} gk_ns_opts;
+
+typedef struct {
+    double logz, logz_err;     /* log evidence and sqrt(H / N) */
+    double info_h;             /* information H (nats) */
+    double max_logl;           /* best log-likelihood seen */
+    int64_t n_iter;            /* retired points */
+    int64_t n_evals;           /* likelihood evaluations */
+    int64_t n_launches;        /* batched launches */
+    double best[GK_NP];        /* best point */
+    double mean[GK_NP], sd[GK_NP];            /* posterior mean and standard deviation */
+    double median[GK_NP], q16[GK_NP], q84[GK_NP];  /* posterior quantiles */
+} gk_ns_result;
+
+gk_status gk_ns_default_opts(gk_ns_opts *opts);
+
+/* Samples the posterior of the model's parameters against the current
+ * observation.  Slots with free_mask[k] != 0 have the uniform prior
+ * [lo_k, hi_k]; the others are fixed at fixed[k] (host arrays).  Blocks.
+ * Posterior arrays of fixed slots hold the fixed value.  If samples is not
+ * NULL, up to cap weighted posterior samples are written as rows of GK_NP + 1
+ * doubles (the parameters, then the normalised weight) and their count to
+ * *n_samples.  GK_ENOTCONV when max_iter was reached (result still filled). */
+gk_status gk_fit_nested(gk_model *model, const double *lo, const double *hi,
+                        const uint8_t *free_mask, const double *fixed, const gk_ns_opts *opts,
+                        gk_ns_result *result, double *samples, int64_t cap, int64_t *n_samples);
+
+/* Batch log-likelihood for gk_nested_sample: theta [n][dim] -> logl [n];
+ * returns 0 on success (non-zero aborts the run with GK_EINVAL). */
+typedef int (*gk_loglike_fn)(const double *theta, int32_t n, int32_t dim, double *logl, void *user);
+
+/* The same sampler over any batch likelihood of dim <= GK_NP parameters with
+ * the uniform prior [lo, hi]; result arrays use their first dim entries. */
+gk_status gk_nested_sample(int32_t dim, const double *lo, const double *hi, gk_loglike_fn fn,
+                           void *user, const gk_ns_opts *opts, gk_ns_result *result,
+                           double *samples, int64_t cap, int64_t *n_samples);
+
+/* Philox4x32-10 block function (for reproducibility checks): out = philox(ctr, key). */
+gk_status gk_philox4x32(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+
 /* Shape of the fine model cube with its halo and the halos themselves:
  * dims = {nx_ext, ny_ext, nz_ext, h_psf, h_lsf}. */
 gk_status gk_model_dims(const gk_model *model, int32_t dims[5]);

@@ -23,9 +23,10 @@ namespace gbk {
 // normal-equation results.
 struct FitWork {
     hipStream_t stream = nullptr;
-    int rows_cap = 0;
-    double *h_params = nullptr, *d_params = nullptr;
-    double *d_resid = nullptr;
+    int rows_cap = 0, resid_cap = 0;
+    double *h_params = nullptr, *d_params = nullptr;  // [rows_cap][NPAR]
+    double *d_chi2 = nullptr, *h_chi2 = nullptr;      // [rows_cap]
+    double *d_resid = nullptr;                        // [resid_cap][2][npix]
     double *d_norm = nullptr, *h_norm = nullptr;
 };
 
@@ -35,6 +36,8 @@ void fit_release(FitWork *w)
     if (w->stream) (void)hipStreamSynchronize(w->stream);
     (void)hipHostFree(w->h_params);
     (void)hipFree(w->d_params);
+    (void)hipFree(w->d_chi2);
+    (void)hipHostFree(w->h_chi2);
     (void)hipFree(w->d_resid);
     (void)hipFree(w->d_norm);
     (void)hipHostFree(w->h_norm);
@@ -50,7 +53,9 @@ constexpr int kMaxFree = NPAR;
 constexpr int kMaxPairs = kMaxFree * (kMaxFree + 1) / 2;
 constexpr int kNormSlots = kMaxPairs + kMaxFree + 1;
 
-gk_status fit_reserve(gk_model *m, int rows)
+// Grows the fitter workspace to `rows` parameter rows (and `resid_rows`
+// residual rows when > 0).
+gk_status fit_reserve(gk_model *m, int rows, int resid_rows)
 {
     if (!m->fit) {
         m->fit = new (std::nothrow) FitWork();
@@ -60,18 +65,29 @@ gk_status fit_reserve(gk_model *m, int rows)
         HIP_TRY(hipHostMalloc((void **)&m->fit->h_norm, sizeof(double) * kNormSlots, 0));
     }
     FitWork *w = m->fit;
-    if (rows <= w->rows_cap) return GK_OK;
-    HIP_TRY(hipStreamSynchronize(w->stream));
-    (void)hipHostFree(w->h_params);
-    (void)hipFree(w->d_params);
-    (void)hipFree(w->d_resid);
-    w->h_params = w->d_params = w->d_resid = nullptr;
-    w->rows_cap = 0;
-    const size_t npix = (size_t)m->d.nx * m->d.ny;
-    HIP_TRY(hipHostMalloc((void **)&w->h_params, sizeof(double) * NPAR * rows, 0));
-    HIP_TRY(dev_alloc(&w->d_params, (size_t)rows * NPAR));
-    HIP_TRY(dev_alloc(&w->d_resid, (size_t)rows * 2 * npix));
-    w->rows_cap = rows;
+    if (rows > w->rows_cap) {
+        HIP_TRY(hipStreamSynchronize(w->stream));
+        (void)hipHostFree(w->h_params);
+        (void)hipFree(w->d_params);
+        (void)hipFree(w->d_chi2);
+        (void)hipHostFree(w->h_chi2);
+        w->h_params = w->d_params = w->d_chi2 = w->h_chi2 = nullptr;
+        w->rows_cap = 0;
+        HIP_TRY(hipHostMalloc((void **)&w->h_params, sizeof(double) * NPAR * rows, 0));
+        HIP_TRY(dev_alloc(&w->d_params, (size_t)rows * NPAR));
+        HIP_TRY(dev_alloc(&w->d_chi2, (size_t)rows));
+        HIP_TRY(hipHostMalloc((void **)&w->h_chi2, sizeof(double) * rows, 0));
+        w->rows_cap = rows;
+    }
+    if (resid_rows > w->resid_cap) {
+        HIP_TRY(hipStreamSynchronize(w->stream));
+        (void)hipFree(w->d_resid);
+        w->d_resid = nullptr;
+        w->resid_cap = 0;
+        const size_t npix = (size_t)m->d.nx * m->d.ny;
+        HIP_TRY(dev_alloc(&w->d_resid, (size_t)resid_rows * 2 * npix));
+        w->resid_cap = resid_rows;
+    }
     return GK_OK;
 }
 
@@ -198,7 +214,7 @@ extern "C" gk_status gk_fit_lm(gk_model *m, double *p_io, const uint8_t *free_ma
     const int nf = (int)fr.size(), rows = 1 + 2 * nf;
     DeviceGuard g(m->device);
     HIP_TRY(g.err);
-    GK_TRY(fit_reserve(m, rows));
+    GK_TRY(fit_reserve(m, rows, rows));
     FitWork *w = m->fit;
     const size_t npix = (size_t)m->d.nx * m->d.ny;
     const int n = (int)(2 * npix);
@@ -338,3 +354,21 @@ extern "C" gk_status gk_fit_lm(gk_model *m, double *p_io, const uint8_t *free_ma
     res->n_evals = n_evals;
     return reason == GK_LM_MAXITER ? GK_ENOTCONV : GK_OK;
 }
+
+namespace gbk {
+
+// Parameter-row and chi-square buffers of the fitter workspace (for the
+// nested sampler and the grid search).
+gk_status fit_reserve_rows(gk_model *m, int rows, double **h_params, double **d_params,
+                           double **d_chi2, double **h_chi2, hipStream_t *stream)
+{
+    GK_TRY(fit_reserve(m, rows, 0));
+    *h_params = m->fit->h_params;
+    *d_params = m->fit->d_params;
+    *d_chi2 = m->fit->d_chi2;
+    *h_chi2 = m->fit->h_chi2;
+    *stream = m->fit->stream;
+    return GK_OK;
+}
+
+}  // namespace gbk

@@ -25,6 +25,7 @@ SYMBOLS = (
     "gk_create_model", "gk_destroy_model", "gk_set_observation", "gk_observation_count",
     "gk_evaluate_batch", "gk_chi2_batch", "gk_residual_batch", "gk_model_dims", "gk_last_error",
     "gk_set_profiling", "gk_read_profile", "gk_lm_default_opts", "gk_fit_lm",
+    "gk_ns_default_opts", "gk_fit_nested", "gk_nested_sample", "gk_philox4x32",
 )
 LM_REASONS = {1: "ftol", 2: "xtol", 3: "lambda", 4: "maxiter"}
 GK_PROF_TIMING, GK_PROF_COUNT = 1, 2
@@ -62,6 +63,82 @@ class LMResult(ctypes.Structure):
                 ("n_evals", ctypes.c_int64), ("errors", ctypes.c_double * NPAR)]
 
 
+class NSOpts(ctypes.Structure):
+    _fields_ = [("n_live", ctypes.c_int32), ("batch", ctypes.c_int32), ("max_iter", ctypes.c_int64),
+                ("enlarge", ctypes.c_double), ("tol", ctypes.c_double), ("seed", ctypes.c_uint64)]
+
+
+class NSResult(ctypes.Structure):
+    _fields_ = [("logz", ctypes.c_double), ("logz_err", ctypes.c_double),
+                ("info_h", ctypes.c_double), ("max_logl", ctypes.c_double),
+                ("n_iter", ctypes.c_int64), ("n_evals", ctypes.c_int64),
+                ("n_launches", ctypes.c_int64)] + [
+                (n, ctypes.c_double * NPAR) for n in ("best", "mean", "sd", "median", "q16", "q84")]
+
+
+LOGLIKE_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.c_int32,
+                              ctypes.c_int32, ctypes.POINTER(ctypes.c_double), ctypes.c_void_p)
+
+
+def _ns_opts(L, **opts):
+    o = NSOpts()
+    _check(L.gk_ns_default_opts(ctypes.byref(o)))
+    for k, v in opts.items():
+        setattr(o, k, v)
+    if "n_live" in opts and "batch" not in opts:
+        o.batch = o.n_live
+    return o
+
+
+def _ns_dict(r: "NSResult", st: int, dim: int, samples=None) -> dict:
+    out = {"logz": r.logz, "logz_err": r.logz_err, "info_h": r.info_h, "max_logl": r.max_logl,
+           "n_iter": r.n_iter, "n_evals": r.n_evals, "n_launches": r.n_launches, "status": st}
+    for n in ("best", "mean", "sd", "median", "q16", "q84"):
+        out[n] = np.array(getattr(r, n)[:dim])
+    if samples is not None:
+        out["samples"] = samples
+    return out
+
+
+def philox4x32(ctr, key):
+    """Philox4x32-10 block of the library (gk_philox4x32)."""
+    L = load()
+    c = (ctypes.c_uint32 * 4)(*ctr)
+    k = (ctypes.c_uint32 * 2)(*key)
+    o = (ctypes.c_uint32 * 4)()
+    _check(L.gk_philox4x32(c, k, o))
+    return list(o)
+
+
+def nested_sample(loglike, lo, hi, want_samples=0, **opts) -> dict:
+    """gk_nested_sample with a Python batch log-likelihood loglike(theta[n, dim]) -> [n]."""
+    L = load()
+    lo = np.ascontiguousarray(lo, dtype=np.float64)
+    hi = np.ascontiguousarray(hi, dtype=np.float64)
+    dim = lo.size
+
+    def cb(theta, n, d, out, user):
+        try:
+            th = np.ctypeslib.as_array(theta, shape=(n, d)).copy()
+            v = np.asarray(loglike(th), dtype=np.float64)
+            np.ctypeslib.as_array(out, shape=(n,))[:] = v
+            return 0
+        except Exception:
+            return 1
+    fn = LOGLIKE_FN(cb)
+    r = NSResult()
+    o = _ns_opts(L, **opts)
+    buf = np.zeros((max(want_samples, 1), NPAR + 1))
+    ns = ctypes.c_int64(0)
+    st = L.gk_nested_sample(dim, lo.ctypes.data, hi.ctypes.data, fn, None, ctypes.byref(o),
+                            ctypes.byref(r), buf.ctypes.data if want_samples else None,
+                            want_samples, ctypes.byref(ns))
+    if st < 0 and st != GK_ENOTCONV:
+        _check(st)
+    smp = buf[: ns.value, list(range(dim)) + [NPAR]] if want_samples else None
+    return _ns_dict(r, st, dim, smp)
+
+
 KERNEL_NAMES = ("k_prep", "k_line_sums", "k_psf_moments", "k_reduce_chi2")
 
 _lib = None
@@ -89,6 +166,15 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.gk_read_profile.argtypes = [vp, ctypes.POINTER(ProfileStats)]
     L.gk_lm_default_opts.argtypes = [ctypes.POINTER(LMOpts)]
     L.gk_fit_lm.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(LMOpts), ctypes.POINTER(LMResult)]
+    L.gk_ns_default_opts.argtypes = [ctypes.POINTER(NSOpts)]
+    L.gk_fit_nested.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(NSOpts),
+                                ctypes.POINTER(NSResult), vp, ctypes.c_int64,
+                                ctypes.POINTER(ctypes.c_int64)]
+    L.gk_nested_sample.argtypes = [ctypes.c_int32, vp, vp, LOGLIKE_FN, vp,
+                                   ctypes.POINTER(NSOpts), ctypes.POINTER(NSResult), vp,
+                                   ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
+    L.gk_philox4x32.argtypes = [ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint32),
+                                ctypes.POINTER(ctypes.c_uint32)]
     L.gk_last_error.restype = ctypes.c_char_p
     for name in SYMBOLS:
         if name != "gk_last_error":
@@ -236,6 +322,25 @@ class Model:
         return {"p": p, "chi2": r.chi2, "n_valid": r.n_valid, "iterations": r.iterations,
                 "reason": LM_REASONS.get(r.reason, str(r.reason)), "n_evals": r.n_evals,
                 "errors": np.array(r.errors[:]), "status": st}
+
+    def fit_nested(self, lo, hi, free, fixed, want_samples=0, **opts) -> dict:
+        """Nested sampling of the model's posterior (gk_fit_nested)."""
+        L = load()
+        lo = np.ascontiguousarray(lo, dtype=np.float64)
+        hi = np.ascontiguousarray(hi, dtype=np.float64)
+        fm = np.ascontiguousarray(free, dtype=np.uint8)
+        fx = np.ascontiguousarray(fixed, dtype=np.float64)
+        r = NSResult()
+        o = _ns_opts(L, **opts)
+        buf = np.zeros((max(want_samples, 1), NPAR + 1))
+        ns = ctypes.c_int64(0)
+        st = L.gk_fit_nested(self._h, lo.ctypes.data, hi.ctypes.data, fm.ctypes.data,
+                             fx.ctypes.data, ctypes.byref(o), ctypes.byref(r),
+                             buf.ctypes.data if want_samples else None, want_samples,
+                             ctypes.byref(ns))
+        if st < 0 and st != GK_ENOTCONV:
+            _check(st)
+        return _ns_dict(r, st, NPAR, buf[: ns.value] if want_samples else None)
 
     def residuals(self, params, out=None, stream=None):
         """resid [B][2][ny][nx] float64 CUDA tensor."""

@@ -1,0 +1,86 @@
+"""Host logic of the library's nested sampler and random generator (no GPU):
+the sampler runs on a Python likelihood through gk_nested_sample."""
+import math
+
+import numpy as np
+import pytest
+
+
+def philox_ref(ctr, key):
+    """Philox4x32-10 from its published definition (Salmon et al. 2011):
+    10 rounds of two 32x32->64 multiplications with a Weyl-sequence key bump."""
+    M0, M1, W0, W1 = 0xD2511F53, 0xCD9E8D57, 0x9E3779B9, 0xBB67AE85
+    c = list(ctr)
+    k0, k1 = key
+    for r in range(10):
+        if r:
+            k0 = (k0 + W0) & 0xFFFFFFFF
+            k1 = (k1 + W1) & 0xFFFFFFFF
+        p0, p1 = M0 * c[0], M1 * c[2]
+        c = [((p1 >> 32) ^ c[1] ^ k0) & 0xFFFFFFFF, p1 & 0xFFFFFFFF,
+             ((p0 >> 32) ^ c[3] ^ k1) & 0xFFFFFFFF, p0 & 0xFFFFFFFF]
+    return c
+
+
+def test_philox_known_answer_and_reference():
+    from paper_1510_01815_amd import gbk
+    # published known-answer vector: zero counter, zero key
+    assert gbk.philox4x32([0, 0, 0, 0], [0, 0]) == [0x6627E8D5, 0xE169C58D, 0xBC57AC4C, 0x9B00DBD8]
+    rng = np.random.default_rng(0)
+    for _ in range(50):
+        ctr = [int(v) for v in rng.integers(0, 2**32, 4)]
+        key = [int(v) for v in rng.integers(0, 2**32, 2)]
+        assert gbk.philox4x32(ctr, key) == philox_ref(ctr, key)
+
+
+def gauss_loglike(mu, sig):
+    def f(th):
+        return -0.5 * np.sum(((th[:, : len(mu)] - mu) / sig) ** 2, axis=1)
+    return f
+
+
+@pytest.mark.parametrize("batch", [100, 400])
+def test_ns_gaussian_evidence_and_moments(batch):
+    """3-D Gaussian likelihood in a wide box: log Z = sum log(sigma sqrt(2 pi)
+    / width); posterior mean mu, sd sigma, 16/50/84% at mu -/+ sigma.  A 4th
+    parameter absent from the likelihood keeps its uniform prior."""
+    from paper_1510_01815_amd import gbk
+    mu = np.array([1.0, -2.0, 0.5])
+    sig = np.array([0.5, 1.0, 0.2])
+    lo = np.array([-6.0, -10.0, -2.0, 0.0])
+    hi = np.array([6.0, 8.0, 3.0, 4.0])
+    r = gbk.nested_sample(gauss_loglike(mu, sig), lo, hi, n_live=400, batch=batch, seed=7)
+    logz_true = float(np.sum(np.log(sig * math.sqrt(2 * math.pi) / (hi[:3] - lo[:3]))))
+    print(r["logz"], r["logz_err"], logz_true, r["n_iter"], r["n_evals"], r["n_launches"])
+    assert r["status"] == 0
+    assert abs(r["logz"] - logz_true) < 3 * r["logz_err"] + 0.1
+    np.testing.assert_allclose(r["mean"][:3], mu, atol=0.1 * sig.max())
+    np.testing.assert_allclose(r["sd"][:3], sig, rtol=0.1)
+    assert np.all(np.abs(r["median"][:3] - mu) <= 0.12 * sig)
+    assert np.all(np.abs(r["q16"][:3] - (mu - sig)) <= 0.15 * sig)
+    assert np.all(np.abs(r["q84"][:3] - (mu + sig)) <= 0.15 * sig)
+    # flat direction: marginal = prior U[0, 4]
+    assert abs(r["mean"][3] - 2.0) < 0.15 and abs(r["sd"][3] - 4 / math.sqrt(12)) < 0.1
+    assert abs(r["max_logl"]) < 0.5
+
+
+def test_ns_reproducible_and_samples():
+    from paper_1510_01815_amd import gbk
+    f = gauss_loglike(np.array([0.3]), np.array([0.1]))
+    a = gbk.nested_sample(f, [-1.0], [1.0], want_samples=100000, n_live=100, seed=3)
+    b = gbk.nested_sample(f, [-1.0], [1.0], want_samples=100000, n_live=100, seed=3)
+    c = gbk.nested_sample(f, [-1.0], [1.0], n_live=100, seed=4)
+    assert a["logz"] == b["logz"] and (a["samples"] == b["samples"]).all()
+    assert a["logz"] != c["logz"]
+    w = a["samples"][:, -1]
+    assert abs(w.sum() - 1.0) < 1e-9 and len(w) == a["n_iter"] + 100
+    assert abs(np.sum(w * a["samples"][:, 0]) - a["mean"][0]) < 1e-12
+
+
+def test_ns_callback_failure_is_an_error():
+    from paper_1510_01815_amd import gbk
+
+    def bad(th):
+        raise RuntimeError("boom")
+    with pytest.raises(gbk.GkError):
+        gbk.nested_sample(bad, [0.0], [1.0], n_live=10)
