@@ -253,6 +253,31 @@ gk_status gk_nested_sample(int32_t dim, const double *lo, const double *hi, gk_l
 /* Philox4x32-10 block function (for reproducibility checks): out = philox(ctr, key). */
 gk_status gk_philox4x32(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 
+/* ---- Nested grids (Sec. 2.3.3) -------------------------------------------
+ * Brute-force search on a regular grid of n nodes per free slot (end points
+ * included) spanning the current box; the node of least chi2 (ties: lowest
+ * linear node index, first free slot varying slowest) centres the next box,
+ * which is that node +- one grid spacing clipped to the initial box.  Each
+ * level's n^d nodes are generated on the device and evaluated in batched
+ * launches; the argmin is reduced on the device.  Stops after max_levels or
+ * when every free slot's spacing is below accuracy[k]. */
+typedef struct {
+    double best[GK_NP];       /* best node of the last level */
+    double chi2;              /* its chi2 */
+    int64_t best_index;       /* its linear node index within the last level */
+    int32_t levels;           /* levels run */
+    int32_t reserved;
+    int64_t n_evals;          /* rows evaluated */
+    double spacing[GK_NP];    /* grid spacing of the last level per slot */
+} gk_grid_result;
+
+/* Free slots: free_mask[k] != 0 searched in [lo_k, hi_k]; others fixed at
+ * fixed[k].  n_per_dim >= 2; n_per_dim^(free slots) <= 2^31 nodes per level.
+ * accuracy may be NULL (then only max_levels stops).  Blocks. */
+gk_status gk_fit_grid(gk_model *model, const double *lo, const double *hi,
+                      const uint8_t *free_mask, const double *fixed, int32_t n_per_dim,
+                      int32_t max_levels, const double *accuracy, gk_grid_result *result);
+
 /* Shape of the fine model cube with its halo and the halos themselves:
  * dims = {nx_ext, ny_ext, nz_ext, h_psf, h_lsf}. */
 gk_status gk_model_dims(const gk_model *model, int32_t dims[5]);

@@ -144,3 +144,46 @@ def model_residuals(d: "O.Desc", obs):
         rs = sw * (m[2].ravel()[mk] - so) / es if obs.W > 0 else np.zeros_like(rv)
         return np.concatenate([rv, rs])
     return resid
+
+
+@dataclass
+class GridResult:
+    best: np.ndarray
+    chi2: float
+    best_index: int
+    levels: int
+    n_evals: int
+    spacing: np.ndarray
+
+
+def nested_grid(chi2_fn, lo0, hi0, free, fixed, n=16, max_levels=3, accuracy=None) -> GridResult:
+    """Nested grids (Sec. 2.3.3): a regular grid of n nodes per free slot (end
+    points included) over the current box; the least-chi2 node (lowest linear
+    index on ties, first free slot varying slowest) centres the next box,
+    node +- one spacing clipped to the initial box.  Stops after max_levels or
+    when every spacing is below accuracy."""
+    slots = [k for k in range(len(fixed)) if free[k]]
+    lo = np.array(lo0, dtype=np.float64).copy()
+    hi = np.array(hi0, dtype=np.float64).copy()
+    best_p, best_v, best_i, n_evals, level = None, math.inf, -1, 0, 0
+    spacing = np.zeros(len(fixed))
+    for level in range(1, max_levels + 1):
+        step = {k: (hi[k] - lo[k]) / (n - 1) for k in slots}
+        best_v, best_i = math.inf, -1
+        for L in range(n ** len(slots)):
+            p = np.array(fixed, dtype=np.float64).copy()
+            rem = L
+            for k in reversed(slots):
+                p[k] = lo[k] + (rem % n) * step[k]
+                rem //= n
+            v = chi2_fn(p)
+            n_evals += 1
+            if v < best_v:
+                best_v, best_i, best_p = v, L, p
+        for k in slots:
+            spacing[k] = step[k]
+            lo[k] = max(best_p[k] - step[k], lo0[k])
+            hi[k] = min(best_p[k] + step[k], hi0[k])
+        if accuracy is not None and all(step[k] < accuracy[k] for k in slots):
+            break
+    return GridResult(best_p, best_v, best_i, level, n_evals, spacing)

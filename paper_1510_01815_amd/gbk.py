@@ -25,7 +25,7 @@ SYMBOLS = (
     "gk_create_model", "gk_destroy_model", "gk_set_observation", "gk_observation_count",
     "gk_evaluate_batch", "gk_chi2_batch", "gk_residual_batch", "gk_model_dims", "gk_last_error",
     "gk_set_profiling", "gk_read_profile", "gk_lm_default_opts", "gk_fit_lm",
-    "gk_ns_default_opts", "gk_fit_nested", "gk_nested_sample", "gk_philox4x32",
+    "gk_ns_default_opts", "gk_fit_nested", "gk_nested_sample", "gk_philox4x32", "gk_fit_grid",
 )
 LM_REASONS = {1: "ftol", 2: "xtol", 3: "lambda", 4: "maxiter"}
 GK_PROF_TIMING, GK_PROF_COUNT = 1, 2
@@ -74,6 +74,13 @@ class NSResult(ctypes.Structure):
                 ("n_iter", ctypes.c_int64), ("n_evals", ctypes.c_int64),
                 ("n_launches", ctypes.c_int64)] + [
                 (n, ctypes.c_double * NPAR) for n in ("best", "mean", "sd", "median", "q16", "q84")]
+
+
+class GridResult(ctypes.Structure):
+    _fields_ = [("best", ctypes.c_double * NPAR), ("chi2", ctypes.c_double),
+                ("best_index", ctypes.c_int64), ("levels", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("n_evals", ctypes.c_int64),
+                ("spacing", ctypes.c_double * NPAR)]
 
 
 LOGLIKE_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.c_int32,
@@ -175,6 +182,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
                                    ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
     L.gk_philox4x32.argtypes = [ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint32),
                                 ctypes.POINTER(ctypes.c_uint32)]
+    L.gk_fit_grid.argtypes = [vp, vp, vp, vp, vp, ctypes.c_int32, ctypes.c_int32, vp,
+                              ctypes.POINTER(GridResult)]
     L.gk_last_error.restype = ctypes.c_char_p
     for name in SYMBOLS:
         if name != "gk_last_error":
@@ -341,6 +350,19 @@ class Model:
         if st < 0 and st != GK_ENOTCONV:
             _check(st)
         return _ns_dict(r, st, NPAR, buf[: ns.value] if want_samples else None)
+
+    def fit_grid(self, lo, hi, free, fixed, n_per_dim=16, max_levels=3, accuracy=None) -> dict:
+        """Nested-grid search (gk_fit_grid)."""
+        L = load()
+        a = [np.ascontiguousarray(v, dtype=np.float64) for v in (lo, hi, fixed)]
+        fm = np.ascontiguousarray(free, dtype=np.uint8)
+        acc = None if accuracy is None else np.ascontiguousarray(accuracy, dtype=np.float64)
+        r = GridResult()
+        _check(L.gk_fit_grid(self._h, a[0].ctypes.data, a[1].ctypes.data, fm.ctypes.data,
+                             a[2].ctypes.data, n_per_dim, max_levels,
+                             None if acc is None else acc.ctypes.data, ctypes.byref(r)))
+        return {"best": np.array(r.best[:]), "chi2": r.chi2, "best_index": r.best_index,
+                "levels": r.levels, "n_evals": r.n_evals, "spacing": np.array(r.spacing[:])}
 
     def residuals(self, params, out=None, stream=None):
         """resid [B][2][ny][nx] float64 CUDA tensor."""

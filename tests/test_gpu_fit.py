@@ -115,3 +115,97 @@ def test_nested_sampling_recovers_truth_and_flat_i0(O, gbk):
         assert abs(r["median"][k] - truth[k]) < 4 * r["sd"][k] + 1e-3, k
     assert abs(r["mean"][9] - 1.25) < 0.1 and abs(r["sd"][9] - 1.5 / math.sqrt(12)) < 0.06
     assert r["median"][8] == 5.0 and r["sd"][8] == 0.0
+
+
+def test_grid_argmin_matches_oracle_bruteforce(O, gbk):
+    """One level of a 6^3 grid over (PA, i, Vt): the least-chi2 node index is
+    the same as the oracle's brute force over the same nodes (first free slot
+    varying slowest), and its chi2 agrees to 1e-6."""
+    grid = I.Grid(12, 12, 24, 30.0, psf_fwhm=2.5, lsf_sigma=30.0)
+    d = oracle_desc(O, grid.as_dict())
+    truth = np.array([6.1, 5.8, 50.0, 45.0, 0.0, 150.0, 2.5, 40.0, 3.0, 1.0, 1.0, 1.0])
+    obs = I.make_observation(O.evaluate(d, truth), 5.0, I.rng_for(70, 0, 0))
+    m = gbk.Model.from_grid(grid)
+    m.set_obs(obs)
+    free = [0, 0, 1, 1, 0, 1, 0, 0, 0, 0, 0, 0]
+    lo = truth.copy(); hi = truth.copy()
+    lo[[2, 3, 5]] = [20.0, 20.0, 80.0]
+    hi[[2, 3, 5]] = [80.0, 70.0, 220.0]
+    r = m.fit_grid(lo, hi, free, truth, n_per_dim=6, max_levels=1)
+    best, bi, L = np.inf, -1, 0
+    for a in range(6):
+        for b in range(6):
+            for c in range(6):
+                p = truth.copy()
+                p[2] = 20.0 + a * 12.0
+                p[3] = 20.0 + b * 10.0
+                p[5] = 80.0 + c * 28.0
+                v, _ = O.eval_chi2(d, p, obs.vel, obs.sig, obs.evel, obs.esig, obs.mask, obs.W)
+                if v < best:
+                    best, bi = v, L
+                L += 1
+    assert r["best_index"] == bi and r["n_evals"] == 216 and r["levels"] == 1
+    assert abs(r["chi2"] - best) <= 1e-6 * best
+
+
+def test_grid_levels_match_oracle_nested_grid(O, gbk):
+    """Three levels of a 6^3 grid over (PA, i, Vt) on a noisy cube: the GPU
+    search and the oracle's reference nested grid pick the same node at every
+    level, so they end on the same node (integer argmin, exact)."""
+    grid = I.Grid(12, 12, 24, 30.0, psf_fwhm=2.5, lsf_sigma=30.0)
+    d = oracle_desc(O, grid.as_dict())
+    truth = np.array([6.1, 5.8, 50.0, 45.0, 0.0, 150.0, 2.5, 40.0, 3.0, 1.0, 1.0, 1.0])
+    obs = I.make_observation(O.evaluate(d, truth), 5.0, I.rng_for(70, 1, 0))
+    m = gbk.Model.from_grid(grid)
+    m.set_obs(obs)
+    free = [0, 0, 1, 1, 0, 1, 0, 0, 0, 0, 0, 0]
+    lo, hi = truth.copy(), truth.copy()
+    lo[[2, 3, 5]] = [20.0, 20.0, 80.0]
+    hi[[2, 3, 5]] = [80.0, 70.0, 220.0]
+    chi2 = lambda p: O.eval_chi2(d, p, obs.vel, obs.sig, obs.evel, obs.esig, obs.mask, obs.W)[0]
+    ref = F.nested_grid(chi2, lo, hi, free, truth, n=6, max_levels=3)
+    r = m.fit_grid(lo, hi, free, truth, n_per_dim=6, max_levels=3)
+    assert r["best_index"] == ref.best_index and r["levels"] == ref.levels == 3
+    np.testing.assert_array_equal(r["best"], ref.best)
+    assert abs(r["chi2"] - ref.chi2) <= 1e-6 * ref.chi2
+
+
+def test_grid_systemic_velocity_bowl(O, gbk):
+    """Vsys alone (W = 0) has an exactly quadratic chi2, so every zoomed box
+    contains the minimum: after 4 levels of 16 nodes the best node is within
+    one final spacing of the closed-form optimum."""
+    grid = I.Grid(16, 16, 96, 10.0, psf_fwhm=2.0, lsf_sigma=15.0, crpix=47.5)
+    truth = np.array([8.0, 7.5, 30.0, 50.0, 0.0, 120.0, 3.0, 25.0, 4.0, 1.0, 1.0, 1.0])
+    base = O.evaluate(oracle_desc(O, grid.as_dict()), truth)
+    obs = I.make_observation(base, 5.0, np.random.default_rng(8), W=0.0)
+    m = gbk.Model.from_grid(grid)
+    m.set_obs(obs)
+    free = [0] * 12
+    free[4] = 1
+    lo, hi = truth.copy(), truth.copy()
+    lo[4], hi[4] = -40.0, 40.0
+    r = m.fit_grid(lo, hi, free, truth, n_per_dim=16, max_levels=4)
+    mk = obs.mask.astype(bool)
+    w = 1.0 / obs.evel.astype(np.float64)[mk] ** 2
+    expect = np.sum(w * (obs.vel.astype(np.float64)[mk] - base[1][mk])) / np.sum(w)
+    assert abs(r["best"][4] - expect) <= r["spacing"][4] and r["spacing"][4] < 0.1
+
+
+def test_grid_five_dims_million_rows_per_level(O, gbk):
+    """The beam-smeared grid workload: (i, PA, Vt, rt, sigma) at 16 nodes per
+    dimension, 1,048,576 rows per level, 3 levels; the search ends deep in the
+    chi2 valley (the i-Vt degeneracy of Sec. 6.1 can leave it off the truth)."""
+    g, truth = I.c4_galaxy(3)
+    d = oracle_desc(O, g.as_dict())
+    obs = I.make_observation(O.evaluate(d, truth), 0.0, I.rng_for(4, 3, 1))
+    m = gbk.Model.from_grid(g)
+    m.set_obs(obs)
+    free = [0, 0, 1, 1, 0, 1, 1, 1, 0, 0, 0, 0]
+    lo, hi = truth.copy(), truth.copy()
+    lo[[2, 3, 5, 6, 7]] = [truth[2] - 40, 5.0, 50.0, 0.5 * g.psf_fwhm, 20.0]
+    hi[[2, 3, 5, 6, 7]] = [truth[2] + 40, 85.0, 300.0, 2.0 * g.psf_fwhm, 100.0]
+    one = m.fit_grid(lo, hi, free, truth, n_per_dim=16, max_levels=1)
+    r = m.fit_grid(lo, hi, free, truth, n_per_dim=16, max_levels=3)
+    print("grid5", one["chi2"], r["chi2"], r["best"][[2, 3, 5, 6, 7]], truth[[2, 3, 5, 6, 7]])
+    assert r["levels"] == 3 and r["n_evals"] == 3 * 16 ** 5
+    assert np.isfinite(r["chi2"]) and r["chi2"] <= one["chi2"] and r["chi2"] < 0.01 * one["chi2"] + 10

@@ -68,3 +68,20 @@ def test_lm_systemic_velocity_weighted_mean(O):
     expect = np.sum(w * (obs.vel.astype(np.float64)[mk] - base[1][mk])) / np.sum(w)
     assert abs(res.p[4] - expect) < 1e-6
     assert abs(res.errors[4] - 1 / math.sqrt(np.sum(w))) < 1e-6
+
+
+def test_nested_grid_quadratic_bowl():
+    """A separable quadratic bowl: every level contains the minimum, so the
+    final best node is within one final spacing of it; node 0 wins ties."""
+    c = np.array([0.3, -1.7])
+    f = lambda p: float(np.sum((p[:2] - c) ** 2 * np.array([1.0, 4.0])))
+    r = F.nested_grid(f, [-5.0, -5.0], [5.0, 5.0], [1, 1], [0.0, 0.0], n=16, max_levels=4)
+    assert np.all(np.abs(r.best - c) <= r.spacing + 1e-12) and r.n_evals == 4 * 256
+    flat = F.nested_grid(lambda p: 1.0, [0.0], [1.0], [1], [0.0], n=5, max_levels=1)
+    assert flat.best_index == 0 and flat.best[0] == 0.0
+
+
+def test_nested_grid_accuracy_stop():
+    r = F.nested_grid(lambda p: (p[0] - 0.25) ** 2, [0.0], [1.0], [1], [0.0], n=11,
+                      max_levels=10, accuracy=[0.01])
+    assert r.levels == 3 and r.spacing[0] < 0.01 and abs(r.best[0] - 0.25) <= r.spacing[0]
