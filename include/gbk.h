@@ -278,6 +278,33 @@ gk_status gk_fit_grid(gk_model *model, const double *lo, const double *hi,
                       const uint8_t *free_mask, const double *fixed, int32_t n_per_dim,
                       int32_t max_levels, const double *accuracy, gk_grid_result *result);
 
+/* ---- Surveys: ragged batches over many models -----------------------------
+ * A survey groups models (galaxies with their own grids, PSFs and
+ * observations) on one device.  A batch lists (model, parameter row) pairs of
+ * any mix of models; every row is evaluated in the same launch chain, each
+ * kernel locating its (row, tile) in the ragged work list. */
+typedef struct gk_survey gk_survey;
+
+/* models [n] must stay alive (and on one device) while the survey is used;
+ * their observations are read at each call.  Errors: GK_EINVAL. */
+gk_status gk_create_survey(gk_model *const *models, int32_t n, gk_survey **out);
+gk_status gk_destroy_survey(gk_survey *survey);
+
+/* chi2 [B] (device) of rows params [B][GK_NP] (host or device) of models
+ * model_idx [B] (host).  Every model needs an observation (GK_ESTATE). */
+gk_status gk_survey_chi2(gk_survey *survey, const int32_t *model_idx, const double *params,
+                         int32_t B, double *chi2, void *hip_stream);
+
+/* Levenberg-Marquardt (the rule of gk_fit_lm) of every galaxy of the survey
+ * at once: each iteration evaluates all unconverged galaxies' trial points and
+ * Jacobian rows in one ragged launch chain and forms their normal equations in
+ * one kernel; converged galaxies drop out.  p_inout [n][GK_NP], lo/hi
+ * [n][GK_NP] (NULL = unbounded), free_mask [GK_NP] shared, results [n].
+ * Blocks.  GK_ENOTCONV if some galaxy reached max_iter. */
+gk_status gk_fit_lm_survey(gk_survey *survey, double *p_inout, const uint8_t *free_mask,
+                           const double *lo, const double *hi, const gk_lm_opts *opts,
+                           gk_lm_result *results);
+
 /* Shape of the fine model cube with its halo and the halos themselves:
  * dims = {nx_ext, ny_ext, nz_ext, h_psf, h_lsf}. */
 gk_status gk_model_dims(const gk_model *model, int32_t dims[5]);

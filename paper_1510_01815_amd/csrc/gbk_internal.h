@@ -45,6 +45,54 @@ struct PsfArgs {
     double *partial;  // [B][ntiles]
 };
 
+// Per-row pointers of one (row, tile) of the PSF/moment pass.
+struct RowPtrs {
+    const double *T;   // the row's three T planes
+    const double *c;   // the row's constants
+    float *maps;       // [3][ny][nx] of the row, or NULL
+    double *resid;     // [2][ny][nx] of the row, or NULL
+    double *partial;   // this tile's chi2 partial, or NULL
+    int tile;
+};
+
+// Device-resident description of one model for ragged multi-model launches.
+struct ModelDev {
+    PsfArgs psf;            // per-model fields of the PSF/moment pass (row pointers unused)
+    const double *wz;       // channel weight table [NZE][4]
+    int NZE, EX, EY, hp, u, rc;
+    double dvf, inv_dvf, vf0;
+    int64_t nvalid;         // unmasked pixels of the observation
+    int fast_hp;            // >= 0: register-blocked u = 1 kernel with this half-width; -1: generic
+    int lds_bytes;          // dynamic LDS of its PSF/moment kernel
+};
+
+// Ragged rows of a multi-model launch (device arrays).
+struct RowMap {
+    const int *row_model;    // [B] model index of each row
+    const int64_t *T_off;    // [B] offset of the row's T planes (doubles)
+    const int *ls_base;      // [B + 1] prefix sum of line-sum tiles
+    const int64_t *part_off; // [B] offset of the row's chi2 partials
+    const int64_t *resid_off;// [B] offset of the row's residual maps, or NULL
+    int B;
+};
+
+// Rows of one PSF-kernel bucket (same kernel variant) and their tile prefix sums.
+struct BucketMap {
+    const int *rows;       // [n] row indices
+    const int *tile_base;  // [n + 1]
+    int n;
+};
+
+hipError_t launch_prep_multi(const double *params, int B, const int *row_model, const ModelDev *md,
+                             double *consts, hipStream_t s);
+hipError_t launch_line_sums_multi(const double *consts, const ModelDev *md, const RowMap &rm,
+                                  int nblocks, double *T, hipStream_t s);
+hipError_t launch_psf_multi(int fast_hp, const ModelDev *md, const RowMap &rm, const BucketMap &bk,
+                            int nblocks, const double *T, const double *consts, double *resid,
+                            double *partial, size_t lds, hipStream_t s);
+hipError_t launch_reduce_multi(const double *partial, const ModelDev *md, const RowMap &rm,
+                               const double *consts, double *chi2, int B, hipStream_t s);
+
 hipError_t launch_prep(const double *params, int B, int rc, double dvf, int hp, int u,
                        double *consts, hipStream_t s);
 hipError_t launch_line_sums(const double *consts, const double *wz, int NZE, int EX, int EY,

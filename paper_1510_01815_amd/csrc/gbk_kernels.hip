@@ -49,13 +49,9 @@ constexpr double kPi = 3.14159265358979323846;
 // ---------------------------------------------------------------------------
 // k_prep: per-row constants (FP64) -- slot layout in gbk_internal.h
 // ---------------------------------------------------------------------------
-__global__ void k_prep(const double *__restrict__ params, int B, int rc, double dvf, int hp,
-                       int u, double *__restrict__ consts)
+__device__ void prep_row(const double *__restrict__ p, double *__restrict__ c, int rc, double dvf,
+                         int hp, int u)
 {
-    int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= B) return;
-    const double *p = params + (size_t)b * NPAR;
-    double *c = consts + (size_t)b * NCONST;
     bool ok = true;
     for (int k = 0; k < NPAR; ++k) ok = ok && isfinite(p[k]);
     ok = ok && p[P_INC] > 0.0 && p[P_INC] < 90.0 && p[P_SIG] > 0.0 && p[P_R0] > 0.0 &&
@@ -98,6 +94,36 @@ __global__ void k_prep(const double *__restrict__ params, int B, int rc, double 
     c[C_YEX] = -invu * cp * se;                  // y_e / cos i, eqs. 2-3
     c[C_YEY] = -invu * sp * se;
     c[C_YE0] = (-bx * cp - by * sp) * se;
+}
+
+__global__ void k_prep(const double *__restrict__ params, int B, int rc, double dvf, int hp,
+                       int u, double *__restrict__ consts)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < B) prep_row(params + (size_t)b * NPAR, consts + (size_t)b * NCONST, rc, dvf, hp, u);
+}
+
+// Row -> model lookup of the ragged multi-model launches: the largest k with
+// base[k] <= x, base[0] = 0 <= x < base[n] (uniform across the block).
+__device__ inline int find_row(const int *__restrict__ base, int n, int x)
+{
+    int lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (base[mid] <= x) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__global__ void k_prep_multi(const double *__restrict__ params, int B,
+                             const int *__restrict__ row_model, const ModelDev *__restrict__ md,
+                             double *__restrict__ consts)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    const ModelDev &m = md[row_model[b]];
+    prep_row(params + (size_t)b * NPAR, consts + (size_t)b * NCONST, m.rc, m.dvf, m.hp, m.u);
 }
 
 // ---------------------------------------------------------------------------
@@ -151,18 +177,19 @@ __device__ inline double exp2_wide(double x)
 // tolerances.  When some lane would start below 2^-1020 (a steep velocity
 // gradient across the wave's square), the wave evaluates exp2 per channel.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_line_sums(const double *__restrict__ consts,
-                                                   const double *__restrict__ wz, int NZE, int EX,
-                                                   int EY, int hp, int u, int rc, double vf0,
-                                                   double inv_dvf, double *__restrict__ T,
-                                                   unsigned long long *__restrict__ support_count)
+// One 16 x 16 tile (tile_x, tile_y) of one row: c = the row's constants,
+// T = the row's three planes, count = this block's 4 support-count slots
+// (measurement only, may be NULL).
+__device__ __forceinline__ void line_sums_tile(const double *__restrict__ c,
+                                               const double *__restrict__ wz, int NZE, int EX,
+                                               int EY, int hp, int u, int rc, double vf0,
+                                               double inv_dvf, double *__restrict__ T, int tile_x,
+                                               int tile_y, unsigned long long *__restrict__ count)
 {
-    const int b = blockIdx.z;
-    const double *c = consts + (size_t)b * NCONST;
     if (c[C_VALID] == 0.0) return;  // uniform over the block
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int gx = (blockIdx.x << 4) + ((wave & 1) << 3) + (lane & 7);
-    const int gy = (blockIdx.y << 4) + ((wave >> 1) << 3) + (lane >> 3);
+    const int gx = (tile_x << 4) + ((wave & 1) << 3) + (lane & 7);
+    const int gy = (tile_y << 4) + ((wave >> 1) << 3) + (lane >> 3);
     const bool in = gx < EX && gy < EY;
 
     // disc geometry, eqs. 1-4: x_e and y_e / cos(i) are affine in the fine
@@ -203,13 +230,12 @@ __global__ __launch_bounds__(256) void k_line_sums(const double *__restrict__ co
     int zlo, nhi;
     wave_min2(lo, NZE - hi, zlo, nhi);
     const int zhi = NZE - nhi;
-    if (support_count) {  // measurement only: voxels inside each lane's own support
+    if (count) {  // measurement only: voxels inside each lane's own support
         int n = max(hi - lo + 1, 0);
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) n += __shfl_xor(n, o, 64);
-        // one slot per (row, wave): launches on a stream are ordered, so += is race-free
-        const size_t blk = ((size_t)b * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-        if (lane == 0) support_count[blk * 4 + wave] += n;
+        // one slot per (block, wave): launches on a stream are ordered, so += is race-free
+        if (lane == 0) count[wave] += n;
     }
 
     // log2 of the brightness factor: I(r) / (sqrt(2 pi) sigma), eq. 5 with the
@@ -250,11 +276,38 @@ __global__ __launch_bounds__(256) void k_line_sums(const double *__restrict__ co
     }
     if (in) {
         const size_t plane = (size_t)EX * EY;
-        double *Tb = T + (size_t)b * 3 * plane + (size_t)gy * EX + gx;
+        double *Tb = T + (size_t)gy * EX + gx;
         Tb[0] = t0;
         Tb[plane] = t1;
         Tb[2 * plane] = t2;
     }
+}
+
+__global__ __launch_bounds__(256) void k_line_sums(const double *__restrict__ consts,
+                                                   const double *__restrict__ wz, int NZE, int EX,
+                                                   int EY, int hp, int u, int rc, double vf0,
+                                                   double inv_dvf, double *__restrict__ T,
+                                                   unsigned long long *__restrict__ support_count)
+{
+    const int b = blockIdx.z;
+    unsigned long long *cnt = nullptr;
+    if (support_count)
+        cnt = support_count + (((size_t)b * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x) * 4;
+    line_sums_tile(consts + (size_t)b * NCONST, wz, NZE, EX, EY, hp, u, rc, vf0, inv_dvf,
+                   T + (size_t)b * 3 * EX * EY, blockIdx.x, blockIdx.y, cnt);
+}
+
+// Ragged rows of several models: block -> (row, tile) through the tile prefix
+// sums of the rows.
+__global__ __launch_bounds__(256) void k_line_sums_multi(const double *__restrict__ consts,
+                                                         const ModelDev *__restrict__ md,
+                                                         RowMap rm, double *__restrict__ T)
+{
+    const int b = find_row(rm.ls_base, rm.B, blockIdx.x);
+    const ModelDev &m = md[rm.row_model[b]];
+    const int t = blockIdx.x - rm.ls_base[b], tiles_x = (m.EX + 15) >> 4;
+    line_sums_tile(consts + (size_t)b * NCONST, m.wz, m.NZE, m.EX, m.EY, m.hp, m.u, m.rc, m.vf0,
+                   m.inv_dvf, T + rm.T_off[b], t % tiles_x, t / tiles_x, nullptr);
 }
 
 // ---------------------------------------------------------------------------
@@ -263,15 +316,15 @@ __global__ __launch_bounds__(256) void k_line_sums(const double *__restrict__ co
 //   sX [LY][TX]  after the x pass
 //   sK [2hp+1]   PSF taps
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_psf_moments(PsfArgs a)
+__device__ __forceinline__ void psf_generic_tile(const PsfArgs &a, const RowPtrs &r)
 {
     extern __shared__ double lds[];
-    const int b = blockIdx.y, tile = blockIdx.x, tid = threadIdx.x;
+    const int tile = r.tile, tid = threadIdx.x;
     const int tx0 = (tile % a.ntx) * a.TXd, ty0 = (tile / a.ntx) * a.TYd;
     const int u = a.u, hp = a.hp, K = 2 * hp + 1;
     const int TX = u * a.TXd, TY = u * a.TYd, LX = TX + 2 * hp, LY = TY + 2 * hp;
     double *sT = lds, *sX = lds + LY * LX, *sK = sX + LY * TX;
-    const double *cb = a.consts + (size_t)b * NCONST;
+    const double *cb = r.c;
     const bool valid = cb[C_VALID] != 0.0;
     const int npx = a.TXd * a.TYd;
 
@@ -288,7 +341,7 @@ __global__ __launch_bounds__(256) void k_psf_moments(PsfArgs a)
         const int gx0 = u * tx0, gy0 = u * ty0;
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
-            const double *Tj = a.T + ((size_t)b * 3 + j) * plane;
+            const double *Tj = r.T + (size_t)j * plane;
             __syncthreads();
             for (int i = tid; i < LY * LX; i += 256) {
                 const int ly = i / LX, lx = i - ly * LX;
@@ -351,8 +404,8 @@ __global__ __launch_bounds__(256) void k_psf_moments(PsfArgs a)
             }
         }
         const size_t npix = (size_t)a.nx * a.ny;
-        if (a.maps) {
-            float *mb = a.maps + (size_t)b * 3 * npix;
+        if (r.maps) {
+            float *mb = r.maps;
             mb[p] = (float)m0;
             mb[npix + p] = (float)m1;
             mb[2 * npix + p] = (float)m2;
@@ -362,14 +415,14 @@ __global__ __launch_bounds__(256) void k_psf_moments(PsfArgs a)
             const double rv = use ? (m1 - (double)a.vo[p]) * a.iev[p] : 0.0;
             const double rs = use ? (m2 - (double)a.so[p]) * a.ies[p] : 0.0;
             if (use) acc += rv * rv + rs * rs;
-            if (a.resid) {
-                double *rb = a.resid + (size_t)b * 2 * npix;
+            if (r.resid) {
+                double *rb = r.resid;
                 rb[p] = valid ? rv : __builtin_nan("");
                 rb[npix + p] = valid ? rs : __builtin_nan("");
             }
         }
     }
-    if (a.partial) {
+    if (r.partial) {
         // fixed-order block reduction: wave butterfly, then waves in order
         for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
         __shared__ double wsum[4];
@@ -377,7 +430,7 @@ __global__ __launch_bounds__(256) void k_psf_moments(PsfArgs a)
         if ((tid & 63) == 0) wsum[tid >> 6] = acc;
         __syncthreads();
         if (tid == 0)
-            a.partial[(size_t)b * a.ntiles + tile] = ((wsum[0] + wsum[1]) + wsum[2]) + wsum[3];
+            *r.partial = ((wsum[0] + wsum[1]) + wsum[2]) + wsum[3];
     }
 }
 
@@ -411,7 +464,7 @@ __device__ inline void window(const double *src, int stride, const double *kp, d
 constexpr int pad_stride(int n) { return n + ((1 - n) % 4 + 4) % 4; }
 
 template <int HP, int TX>
-__global__ __launch_bounds__(256) void k_psf_moments_u1(PsfArgs a)
+__device__ __forceinline__ void psf_u1_tile(const PsfArgs &a, const RowPtrs &r)
 {
     extern __shared__ double lds[];
     constexpr int TY = 32, K = 2 * HP + 1;
@@ -419,10 +472,10 @@ __global__ __launch_bounds__(256) void k_psf_moments_u1(PsfArgs a)
     constexpr int ST = pad_stride(LX), SX = pad_stride(TX);
     constexpr int RPT = TX * TY / 256;       // rows per thread in the y pass
     constexpr int TPR = TX / 4;              // x-pass tasks per row
-    const int b = blockIdx.y, tile = blockIdx.x, tid = threadIdx.x;
+    const int tile = r.tile, tid = threadIdx.x;
     const int tx0 = (tile % a.ntx) * TX, ty0 = (tile / a.ntx) * TY;
     double *sT = lds, *sX = lds + LY * ST;
-    const double *cb = a.consts + (size_t)b * NCONST;
+    const double *cb = r.c;
     const bool valid = cb[C_VALID] != 0.0;
     double kp[K];
 #pragma unroll
@@ -450,7 +503,7 @@ __global__ __launch_bounds__(256) void k_psf_moments_u1(PsfArgs a)
             gok[i] = f < LY * LX && gy < a.EY && gx < a.EX;
             goff[i] = gok[i] ? gy * a.EX + gx : 0;
         }
-        const double *Tb = a.T + (size_t)b * 3 * plane;
+        const double *Tb = r.T;
         double pre[NLD];
 #pragma unroll
         for (int i = 0; i < NLD; ++i) pre[i] = gok[i] ? Tb[goff[i]] : 0.0;
@@ -501,8 +554,8 @@ __global__ __launch_bounds__(256) void k_psf_moments_u1(PsfArgs a)
             m1 = cb[C_VSYS];
             m2 = 0.0;
         }
-        if (a.maps) {
-            float *mb = a.maps + (size_t)b * 3 * npix;
+        if (r.maps) {
+            float *mb = r.maps;
             mb[p] = (float)m0;
             mb[npix + p] = (float)m1;
             mb[2 * npix + p] = (float)m2;
@@ -512,22 +565,84 @@ __global__ __launch_bounds__(256) void k_psf_moments_u1(PsfArgs a)
             const double rv = use ? (m1 - (double)a.vo[p]) * a.iev[p] : 0.0;
             const double rs = use ? (m2 - (double)a.so[p]) * a.ies[p] : 0.0;
             if (use) acc += rv * rv + rs * rs;
-            if (a.resid) {
-                double *rb = a.resid + (size_t)b * 2 * npix;
+            if (r.resid) {
+                double *rb = r.resid;
                 rb[p] = valid ? rv : __builtin_nan("");
                 rb[npix + p] = valid ? rs : __builtin_nan("");
             }
         }
     }
-    if (a.partial) {
+    if (r.partial) {
         for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
         __shared__ double wsum[4];
         __syncthreads();
         if ((tid & 63) == 0) wsum[tid >> 6] = acc;
         __syncthreads();
         if (tid == 0)
-            a.partial[(size_t)b * a.ntiles + tile] = ((wsum[0] + wsum[1]) + wsum[2]) + wsum[3];
+            *r.partial = ((wsum[0] + wsum[1]) + wsum[2]) + wsum[3];
     }
+}
+
+// Row pointers of a single-model launch (row = blockIdx.y, tile = blockIdx.x).
+__device__ __forceinline__ RowPtrs single_row(const PsfArgs &a)
+{
+    const int b = blockIdx.y;
+    const size_t npix = (size_t)a.nx * a.ny;
+    RowPtrs r;
+    r.T = a.T + (size_t)b * 3 * a.EX * a.EY;
+    r.c = a.consts + (size_t)b * NCONST;
+    r.maps = a.maps ? a.maps + (size_t)b * 3 * npix : nullptr;
+    r.resid = a.resid ? a.resid + (size_t)b * 2 * npix : nullptr;
+    r.partial = a.partial ? a.partial + (size_t)b * a.ntiles + blockIdx.x : nullptr;
+    r.tile = blockIdx.x;
+    return r;
+}
+
+__global__ __launch_bounds__(256) void k_psf_moments(PsfArgs a) { psf_generic_tile(a, single_row(a)); }
+
+template <int HP, int TX>
+__global__ __launch_bounds__(256) void k_psf_moments_u1(PsfArgs a)
+{
+    psf_u1_tile<HP, TX>(a, single_row(a));
+}
+
+// Row pointers of a ragged multi-model launch over one bucket of rows.
+__device__ __forceinline__ RowPtrs multi_row(const ModelDev *md, const RowMap &rm,
+                                             const BucketMap &bk, const double *T,
+                                             const double *consts, double *resid,
+                                             double *partial, PsfArgs &a)
+{
+    const int i = find_row(bk.tile_base, bk.n, blockIdx.x);
+    const int b = bk.rows[i];
+    a = md[rm.row_model[b]].psf;
+    RowPtrs r;
+    r.tile = blockIdx.x - bk.tile_base[i];
+    r.T = T + rm.T_off[b];
+    r.c = consts + (size_t)b * NCONST;
+    r.maps = nullptr;
+    r.resid = resid ? resid + rm.resid_off[b] : nullptr;
+    r.partial = partial ? partial + rm.part_off[b] + r.tile : nullptr;
+    return r;
+}
+
+__global__ __launch_bounds__(256) void k_psf_generic_multi(const ModelDev *md, RowMap rm,
+                                                           BucketMap bk, const double *T,
+                                                           const double *consts, double *resid,
+                                                           double *partial)
+{
+    PsfArgs a;
+    const RowPtrs r = multi_row(md, rm, bk, T, consts, resid, partial, a);
+    psf_generic_tile(a, r);
+}
+
+template <int HP>
+__global__ __launch_bounds__(256) void k_psf_u1_multi(const ModelDev *md, RowMap rm, BucketMap bk,
+                                                      const double *T, const double *consts,
+                                                      double *resid, double *partial)
+{
+    PsfArgs a;
+    const RowPtrs r = multi_row(md, rm, bk, T, consts, resid, partial, a);
+    psf_u1_tile<HP, 32>(a, r);
 }
 
 template <int HP, int TX> void launch_u1(const PsfArgs &a, dim3 grid, size_t lds, hipStream_t s)
@@ -562,9 +677,73 @@ __global__ __launch_bounds__(64) void k_reduce_chi2(const double *__restrict__ p
     }
 }
 
+__global__ __launch_bounds__(64) void k_reduce_chi2_multi(const double *__restrict__ partial,
+                                                          const ModelDev *__restrict__ md,
+                                                          RowMap rm,
+                                                          const double *__restrict__ consts,
+                                                          double *__restrict__ chi2)
+{
+    const int b = blockIdx.x, lane = threadIdx.x;
+    const ModelDev &m = md[rm.row_model[b]];
+    const int ntiles = m.psf.ntiles;
+    const double *pp = partial + rm.part_off[b];
+    double s = 0.0;
+    for (int t = lane; t < ntiles; t += 64) s += pp[t];
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if (lane == 0) chi2[b] = consts[(size_t)b * NCONST + C_VALID] != 0.0 ? s : __builtin_inf();
+}
+
 // ---------------------------------------------------------------------------
 // launch wrappers
 // ---------------------------------------------------------------------------
+template <int HP> void launch_u1_multi(const ModelDev *md, const RowMap &rm, const BucketMap &bk,
+                                       int nblocks, const double *T, const double *consts,
+                                       double *resid, double *partial, size_t lds, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_psf_u1_multi<HP>, dim3(nblocks), dim3(256), lds, s, md, rm, bk, T, consts,
+                       resid, partial);
+}
+using MultiFn = void (*)(const ModelDev *, const RowMap &, const BucketMap &, int, const double *,
+                         const double *, double *, double *, size_t, hipStream_t);
+template <int... H> constexpr auto make_multi_table(std::integer_sequence<int, H...>)
+{
+    return std::array<MultiFn, sizeof...(H)>{&launch_u1_multi<H>...};
+}
+static const auto kU1MultiTable = make_multi_table(std::make_integer_sequence<int, kMaxFastHalo + 1>{});
+
+hipError_t launch_prep_multi(const double *params, int B, const int *row_model, const ModelDev *md,
+                             double *consts, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_prep_multi, dim3((B + 63) / 64), dim3(64), 0, s, params, B, row_model, md,
+                       consts);
+    return hipGetLastError();
+}
+
+hipError_t launch_line_sums_multi(const double *consts, const ModelDev *md, const RowMap &rm,
+                                  int nblocks, double *T, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_line_sums_multi, dim3(nblocks), dim3(256), 0, s, consts, md, rm, T);
+    return hipGetLastError();
+}
+
+hipError_t launch_psf_multi(int fast_hp, const ModelDev *md, const RowMap &rm, const BucketMap &bk,
+                            int nblocks, const double *T, const double *consts, double *resid,
+                            double *partial, size_t lds, hipStream_t s)
+{
+    if (fast_hp >= 0)
+        kU1MultiTable[fast_hp](md, rm, bk, nblocks, T, consts, resid, partial, lds, s);
+    else
+        hipLaunchKernelGGL(k_psf_generic_multi, dim3(nblocks), dim3(256), lds, s, md, rm, bk, T,
+                           consts, resid, partial);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_multi(const double *partial, const ModelDev *md, const RowMap &rm,
+                               const double *consts, double *chi2, int B, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_reduce_chi2_multi, dim3(B), dim3(64), 0, s, partial, md, rm, consts, chi2);
+    return hipGetLastError();
+}
 hipError_t launch_prep(const double *params, int B, int rc, double dvf, int hp, int u,
                        double *consts, hipStream_t s)
 {

@@ -26,6 +26,7 @@ SYMBOLS = (
     "gk_evaluate_batch", "gk_chi2_batch", "gk_residual_batch", "gk_model_dims", "gk_last_error",
     "gk_set_profiling", "gk_read_profile", "gk_lm_default_opts", "gk_fit_lm",
     "gk_ns_default_opts", "gk_fit_nested", "gk_nested_sample", "gk_philox4x32", "gk_fit_grid",
+    "gk_create_survey", "gk_destroy_survey", "gk_survey_chi2", "gk_fit_lm_survey",
 )
 LM_REASONS = {1: "ftol", 2: "xtol", 3: "lambda", 4: "maxiter"}
 GK_PROF_TIMING, GK_PROF_COUNT = 1, 2
@@ -184,6 +185,11 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
                                 ctypes.POINTER(ctypes.c_uint32)]
     L.gk_fit_grid.argtypes = [vp, vp, vp, vp, vp, ctypes.c_int32, ctypes.c_int32, vp,
                               ctypes.POINTER(GridResult)]
+    L.gk_create_survey.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, ctypes.POINTER(vp)]
+    L.gk_destroy_survey.argtypes = [vp]
+    L.gk_survey_chi2.argtypes = [vp, vp, vp, i32, vp, vp]
+    L.gk_fit_lm_survey.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(LMOpts),
+                                   ctypes.POINTER(LMResult)]
     L.gk_last_error.restype = ctypes.c_char_p
     for name in SYMBOLS:
         if name != "gk_last_error":
@@ -374,3 +380,62 @@ class Model:
         self.last_status = _check(load().gk_residual_batch(self._h, p, B, out.data_ptr(),
                                                            _stream_ptr(stream)))
         return out
+
+
+class Survey:
+    """A set of models on one device evaluated in ragged batches (gk_create_survey)."""
+
+    def __init__(self, models):
+        L = load()
+        self.models = list(models)
+        arr = (ctypes.c_void_p * len(self.models))(*[m._h.value for m in self.models])
+        h = ctypes.c_void_p()
+        _check(L.gk_create_survey(arr, len(self.models), ctypes.byref(h)))
+        self._h = h
+        self.device = self.models[0].device
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().gk_destroy_survey(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def chi2(self, model_idx, params, out=None, stream=None):
+        """chi2 [B] float64 CUDA tensor of rows params [B][12] of models model_idx [B]."""
+        import torch
+        idx = np.ascontiguousarray(model_idx, dtype=np.int32)
+        p, B, keep = _params_arg(params)
+        if out is None:
+            out = torch.empty(B, dtype=torch.float64, device=f"cuda:{self.device}")
+        _check(load().gk_survey_chi2(self._h, idx.ctypes.data, p, B, out.data_ptr(),
+                                     _stream_ptr(stream)))
+        return out
+
+    def fit_lm(self, p0, free, lo=None, hi=None, **opts):
+        """Levenberg-Marquardt of every galaxy at once (gk_fit_lm_survey)."""
+        L = load()
+        o = LMOpts()
+        _check(L.gk_lm_default_opts(ctypes.byref(o)))
+        for k, v in opts.items():
+            setattr(o, k, v)
+        n = len(self.models)
+        p = np.ascontiguousarray(p0, dtype=np.float64).reshape(n, NPAR).copy()
+        fm = np.ascontiguousarray(free, dtype=np.uint8)
+        lo_a = None if lo is None else np.ascontiguousarray(lo, dtype=np.float64).reshape(n, NPAR)
+        hi_a = None if hi is None else np.ascontiguousarray(hi, dtype=np.float64).reshape(n, NPAR)
+        res = (LMResult * n)()
+        st = L.gk_fit_lm_survey(self._h, p.ctypes.data, fm.ctypes.data,
+                                None if lo_a is None else lo_a.ctypes.data,
+                                None if hi_a is None else hi_a.ctypes.data, ctypes.byref(o), res)
+        if st < 0 and st != GK_ENOTCONV:
+            _check(st)
+        return {"p": p, "chi2": np.array([r.chi2 for r in res]),
+                "iterations": np.array([r.iterations for r in res]),
+                "reason": [LM_REASONS.get(r.reason, str(r.reason)) for r in res],
+                "n_evals": np.array([r.n_evals for r in res]),
+                "errors": np.array([r.errors[:] for r in res]), "status": st}
