@@ -225,6 +225,11 @@ typedef struct {
     double best[GK_NP];        /* best point */
     double mean[GK_NP], sd[GK_NP];            /* posterior mean and standard deviation */
     double median[GK_NP], q16[GK_NP], q84[GK_NP];  /* posterior quantiles */
+    /* surrogate screening (gk_fit_nested_screened; 0 otherwise) */
+    int64_t n_screened;        /* candidates judged by the surrogate */
+    int64_t n_rejected;        /* of those, discarded without a plain evaluation */
+    int64_t n_audited;         /* discarded ones evaluated anyway (audit draws) */
+    int64_t n_audit_miss;      /* audited ones that the plain chi2 would have accepted */
 } gk_ns_result;
 
 gk_status gk_ns_default_opts(gk_ns_opts *opts);
@@ -304,6 +309,95 @@ gk_status gk_survey_chi2(gk_survey *survey, const int32_t *model_idx, const doub
 gk_status gk_fit_lm_survey(gk_survey *survey, double *p_inout, const uint8_t *free_mask,
                            const double *lo, const double *hi, const gk_lm_opts *opts,
                            gk_lm_result *results);
+
+/* ---- Learned surrogate of the moment maps (not part of the paper) ----------
+ * A multilayer perceptron maps a parameter row to the velocity and dispersion
+ * maps of one instrument (the grid, PSF and LSF of the model it is created
+ * from).  Inputs: slots x0 y0 PA i Vsys Vt rt sigma r0 I0, each scaled from
+ * the box [lo, hi] to [-1, 1] (0 where lo == hi), PA as (cos PA, sin PA),
+ * zero-padded to 32.  `layers` hidden layers of width `hidden` with the exact
+ * GELU z Phi(z); a linear output layer of 2 nx ny values: m1 / 300 then
+ * m2 / 100 (km/s), row-major.  Weights and activations BF16, products on the
+ * matrix cores with FP32 accumulation, FP32 master weights.
+ * Training minimises sum mask (y - t)^2 / sum mask with Adam (beta 0.9 /
+ * 0.999, eps 1e-8), where t are the plain evaluation's maps of rows drawn
+ * uniformly in the box on the device (Philox4x32-10 keyed by `seed`) and
+ * mask marks spaxels whose flux is at least 1% of the row's peak.
+ * Initial weights: He normal for hidden layers, 1/sqrt(fan-in) for the
+ * output layer, zero biases.  The surrogate keeps a pointer to the model:
+ * the model must outlive it, and calls on one surrogate must not overlap. */
+typedef struct gk_surrogate gk_surrogate;
+
+typedef struct {
+    int32_t hidden;     /* width, multiple of 32; default 1024 */
+    int32_t layers;     /* hidden layers; default 4 */
+    int32_t batch;      /* rows per training step and per inference chunk, multiple of 32; default 512 */
+    int32_t reserved;
+    double lr;          /* Adam step size at the start of each training call; default 1e-3 */
+    double lr_final;    /* ... decayed by a half cosine to this at its end; default 1e-5 */
+    uint64_t seed;      /* weight initialisation and training draws; default 1 */
+} gk_surrogate_opts;
+
+gk_status gk_surrogate_default_opts(gk_surrogate_opts *opts);
+
+/* lo/hi [GK_NP] (host): the box of the training draws and of the input
+ * scaling; it must lie in the parameter domain.  The model needs upsample 1
+ * and nx * ny a multiple of 16.  Errors: GK_EINVAL, GK_ENOMEM, GK_EDEVICE. */
+gk_status gk_surrogate_create(gk_model *instrument, const double *lo, const double *hi,
+                              const gk_surrogate_opts *opts, gk_surrogate **out);
+gk_status gk_surrogate_destroy(gk_surrogate *s);
+
+/* Runs `steps` Adam steps of `batch` fresh draws each; losses [steps] (host,
+ * may be NULL) receives each step's loss before its update.  Blocks. */
+gk_status gk_surrogate_train(gk_surrogate *s, int64_t steps, float *losses);
+
+/* Number of floats in the weight vector: for each layer (the output layer
+ * last) W [out][in] row-major, then b [out]; the first layer has in = 32. */
+int64_t gk_surrogate_weight_count(const gk_surrogate *s);
+/* Host copies of the master weights; set_weights also resets Adam.  Block. */
+gk_status gk_surrogate_get_weights(gk_surrogate *s, float *w, int64_t n);
+gk_status gk_surrogate_set_weights(gk_surrogate *s, const float *w, int64_t n);
+
+/* Loss and its gradient (host, weight-vector layout) on the rows params
+ * [B][GK_NP] (host or device; B a multiple of 32), targets from the plain
+ * evaluation; no update.  Blocks. */
+gk_status gk_surrogate_gradients(gk_surrogate *s, const double *params, int32_t B, float *grads,
+                                 double *loss);
+
+/* maps [B][2][ny][nx] (device, km/s: m1 then m2) predicted for params
+ * [B][GK_NP] (host or device), enqueued on hip_stream. */
+gk_status gk_surrogate_predict(gk_surrogate *s, const double *params, int32_t B, float *maps,
+                               void *hip_stream);
+
+/* chi2 [B] (device) of the predicted maps against the observation of `model`
+ * (eq. 11 with the model's mask, errors and W); +INF for rows outside the
+ * parameter domain.  The model must have the surrogate's instrument. */
+gk_status gk_surrogate_chi2(gk_surrogate *s, gk_model *model, const double *params, int32_t B,
+                            double *chi2, void *hip_stream);
+
+/* Nested sampling as gk_fit_nested, with every round's candidates screened by
+ * the surrogate.  With chi2_floor the plain chi2 of the lowest live point at
+ * the start of the round and `shift` the largest surrogate-minus-plain chi2
+ * seen on the previous round's plainly evaluated candidates (0 before the
+ * first), a candidate whose surrogate chi2 exceeds chi2_floor + shift +
+ * margin is discarded, except that a Philox draw keeps it with probability
+ * audit (the audit sample measures the screen); every other candidate gets
+ * the plain chi2, which alone decides acceptance, posterior and evidence.
+ * With a useless surrogate the screen passes everything and the run is the
+ * plain one.  margin >= 0, 0 <= audit <= 1.  Blocks. */
+gk_status gk_fit_nested_screened(gk_model *model, gk_surrogate *s, const double *lo,
+                                 const double *hi, const uint8_t *free_mask, const double *fixed,
+                                 const gk_ns_opts *opts, double margin, double audit,
+                                 gk_ns_result *result, double *samples, int64_t cap,
+                                 int64_t *n_samples);
+
+/* BF16 GEMM of the surrogate: C [M][N] (f32, row stride ldc) = sum_k A(m, k)
+ * B(n, k), A(m, k) = trans_a ? A[k lda + m] : A[m lda + k], B likewise; BF16
+ * operands as uint16 bit patterns; all device memory; K a multiple of 32,
+ * lda and ldb multiples of 8, operands 16-byte aligned.  Enqueued on hip_stream. */
+gk_status gk_gemm_bf16(int32_t trans_a, int32_t trans_b, int32_t M, int32_t N, int32_t K,
+                       const uint16_t *A, int32_t lda, const uint16_t *B, int32_t ldb, float *C,
+                       int32_t ldc, void *hip_stream);
 
 /* Shape of the fine model cube with its halo and the halos themselves:
  * dims = {nx_ext, ny_ext, nz_ext, h_psf, h_lsf}. */

@@ -1,0 +1,913 @@
+// gbk_mlp.hip -- learned surrogate of the velocity and dispersion maps: a
+// multilayer perceptron with BF16 weights and activations, FP32 accumulation
+// on the matrix cores, FP32 master weights and Adam, trained on maps that the
+// plain evaluation (Sec. 2.2) streams into it.  It is not part of the paper:
+// the nested sampler (Sec. 2.3.2) uses it to screen candidates.
+//
+//   x = encode(p)      slots x0 y0 PA i Vsys Vt rt sigma r0 I0: each mapped
+//                      from its box to [-1, 1] (0 where the box is a point),
+//                      PA as (cos PA, sin PA); zero padding to 32 inputs
+//   h_l = gelu(h_{l-1} W_l^T + b_l)   l = 1..L, gelu(z) = z Phi(z) (erf form)
+//   y = h_L W_o^T + b_o                velocity map / 300, dispersion map / 100
+//   loss = sum mask (y - t)^2 / sum mask, mask: truth flux >= 1% of its peak
+//
+// GEMM: C[M][N] = sum_k A(m, k) B(n, k) on 128 x 128 tiles, K steps of 32;
+// four waves own a 64 x 64 quarter each as 4 x 4 tiles of the 16x16x32 BF16
+// MFMA.  Operands are staged through LDS as [row][k], so each operand may be
+// stored k-contiguous or k-strided: the forward product and the two backward
+// products (data and weight gradients) need all of those patterns.
+#include <hip/hip_runtime.h>
+
+#include <cfloat>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "gbk_model.h"
+#include "gbk_rng.h"
+#include "gbk_surrogate.h"
+
+using namespace gbk;
+
+typedef __bf16 bf16;
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+namespace {
+
+constexpr int GBM = 128, GBN = 128, GBK = 32, LDK = GBK + 8;  // LDS rows padded by 16 bytes
+constexpr int kInPad = 32;
+constexpr float kVelScale = 300.0f, kSigScale = 100.0f;
+constexpr int kRedBlocks = 256;
+
+enum Epi {
+    EPI_F32 = 0,    // C (f32) = acc + bias
+    EPI_GELU = 1,   // Z (f32, if not NULL) = acc + bias, H (bf16) = gelu(acc + bias)
+    EPI_DGELU = 2,  // H (bf16) = acc * gelu'(Z)
+};
+
+struct GemmArgs {
+    const bf16 *A, *B;
+    int lda, ldb;       // row strides in elements
+    int M, N, K;        // K % 32 == 0
+    const float *bias;  // [N] or NULL
+    float *C;           // EPI_F32 output
+    float *Z;           // EPI_GELU pre-activation out, EPI_DGELU pre-activation in
+    bf16 *H;            // bf16 output
+    int ldc;
+};
+
+__device__ inline float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+__device__ inline float gelu_grad(float z)
+{
+    return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) +
+           z * expf(-0.5f * z * z) * 0.39894228040143268f;
+}
+
+// stages the 128 x 32 block (rows r0.., k0..) of X(row, k) into S[row][k]:
+// trans == false: X(row, k) = X[row * ldx + k]; true: X[k * ldx + row]
+__device__ inline void stage_tile(const bf16 *__restrict__ X, int ldx, int rows, bool trans, int r0,
+                                  int k0, bf16 *__restrict__ S, int tid)
+{
+    const bf16 zero = (bf16)0.0f;
+    if (!trans) {  // thread -> row tid / 2, 16 consecutive k
+        const int r = tid >> 1, kh = (tid & 1) * 16, row = r0 + r;
+        bf16 *dst = S + r * LDK + kh;
+        if (row < rows) {
+            const uint4 *src = reinterpret_cast<const uint4 *>(X + (size_t)row * ldx + k0 + kh);
+            const uint4 a = src[0], b = src[1];
+            reinterpret_cast<uint4 *>(dst)[0] = a;
+            reinterpret_cast<uint4 *>(dst)[1] = b;
+        } else {
+            const uint4 z = {0u, 0u, 0u, 0u};
+            reinterpret_cast<uint4 *>(dst)[0] = z;
+            reinterpret_cast<uint4 *>(dst)[1] = z;
+        }
+    } else {  // thread -> k tid / 8, 16 consecutive rows
+        const int kk = tid >> 3, rc = (tid & 7) * 16;
+        const bf16 *src = X + (size_t)(k0 + kk) * ldx + r0 + rc;
+        bf16 v[16];
+        if (r0 + rc + 16 <= rows) {
+            reinterpret_cast<uint4 *>(v)[0] = reinterpret_cast<const uint4 *>(src)[0];
+            reinterpret_cast<uint4 *>(v)[1] = reinterpret_cast<const uint4 *>(src)[1];
+        } else {
+#pragma unroll
+            for (int j = 0; j < 16; ++j) v[j] = (r0 + rc + j < rows) ? src[j] : zero;
+        }
+#pragma unroll
+        for (int j = 0; j < 16; ++j) S[(rc + j) * LDK + kk] = v[j];
+    }
+}
+
+template <bool TA, bool TB, int EPI>
+__global__ __launch_bounds__(256) void k_gemm(GemmArgs g)
+{
+    __shared__ __attribute__((aligned(16))) bf16 As[GBM * LDK];
+    __shared__ __attribute__((aligned(16))) bf16 Bs[GBN * LDK];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave & 1, wn = wave >> 1;
+    const int m0 = blockIdx.y * GBM, n0 = blockIdx.x * GBN;
+    f32x4 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    for (int k0 = 0; k0 < g.K; k0 += GBK) {
+        stage_tile(g.A, g.lda, g.M, TA, m0, k0, As, tid);
+        stage_tile(g.B, g.ldb, g.N, TB, n0, k0, Bs, tid);
+        __syncthreads();
+        bf16x8 af[4], bfr[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            af[i] = *reinterpret_cast<const bf16x8 *>(As + (wm * 64 + i * 16 + (lane & 15)) * LDK +
+                                                      (lane >> 4) * 8);
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            bfr[j] = *reinterpret_cast<const bf16x8 *>(Bs + (wn * 64 + j * 16 + (lane & 15)) * LDK +
+                                                       (lane >> 4) * 8);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+        __syncthreads();
+    }
+    // a lane holds rows 4 (lane / 16) + r, column lane % 16, of each 16 x 16 tile
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int n = n0 + wn * 64 + j * 16 + (lane & 15);
+            if (n >= g.N) continue;
+            const float bn = g.bias ? g.bias[n] : 0.0f;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int m = m0 + wm * 64 + i * 16 + (lane >> 4) * 4 + r;
+                if (m >= g.M) continue;
+                const size_t o = (size_t)m * g.ldc + n;
+                if (EPI == EPI_F32) {
+                    g.C[o] = acc[i][j][r] + bn;
+                } else if (EPI == EPI_GELU) {
+                    const float z = acc[i][j][r] + bn;
+                    if (g.Z) g.Z[o] = z;
+                    g.H[o] = (bf16)gelu(z);
+                } else {
+                    g.H[o] = (bf16)(acc[i][j][r] * gelu_grad(g.Z[o]));
+                }
+            }
+        }
+}
+
+// uniform draws of parameter rows in the box: slot s = lo_s + u (hi_s - lo_s),
+// u from Philox4x32-10 with counter (row, step, step >> 32, block) and the seed as key
+__global__ void k_draw(uint64_t seed, uint64_t step, int B, const double *__restrict__ lo,
+                       const double *__restrict__ hi, double *__restrict__ p)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32) ^ 0x73757272u};
+    uint32_t r[12];
+    for (int j = 0; j < 3; ++j) {
+        const uint32_t c[4] = {(uint32_t)b, (uint32_t)step, (uint32_t)(step >> 32), (uint32_t)j};
+        philox4x32_10(c, key, r + 4 * j);
+    }
+    for (int s = 0; s < NPAR; ++s) {
+        const double u = ((double)r[s] + 0.5) * 0x1.0p-32;
+        p[(size_t)b * NPAR + s] = hi[s] > lo[s] ? lo[s] + u * (hi[s] - lo[s]) : lo[s];
+    }
+}
+
+__global__ void k_encode(const double *__restrict__ p, int B, const double *__restrict__ lo,
+                         const double *__restrict__ hi, bf16 *__restrict__ x)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    const double *r = p + (size_t)b * NPAR;
+    bf16 *o = x + (size_t)b * kInPad;
+    int col = 0;
+    for (int s = 0; s <= P_I0; ++s) {
+        if (s == P_PA) {
+            const double a = r[s] * (M_PI / 180.0);
+            o[col++] = (bf16)(float)cos(a);
+            o[col++] = (bf16)(float)sin(a);
+        } else {
+            const double w = hi[s] - lo[s];
+            o[col++] = (bf16)(float)(w > 0.0 ? 2.0 * (r[s] - lo[s]) / w - 1.0 : 0.0);
+        }
+    }
+    for (; col < kInPad; ++col) o[col] = (bf16)0.0f;
+}
+
+// Targets and mask of one row per block from maps [B][3][npix]; cnt[b] = ones in the mask.
+__global__ __launch_bounds__(256) void k_targets(const float *__restrict__ maps, int npix,
+                                                 float *__restrict__ t, float *__restrict__ mask,
+                                                 unsigned *__restrict__ cnt)
+{
+    const int b = blockIdx.x;
+    const float *m = maps + (size_t)b * 3 * npix;
+    float mx = 0.0f;
+    for (int i = threadIdx.x; i < npix; i += 256) mx = fmaxf(mx, m[i]);  // NaN rows stay 0
+    for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o, 64));
+    __shared__ float ws[4];
+    __shared__ unsigned wc[4];
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    mx = fmaxf(fmaxf(ws[0], ws[1]), fmaxf(ws[2], ws[3]));
+    float *tb = t + (size_t)b * 2 * npix;
+    float *mb = mask + (size_t)b * 2 * npix;
+    unsigned c = 0;
+    for (int i = threadIdx.x; i < npix; i += 256) {
+        const float v = m[npix + i], s = m[2 * npix + i];
+        const bool use = mx > 0.0f && m[i] >= 0.01f * mx && isfinite(v) && isfinite(s);
+        tb[i] = use ? v / kVelScale : 0.0f;
+        tb[npix + i] = use ? s / kSigScale : 0.0f;
+        mb[i] = mb[npix + i] = use ? 1.0f : 0.0f;
+        c += use ? 2u : 0u;
+    }
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+    if ((threadIdx.x & 63) == 0) wc[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) cnt[b] = wc[0] + wc[1] + wc[2] + wc[3];
+}
+
+// dY = 2 mask (y - t) / count (bf16), count = sum of cnt[0..B); per-block sums of
+// mask (y - t)^2 into partial[]
+__global__ __launch_bounds__(256) void k_mse_grad(const float *__restrict__ y,
+                                                  const float *__restrict__ t,
+                                                  const float *__restrict__ mask, size_t n,
+                                                  const unsigned *__restrict__ cnt, int B,
+                                                  bf16 *__restrict__ dy, double *__restrict__ partial)
+{
+    __shared__ unsigned long long wt[4];
+    __shared__ double ws[4];
+    unsigned long long c = 0;
+    for (int b = threadIdx.x; b < B; b += 256) c += cnt[b];
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+    if ((threadIdx.x & 63) == 0) wt[threadIdx.x >> 6] = c;
+    __syncthreads();
+    const unsigned long long total = wt[0] + wt[1] + wt[2] + wt[3];
+    const float scale = 2.0f / (float)(total > 0 ? total : 1);
+    double acc = 0.0;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+        const float r = (y[i] - t[i]) * mask[i];
+        acc += (double)r * r;
+        dy[i] = (bf16)(scale * r);
+    }
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) partial[blockIdx.x] = ((ws[0] + ws[1]) + ws[2]) + ws[3];
+}
+
+// loss = sum(partial) / count, in a fixed order
+__global__ __launch_bounds__(256) void k_loss_finish(const double *__restrict__ partial, int np,
+                                                     const unsigned *__restrict__ cnt, int B,
+                                                     float *__restrict__ loss)
+{
+    __shared__ double ws[256];
+    __shared__ unsigned long long wc[256];
+    double a = 0.0;
+    unsigned long long c = 0;
+    for (int i = threadIdx.x; i < np; i += 256) a += partial[i];
+    for (int b = threadIdx.x; b < B; b += 256) c += cnt[b];
+    ws[threadIdx.x] = a;
+    wc[threadIdx.x] = c;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            ws[threadIdx.x] += ws[threadIdx.x + s];
+            wc[threadIdx.x] += wc[threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *loss = (float)(ws[0] / (double)(wc[0] > 0 ? wc[0] : 1));
+}
+
+// db[n] = sum_m d[m][n]
+__global__ void k_colsum(const bf16 *__restrict__ d, int M, int N, float *__restrict__ db)
+{
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    float s = 0.0f;
+    for (int m = 0; m < M; ++m) s += (float)d[(size_t)m * N + n];
+    db[n] = s;
+}
+
+__global__ void k_adam(float *__restrict__ w, const float *__restrict__ g, float *__restrict__ m,
+                       float *__restrict__ v, bf16 *__restrict__ wb, size_t n, float lr, float c1,
+                       float c2)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = 0.9f * m[i] + 0.1f * gi, vi = 0.999f * v[i] + 0.001f * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float wi = w[i] - lr * (mi * c1) / (sqrtf(vi * c2) + 1e-8f);
+    w[i] = wi;
+    if (wb) wb[i] = (bf16)wi;
+}
+
+__global__ void k_to_bf16(const float *__restrict__ a, bf16 *__restrict__ b, size_t n)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = (bf16)a[i];
+}
+
+// chi2 of predicted maps against the observation (one row per block), INF for
+// rows outside the parameter domain
+__global__ __launch_bounds__(256) void k_surrogate_chi2(const float *__restrict__ y, int npix,
+                                                        const uint8_t *__restrict__ mask,
+                                                        const float *__restrict__ vo,
+                                                        const float *__restrict__ so,
+                                                        const double *__restrict__ iev,
+                                                        const double *__restrict__ ies,
+                                                        const double *__restrict__ params, int rc,
+                                                        double *__restrict__ chi2)
+{
+    const int b = blockIdx.x;
+    const float *yb = y + (size_t)b * 2 * npix;
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < npix; i += 256) {
+        if (!mask[i]) continue;
+        // the maps as gk_surrogate_predict returns them (scaled in FP32)
+        const double rv = ((double)(yb[i] * kVelScale) - vo[i]) * iev[i];
+        const double rs = ((double)(yb[npix + i] * kSigScale) - so[i]) * ies[i];
+        acc += rv * rv + rs * rs;
+    }
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    __shared__ double ws[4];
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double *p = params + (size_t)b * NPAR;
+        bool ok = true;
+        for (int s = 0; s < NPAR; ++s) ok = ok && isfinite(p[s]);
+        ok = ok && p[P_INC] > 0.0 && p[P_INC] < 90.0 && p[P_SIG] > 0.0 && p[P_R0] > 0.0 &&
+             p[P_RT] > 0.0 && (rc != RC_EPINAT || p[P_G] > 0.0);
+        chi2[b] = ok ? ((ws[0] + ws[1]) + ws[2]) + ws[3] : __builtin_inf();
+    }
+}
+
+__global__ void k_scale_maps(const float *__restrict__ y, int npix, size_t n, float *__restrict__ maps)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const size_t r = i % (2 * (size_t)npix);
+    maps[i] = y[i] * (r < (size_t)npix ? kVelScale : kSigScale);
+}
+
+bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+
+template <bool TA, bool TB, int EPI> gk_status gemm(const GemmArgs &g, hipStream_t s)
+{
+    if (g.M <= 0 || g.N <= 0 || g.K <= 0 || g.K % GBK || g.lda % 8 || g.ldb % 8 ||
+        !aligned16(g.A) || !aligned16(g.B))
+        return fail(GK_EINVAL, "GEMM shape %dx%dx%d (lda %d, ldb %d) not supported", g.M, g.N,
+                    g.K, g.lda, g.ldb);
+    if ((TA ? g.lda < g.M : g.lda < g.K) || (TB ? g.ldb < g.N : g.ldb < g.K) || g.ldc < g.N)
+        return fail(GK_EINVAL, "GEMM leading dimension too small");
+    const int gy = (g.M + GBM - 1) / GBM;
+    if (gy > 65535) return fail(GK_EINVAL, "GEMM M = %d too large", g.M);
+    dim3 grid((g.N + GBN - 1) / GBN, gy);
+    hipLaunchKernelGGL((k_gemm<TA, TB, EPI>), grid, dim3(256), 0, s, g);
+    HIP_TRY(hipGetLastError());
+    return GK_OK;
+}
+
+unsigned blocks(size_t n, unsigned t = 256) { return (unsigned)((n + t - 1) / t); }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// surrogate object
+// ---------------------------------------------------------------------------
+struct gk_surrogate {
+    gk_model *model = nullptr;  // the instrument whose plain evaluation trains the network
+    int device = 0;
+    gk_surrogate_opts o{};
+    int npix = 0, nout = 0, layers = 0;
+    double lo[NPAR]{}, hi[NPAR]{};
+    double *d_lo = nullptr, *d_hi = nullptr;
+    int64_t step = 0;  // Adam steps taken
+    hipStream_t stream = nullptr;
+    // layer l = 0..layers (the last is the output layer): W_l [out][in], b_l [out]
+    std::vector<int> fin, fout;
+    std::vector<float *> W, b, gW, gb, mW, vW, mb, vb;
+    std::vector<bf16 *> Wb;
+    // per-row buffers for cap rows
+    int cap = 0;
+    bf16 *X = nullptr, *dY = nullptr;
+    std::vector<bf16 *> H, dH;
+    std::vector<float *> Z;
+    float *Y = nullptr, *T = nullptr, *Mask = nullptr, *maps = nullptr, *d_loss = nullptr;
+    unsigned *cnt = nullptr;
+    double *d_params = nullptr, *h_params = nullptr, *d_partial = nullptr;
+    hipEvent_t ev_staged = nullptr;  // recorded after the last copy out of h_params
+    int loss_cap = 0;
+
+    size_t weight_count() const
+    {
+        size_t n = 0;
+        for (int l = 0; l <= layers; ++l) n += (size_t)fout[l] * fin[l] + fout[l];
+        return n;
+    }
+    void free_rows()
+    {
+        auto F = [](void *p) { if (p) (void)hipFree(p); };
+        F(X);
+        F(dY);
+        for (bf16 *p : H) F(p);
+        for (bf16 *p : dH) F(p);
+        for (float *p : Z) F(p);
+        H.clear();
+        dH.clear();
+        Z.clear();
+        F(Y);
+        F(T);
+        F(Mask);
+        F(maps);
+        F(cnt);
+        F(d_params);
+        F(d_partial);
+        if (h_params) {
+            if (ev_staged) (void)hipEventSynchronize(ev_staged);
+            (void)hipHostFree(h_params);
+        }
+        X = dY = nullptr;
+        Y = T = Mask = maps = nullptr;
+        cnt = nullptr;
+        d_params = h_params = d_partial = nullptr;
+        cap = 0;
+    }
+    void release()
+    {
+        if (stream) (void)hipStreamSynchronize(stream);
+        free_rows();
+        for (auto *v : {&W, &b, &gW, &gb, &mW, &vW, &mb, &vb})
+            for (float *p : *v) (void)hipFree(p);
+        for (bf16 *p : Wb) (void)hipFree(p);
+        (void)hipFree(d_lo);
+        (void)hipFree(d_hi);
+        (void)hipFree(d_loss);
+        if (ev_staged) (void)hipEventDestroy(ev_staged);
+        if (stream) (void)hipStreamDestroy(stream);
+    }
+};
+
+namespace {
+
+gk_status reserve_rows(gk_surrogate *s, int rows)
+{
+    if (rows <= s->cap) return GK_OK;
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    s->free_rows();
+    rows = (rows + 31) / 32 * 32;
+    const size_t R = (size_t)rows, hid = (size_t)s->o.hidden;
+    HIP_TRY(hipMalloc((void **)&s->X, R * kInPad * sizeof(bf16)));
+    for (int l = 0; l < s->layers; ++l) {
+        bf16 *h, *dh;
+        float *z;
+        HIP_TRY(hipMalloc((void **)&h, R * hid * sizeof(bf16)));
+        s->H.push_back(h);
+        HIP_TRY(hipMalloc((void **)&dh, R * hid * sizeof(bf16)));
+        s->dH.push_back(dh);
+        HIP_TRY(hipMalloc((void **)&z, R * hid * sizeof(float)));
+        s->Z.push_back(z);
+    }
+    const size_t no = (size_t)s->nout;
+    HIP_TRY(hipMalloc((void **)&s->Y, R * no * sizeof(float)));
+    HIP_TRY(hipMalloc((void **)&s->T, R * no * sizeof(float)));
+    HIP_TRY(hipMalloc((void **)&s->Mask, R * no * sizeof(float)));
+    HIP_TRY(hipMalloc((void **)&s->dY, R * no * sizeof(bf16)));
+    HIP_TRY(hipMalloc((void **)&s->maps, R * 3 * s->npix * sizeof(float)));
+    HIP_TRY(hipMalloc((void **)&s->cnt, R * sizeof(unsigned)));
+    HIP_TRY(hipMalloc((void **)&s->d_params, R * NPAR * sizeof(double)));
+    HIP_TRY(hipHostMalloc((void **)&s->h_params, R * NPAR * sizeof(double), 0));
+    HIP_TRY(hipMalloc((void **)&s->d_partial, kRedBlocks * sizeof(double)));
+    s->cap = rows;
+    return GK_OK;
+}
+
+// forward pass of M rows whose inputs are in s->X; keeps pre-activations if `keep`
+gk_status forward(gk_surrogate *s, int M, bool keep, hipStream_t st)
+{
+    const bf16 *h = s->X;
+    int in = kInPad;
+    for (int l = 0; l < s->layers; ++l) {
+        GemmArgs g{h, s->Wb[l], in, in, M, s->o.hidden, in, s->b[l], nullptr,
+                   keep ? s->Z[l] : nullptr, s->H[l], s->o.hidden};
+        GK_TRY((gemm<false, false, EPI_GELU>(g, st)));
+        h = s->H[l];
+        in = s->o.hidden;
+    }
+    const int L = s->layers;
+    GemmArgs g{h, s->Wb[L], in, in, M, s->nout, in, s->b[L], s->Y, nullptr, nullptr, s->nout};
+    return gemm<false, false, EPI_F32>(g, st);
+}
+
+// targets from the plain evaluation of the rows in s->d_params, loss gradient,
+// backward pass into gW/gb; the loss goes to *loss_dev
+gk_status loss_and_grads(gk_surrogate *s, int M, float *loss_dev, hipStream_t st)
+{
+    GK_TRY(run_batch(s->model, s->d_params, M, s->maps, nullptr, nullptr, nullptr, st));
+    hipLaunchKernelGGL(k_targets, dim3(M), dim3(256), 0, st, s->maps, s->npix, s->T, s->Mask, s->cnt);
+    hipLaunchKernelGGL(k_encode, dim3(blocks(M, 64)), dim3(64), 0, st, s->d_params, M, s->d_lo,
+                       s->d_hi, s->X);
+    HIP_TRY(hipGetLastError());
+    GK_TRY(forward(s, M, true, st));
+    const size_t n = (size_t)M * s->nout;
+    hipLaunchKernelGGL(k_mse_grad, dim3(kRedBlocks), dim3(256), 0, st, s->Y, s->T, s->Mask, n,
+                       s->cnt, M, s->dY, s->d_partial);
+    hipLaunchKernelGGL(k_loss_finish, dim3(1), dim3(256), 0, st, s->d_partial, kRedBlocks, s->cnt,
+                       M, loss_dev);
+    HIP_TRY(hipGetLastError());
+    // backward: layer l has input h_{l-1} (X for l = 0) and output gradient d_l
+    const int L = s->layers, hid = s->o.hidden;
+    const bf16 *d = s->dY;
+    for (int l = L; l >= 0; --l) {
+        const int in = s->fin[l], out = s->fout[l];
+        const bf16 *hin = l ? s->H[l - 1] : s->X;
+        // gW_l[o][i] = sum_b d[b][o] hin[b][i]
+        GemmArgs gw{d, hin, out, in, out, in, M, nullptr, s->gW[l], nullptr, nullptr, in};
+        GK_TRY((gemm<true, true, EPI_F32>(gw, st)));
+        hipLaunchKernelGGL(k_colsum, dim3(blocks(out)), dim3(256), 0, st, d, M, out, s->gb[l]);
+        HIP_TRY(hipGetLastError());
+        if (l == 0) break;
+        // d_{l-1}[b][i] = (sum_o d[b][o] W_l[o][i]) gelu'(Z_{l-1}[b][i])
+        GemmArgs gd{d, s->Wb[l], out, in, M, in, out, nullptr, nullptr, s->Z[l - 1], s->dH[l - 1], hid};
+        GK_TRY((gemm<false, true, EPI_DGELU>(gd, st)));
+        d = s->dH[l - 1];
+    }
+    return GK_OK;
+}
+
+gk_status adam(gk_surrogate *s, double lr, hipStream_t st)
+{
+    s->step += 1;
+    const double t = (double)s->step;
+    const float c1 = (float)(1.0 / (1.0 - std::pow(0.9, t)));
+    const float c2 = (float)(1.0 / (1.0 - std::pow(0.999, t)));
+    for (int l = 0; l <= s->layers; ++l) {
+        const size_t nw = (size_t)s->fout[l] * s->fin[l], nb = (size_t)s->fout[l];
+        hipLaunchKernelGGL(k_adam, dim3(blocks(nw)), dim3(256), 0, st, s->W[l], s->gW[l], s->mW[l],
+                           s->vW[l], s->Wb[l], nw, (float)lr, c1, c2);
+        hipLaunchKernelGGL(k_adam, dim3(blocks(nb)), dim3(256), 0, st, s->b[l], s->gb[l], s->mb[l],
+                           s->vb[l], (bf16 *)nullptr, nb, (float)lr, c1, c2);
+    }
+    HIP_TRY(hipGetLastError());
+    return GK_OK;
+}
+
+// rows (host or device) -> s->d_params (on st)
+gk_status stage_params(gk_surrogate *s, const double *params, int B, hipStream_t st)
+{
+    const PtrKind pk = pointer_kind(params);
+    if (pk == PTR_BAD) return fail(GK_EINVAL, "params pointer of unknown kind");
+    GK_TRY(reserve_rows(s, B));
+    if (pk == PTR_DEVICE) {
+        HIP_TRY(hipMemcpyAsync(s->d_params, params, sizeof(double) * NPAR * B,
+                               hipMemcpyDeviceToDevice, st));
+    } else {
+        HIP_TRY(hipEventSynchronize(s->ev_staged));  // the pinned rows may still feed a copy
+        std::memcpy(s->h_params, params, sizeof(double) * NPAR * B);
+        HIP_TRY(hipMemcpyAsync(s->d_params, s->h_params, sizeof(double) * NPAR * B,
+                               hipMemcpyHostToDevice, st));
+        HIP_TRY(hipEventRecord(s->ev_staged, st));
+    }
+    return GK_OK;
+}
+
+gk_status infer(gk_surrogate *s, int B, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_encode, dim3(blocks(B, 64)), dim3(64), 0, st, s->d_params, B, s->d_lo,
+                       s->d_hi, s->X);
+    HIP_TRY(hipGetLastError());
+    return forward(s, B, false, st);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// internal entry used by the screened sampler
+// ---------------------------------------------------------------------------
+gk_status gbk::surrogate_chi2(gk_surrogate *s, gk_model *obs, const double *d_params, int B,
+                              double *d_chi2, hipStream_t st)
+{
+    for (int r0 = 0; r0 < B; r0 += s->o.batch) {
+        const int n = std::min(s->o.batch, B - r0);
+        GK_TRY(stage_params(s, d_params + (size_t)r0 * NPAR, n, st));
+        GK_TRY(infer(s, n, st));
+        hipLaunchKernelGGL(k_surrogate_chi2, dim3(n), dim3(256), 0, st, s->Y, s->npix, obs->d_mask,
+                           obs->d_vo, obs->d_so, obs->d_iev, obs->d_ies, s->d_params, obs->d.rc,
+                           d_chi2 + r0);
+        HIP_TRY(hipGetLastError());
+    }
+    return GK_OK;
+}
+
+bool gbk::surrogate_matches(const gk_surrogate *s, const gk_model *m)
+{
+    const gk_model_desc &a = s->model->d, &b = m->d;
+    return a.nx == b.nx && a.ny == b.ny && a.nz == b.nz && a.upsample == b.upsample &&
+           a.dv_kms == b.dv_kms && a.v0_kms == b.v0_kms && a.crpix == b.crpix &&
+           a.psf_fwhm_pix == b.psf_fwhm_pix && a.lsf_sigma_kms == b.lsf_sigma_kms &&
+           a.kernel_radius_sigma == b.kernel_radius_sigma && a.rc == b.rc;
+}
+
+int gbk::surrogate_device(const gk_surrogate *s) { return s->device; }
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+gk_status gk_surrogate_default_opts(gk_surrogate_opts *o)
+{
+    if (!o) return fail(GK_EINVAL, "opts is NULL");
+    std::memset(o, 0, sizeof *o);
+    o->hidden = 1024;
+    o->layers = 4;
+    o->batch = 512;
+    o->lr = 1e-3;
+    o->lr_final = 1e-5;
+    o->seed = 1;
+    return GK_OK;
+}
+
+gk_status gk_surrogate_create(gk_model *m, const double *lo, const double *hi,
+                              const gk_surrogate_opts *o_in, gk_surrogate **out)
+{
+    if (!m || !lo || !hi || !out) return fail(GK_EINVAL, "NULL argument");
+    *out = nullptr;
+    gk_surrogate_opts o;
+    gk_surrogate_default_opts(&o);
+    if (o_in) o = *o_in;
+    if (o.hidden < 32 || o.hidden % 32 || o.hidden > 8192 || o.layers < 1 || o.layers > 16 ||
+        o.batch < 32 || o.batch % 32 || o.batch > 65536 || !(o.lr > 0.0) || !(o.lr_final > 0.0))
+        return fail(GK_EINVAL, "invalid surrogate options (hidden and batch multiples of 32)");
+    for (int k = 0; k < NPAR; ++k)
+        if (!(hi[k] >= lo[k]) || !std::isfinite(lo[k]) || !std::isfinite(hi[k]))
+            return fail(GK_EINVAL, "invalid box in slot %d", k);
+    if (m->d.rc == RC_EPINAT && (hi[P_A] > lo[P_A] || hi[P_G] > lo[P_G]))
+        return fail(GK_EINVAL, "the surrogate does not take the Epinat shape slots as inputs");
+    if (m->d.upsample != 1) return fail(GK_EINVAL, "the surrogate needs upsample = 1");
+    if ((m->d.nx * m->d.ny) % 16)
+        return fail(GK_EINVAL, "the surrogate needs nx * ny to be a multiple of 16");
+    if (!(lo[P_INC] > 0.0 && hi[P_INC] < 90.0 && lo[P_SIG] > 0.0 && lo[P_R0] > 0.0 && lo[P_RT] > 0.0))
+        return fail(GK_EINVAL, "the box leaves the parameter domain");
+    auto *s = new (std::nothrow) gk_surrogate;
+    if (!s) return fail(GK_ENOMEM, "out of host memory");
+    s->model = m;
+    s->device = m->device;
+    s->o = o;
+    s->npix = m->d.nx * m->d.ny;
+    s->nout = 2 * s->npix;
+    s->layers = o.layers;
+    std::memcpy(s->lo, lo, sizeof s->lo);
+    std::memcpy(s->hi, hi, sizeof s->hi);
+    DeviceGuard g(m->device);
+    auto fail_free = [&](gk_status st) {
+        s->release();
+        delete s;
+        return st;
+    };
+    if (g.err != hipSuccess) return fail_free(fail(GK_EDEVICE, "hipSetDevice failed"));
+    auto init = [&]() -> gk_status {
+        HIP_TRY(hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking));
+        HIP_TRY(hipEventCreateWithFlags(&s->ev_staged, hipEventDisableTiming));
+        HIP_TRY(hipMalloc((void **)&s->d_lo, sizeof s->lo));
+        HIP_TRY(hipMalloc((void **)&s->d_hi, sizeof s->hi));
+        HIP_TRY(hipMemcpy(s->d_lo, s->lo, sizeof s->lo, hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(s->d_hi, s->hi, sizeof s->hi, hipMemcpyHostToDevice));
+        for (int l = 0; l <= s->layers; ++l) {
+            s->fin.push_back(l ? o.hidden : kInPad);
+            s->fout.push_back(l < s->layers ? o.hidden : s->nout);
+        }
+        // He initialisation for the GELU layers, 1/sqrt(fan-in) for the output
+        // layer, zero biases; weights drawn from Philox normals
+        Rng rng(o.seed, 0x6d6c70u);
+        for (int l = 0; l <= s->layers; ++l) {
+            const size_t nw = (size_t)s->fout[l] * s->fin[l], nb = (size_t)s->fout[l];
+            const int fan = l ? s->fin[l] : 11;
+            const double sd = (l < s->layers ? std::sqrt(2.0) : 1.0) / std::sqrt((double)fan);
+            std::vector<float> w(nw, 0.0f);
+            for (size_t r = 0; r < (size_t)s->fout[l]; ++r)
+                for (int c = 0; c < s->fin[l]; ++c)
+                    w[r * s->fin[l] + c] = (l == 0 && c >= 11) ? 0.0f : (float)(sd * rng.normal());
+            float *p;
+            bf16 *pb;
+            for (auto *v : {&s->W, &s->gW, &s->mW, &s->vW}) {
+                HIP_TRY(hipMalloc((void **)&p, nw * sizeof(float)));
+                HIP_TRY(hipMemset(p, 0, nw * sizeof(float)));
+                v->push_back(p);
+            }
+            for (auto *v : {&s->b, &s->gb, &s->mb, &s->vb}) {
+                HIP_TRY(hipMalloc((void **)&p, nb * sizeof(float)));
+                HIP_TRY(hipMemset(p, 0, nb * sizeof(float)));
+                v->push_back(p);
+            }
+            HIP_TRY(hipMalloc((void **)&pb, nw * sizeof(bf16)));
+            s->Wb.push_back(pb);
+            HIP_TRY(hipMemcpy(s->W[l], w.data(), nw * sizeof(float), hipMemcpyHostToDevice));
+            hipLaunchKernelGGL(k_to_bf16, dim3(blocks(nw)), dim3(256), 0, s->stream, s->W[l], pb, nw);
+            HIP_TRY(hipGetLastError());
+        }
+        GK_TRY(reserve_rows(s, o.batch));
+        HIP_TRY(hipStreamSynchronize(s->stream));
+        return GK_OK;
+    };
+    const gk_status st = init();
+    if (st < 0) return fail_free(st);
+    *out = s;
+    return GK_OK;
+}
+
+gk_status gk_surrogate_destroy(gk_surrogate *s)
+{
+    if (!s) return GK_OK;
+    DeviceGuard g(s->device);
+    s->release();
+    delete s;
+    return GK_OK;
+}
+
+int64_t gk_surrogate_weight_count(const gk_surrogate *s) { return s ? (int64_t)s->weight_count() : -1; }
+
+gk_status gk_surrogate_get_weights(gk_surrogate *s, float *w, int64_t n)
+{
+    if (!s || !w) return fail(GK_EINVAL, "NULL argument");
+    if (n != (int64_t)s->weight_count()) return fail(GK_EINVAL, "weight count mismatch");
+    DeviceGuard g(s->device);
+    HIP_TRY(g.err);
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    for (int l = 0; l <= s->layers; ++l) {
+        const size_t nw = (size_t)s->fout[l] * s->fin[l], nb = (size_t)s->fout[l];
+        HIP_TRY(hipMemcpy(w, s->W[l], nw * sizeof(float), hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(w + nw, s->b[l], nb * sizeof(float), hipMemcpyDeviceToHost));
+        w += nw + nb;
+    }
+    return GK_OK;
+}
+
+gk_status gk_surrogate_set_weights(gk_surrogate *s, const float *w, int64_t n)
+{
+    if (!s || !w) return fail(GK_EINVAL, "NULL argument");
+    if (n != (int64_t)s->weight_count()) return fail(GK_EINVAL, "weight count mismatch");
+    DeviceGuard g(s->device);
+    HIP_TRY(g.err);
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    for (int l = 0; l <= s->layers; ++l) {
+        const size_t nw = (size_t)s->fout[l] * s->fin[l], nb = (size_t)s->fout[l];
+        HIP_TRY(hipMemcpy(s->W[l], w, nw * sizeof(float), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(s->b[l], w + nw, nb * sizeof(float), hipMemcpyHostToDevice));
+        hipLaunchKernelGGL(k_to_bf16, dim3(blocks(nw)), dim3(256), 0, s->stream, s->W[l], s->Wb[l], nw);
+        HIP_TRY(hipGetLastError());
+        w += nw + nb;
+    }
+    // a fresh optimiser state goes with new weights
+    for (int l = 0; l <= s->layers; ++l) {
+        const size_t nw = (size_t)s->fout[l] * s->fin[l], nb = (size_t)s->fout[l];
+        HIP_TRY(hipMemsetAsync(s->mW[l], 0, nw * sizeof(float), s->stream));
+        HIP_TRY(hipMemsetAsync(s->vW[l], 0, nw * sizeof(float), s->stream));
+        HIP_TRY(hipMemsetAsync(s->mb[l], 0, nb * sizeof(float), s->stream));
+        HIP_TRY(hipMemsetAsync(s->vb[l], 0, nb * sizeof(float), s->stream));
+    }
+    s->step = 0;
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    return GK_OK;
+}
+
+gk_status gk_surrogate_train(gk_surrogate *s, int64_t steps, float *losses)
+{
+    if (!s) return fail(GK_EINVAL, "surrogate is NULL");
+    if (steps < 0) return fail(GK_EINVAL, "negative step count");
+    if (steps == 0) return GK_OK;
+    DeviceGuard g(s->device);
+    HIP_TRY(g.err);
+    hipStream_t st = s->stream;
+    GK_TRY(reserve_rows(s, s->o.batch));
+    const int64_t chunk = 4096;  // losses are gathered per chunk of steps
+    if (s->loss_cap < chunk) {
+        HIP_TRY(hipStreamSynchronize(st));
+        if (s->d_loss) (void)hipFree(s->d_loss);
+        s->d_loss = nullptr;
+        s->loss_cap = 0;
+        HIP_TRY(hipMalloc((void **)&s->d_loss, chunk * sizeof(float)));
+        s->loss_cap = (int)chunk;
+    }
+    const int B = s->o.batch;
+    for (int64_t t0 = 0; t0 < steps; t0 += chunk) {
+        const int64_t n = std::min<int64_t>(chunk, steps - t0);
+        for (int64_t t = t0; t < t0 + n; ++t) {
+            // cosine decay from lr to lr_final over the steps of this call
+            const double f = steps > 1 ? (double)t / (double)(steps - 1) : 0.0;
+            const double lr = s->o.lr_final + 0.5 * (s->o.lr - s->o.lr_final) * (1.0 + std::cos(M_PI * f));
+            hipLaunchKernelGGL(k_draw, dim3(blocks(B, 64)), dim3(64), 0, st, s->o.seed,
+                               (uint64_t)s->step, B, s->d_lo, s->d_hi, s->d_params);
+            HIP_TRY(hipGetLastError());
+            GK_TRY(loss_and_grads(s, B, s->d_loss + (t - t0), st));
+            GK_TRY(adam(s, lr, st));
+        }
+        if (losses)
+            HIP_TRY(hipMemcpyAsync(losses + t0, s->d_loss, n * sizeof(float), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+    }
+    return GK_OK;
+}
+
+gk_status gk_surrogate_gradients(gk_surrogate *s, const double *params, int32_t B, float *grads,
+                                 double *loss)
+{
+    if (!s || !params || !grads) return fail(GK_EINVAL, "NULL argument");
+    if (B <= 0 || B > 65536) return fail(GK_EINVAL, "invalid batch size %d", B);
+    if (B % 32) return fail(GK_EINVAL, "gradient batches must be a multiple of 32 rows");
+    DeviceGuard g(s->device);
+    HIP_TRY(g.err);
+    hipStream_t st = s->stream;
+    GK_TRY(stage_params(s, params, B, st));
+    if (!s->d_loss) {
+        HIP_TRY(hipMalloc((void **)&s->d_loss, 4096 * sizeof(float)));
+        s->loss_cap = 4096;
+    }
+    GK_TRY(loss_and_grads(s, B, s->d_loss, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    float lf;
+    HIP_TRY(hipMemcpy(&lf, s->d_loss, sizeof lf, hipMemcpyDeviceToHost));
+    if (loss) *loss = lf;
+    for (int l = 0; l <= s->layers; ++l) {
+        const size_t nw = (size_t)s->fout[l] * s->fin[l], nb = (size_t)s->fout[l];
+        HIP_TRY(hipMemcpy(grads, s->gW[l], nw * sizeof(float), hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(grads + nw, s->gb[l], nb * sizeof(float), hipMemcpyDeviceToHost));
+        grads += nw + nb;
+    }
+    return GK_OK;
+}
+
+gk_status gk_surrogate_predict(gk_surrogate *s, const double *params, int32_t B, float *maps,
+                               void *stream)
+{
+    if (!s) return fail(GK_EINVAL, "surrogate is NULL");
+    if (B < 0) return fail(GK_EINVAL, "negative batch size");
+    if (B == 0) return GK_OK;
+    if (!params || !maps) return fail(GK_EINVAL, "NULL argument");
+    if (pointer_kind(maps) != PTR_DEVICE) return fail(GK_EINVAL, "maps must be device memory");
+    DeviceGuard g(s->device);
+    HIP_TRY(g.err);
+    hipStream_t st = (hipStream_t)stream;
+    for (int r0 = 0; r0 < B; r0 += s->o.batch) {
+        const int n = std::min(s->o.batch, B - r0);
+        GK_TRY(stage_params(s, params + (size_t)r0 * NPAR, n, st));
+        GK_TRY(infer(s, n, st));
+        const size_t ne = (size_t)n * s->nout;
+        hipLaunchKernelGGL(k_scale_maps, dim3(blocks(ne)), dim3(256), 0, st, s->Y, s->npix, ne,
+                           maps + (size_t)r0 * s->nout);
+        HIP_TRY(hipGetLastError());
+    }
+    return GK_OK;
+}
+
+gk_status gk_surrogate_chi2(gk_surrogate *s, gk_model *m, const double *params, int32_t B,
+                            double *chi2, void *stream)
+{
+    if (!s || !m) return fail(GK_EINVAL, "NULL argument");
+    if (B < 0) return fail(GK_EINVAL, "negative batch size");
+    if (B == 0) return GK_OK;
+    if (!params || !chi2) return fail(GK_EINVAL, "NULL argument");
+    if (!m->has_obs) return fail(GK_ESTATE, "no observation set");
+    if (!surrogate_matches(s, m)) return fail(GK_EINVAL, "model instrument differs from the surrogate's");
+    if (m->device != s->device) return fail(GK_EINVAL, "model and surrogate on different devices");
+    if (pointer_kind(chi2) != PTR_DEVICE) return fail(GK_EINVAL, "chi2 must be device memory");
+    DeviceGuard g(s->device);
+    HIP_TRY(g.err);
+    hipStream_t st = (hipStream_t)stream;
+    for (int r0 = 0; r0 < B; r0 += s->o.batch) {
+        const int n = std::min(s->o.batch, B - r0);
+        GK_TRY(stage_params(s, params + (size_t)r0 * NPAR, n, st));
+        GK_TRY(infer(s, n, st));
+        hipLaunchKernelGGL(k_surrogate_chi2, dim3(n), dim3(256), 0, st, s->Y, s->npix, m->d_mask,
+                           m->d_vo, m->d_so, m->d_iev, m->d_ies, s->d_params, m->d.rc, chi2 + r0);
+        HIP_TRY(hipGetLastError());
+    }
+    return GK_OK;
+}
+
+gk_status gk_gemm_bf16(int32_t trans_a, int32_t trans_b, int32_t M, int32_t N, int32_t K,
+                       const uint16_t *A, int32_t lda, const uint16_t *B, int32_t ldb, float *C,
+                       int32_t ldc, void *stream)
+{
+    if (!A || !B || !C) return fail(GK_EINVAL, "NULL argument");
+    for (const void *p : {(const void *)A, (const void *)B, (const void *)C})
+        if (pointer_kind(p) != PTR_DEVICE) return fail(GK_EINVAL, "GEMM operands must be device memory");
+    GemmArgs g{reinterpret_cast<const bf16 *>(A), reinterpret_cast<const bf16 *>(B), lda, ldb, M, N, K,
+               nullptr, C, nullptr, nullptr, ldc};
+    hipStream_t s = (hipStream_t)stream;
+    if (!trans_a && !trans_b) return gemm<false, false, EPI_F32>(g, s);
+    if (!trans_a && trans_b) return gemm<false, true, EPI_F32>(g, s);
+    if (trans_a && trans_b) return gemm<true, true, EPI_F32>(g, s);
+    return gemm<true, false, EPI_F32>(g, s);
+}
+
+}  // extern "C"

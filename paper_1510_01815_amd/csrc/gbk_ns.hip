@@ -2,8 +2,9 @@
 // Philox4x32-10 counter-based generator it draws from.
 //
 // The driver is generic over a batch log-likelihood; gk_fit_nested plugs in
-// the model's chi-square (one launch per round), gk_nested_sample a host
-// callback.  The algorithm is written out in gbk.h.
+// the model's chi-square (one launch per round), gk_fit_nested_screened the
+// surrogate screen in front of it, gk_nested_sample a host callback.  The
+// algorithm is written out in gbk.h.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -16,6 +17,7 @@
 
 #include "gbk_model.h"
 #include "gbk_rng.h"
+#include "gbk_surrogate.h"
 
 using namespace gbk;
 
@@ -51,7 +53,11 @@ bool cholesky(std::vector<double> &M, int d)
 // Volume of the unit d-ball.
 double ball_volume(int d) { return std::pow(M_PI, 0.5 * d) / std::tgamma(0.5 * d + 1.0); }
 
-using BatchLogL = std::function<gk_status(const std::vector<double> &u, int n, std::vector<double> &logl)>;
+// Batch log-likelihood of n unit-cube points; floor is the lowest live
+// log-likelihood when the batch was drawn (candidates at or below it cannot
+// be accepted in this round).
+using BatchLogL = std::function<gk_status(const std::vector<double> &u, int n, double floor,
+                                          std::vector<double> &logl)>;
 
 struct Point {
     std::vector<double> u;
@@ -70,7 +76,7 @@ gk_status ns_run(int d, const BatchLogL &eval, const gk_ns_opts &o, gk_ns_result
     std::vector<double> ub((size_t)std::max(N, B) * d), lb;
     for (int i = 0; i < N; ++i)
         for (int k = 0; k < d; ++k) ub[(size_t)i * d + k] = rng.uniform();
-    GK_TRY(eval(ub, N, lb));
+    GK_TRY(eval(ub, N, -DBL_MAX, lb));
     int64_t n_evals = N, n_launch = 1;
     for (int i = 0; i < N; ++i) {
         live[i].u.assign(ub.begin() + (size_t)i * d, ub.begin() + (size_t)(i + 1) * d);
@@ -85,6 +91,10 @@ gk_status ns_run(int d, const BatchLogL &eval, const gk_ns_opts &o, gk_ns_result
             max_logl = p.logl;
             best = p.u;
         }
+    // min-heap of (logl, index): the lowest live point, ties to the lowest index
+    std::vector<std::pair<double, int>> heap(N);
+    for (int i = 0; i < N; ++i) heap[i] = {live[i].logl, i};
+    std::make_heap(heap.begin(), heap.end(), std::greater<>());
     const double log_shrink = std::log1p(-std::exp(-1.0 / N));  // log(1 - e^{-1/N})
     int64_t k = 0;
     bool done = false;
@@ -145,15 +155,16 @@ gk_status ns_run(int d, const BatchLogL &eval, const gk_ns_opts &o, gk_ns_result
                 if (inside) break;
             }
         }
-        GK_TRY(eval(ub, B, lb));
+        GK_TRY(eval(ub, B, heap.front().first, lb));
         n_evals += B;
         ++n_launch;
         for (int c = 0; c < B && !done; ++c) {
             const double lc = std::isfinite(lb[c]) ? lb[c] : -DBL_MAX;
-            int imin = 0;
-            for (int i = 1; i < N; ++i)
-                if (live[i].logl < live[imin].logl) imin = i;
+            const int imin = heap.front().second;
             if (!(lc > live[imin].logl)) continue;
+            std::pop_heap(heap.begin(), heap.end(), std::greater<>());
+            heap.back() = {lc, imin};
+            std::push_heap(heap.begin(), heap.end(), std::greater<>());
             ++k;
             const double logwt = live[imin].logl + (-(double)(k - 1) / N + log_shrink);
             logz = logaddexp(logz, logwt);
@@ -165,9 +176,8 @@ gk_status ns_run(int d, const BatchLogL &eval, const gk_ns_opts &o, gk_ns_result
                 max_logl = lc;
                 best = live[imin].u;
             }
-            double lmax = -INFINITY;
-            for (auto &p : live) lmax = std::max(lmax, p.logl);
-            if (logaddexp(logz, lmax - (double)k / N) - logz < o.tol) done = true;
+            // the retired point is the lowest, so the live maximum is the running one
+            if (logaddexp(logz, max_logl - (double)k / N) - logz < o.tol) done = true;
             if (k >= o.max_iter) {
                 done = true;
                 capped = true;
@@ -279,7 +289,7 @@ extern "C" gk_status gk_nested_sample(int32_t dim, const double *lo, const doubl
     for (int a = 0; a < dim; ++a)
         if (!(hi[a] > lo[a])) return fail(GK_EINVAL, "empty prior range in dimension %d", a);
     std::vector<double> theta;
-    BatchLogL eval = [&](const std::vector<double> &u, int n, std::vector<double> &logl) -> gk_status {
+    BatchLogL eval = [&](const std::vector<double> &u, int n, double, std::vector<double> &logl) -> gk_status {
         theta.resize((size_t)n * dim);
         for (int i = 0; i < n; ++i)
             for (int a = 0; a < dim; ++a)
@@ -315,10 +325,13 @@ gk_status fit_reserve_rows(gk_model *m, int rows, double **h_params, double **d_
                            double **d_chi2, double **h_chi2, hipStream_t *stream);
 }
 
-extern "C" gk_status gk_fit_nested(gk_model *m, const double *lo, const double *hi,
-                                   const uint8_t *free_mask, const double *fixed,
-                                   const gk_ns_opts *o_in, gk_ns_result *res, double *samples,
-                                   int64_t cap, int64_t *n_samples)
+namespace {
+
+// Plain (s == NULL) or surrogate-screened nested sampling of a model.
+gk_status fit_nested(gk_model *m, gk_surrogate *sur, const double *lo, const double *hi,
+                     const uint8_t *free_mask, const double *fixed, const gk_ns_opts *o_in,
+                     double margin, double audit, gk_ns_result *res, double *samples, int64_t cap,
+                     int64_t *n_samples)
 {
     if (!m || !lo || !hi || !free_mask || !fixed || !res) return fail(GK_EINVAL, "NULL argument");
     if (!m->has_obs) return fail(GK_ESTATE, "no observation set");
@@ -326,6 +339,12 @@ extern "C" gk_status gk_fit_nested(gk_model *m, const double *lo, const double *
     gk_ns_default_opts(&o);
     if (o_in) o = *o_in;
     GK_TRY(check_opts(o));
+    if (sur) {
+        if (!(margin >= 0.0) || !(audit >= 0.0 && audit <= 1.0))
+            return fail(GK_EINVAL, "margin must be >= 0 and audit in [0, 1]");
+        if (!surrogate_matches(sur, m)) return fail(GK_EINVAL, "model instrument differs from the surrogate's");
+        if (surrogate_device(sur) != m->device) return fail(GK_EINVAL, "model and surrogate on different devices");
+    }
     std::vector<int> fr;
     for (int k = 0; k < NPAR; ++k) {
         if (!free_mask[k]) continue;
@@ -339,27 +358,98 @@ extern "C" gk_status gk_fit_nested(gk_model *m, const double *lo, const double *
     double *h_params, *d_params, *d_chi2, *h_chi2;
     hipStream_t stream;
     const int rows = std::max(o.n_live, o.batch);
-    GK_TRY(fit_reserve_rows(m, rows, &h_params, &d_params, &d_chi2, &h_chi2, &stream));
-    BatchLogL eval = [&](const std::vector<double> &u, int n, std::vector<double> &logl) -> gk_status {
-        for (int i = 0; i < n; ++i) {
-            double *row = h_params + (size_t)i * NPAR;
+    // chi2 rows, then (screened) surrogate chi2 rows
+    GK_TRY(fit_reserve_rows(m, 2 * rows, &h_params, &d_params, &d_chi2, &h_chi2, &stream));
+    double *d_chi2s = d_chi2 + rows, *h_chi2s = h_chi2 + rows;
+    std::memset(res, 0, sizeof *res);
+    auto fill_rows = [&](const std::vector<double> &u, const std::vector<int> &idx) {
+        for (size_t i = 0; i < idx.size(); ++i) {
+            double *row = h_params + i * NPAR;
             std::memcpy(row, fixed, sizeof(double) * NPAR);
             for (int a = 0; a < d; ++a)
-                row[fr[a]] = lo[fr[a]] + u[(size_t)i * d + a] * (hi[fr[a]] - lo[fr[a]]);
+                row[fr[a]] = lo[fr[a]] + u[(size_t)idx[i] * d + a] * (hi[fr[a]] - lo[fr[a]]);
         }
+    };
+    // plain chi2 of the rows in h_params [0, n) into h_chi2
+    auto plain = [&](int n) -> gk_status {
+        if (n == 0) return GK_OK;
         HIP_TRY(hipMemcpyAsync(d_params, h_params, sizeof(double) * NPAR * n, hipMemcpyHostToDevice,
                                stream));
         GK_TRY(run_batch(m, d_params, n, nullptr, nullptr, d_chi2, nullptr, stream));
         HIP_TRY(hipMemcpyAsync(h_chi2, d_chi2, sizeof(double) * n, hipMemcpyDeviceToHost, stream));
         HIP_TRY(hipStreamSynchronize(stream));
-        logl.resize(n);
-        for (int i = 0; i < n; ++i) logl[i] = -0.5 * h_chi2[i];
         return GK_OK;
     };
-    std::memset(res, 0, sizeof *res);
+    std::vector<int> all, keep;
+    int64_t n_plain = 0;
+    Rng audit_rng(o.seed, 0x617564u);
+    std::vector<double> recent;  // surrogate-minus-plain chi2 of the latest plain evaluations
+    size_t recent_pos = 0;
+    double shift = 0.0;
+    BatchLogL eval = [&](const std::vector<double> &u, int n, double floor,
+                         std::vector<double> &logl) -> gk_status {
+        logl.assign(n, -INFINITY);
+        all.resize(n);
+        std::iota(all.begin(), all.end(), 0);
+        keep.clear();
+        if (!sur) {
+            fill_rows(u, all);
+            GK_TRY(plain(n));
+            n_plain += n;
+            for (int i = 0; i < n; ++i) logl[i] = -0.5 * h_chi2[i];
+            return GK_OK;
+        }
+        // surrogate chi2 of every candidate
+        fill_rows(u, all);
+        HIP_TRY(hipMemcpyAsync(d_params, h_params, sizeof(double) * NPAR * n, hipMemcpyHostToDevice,
+                               stream));
+        GK_TRY(surrogate_chi2(sur, m, d_params, n, d_chi2s, stream));
+        HIP_TRY(hipMemcpyAsync(h_chi2s, d_chi2s, sizeof(double) * n, hipMemcpyDeviceToHost, stream));
+        HIP_TRY(hipStreamSynchronize(stream));
+        const double chi2_floor = floor > -DBL_MAX ? -2.0 * floor : INFINITY;
+        const double cut = chi2_floor + shift + margin;
+        std::vector<char> audited(n, 0);
+        for (int i = 0; i < n; ++i) {
+            const double a = audit_rng.uniform();  // one draw per candidate, used or not
+            if (!(h_chi2s[i] > cut)) {
+                keep.push_back(i);
+            } else if (a < audit) {
+                keep.push_back(i);
+                audited[i] = 1;
+            }
+        }
+        res->n_screened += n;
+        res->n_rejected += n - (int64_t)keep.size();
+        fill_rows(u, keep);
+        GK_TRY(plain((int)keep.size()));
+        n_plain += (int64_t)keep.size();
+        const size_t window = (size_t)std::max(o.n_live, o.batch);
+        for (size_t j = 0; j < keep.size(); ++j) {
+            const int i = keep[j];
+            const double c = h_chi2[j];
+            logl[i] = -0.5 * c;
+            if (audited[i]) {
+                res->n_audited += 1;
+                res->n_audit_miss += c < chi2_floor;
+            }
+            const double delta = h_chi2s[i] - c;
+            if (std::isfinite(delta)) {
+                if (recent.size() < window) {
+                    recent.push_back(delta);
+                } else {
+                    recent[recent_pos] = delta;
+                    recent_pos = (recent_pos + 1) % window;
+                }
+            }
+        }
+        shift = 0.0;
+        for (double v : recent) shift = std::max(shift, v);
+        return GK_OK;
+    };
     std::vector<std::pair<std::vector<double>, double>> post;
     bool capped = false;
     GK_TRY(ns_run(d, eval, o, res, post, capped));
+    res->n_evals = n_plain;  // plain evaluations only
     double best_u[GK_NP];
     std::memcpy(best_u, res->best, sizeof best_u);
     for (int k = 0; k < NPAR; ++k) {
@@ -383,4 +473,26 @@ extern "C" gk_status gk_fit_nested(gk_model *m, const double *lo, const double *
         *n_samples = n;
     }
     return capped ? GK_ENOTCONV : GK_OK;
+}
+
+}  // namespace
+
+extern "C" gk_status gk_fit_nested(gk_model *m, const double *lo, const double *hi,
+                                   const uint8_t *free_mask, const double *fixed,
+                                   const gk_ns_opts *o_in, gk_ns_result *res, double *samples,
+                                   int64_t cap, int64_t *n_samples)
+{
+    return fit_nested(m, nullptr, lo, hi, free_mask, fixed, o_in, 0.0, 0.0, res, samples, cap,
+                      n_samples);
+}
+
+extern "C" gk_status gk_fit_nested_screened(gk_model *m, gk_surrogate *s, const double *lo,
+                                            const double *hi, const uint8_t *free_mask,
+                                            const double *fixed, const gk_ns_opts *o_in,
+                                            double margin, double audit, gk_ns_result *res,
+                                            double *samples, int64_t cap, int64_t *n_samples)
+{
+    if (!s) return fail(GK_EINVAL, "surrogate is NULL");
+    return fit_nested(m, s, lo, hi, free_mask, fixed, o_in, margin, audit, res, samples, cap,
+                      n_samples);
 }

@@ -1,5 +1,8 @@
-// gbk_rng.h -- private: Philox4x32-10 counter-based generator (host code).
+// gbk_rng.h -- private: Philox4x32-10 counter-based generator (the block
+// function for host and device code, a sequential stream for host code).
 #pragma once
+#include <hip/hip_runtime.h>
+
 #include <cmath>
 #include <cstdint>
 
@@ -9,7 +12,7 @@ namespace gbk {
 constexpr uint32_t kPhiloxM0 = 0xD2511F53u, kPhiloxM1 = 0xCD9E8D57u;
 constexpr uint32_t kPhiloxW0 = 0x9E3779B9u, kPhiloxW1 = 0xBB67AE85u;
 
-inline void philox4x32_10(const uint32_t in[4], const uint32_t key_in[2], uint32_t out[4])
+__host__ __device__ inline void philox4x32_10(const uint32_t in[4], const uint32_t key_in[2], uint32_t out[4])
 {
     uint32_t c0 = in[0], c1 = in[1], c2 = in[2], c3 = in[3];
     uint32_t k0 = key_in[0], k1 = key_in[1];

@@ -27,6 +27,10 @@ SYMBOLS = (
     "gk_set_profiling", "gk_read_profile", "gk_lm_default_opts", "gk_fit_lm",
     "gk_ns_default_opts", "gk_fit_nested", "gk_nested_sample", "gk_philox4x32", "gk_fit_grid",
     "gk_create_survey", "gk_destroy_survey", "gk_survey_chi2", "gk_fit_lm_survey",
+    "gk_surrogate_default_opts", "gk_surrogate_create", "gk_surrogate_destroy",
+    "gk_surrogate_train", "gk_surrogate_weight_count", "gk_surrogate_get_weights",
+    "gk_surrogate_set_weights", "gk_surrogate_gradients", "gk_surrogate_predict",
+    "gk_surrogate_chi2", "gk_fit_nested_screened", "gk_gemm_bf16",
 )
 LM_REASONS = {1: "ftol", 2: "xtol", 3: "lambda", 4: "maxiter"}
 GK_PROF_TIMING, GK_PROF_COUNT = 1, 2
@@ -74,7 +78,14 @@ class NSResult(ctypes.Structure):
                 ("info_h", ctypes.c_double), ("max_logl", ctypes.c_double),
                 ("n_iter", ctypes.c_int64), ("n_evals", ctypes.c_int64),
                 ("n_launches", ctypes.c_int64)] + [
-                (n, ctypes.c_double * NPAR) for n in ("best", "mean", "sd", "median", "q16", "q84")]
+                (n, ctypes.c_double * NPAR) for n in ("best", "mean", "sd", "median", "q16", "q84")] + [
+                (n, ctypes.c_int64) for n in ("n_screened", "n_rejected", "n_audited", "n_audit_miss")]
+
+
+class SurrogateOpts(ctypes.Structure):
+    _fields_ = [("hidden", ctypes.c_int32), ("layers", ctypes.c_int32), ("batch", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("lr", ctypes.c_double), ("lr_final", ctypes.c_double),
+                ("seed", ctypes.c_uint64)]
 
 
 class GridResult(ctypes.Structure):
@@ -100,7 +111,9 @@ def _ns_opts(L, **opts):
 
 def _ns_dict(r: "NSResult", st: int, dim: int, samples=None) -> dict:
     out = {"logz": r.logz, "logz_err": r.logz_err, "info_h": r.info_h, "max_logl": r.max_logl,
-           "n_iter": r.n_iter, "n_evals": r.n_evals, "n_launches": r.n_launches, "status": st}
+           "n_iter": r.n_iter, "n_evals": r.n_evals, "n_launches": r.n_launches, "status": st,
+           "n_screened": r.n_screened, "n_rejected": r.n_rejected, "n_audited": r.n_audited,
+           "n_audit_miss": r.n_audit_miss}
     for n in ("best", "mean", "sd", "median", "q16", "q84"):
         out[n] = np.array(getattr(r, n)[:dim])
     if samples is not None:
@@ -190,9 +203,24 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.gk_survey_chi2.argtypes = [vp, vp, vp, i32, vp, vp]
     L.gk_fit_lm_survey.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(LMOpts),
                                    ctypes.POINTER(LMResult)]
+    L.gk_surrogate_default_opts.argtypes = [ctypes.POINTER(SurrogateOpts)]
+    L.gk_surrogate_create.argtypes = [vp, vp, vp, ctypes.POINTER(SurrogateOpts), ctypes.POINTER(vp)]
+    L.gk_surrogate_destroy.argtypes = [vp]
+    L.gk_surrogate_train.argtypes = [vp, ctypes.c_int64, vp]
+    L.gk_surrogate_weight_count.argtypes = [vp]
+    L.gk_surrogate_get_weights.argtypes = [vp, vp, ctypes.c_int64]
+    L.gk_surrogate_set_weights.argtypes = [vp, vp, ctypes.c_int64]
+    L.gk_surrogate_gradients.argtypes = [vp, vp, i32, vp, ctypes.POINTER(ctypes.c_double)]
+    L.gk_surrogate_predict.argtypes = [vp, vp, i32, vp, vp]
+    L.gk_surrogate_chi2.argtypes = [vp, vp, vp, i32, vp, vp]
+    L.gk_fit_nested_screened.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.POINTER(NSOpts), dp, dp,
+                                         ctypes.POINTER(NSResult), vp, ctypes.c_int64, i64p]
+    L.gk_gemm_bf16.argtypes = [i32, i32, i32, i32, i32, vp, i32, vp, i32, vp, i32, vp]
     L.gk_last_error.restype = ctypes.c_char_p
     for name in SYMBOLS:
-        if name != "gk_last_error":
+        if name == "gk_surrogate_weight_count":
+            L.gk_surrogate_weight_count.restype = ctypes.c_int64
+        elif name != "gk_last_error":
             getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -439,3 +467,118 @@ class Survey:
                 "reason": [LM_REASONS.get(r.reason, str(r.reason)) for r in res],
                 "n_evals": np.array([r.n_evals for r in res]),
                 "errors": np.array([r.errors[:] for r in res]), "status": st}
+
+
+def gemm_bf16(A, B, trans_a=False, trans_b=False, M=None, N=None, K=None, C=None, stream=None):
+    """C [M][N] float32 = sum_k A(m, k) B(n, k) on the surrogate's BF16 GEMM
+    (gk_gemm_bf16).  A, B: 2-D bfloat16 CUDA tensors in the stored layout."""
+    import torch
+    if A.dtype != torch.bfloat16 or B.dtype != torch.bfloat16:
+        raise ValueError("A and B must be bfloat16")
+    M = M if M is not None else (A.shape[1] if trans_a else A.shape[0])
+    K = K if K is not None else (A.shape[0] if trans_a else A.shape[1])
+    N = N if N is not None else (B.shape[1] if trans_b else B.shape[0])
+    if C is None:
+        C = torch.empty((M, N), dtype=torch.float32, device=A.device)
+    _check(load().gk_gemm_bf16(int(trans_a), int(trans_b), M, N, K, A.data_ptr(), A.stride(0),
+                               B.data_ptr(), B.stride(0), C.data_ptr(), C.stride(0),
+                               _stream_ptr(stream)))
+    return C
+
+
+class Surrogate:
+    """MLP emulator of the moment maps of one instrument (gk_surrogate_create)."""
+
+    def __init__(self, model: "Model", lo, hi, **opts):
+        L = load()
+        o = SurrogateOpts()
+        _check(L.gk_surrogate_default_opts(ctypes.byref(o)))
+        for k, v in opts.items():
+            setattr(o, k, v)
+        self.opts = o
+        self.model = model  # the model must outlive the surrogate
+        self.lo = np.ascontiguousarray(lo, dtype=np.float64)
+        self.hi = np.ascontiguousarray(hi, dtype=np.float64)
+        h = ctypes.c_void_p()
+        _check(L.gk_surrogate_create(model._h, self.lo.ctypes.data, self.hi.ctypes.data,
+                                     ctypes.byref(o), ctypes.byref(h)))
+        self._h = h
+        self.device = model.device
+        self.nx, self.ny = model.nx, model.ny
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().gk_surrogate_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def train(self, steps: int) -> np.ndarray:
+        """Runs `steps` Adam steps; returns each step's loss."""
+        losses = np.zeros(max(steps, 1), dtype=np.float32)
+        _check(load().gk_surrogate_train(self._h, steps, losses.ctypes.data))
+        return losses[:steps]
+
+    def weight_count(self) -> int:
+        return int(load().gk_surrogate_weight_count(self._h))
+
+    def get_weights(self) -> np.ndarray:
+        w = np.zeros(self.weight_count(), dtype=np.float32)
+        _check(load().gk_surrogate_get_weights(self._h, w.ctypes.data, w.size))
+        return w
+
+    def set_weights(self, w) -> None:
+        w = np.ascontiguousarray(w, dtype=np.float32)
+        _check(load().gk_surrogate_set_weights(self._h, w.ctypes.data, w.size))
+
+    def gradients(self, params):
+        """(loss, gradient vector) on rows params [B][12] (B a multiple of 32)."""
+        p, B, keep = _params_arg(params)
+        g = np.zeros(self.weight_count(), dtype=np.float32)
+        loss = ctypes.c_double(0.0)
+        _check(load().gk_surrogate_gradients(self._h, p, B, g.ctypes.data, ctypes.byref(loss)))
+        return loss.value, g
+
+    def predict(self, params, out=None, stream=None):
+        """maps [B][2][ny][nx] float32 CUDA tensor (m1, m2 in km/s)."""
+        import torch
+        p, B, keep = _params_arg(params)
+        if out is None:
+            out = torch.empty((B, 2, self.ny, self.nx), dtype=torch.float32,
+                              device=f"cuda:{self.device}")
+        _check(load().gk_surrogate_predict(self._h, p, B, out.data_ptr(), _stream_ptr(stream)))
+        return out
+
+    def chi2(self, model: "Model", params, out=None, stream=None):
+        """Surrogate chi2 [B] float64 CUDA tensor against model's observation."""
+        import torch
+        p, B, keep = _params_arg(params)
+        if out is None:
+            out = torch.empty(B, dtype=torch.float64, device=f"cuda:{self.device}")
+        _check(load().gk_surrogate_chi2(self._h, model._h, p, B, out.data_ptr(), _stream_ptr(stream)))
+        return out
+
+    def fit_nested(self, model: "Model", lo, hi, free, fixed, margin=25.0, audit=0.0,
+                   want_samples=0, **opts) -> dict:
+        """Surrogate-screened nested sampling (gk_fit_nested_screened)."""
+        L = load()
+        lo = np.ascontiguousarray(lo, dtype=np.float64)
+        hi = np.ascontiguousarray(hi, dtype=np.float64)
+        fm = np.ascontiguousarray(free, dtype=np.uint8)
+        fx = np.ascontiguousarray(fixed, dtype=np.float64)
+        r = NSResult()
+        o = _ns_opts(L, **opts)
+        buf = np.zeros((max(want_samples, 1), NPAR + 1))
+        ns = ctypes.c_int64(0)
+        st = L.gk_fit_nested_screened(model._h, self._h, lo.ctypes.data, hi.ctypes.data,
+                                      fm.ctypes.data, fx.ctypes.data, ctypes.byref(o), margin,
+                                      audit, ctypes.byref(r),
+                                      buf.ctypes.data if want_samples else None, want_samples,
+                                      ctypes.byref(ns))
+        if st < 0 and st != GK_ENOTCONV:
+            _check(st)
+        return _ns_dict(r, st, NPAR, buf[: ns.value] if want_samples else None)
