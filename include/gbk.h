@@ -84,8 +84,17 @@ typedef struct {
     double lsf_sigma_kms;        /* >= 0; 0 = no LSF */
     double kernel_radius_sigma;  /* R > 0 (4 is the usual choice) */
     int32_t rc;                  /* GK_RC_* */
-    int32_t reserved;            /* must be 0 */
+    int32_t conv_mode;           /* GK_CONV_*: how the spatial PSF convolution runs */
 } gk_model_desc;
+
+/* Spatial PSF convolution: AUTO takes the direct LDS-tiled passes while the
+ * PSF half-width fits them (at most 16 fine pixels for the register-blocked
+ * u = 1 kernel, the LDS budget otherwise) and the FFT path beyond; DIRECT
+ * and FFT force one (DIRECT fails for a PSF too wide for LDS).  The FFT path
+ * convolves along x, then along y, with radix-2 FFTs of the next power of
+ * two >= the padded extent (eq. 10) in FP64; its results equal the direct
+ * path's up to rounding of order log2(P) * 1e-16 of the largest plane value. */
+enum { GK_CONV_AUTO = 0, GK_CONV_DIRECT = 1, GK_CONV_FFT = 2 };
 
 /* Creates a model for one instrument grid on HIP device `device`.
  * Errors: GK_EINVAL (bad descriptor), GK_ENOMEM, GK_EDEVICE. */
@@ -402,6 +411,25 @@ gk_status gk_gemm_bf16(int32_t trans_a, int32_t trans_b, int32_t M, int32_t N, i
 /* Shape of the fine model cube with its halo and the halos themselves:
  * dims = {nx_ext, ny_ext, nz_ext, h_psf, h_lsf}. */
 gk_status gk_model_dims(const gk_model *model, int32_t dims[5]);
+
+/* Launch mode of the evaluation calls (gk_evaluate_batch, gk_chi2_batch,
+ * gk_residual_batch and the fitters' batched evaluations) whose rows are in
+ * device memory and whose stream is not the null stream.  GK_LAUNCH_GRAPH
+ * (the default): the second call with the same rows pointer, batch size,
+ * output pointers and stream records the call's launch chain (every chunk's
+ * kernels) in a HIP graph, and later such calls replay it; the rows' values
+ * may change between calls (the kernels read them when they run).  A graph
+ * is dropped when the model's scratch grows or its observation is set, and
+ * at most 8 are kept (oldest dropped first).  GK_LAUNCH_EAGER launches every
+ * kernel each time.  Profiling (gk_set_profiling) always launches eagerly.
+ * Results are identical in both modes. */
+enum { GK_LAUNCH_EAGER = 0, GK_LAUNCH_GRAPH = 1 };
+gk_status gk_set_launch_mode(gk_model *model, int32_t mode);
+/* graph replays made by the model so far */
+gk_status gk_graph_launches(const gk_model *model, int64_t *count);
+
+/* The spatial convolution path the model runs: GK_CONV_DIRECT or GK_CONV_FFT. */
+gk_status gk_model_conv_path(const gk_model *model, int32_t *conv_mode);
 
 /* Message of the last failed call on this host thread ("" if none). */
 const char *gk_last_error(void);

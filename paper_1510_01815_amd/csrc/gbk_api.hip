@@ -138,31 +138,80 @@ void choose_tile(gk_model *m)
     m->lds_bytes = psf_lds_bytes(tx, ty, m->d.upsample, m->hp);
 }
 
+// log2 of the smallest power of two >= n
+int ceil_log2(int n)
+{
+    int l = 0;
+    while ((1 << l) < n) ++l;
+    return l;
+}
+
+int bit_reverse(int i, int bits)
+{
+    int r = 0;
+    for (int k = 0; k < bits; ++k) r = (r << 1) | ((i >> k) & 1);
+    return r;
+}
+
+// Sizes, twiddles and PSF spectra of the FFT path; false if a line or a
+// column block does not fit the LDS budget.
+bool setup_fft(gk_model *m, const std::vector<double> &kp, std::vector<double2> &twx,
+               std::vector<double2> &twy, std::vector<double> &kbx, std::vector<double> &kby)
+{
+    FftArgs &f = m->fft;
+    f.EX = m->EX;
+    f.EY = m->EY;
+    f.NXF = m->NX;
+    f.hp = m->hp;
+    f.logPX = std::max(1, ceil_log2(m->EX));
+    f.logPY = std::max(1, ceil_log2(m->EY));
+    f.PX = 1 << f.logPX;
+    f.PY = 1 << f.logPY;
+    if ((size_t)f.PX * sizeof(double2) > kMaxLds) return false;
+    f.NLX = std::max<int>(1, (int)(32768 / (sizeof(double2) * f.PX)));
+    f.DC = 0;
+    for (int dc = 8; dc >= 1; dc /= 2) {
+        f.DC = dc;
+        if (fft_y_lds_bytes(f, m->d.upsample) <= kMaxLds) break;
+        f.DC = 0;
+    }
+    if (f.DC == 0) return false;
+    f.ncb = (m->d.nx + f.DC - 1) / f.DC;
+    m->ntiles = f.ncb;  // chi-square partials per row
+    // tw[k] = exp(-2 pi i k / P); spectrum of the circularly placed taps,
+    // real because they are symmetric, scaled by 1/P, in bit-reversed order
+    auto make = [&](int P, int logP, std::vector<double2> &tw, std::vector<double> &kb) {
+        tw.resize(P / 2);
+        for (int k = 0; k < P / 2; ++k) {
+            const double a = 2.0 * M_PI * k / P;
+            tw[k] = double2{std::cos(a), -std::sin(a)};
+        }
+        const int h = (int)kp.size() / 2;
+        std::vector<double> spec(P);
+        for (int q = 0; q < P; ++q) {
+            double s = 0.0;
+            for (int t = -h; t <= h; ++t) {
+                const long r = (((long)q * t) % P + P) % P;  // exact phase index
+                s += kp[t + h] * std::cos(2.0 * M_PI * (double)r / P);
+            }
+            spec[q] = s / P;
+        }
+        kb.resize(P);
+        for (int i = 0; i < P; ++i) kb[i] = spec[bit_reverse(i, logP)];
+    };
+    make(f.PX, f.logPX, twx, kbx);
+    make(f.PY, f.logPY, twy, kby);
+    return true;
+}
+
 }  // namespace
 
-gk_status gbk::run_batch(gk_model *m, const double *params, int32_t B, float *maps,
-                          double *resid, double *chi2, int64_t *nvalid, void *stream)
+namespace {
+
+// Enqueues the launch chain of B rows (every chunk) on s.
+gk_status enqueue_batch(gk_model *m, const double *params, PtrKind pk, int32_t B, float *maps,
+                        double *resid, double *chi2, int64_t *nvalid, hipStream_t s)
 {
-    if (!m) return fail(GK_EINVAL, "model is NULL");
-    if (B < 0) return fail(GK_EINVAL, "negative batch size %d", B);
-    if (B == 0) return GK_OK;
-    if (!params) return fail(GK_EINVAL, "params is NULL");
-    if ((resid || chi2) && !m->has_obs) return fail(GK_ESTATE, "no observation set");
-    DeviceGuard g(m->device);
-    HIP_TRY(g.err);
-    hipStream_t s = (hipStream_t)stream;
-
-    for (const void *out : {(const void *)maps, (const void *)resid, (const void *)chi2,
-                            (const void *)nvalid}) {
-        if (out && pointer_kind(out) != PTR_DEVICE)
-            return fail(GK_EINVAL, "output arrays must be device memory");
-    }
-    PtrKind pk = pointer_kind(params);
-    if (pk == PTR_BAD) return fail(GK_EINVAL, "params pointer of unknown kind");
-    int n_bad = 0;
-    if (pk == PTR_HOST)
-        for (int b = 0; b < B; ++b) n_bad += !row_valid(params + (size_t)b * NPAR, m->d.rc);
-
     const int chunk = std::min<int>(B, m->chunk_rows());
     HIP_TRY(m->reserve(chunk));
     const bool timing = m->prof_flags & GK_PROF_TIMING;
@@ -232,20 +281,134 @@ gk_status gbk::run_batch(gk_model *m, const double *params, int32_t B, float *ma
         a.maps = maps ? maps + (size_t)b0 * 3 * npix : nullptr;
         a.resid = resid ? resid + (size_t)b0 * 2 * npix : nullptr;
         a.partial = chi2 ? m->d_partial : nullptr;
-        HIP_TRY(timed(2, [&] { return launch_psf_moments(a, nb, m->lds_bytes, s); }));
+        if (m->use_fft) {
+            FftArgs f = m->fft;
+            f.T = m->d_T;
+            f.U = m->d_U;
+            HIP_TRY(timed(2, [&] {
+                hipError_t e = launch_fft_x(f, nb, s);
+                return e == hipSuccess ? launch_fft_y_moments(f, a, nb, s) : e;
+            }));
+        } else {
+            HIP_TRY(timed(2, [&] { return launch_psf_moments(a, nb, m->lds_bytes, s); }));
+        }
         if (chi2)
             HIP_TRY(timed(3, [&] {
                 return launch_reduce_chi2(m->d_partial, m->ntiles, m->d_consts, m->nvalid,
                                           chi2 + b0, nvalid ? nvalid + b0 : nullptr, nb, s);
             }));
     }
-    return n_bad ? GK_PARTIAL : GK_OK;
+    return GK_OK;
+}
+
+constexpr size_t kMaxGraphs = 8;
+
+}  // namespace
+
+gk_status gbk::run_batch(gk_model *m, const double *params, int32_t B, float *maps,
+                          double *resid, double *chi2, int64_t *nvalid, void *stream)
+{
+    if (!m) return fail(GK_EINVAL, "model is NULL");
+    if (B < 0) return fail(GK_EINVAL, "negative batch size %d", B);
+    if (B == 0) return GK_OK;
+    if (!params) return fail(GK_EINVAL, "params is NULL");
+    if ((resid || chi2) && !m->has_obs) return fail(GK_ESTATE, "no observation set");
+    DeviceGuard g(m->device);
+    HIP_TRY(g.err);
+    hipStream_t s = (hipStream_t)stream;
+
+    for (const void *out : {(const void *)maps, (const void *)resid, (const void *)chi2,
+                            (const void *)nvalid}) {
+        if (out && pointer_kind(out) != PTR_DEVICE)
+            return fail(GK_EINVAL, "output arrays must be device memory");
+    }
+    PtrKind pk = pointer_kind(params);
+    if (pk == PTR_BAD) return fail(GK_EINVAL, "params pointer of unknown kind");
+    int n_bad = 0;
+    if (pk == PTR_HOST)
+        for (int b = 0; b < B; ++b) n_bad += !row_valid(params + (size_t)b * NPAR, m->d.rc);
+
+    const bool graphable = m->launch_mode == GK_LAUNCH_GRAPH && pk == PTR_DEVICE &&
+                           !m->prof_flags && s != nullptr;
+    if (!graphable) {
+        GK_TRY(enqueue_batch(m, params, pk, B, maps, resid, chi2, nvalid, s));
+        return n_bad ? GK_PARTIAL : GK_OK;
+    }
+    // scratch first, so that recording allocates nothing
+    HIP_TRY(m->reserve(std::min<int>(B, m->chunk_rows())));
+    const gk_model::GraphKey key{params, maps, resid, chi2, nvalid, s, B, m->gen};
+    for (auto &g : m->graphs)
+        if (g.key == key) {
+            HIP_TRY(hipGraphLaunch(g.exec, s));
+            ++m->graph_launches;
+            return GK_OK;
+        }
+    auto it = std::find(m->seen.begin(), m->seen.end(), key);
+    if (it == m->seen.end()) {  // first sighting: run eagerly, remember the key
+        if (m->seen.size() >= 2 * kMaxGraphs) m->seen.erase(m->seen.begin());
+        m->seen.push_back(key);
+        GK_TRY(enqueue_batch(m, params, pk, B, maps, resid, chi2, nvalid, s));
+        return GK_OK;
+    }
+    m->seen.erase(it);
+    // second sighting: record the chain, then launch the graph
+    HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
+    const gk_status st = enqueue_batch(m, params, pk, B, maps, resid, chi2, nvalid, s);
+    hipGraph_t graph = nullptr;
+    const hipError_t ec = hipStreamEndCapture(s, &graph);
+    if (st < 0 || ec != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        if (st < 0) return st;
+        HIP_TRY(ec);
+    }
+    hipGraphExec_t exec = nullptr;
+    const hipError_t ei = hipGraphInstantiateWithFlags(&exec, graph, 0);
+    if (ei != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        HIP_TRY(ei);
+    }
+    if (m->graphs.size() >= kMaxGraphs) {
+        (void)hipGraphExecDestroy(m->graphs.front().exec);
+        (void)hipGraphDestroy(m->graphs.front().graph);
+        m->graphs.erase(m->graphs.begin());
+    }
+    m->graphs.push_back({key, graph, exec});
+    HIP_TRY(hipGraphLaunch(exec, s));
+    ++m->graph_launches;
+    return GK_OK;
 }
 
 
 extern "C" {
 
 const char *gk_last_error(void) { return g_err.c_str(); }
+
+gk_status gk_set_launch_mode(gk_model *m, int32_t mode)
+{
+    if (!m) return fail(GK_EINVAL, "model is NULL");
+    if (mode != GK_LAUNCH_EAGER && mode != GK_LAUNCH_GRAPH)
+        return fail(GK_EINVAL, "unknown launch mode %d", mode);
+    DeviceGuard g(m->device);
+    HIP_TRY(g.err);
+    HIP_TRY(hipDeviceSynchronize());  // recorded graphs may still run
+    m->drop_graphs();
+    m->launch_mode = mode;
+    return GK_OK;
+}
+
+gk_status gk_graph_launches(const gk_model *m, int64_t *count)
+{
+    if (!m || !count) return fail(GK_EINVAL, "NULL argument");
+    *count = m->graph_launches;
+    return GK_OK;
+}
+
+gk_status gk_model_conv_path(const gk_model *m, int32_t *conv_mode)
+{
+    if (!m || !conv_mode) return fail(GK_EINVAL, "NULL argument");
+    *conv_mode = m->use_fft ? GK_CONV_FFT : GK_CONV_DIRECT;
+    return GK_OK;
+}
 
 gk_status gk_create_model(const gk_model_desc *desc, int device, gk_model **out)
 {
@@ -263,7 +426,8 @@ gk_status gk_create_model(const gk_model_desc *desc, int device, gk_model **out)
     if (!(d.kernel_radius_sigma > 0.0) || d.kernel_radius_sigma > 16.0)
         return fail(GK_EINVAL, "kernel radius must be in (0, 16]");
     if (d.rc < GK_RC_ARCTAN || d.rc > GK_RC_BOISSIER) return fail(GK_EINVAL, "unknown rotation curve");
-    if (d.reserved != 0) return fail(GK_EINVAL, "reserved field must be 0");
+    if (d.conv_mode < GK_CONV_AUTO || d.conv_mode > GK_CONV_FFT)
+        return fail(GK_EINVAL, "unknown convolution mode %d", d.conv_mode);
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
         return fail(GK_EINVAL, "no HIP device %d", device);
@@ -313,9 +477,20 @@ gk_status gk_create_model(const gk_model_desc *desc, int device, gk_model **out)
         wz[4 * (size_t)zp + 2] = w2 / u;
     }
     choose_tile(m);
-    if (m->lds_bytes > kMaxLds) {
+    const bool direct_ok = m->lds_bytes <= kMaxLds;
+    if (d.conv_mode == GK_CONV_DIRECT && !direct_ok) {
         delete m;
         return fail(GK_EINVAL, "PSF too wide for the direct convolution path");
+    }
+    m->use_fft = d.conv_mode == GK_CONV_FFT ||
+                 (d.conv_mode == GK_CONV_AUTO && (!direct_ok || m->hp > kMaxFastHalo));
+    std::vector<double2> twx, twy;
+    std::vector<double> kbx, kby;
+    if (m->use_fft) {
+        if (!setup_fft(m, kp, twx, twy, kbx, kby)) {
+            delete m;
+            return fail(GK_EINVAL, "model grid too large for the FFT convolution path");
+        }
     }
 
     DeviceGuard g(device);
@@ -326,6 +501,21 @@ gk_status gk_create_model(const gk_model_desc *desc, int device, gk_model **out)
         e = hipMemcpy(m->d_kp, kp.data(), kp.size() * sizeof(double), hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = hipMemcpy(m->d_wz, wz.data(), wz.size() * sizeof(double), hipMemcpyHostToDevice);
+    if (m->use_fft) {
+        auto up = [&](auto **dst, const auto &v) {
+            if (e == hipSuccess) e = dev_alloc(dst, v.size());
+            if (e == hipSuccess)
+                e = hipMemcpy(*dst, v.data(), v.size() * sizeof(v[0]), hipMemcpyHostToDevice);
+        };
+        up(&m->d_twx, twx);
+        up(&m->d_twy, twy);
+        up(&m->d_kbx, kbx);
+        up(&m->d_kby, kby);
+        m->fft.twx = m->d_twx;
+        m->fft.twy = m->d_twy;
+        m->fft.kbx = m->d_kbx;
+        m->fft.kby = m->d_kby;
+    }
     if (e != hipSuccess) {
         m->release();
         delete m;
@@ -458,6 +648,7 @@ gk_status gk_set_observation(gk_model *m, const float *vel, const float *sig, co
     HIP_TRY(hipMemcpy(m->d_mask, mk.data(), n, hipMemcpyHostToDevice));
     m->nvalid = nv;
     m->has_obs = true;
+    m->drop_graphs();  // recorded chains hold the observation's pointers and count
     return GK_OK;
 }
 

@@ -99,6 +99,25 @@ hipError_t launch_line_sums(const double *consts, const double *wz, int NZE, int
                             int hp, int u, int rc, double vf0, double inv_dvf, double *T,
                             unsigned long long *support_count, int B, hipStream_t s);
 hipError_t launch_psf_moments(const PsfArgs &a, int B, size_t lds_bytes, hipStream_t s);
+
+// FFT path of the spatial convolution (gbk_fft.hip): k_fft_x convolves every
+// line of the T planes along x into U [B][3][EY][NXF]; k_fft_y_moments
+// convolves columns of U along y and forms block sums, moments and chi2
+// partials [B][ncb] (one per block of DC data columns).
+struct FftArgs {
+    const double *T;      // [B][3][EY][EX]
+    double *U;            // [B][3][EY][NXF]
+    int EX, EY, NXF, hp;
+    int PX, PY, logPX, logPY;
+    int NLX;              // complex lines per k_fft_x block
+    int DC, ncb;          // data columns per k_fft_y_moments block, number of such blocks
+    const double2 *twx, *twy;  // exp(-2 pi i k / P), k < P / 2
+    const double *kbx, *kby;   // PSF spectra / P, bit-reversed order
+};
+size_t fft_x_lds_bytes(const FftArgs &f);
+size_t fft_y_lds_bytes(const FftArgs &f, int u);
+hipError_t launch_fft_x(const FftArgs &f, int B, hipStream_t s);
+hipError_t launch_fft_y_moments(const FftArgs &f, const PsfArgs &a, int B, hipStream_t s);
 hipError_t launch_reduce_chi2(const double *partial, int ntiles, const double *consts,
                               int64_t nvalid_obs, double *chi2, int64_t *nvalid, int B,
                               hipStream_t s);

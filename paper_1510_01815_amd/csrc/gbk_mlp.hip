@@ -36,15 +36,27 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 namespace {
 
-constexpr int GBM = 128, GBN = 128, GBK = 32, LDK = GBK + 8;  // LDS rows padded by 16 bytes
 constexpr int kInPad = 32;
 constexpr float kVelScale = 300.0f, kSigScale = 100.0f;
 constexpr int kRedBlocks = 256;
+constexpr int GBK = 64, LDK = GBK + 8;  // K depth of a stage; LDS rows padded by 16 bytes
 
 enum Epi {
     EPI_F32 = 0,    // C (f32) = acc + bias
     EPI_GELU = 1,   // Z (f32, if not NULL) = acc + bias, H (bf16) = gelu(acc + bias)
     EPI_DGELU = 2,  // H (bf16) = acc * gelu'(Z)
+    EPI_CHI2 = 3,   // per-row partial chi2 of (acc + bias) scaled to maps against an observation
+};
+
+// observation terms of the fused chi2 epilogue: column n < npix is the velocity
+// map at pixel n, n >= npix the dispersion map at pixel n - npix
+struct ObsArgs {
+    const uint8_t *mask;
+    const float *vo, *so;
+    const double *iev, *ies;
+    int npix;
+    double *partial;  // [M][nparts]
+    int nparts;
 };
 
 struct GemmArgs {
@@ -56,6 +68,7 @@ struct GemmArgs {
     float *Z;           // EPI_GELU pre-activation out, EPI_DGELU pre-activation in
     bf16 *H;            // bf16 output
     int ldc;
+    ObsArgs obs;
 };
 
 __device__ inline float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
@@ -65,99 +78,199 @@ __device__ inline float gelu_grad(float z)
            z * expf(-0.5f * z * z) * 0.39894228040143268f;
 }
 
-// stages the 128 x 32 block (rows r0.., k0..) of X(row, k) into S[row][k]:
-// trans == false: X(row, k) = X[row * ldx + k]; true: X[k * ldx + row]
-__device__ inline void stage_tile(const bf16 *__restrict__ X, int ldx, int rows, bool trans, int r0,
-                                  int k0, bf16 *__restrict__ S, int tid)
+// Global -> registers for one stage: the R x 64 block (rows r0.., k0..) of
+// X(row, k), X(row, k) = X[row * ldx + k] (TR false) or X[k * ldx + row] (TR
+// true), as uint4 chunks of 8 bf16; out-of-range elements are zero.
+template <int R, bool TR>
+__device__ inline void load_stage(const uint16_t *__restrict__ X, int ldx, int rows, int K, int r0,
+                                  int k0, uint4 (&reg)[R / 32], int tid)
 {
-    const bf16 zero = (bf16)0.0f;
-    if (!trans) {  // thread -> row tid / 2, 16 consecutive k
-        const int r = tid >> 1, kh = (tid & 1) * 16, row = r0 + r;
-        bf16 *dst = S + r * LDK + kh;
-        if (row < rows) {
-            const uint4 *src = reinterpret_cast<const uint4 *>(X + (size_t)row * ldx + k0 + kh);
-            const uint4 a = src[0], b = src[1];
-            reinterpret_cast<uint4 *>(dst)[0] = a;
-            reinterpret_cast<uint4 *>(dst)[1] = b;
-        } else {
-            const uint4 z = {0u, 0u, 0u, 0u};
-            reinterpret_cast<uint4 *>(dst)[0] = z;
-            reinterpret_cast<uint4 *>(dst)[1] = z;
-        }
-    } else {  // thread -> k tid / 8, 16 consecutive rows
-        const int kk = tid >> 3, rc = (tid & 7) * 16;
-        const bf16 *src = X + (size_t)(k0 + kk) * ldx + r0 + rc;
-        bf16 v[16];
-        if (r0 + rc + 16 <= rows) {
-            reinterpret_cast<uint4 *>(v)[0] = reinterpret_cast<const uint4 *>(src)[0];
-            reinterpret_cast<uint4 *>(v)[1] = reinterpret_cast<const uint4 *>(src)[1];
-        } else {
 #pragma unroll
-            for (int j = 0; j < 16; ++j) v[j] = (r0 + rc + j < rows) ? src[j] : zero;
-        }
+    for (int i = 0; i < R / 32; ++i) {
+        const int c = tid + i * 256;
+        if (!TR) {  // chunk = 8 consecutive k of one row
+            const int row = c >> 3, kc = (c & 7) * 8;
+            const bool ok = r0 + row < rows && k0 + kc < K;
+            reg[i] = ok ? *reinterpret_cast<const uint4 *>(X + (size_t)(r0 + row) * ldx + k0 + kc)
+                        : uint4{0u, 0u, 0u, 0u};
+        } else {  // chunk = 8 consecutive rows of one k
+            const int kk = c / (R / 8), rc = (c % (R / 8)) * 8;
+            const uint16_t *src = X + (size_t)(k0 + kk) * ldx + r0 + rc;
+            if (k0 + kk >= K) {
+                reg[i] = uint4{0u, 0u, 0u, 0u};
+            } else if (r0 + rc + 8 <= rows) {
+                reg[i] = *reinterpret_cast<const uint4 *>(src);
+            } else {
+                uint16_t v[8];
 #pragma unroll
-        for (int j = 0; j < 16; ++j) S[(rc + j) * LDK + kk] = v[j];
+                for (int j = 0; j < 8; ++j) v[j] = (r0 + rc + j < rows) ? src[j] : (uint16_t)0;
+                reg[i] = *reinterpret_cast<const uint4 *>(v);
+            }
+        }
     }
 }
 
-template <bool TA, bool TB, int EPI>
+// registers -> LDS S[row][k] (row stride LDK)
+template <int R, bool TR>
+__device__ inline void store_stage(const uint4 (&reg)[R / 32], uint16_t *__restrict__ S, int tid)
+{
+#pragma unroll
+    for (int i = 0; i < R / 32; ++i) {
+        const int c = tid + i * 256;
+        if (!TR) {
+            const int row = c >> 3, kc = (c & 7) * 8;
+            *reinterpret_cast<uint4 *>(S + row * LDK + kc) = reg[i];
+        } else {
+            const int kk = c / (R / 8), rc = (c % (R / 8)) * 8;
+            const uint16_t *v = reinterpret_cast<const uint16_t *>(&reg[i]);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) S[(rc + j) * LDK + kk] = v[j];
+        }
+    }
+}
+
+// C[M][N] = sum_k A(m, k) B(n, k) on BM x BN tiles, 4 waves of (BM/2) x (BN/2).
+// The MFMA takes the B fragment as its row operand, so a lane's four results
+// are four consecutive columns n of one row m (vector stores in the epilogue).
+template <int BM, int BN, bool TA, bool TB, int EPI>
 __global__ __launch_bounds__(256) void k_gemm(GemmArgs g)
 {
-    __shared__ __attribute__((aligned(16))) bf16 As[GBM * LDK];
-    __shared__ __attribute__((aligned(16))) bf16 Bs[GBN * LDK];
+    constexpr int WM = BM / 2, WN = BN / 2, TM = WM / 16, TN = WN / 16;
+    __shared__ __attribute__((aligned(16))) uint16_t As[BM * LDK];
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[BN * LDK];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave & 1, wn = wave >> 1;
-    const int m0 = blockIdx.y * GBM, n0 = blockIdx.x * GBN;
-    f32x4 acc[4][4];
+    const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+    const uint16_t *A = reinterpret_cast<const uint16_t *>(g.A);
+    const uint16_t *B = reinterpret_cast<const uint16_t *>(g.B);
+    f32x4 acc[TM][TN];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < TM; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int j = 0; j < TN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
+    uint4 ra[BM / 32], rb[BN / 32];
+    load_stage<BM, TA>(A, g.lda, g.M, g.K, m0, 0, ra, tid);
+    load_stage<BN, TB>(B, g.ldb, g.N, g.K, n0, 0, rb, tid);
     for (int k0 = 0; k0 < g.K; k0 += GBK) {
-        stage_tile(g.A, g.lda, g.M, TA, m0, k0, As, tid);
-        stage_tile(g.B, g.ldb, g.N, TB, n0, k0, Bs, tid);
+        store_stage<BM, TA>(ra, As, tid);
+        store_stage<BN, TB>(rb, Bs, tid);
         __syncthreads();
-        bf16x8 af[4], bfr[4];
+        if (k0 + GBK < g.K) {  // the next stage's loads overlap this stage's products
+            load_stage<BM, TA>(A, g.lda, g.M, g.K, m0, k0 + GBK, ra, tid);
+            load_stage<BN, TB>(B, g.ldb, g.N, g.K, n0, k0 + GBK, rb, tid);
+        }
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-            af[i] = *reinterpret_cast<const bf16x8 *>(As + (wm * 64 + i * 16 + (lane & 15)) * LDK +
-                                                      (lane >> 4) * 8);
+        for (int kk = 0; kk < GBK; kk += 32) {
+            bf16x8 af[TM], bfr[TN];
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
-            bfr[j] = *reinterpret_cast<const bf16x8 *>(Bs + (wn * 64 + j * 16 + (lane & 15)) * LDK +
-                                                       (lane >> 4) * 8);
+            for (int i = 0; i < TM; ++i)
+                af[i] = *reinterpret_cast<const bf16x8 *>(
+                    As + (wm * WM + i * 16 + (lane & 15)) * LDK + kk + (lane >> 4) * 8);
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+            for (int j = 0; j < TN; ++j)
+                bfr[j] = *reinterpret_cast<const bf16x8 *>(
+                    Bs + (wn * WN + j * 16 + (lane & 15)) * LDK + kk + (lane >> 4) * 8);
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int j = 0; j < TN; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bfr[j], af[i], acc[i][j], 0, 0, 0);
+        }
         __syncthreads();
     }
-    // a lane holds rows 4 (lane / 16) + r, column lane % 16, of each 16 x 16 tile
+
+    // lane: row m = ... + lane % 16, columns n = ... + 4 (lane / 16) + r
+    double row_chi2[TM];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < TM; ++i) row_chi2[i] = 0.0;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int n = n0 + wn * 64 + j * 16 + (lane & 15);
-            if (n >= g.N) continue;
-            const float bn = g.bias ? g.bias[n] : 0.0f;
+    for (int i = 0; i < TM; ++i) {
+        const int m = m0 + wm * WM + i * 16 + (lane & 15);
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int m = m0 + wm * 64 + i * 16 + (lane >> 4) * 4 + r;
-                if (m >= g.M) continue;
-                const size_t o = (size_t)m * g.ldc + n;
-                if (EPI == EPI_F32) {
-                    g.C[o] = acc[i][j][r] + bn;
-                } else if (EPI == EPI_GELU) {
-                    const float z = acc[i][j][r] + bn;
-                    if (g.Z) g.Z[o] = z;
-                    g.H[o] = (bf16)gelu(z);
+        for (int j = 0; j < TN; ++j) {
+            const int nb = n0 + wn * WN + j * 16 + 4 * (lane >> 4);
+            if (m >= g.M || nb >= g.N) continue;
+            float v[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) v[r] = acc[i][j][r];
+            const size_t o = (size_t)m * g.ldc + nb;
+            const bool full = nb + 4 <= g.N && (g.ldc & 3) == 0;
+            if (EPI == EPI_F32 || EPI == EPI_GELU || EPI == EPI_CHI2) {
+                if (g.bias)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) v[r] += (nb + r < g.N) ? g.bias[nb + r] : 0.0f;
+            }
+            if (EPI == EPI_F32) {
+                if (full) {
+                    *reinterpret_cast<float4 *>(g.C + o) = float4{v[0], v[1], v[2], v[3]};
                 } else {
-                    g.H[o] = (bf16)(acc[i][j][r] * gelu_grad(g.Z[o]));
+                    for (int r = 0; r < 4 && nb + r < g.N; ++r) g.C[o + r] = v[r];
+                }
+            } else if (EPI == EPI_GELU || EPI == EPI_DGELU) {
+                uint16_t hb[4];
+                if (EPI == EPI_GELU) {
+                    if (g.Z) {
+                        if (full) {
+                            *reinterpret_cast<float4 *>(g.Z + o) = float4{v[0], v[1], v[2], v[3]};
+                        } else {
+                            for (int r = 0; r < 4 && nb + r < g.N; ++r) g.Z[o + r] = v[r];
+                        }
+                    }
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const bf16 h = (bf16)gelu(v[r]);
+                        hb[r] = *reinterpret_cast<const uint16_t *>(&h);
+                    }
+                } else {
+                    float z[4];
+                    if (full) {
+                        const float4 zz = *reinterpret_cast<const float4 *>(g.Z + o);
+                        z[0] = zz.x, z[1] = zz.y, z[2] = zz.z, z[3] = zz.w;
+                    } else {
+                        for (int r = 0; r < 4; ++r) z[r] = (nb + r < g.N) ? g.Z[o + r] : 0.0f;
+                    }
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const bf16 h = (bf16)(v[r] * gelu_grad(z[r]));
+                        hb[r] = *reinterpret_cast<const uint16_t *>(&h);
+                    }
+                }
+                uint16_t *H = reinterpret_cast<uint16_t *>(g.H);
+                if (full) {
+                    *reinterpret_cast<uint2 *>(H + o) = *reinterpret_cast<const uint2 *>(hb);
+                } else {
+                    for (int r = 0; r < 4 && nb + r < g.N; ++r) H[o + r] = hb[r];
+                }
+            } else {  // EPI_CHI2: the maps as gk_surrogate_predict returns them (FP32 scaling)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int n = nb + r;
+                    if (n >= g.N) continue;
+                    const bool vel = n < g.obs.npix;
+                    const int p = vel ? n : n - g.obs.npix;
+                    if (!g.obs.mask[p]) continue;
+                    const float y = v[r] * (vel ? kVelScale : kSigScale);
+                    const double d = ((double)y - (vel ? g.obs.vo[p] : g.obs.so[p])) *
+                                     (vel ? g.obs.iev[p] : g.obs.ies[p]);
+                    row_chi2[i] += d * d;
                 }
             }
         }
+    }
+    if (EPI == EPI_CHI2) {
+        // lanes l, l ^ 16, l ^ 32, l ^ 48 hold the same row: sum them, then one
+        // partial per (row, block column, wave column), no atomics
+        const int part = blockIdx.x * 2 + wn;
+#pragma unroll
+        for (int i = 0; i < TM; ++i) {
+            double c = row_chi2[i];
+            c += __shfl_xor(c, 16, 64);
+            c += __shfl_xor(c, 32, 64);
+            const int m = m0 + wm * WM + i * 16 + (lane & 15);
+            if (lane < 16 && m < g.M) g.obs.partial[(size_t)m * g.obs.nparts + part] = c;
+        }
+    }
 }
 
 // uniform draws of parameter rows in the box: slot s = lo_s + u (hi_s - lo_s),
@@ -316,39 +429,21 @@ __global__ void k_to_bf16(const float *__restrict__ a, bf16 *__restrict__ b, siz
     if (i < n) b[i] = (bf16)a[i];
 }
 
-// chi2 of predicted maps against the observation (one row per block), INF for
-// rows outside the parameter domain
-__global__ __launch_bounds__(256) void k_surrogate_chi2(const float *__restrict__ y, int npix,
-                                                        const uint8_t *__restrict__ mask,
-                                                        const float *__restrict__ vo,
-                                                        const float *__restrict__ so,
-                                                        const double *__restrict__ iev,
-                                                        const double *__restrict__ ies,
-                                                        const double *__restrict__ params, int rc,
-                                                        double *__restrict__ chi2)
+// chi2[m] = sum of the row's epilogue partials in a fixed order; +INF for rows
+// outside the parameter domain
+__global__ void k_chi2_finish(const double *__restrict__ partial, int nparts, int M,
+                              const double *__restrict__ params, int rc, double *__restrict__ chi2)
 {
-    const int b = blockIdx.x;
-    const float *yb = y + (size_t)b * 2 * npix;
-    double acc = 0.0;
-    for (int i = threadIdx.x; i < npix; i += 256) {
-        if (!mask[i]) continue;
-        // the maps as gk_surrogate_predict returns them (scaled in FP32)
-        const double rv = ((double)(yb[i] * kVelScale) - vo[i]) * iev[i];
-        const double rs = ((double)(yb[npix + i] * kSigScale) - so[i]) * ies[i];
-        acc += rv * rv + rs * rs;
-    }
-    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
-    __shared__ double ws[4];
-    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = acc;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const double *p = params + (size_t)b * NPAR;
-        bool ok = true;
-        for (int s = 0; s < NPAR; ++s) ok = ok && isfinite(p[s]);
-        ok = ok && p[P_INC] > 0.0 && p[P_INC] < 90.0 && p[P_SIG] > 0.0 && p[P_R0] > 0.0 &&
-             p[P_RT] > 0.0 && (rc != RC_EPINAT || p[P_G] > 0.0);
-        chi2[b] = ok ? ((ws[0] + ws[1]) + ws[2]) + ws[3] : __builtin_inf();
-    }
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= M) return;
+    double c = 0.0;
+    for (int j = 0; j < nparts; ++j) c += partial[(size_t)m * nparts + j];
+    const double *p = params + (size_t)m * NPAR;
+    bool ok = true;
+    for (int k = 0; k < NPAR; ++k) ok = ok && isfinite(p[k]);
+    ok = ok && p[P_INC] > 0.0 && p[P_INC] < 90.0 && p[P_SIG] > 0.0 && p[P_R0] > 0.0 &&
+         p[P_RT] > 0.0 && (rc != RC_EPINAT || p[P_G] > 0.0);
+    chi2[m] = ok ? c : __builtin_inf();
 }
 
 __global__ void k_scale_maps(const float *__restrict__ y, int npix, size_t n, float *__restrict__ maps)
@@ -359,20 +454,35 @@ __global__ void k_scale_maps(const float *__restrict__ y, int npix, size_t n, fl
     maps[i] = y[i] * (r < (size_t)npix ? kVelScale : kSigScale);
 }
 
-bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }  // NULL passes
+
+// Tile edge for an M x N product: 128 when that still gives two tiles per
+// compute unit, else 64 (more, smaller tiles for the narrow layers).
+int gemm_tile(int M, int N)
+{
+    const long t = (long)((M + 127) / 128) * ((N + 127) / 128);
+    return t >= 512 ? 128 : 64;
+}
 
 template <bool TA, bool TB, int EPI> gk_status gemm(const GemmArgs &g, hipStream_t s)
 {
-    if (g.M <= 0 || g.N <= 0 || g.K <= 0 || g.K % GBK || g.lda % 8 || g.ldb % 8 ||
-        !aligned16(g.A) || !aligned16(g.B))
-        return fail(GK_EINVAL, "GEMM shape %dx%dx%d (lda %d, ldb %d) not supported", g.M, g.N,
-                    g.K, g.lda, g.ldb);
-    if ((TA ? g.lda < g.M : g.lda < g.K) || (TB ? g.ldb < g.N : g.ldb < g.K) || g.ldc < g.N)
+    if (g.M <= 0 || g.N <= 0 || g.K <= 0 || g.K % 32 || g.lda % 8 || g.ldb % 8 ||
+        !aligned16(g.A) || !aligned16(g.B) || !aligned16(g.C) || !aligned16(g.Z) || !aligned16(g.H))
+        return fail(GK_EINVAL, "GEMM shape %dx%dx%d (lda %d, ldb %d) or alignment not supported",
+                    g.M, g.N, g.K, g.lda, g.ldb);
+    if ((TA ? g.lda < g.M : g.lda < g.K) || (TB ? g.ldb < g.N : g.ldb < g.K) ||
+        (EPI != EPI_CHI2 && g.ldc < g.N))
         return fail(GK_EINVAL, "GEMM leading dimension too small");
-    const int gy = (g.M + GBM - 1) / GBM;
+    const int T = gemm_tile(g.M, g.N);
+    const int gy = (g.M + T - 1) / T;
     if (gy > 65535) return fail(GK_EINVAL, "GEMM M = %d too large", g.M);
-    dim3 grid((g.N + GBN - 1) / GBN, gy);
-    hipLaunchKernelGGL((k_gemm<TA, TB, EPI>), grid, dim3(256), 0, s, g);
+    dim3 grid((g.N + T - 1) / T, gy);
+    if (EPI == EPI_CHI2 && g.obs.nparts != 2 * (int)grid.x)
+        return fail(GK_EINVAL, "chi2 partial count mismatch");
+    if (T == 128)
+        hipLaunchKernelGGL((k_gemm<128, 128, TA, TB, EPI>), grid, dim3(256), 0, s, g);
+    else
+        hipLaunchKernelGGL((k_gemm<64, 64, TA, TB, EPI>), grid, dim3(256), 0, s, g);
     HIP_TRY(hipGetLastError());
     return GK_OK;
 }
@@ -405,6 +515,7 @@ struct gk_surrogate {
     float *Y = nullptr, *T = nullptr, *Mask = nullptr, *maps = nullptr, *d_loss = nullptr;
     unsigned *cnt = nullptr;
     double *d_params = nullptr, *h_params = nullptr, *d_partial = nullptr;
+    double *d_cpart = nullptr;  // [cap][2 ceil(nout / 64)] chi2 partials of the output layer
     hipEvent_t ev_staged = nullptr;  // recorded after the last copy out of h_params
     int loss_cap = 0;
 
@@ -432,6 +543,7 @@ struct gk_surrogate {
         F(cnt);
         F(d_params);
         F(d_partial);
+        F(d_cpart);
         if (h_params) {
             if (ev_staged) (void)hipEventSynchronize(ev_staged);
             (void)hipHostFree(h_params);
@@ -439,7 +551,7 @@ struct gk_surrogate {
         X = dY = nullptr;
         Y = T = Mask = maps = nullptr;
         cnt = nullptr;
-        d_params = h_params = d_partial = nullptr;
+        d_params = h_params = d_partial = d_cpart = nullptr;
         cap = 0;
     }
     void release()
@@ -487,12 +599,13 @@ gk_status reserve_rows(gk_surrogate *s, int rows)
     HIP_TRY(hipMalloc((void **)&s->d_params, R * NPAR * sizeof(double)));
     HIP_TRY(hipHostMalloc((void **)&s->h_params, R * NPAR * sizeof(double), 0));
     HIP_TRY(hipMalloc((void **)&s->d_partial, kRedBlocks * sizeof(double)));
+    HIP_TRY(hipMalloc((void **)&s->d_cpart, R * 2 * ((no + 63) / 64) * sizeof(double)));
     s->cap = rows;
     return GK_OK;
 }
 
-// forward pass of M rows whose inputs are in s->X; keeps pre-activations if `keep`
-gk_status forward(gk_surrogate *s, int M, bool keep, hipStream_t st)
+// hidden layers of M rows whose inputs are in s->X; keeps pre-activations if `keep`
+gk_status hidden_layers(gk_surrogate *s, int M, bool keep, hipStream_t st)
 {
     const bf16 *h = s->X;
     int in = kInPad;
@@ -503,9 +616,21 @@ gk_status forward(gk_surrogate *s, int M, bool keep, hipStream_t st)
         h = s->H[l];
         in = s->o.hidden;
     }
-    const int L = s->layers;
-    GemmArgs g{h, s->Wb[L], in, in, M, s->nout, in, s->b[L], s->Y, nullptr, nullptr, s->nout};
+    return GK_OK;
+}
+
+// output layer into s->Y (scaled maps)
+gk_status output_layer(gk_surrogate *s, int M, hipStream_t st)
+{
+    const int L = s->layers, in = s->o.hidden;
+    GemmArgs g{s->H[L - 1], s->Wb[L], in, in, M, s->nout, in, s->b[L], s->Y, nullptr, nullptr, s->nout};
     return gemm<false, false, EPI_F32>(g, st);
+}
+
+gk_status forward(gk_surrogate *s, int M, bool keep, hipStream_t st)
+{
+    GK_TRY(hidden_layers(s, M, keep, st));
+    return output_layer(s, M, st);
 }
 
 // targets from the plain evaluation of the rows in s->d_params, loss gradient,
@@ -580,12 +705,33 @@ gk_status stage_params(gk_surrogate *s, const double *params, int B, hipStream_t
     return GK_OK;
 }
 
-gk_status infer(gk_surrogate *s, int B, hipStream_t st)
+// inference chunk: rows per pass through the network
+int infer_chunk(const gk_surrogate *s) { return std::max(s->o.batch, 2048); }
+
+gk_status encode_rows(gk_surrogate *s, int B, hipStream_t st)
 {
     hipLaunchKernelGGL(k_encode, dim3(blocks(B, 64)), dim3(64), 0, st, s->d_params, B, s->d_lo,
                        s->d_hi, s->X);
     HIP_TRY(hipGetLastError());
-    return forward(s, B, false, st);
+    return GK_OK;
+}
+
+// surrogate chi2 of the B rows in s->d_params against m's observation: the
+// output layer reduces its own residuals, so the maps never reach memory
+gk_status infer_chi2(gk_surrogate *s, gk_model *m, int B, double *chi2, hipStream_t st)
+{
+    GK_TRY(encode_rows(s, B, st));
+    GK_TRY(hidden_layers(s, B, false, st));
+    const int L = s->layers, in = s->o.hidden;
+    const int T = gemm_tile(B, s->nout);
+    ObsArgs ob{m->d_mask, m->d_vo, m->d_so, m->d_iev, m->d_ies, s->npix, s->d_cpart,
+               2 * ((s->nout + T - 1) / T)};
+    GemmArgs g{s->H[L - 1], s->Wb[L], in, in, B, s->nout, in, s->b[L], nullptr, nullptr, nullptr, 0, ob};
+    GK_TRY((gemm<false, false, EPI_CHI2>(g, st)));
+    hipLaunchKernelGGL(k_chi2_finish, dim3(blocks(B)), dim3(256), 0, st, s->d_cpart, ob.nparts, B,
+                       s->d_params, m->d.rc, chi2);
+    HIP_TRY(hipGetLastError());
+    return GK_OK;
 }
 
 }  // namespace
@@ -596,14 +742,10 @@ gk_status infer(gk_surrogate *s, int B, hipStream_t st)
 gk_status gbk::surrogate_chi2(gk_surrogate *s, gk_model *obs, const double *d_params, int B,
                               double *d_chi2, hipStream_t st)
 {
-    for (int r0 = 0; r0 < B; r0 += s->o.batch) {
-        const int n = std::min(s->o.batch, B - r0);
+    for (int r0 = 0; r0 < B; r0 += infer_chunk(s)) {
+        const int n = std::min(infer_chunk(s), B - r0);
         GK_TRY(stage_params(s, d_params + (size_t)r0 * NPAR, n, st));
-        GK_TRY(infer(s, n, st));
-        hipLaunchKernelGGL(k_surrogate_chi2, dim3(n), dim3(256), 0, st, s->Y, s->npix, obs->d_mask,
-                           obs->d_vo, obs->d_so, obs->d_iev, obs->d_ies, s->d_params, obs->d.rc,
-                           d_chi2 + r0);
-        HIP_TRY(hipGetLastError());
+        GK_TRY(infer_chi2(s, obs, n, d_chi2 + r0, st));
     }
     return GK_OK;
 }
@@ -857,10 +999,11 @@ gk_status gk_surrogate_predict(gk_surrogate *s, const double *params, int32_t B,
     DeviceGuard g(s->device);
     HIP_TRY(g.err);
     hipStream_t st = (hipStream_t)stream;
-    for (int r0 = 0; r0 < B; r0 += s->o.batch) {
-        const int n = std::min(s->o.batch, B - r0);
+    for (int r0 = 0; r0 < B; r0 += infer_chunk(s)) {
+        const int n = std::min(infer_chunk(s), B - r0);
         GK_TRY(stage_params(s, params + (size_t)r0 * NPAR, n, st));
-        GK_TRY(infer(s, n, st));
+        GK_TRY(encode_rows(s, n, st));
+        GK_TRY(forward(s, n, false, st));
         const size_t ne = (size_t)n * s->nout;
         hipLaunchKernelGGL(k_scale_maps, dim3(blocks(ne)), dim3(256), 0, st, s->Y, s->npix, ne,
                            maps + (size_t)r0 * s->nout);
@@ -883,13 +1026,10 @@ gk_status gk_surrogate_chi2(gk_surrogate *s, gk_model *m, const double *params, 
     DeviceGuard g(s->device);
     HIP_TRY(g.err);
     hipStream_t st = (hipStream_t)stream;
-    for (int r0 = 0; r0 < B; r0 += s->o.batch) {
-        const int n = std::min(s->o.batch, B - r0);
+    for (int r0 = 0; r0 < B; r0 += infer_chunk(s)) {
+        const int n = std::min(infer_chunk(s), B - r0);
         GK_TRY(stage_params(s, params + (size_t)r0 * NPAR, n, st));
-        GK_TRY(infer(s, n, st));
-        hipLaunchKernelGGL(k_surrogate_chi2, dim3(n), dim3(256), 0, st, s->Y, s->npix, m->d_mask,
-                           m->d_vo, m->d_so, m->d_iev, m->d_ies, s->d_params, m->d.rc, chi2 + r0);
-        HIP_TRY(hipGetLastError());
+        GK_TRY(infer_chi2(s, m, n, chi2 + r0, st));
     }
     return GK_OK;
 }

@@ -76,6 +76,11 @@ struct gk_model {
     int TXd = 0, TYd = 0, ntx = 0, nty = 0, ntiles = 0;
     size_t lds_bytes = 0;
     double *d_kp = nullptr, *d_wz = nullptr;
+    // FFT path of the spatial convolution (gbk_fft.hip)
+    bool use_fft = false;
+    gbk::FftArgs fft{};  // sizes, twiddles and spectra; T/U set per chunk
+    double2 *d_twx = nullptr, *d_twy = nullptr;
+    double *d_kbx = nullptr, *d_kby = nullptr, *d_U = nullptr;
     // observation
     bool has_obs = false;
     int64_t nvalid = 0;
@@ -95,10 +100,46 @@ struct gk_model {
     int64_t prof_rows = 0;
     // fitter workspace (gbk_fit.hip), created on first use
     gbk::FitWork *fit = nullptr;
+    // HIP graphs of repeated launch chains (run_batch); gen changes whenever a
+    // pointer or size baked into a recorded chain may have changed
+    struct GraphKey {
+        const void *params, *maps, *resid, *chi2, *nvalid;
+        hipStream_t stream;
+        int B;
+        uint64_t gen;
+        bool operator==(const GraphKey &o) const
+        {
+            return params == o.params && maps == o.maps && resid == o.resid && chi2 == o.chi2 &&
+                   nvalid == o.nvalid && stream == o.stream && B == o.B && gen == o.gen;
+        }
+    };
+    struct GraphEntry {
+        GraphKey key;
+        hipGraph_t graph;
+        hipGraphExec_t exec;
+    };
+    int launch_mode = GK_LAUNCH_GRAPH;
+    uint64_t gen = 0;
+    std::vector<GraphEntry> graphs;  // at most kMaxGraphs, oldest first
+    std::vector<GraphKey> seen;      // keys met once, not yet recorded
+    int64_t graph_launches = 0;
+
+    void drop_graphs()
+    {
+        if (!graphs.empty()) (void)hipDeviceSynchronize();  // a replay may still run
+        for (auto &g : graphs) {
+            (void)hipGraphExecDestroy(g.exec);
+            (void)hipGraphDestroy(g.graph);
+        }
+        graphs.clear();
+        seen.clear();
+        ++gen;
+    }
 
     int chunk_rows() const
     {
         size_t per = (size_t)3 * EX * EY * sizeof(double);
+        if (use_fft) per += (size_t)3 * EY * NX * sizeof(double);
         size_t n = std::max<size_t>(1, gbk::kScratchBudget / per);
         return (int)std::min<size_t>(n, 65535);
     }
@@ -111,15 +152,17 @@ struct gk_model {
     hipError_t reserve(int rows)
     {
         if (rows <= cap) return hipSuccess;
+        drop_graphs();
         (void)hipFree(d_params);
         (void)hipFree(d_consts);
         (void)hipFree(d_T);
         (void)hipFree(d_partial);
+        (void)hipFree(d_U);
         if (h_params) {
             if (ev_staged) (void)hipEventSynchronize(ev_staged);
             (void)hipHostFree(h_params);
         }
-        d_params = d_consts = d_T = d_partial = h_params = nullptr;
+        d_params = d_consts = d_T = d_partial = h_params = d_U = nullptr;
         cap = 0;
         hipError_t e;
         if (!ev_staged && (e = hipEventCreateWithFlags(&ev_staged, hipEventDisableTiming)) != hipSuccess)
@@ -130,6 +173,7 @@ struct gk_model {
         if ((e = gbk::dev_alloc(&d_consts, (size_t)rows * gbk::NCONST)) != hipSuccess) return e;
         if ((e = gbk::dev_alloc(&d_T, (size_t)rows * 3 * EX * EY)) != hipSuccess) return e;
         if ((e = gbk::dev_alloc(&d_partial, (size_t)rows * ntiles)) != hipSuccess) return e;
+        if (use_fft && (e = gbk::dev_alloc(&d_U, (size_t)rows * 3 * EY * NX)) != hipSuccess) return e;
         cap = rows;
         return hipSuccess;
     }
@@ -147,6 +191,12 @@ struct gk_model {
         (void)hipFree(d_consts);
         (void)hipFree(d_T);
         (void)hipFree(d_partial);
+        (void)hipFree(d_U);
+        (void)hipFree(d_twx);
+        (void)hipFree(d_twy);
+        (void)hipFree(d_kbx);
+        (void)hipFree(d_kby);
+        drop_graphs();
         gbk::fit_release(fit);
         fit = nullptr;
         if (h_params) (void)hipHostFree(h_params);

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(PKG, "libgbk.so")
 GK_OK, GK_PARTIAL, GK_EINVAL, GK_ENOMEM, GK_EDEVICE, GK_ENOTCONV, GK_ESTATE = 0, 1, -1, -2, -3, -4, -5
 NPAR = 12
 RC = {"arctan": 0, "epinat": 1, "boissier": 2}
+CONV = {"auto": 0, "direct": 1, "fft": 2}
 
 # exported symbols, kept in step with include/gbk.h
 SYMBOLS = (
@@ -30,7 +31,8 @@ SYMBOLS = (
     "gk_surrogate_default_opts", "gk_surrogate_create", "gk_surrogate_destroy",
     "gk_surrogate_train", "gk_surrogate_weight_count", "gk_surrogate_get_weights",
     "gk_surrogate_set_weights", "gk_surrogate_gradients", "gk_surrogate_predict",
-    "gk_surrogate_chi2", "gk_fit_nested_screened", "gk_gemm_bf16",
+    "gk_surrogate_chi2", "gk_fit_nested_screened", "gk_gemm_bf16", "gk_model_conv_path",
+    "gk_set_launch_mode", "gk_graph_launches",
 )
 LM_REASONS = {1: "ftol", 2: "xtol", 3: "lambda", 4: "maxiter"}
 GK_PROF_TIMING, GK_PROF_COUNT = 1, 2
@@ -48,7 +50,7 @@ class ModelDesc(ctypes.Structure):
                 ("v0_kms", ctypes.c_double), ("crpix", ctypes.c_double),
                 ("psf_fwhm_pix", ctypes.c_double), ("lsf_sigma_kms", ctypes.c_double),
                 ("kernel_radius_sigma", ctypes.c_double), ("rc", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("conv_mode", ctypes.c_int32)]
 
 
 class ProfileStats(ctypes.Structure):
@@ -216,6 +218,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.gk_fit_nested_screened.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.POINTER(NSOpts), dp, dp,
                                          ctypes.POINTER(NSResult), vp, ctypes.c_int64, i64p]
     L.gk_gemm_bf16.argtypes = [i32, i32, i32, i32, i32, vp, i32, vp, i32, vp, i32, vp]
+    L.gk_model_conv_path.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
+    L.gk_set_launch_mode.argtypes = [vp, ctypes.c_int32]
+    L.gk_graph_launches.argtypes = [vp, i64p]
     L.gk_last_error.restype = ctypes.c_char_p
     for name in SYMBOLS:
         if name == "gk_surrogate_weight_count":
@@ -259,22 +264,24 @@ class Model:
     """One instrument grid on one device; see gk_create_model."""
 
     def __init__(self, nx, ny, nz, dv, psf_fwhm=0.0, lsf_sigma=0.0, u=1, v0=0.0, crpix=None,
-                 R=4.0, rc=0, device=0):
+                 R=4.0, rc=0, device=0, conv="auto"):
         L = load()
         if isinstance(rc, str):
             rc = RC[rc]
+        if isinstance(conv, str):
+            conv = CONV[conv]
         self.desc = ModelDesc(nx, ny, nz, u, dv, v0, nz / 2.0 if crpix is None else crpix,
-                              psf_fwhm, lsf_sigma, R, rc, 0)
+                              psf_fwhm, lsf_sigma, R, rc, conv)
         self.nx, self.ny, self.nz, self.device = nx, ny, nz, device
         h = ctypes.c_void_p()
         _check(L.gk_create_model(ctypes.byref(self.desc), device, ctypes.byref(h)))
         self._h = h
 
     @classmethod
-    def from_grid(cls, grid, device=0):
+    def from_grid(cls, grid, device=0, conv="auto"):
         d = grid.as_dict() if hasattr(grid, "as_dict") else dict(grid)
         return cls(d["nx"], d["ny"], d["nz"], d["dv"], d["psf_fwhm"], d["lsf_sigma"], d["u"],
-                   d["v0"], d["crpix"], d["R"], d["rc"], device)
+                   d["v0"], d["crpix"], d["R"], d["rc"], device, conv)
 
     def close(self):
         if getattr(self, "_h", None):
@@ -305,6 +312,21 @@ class Model:
 
     def set_obs(self, obs):
         self.set_observation(obs.vel, obs.sig, obs.evel, obs.esig, obs.mask, obs.W)
+
+    def set_launch_mode(self, mode: str) -> None:
+        """"graph" (default: repeated device-row calls replay a HIP graph) or "eager"."""
+        _check(load().gk_set_launch_mode(self._h, {"eager": 0, "graph": 1}[mode]))
+
+    def graph_launches(self) -> int:
+        n = ctypes.c_int64()
+        _check(load().gk_graph_launches(self._h, ctypes.byref(n)))
+        return n.value
+
+    def conv_path(self) -> str:
+        """"direct" or "fft": the spatial convolution the model runs."""
+        c = ctypes.c_int32()
+        _check(load().gk_model_conv_path(self._h, ctypes.byref(c)))
+        return {1: "direct", 2: "fft"}[c.value]
 
     def n_valid(self) -> int:
         n = ctypes.c_int64()

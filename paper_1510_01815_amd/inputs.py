@@ -190,6 +190,30 @@ def c5_grid() -> Grid:
     return Grid(64, 64, 64, 30.0, psf_fwhm=2.5, lsf_sigma=30.0, rc=RC_ARCTAN)
 
 
+def c5_box() -> tuple[np.ndarray, np.ndarray]:
+    """Prior box of the surrogate workload (the single-galaxy box on a 64 px
+    grid, PSF FWHM 2.5): the training range of the surrogate and the nested
+    sampler's prior; a and g are fixed at 1 (arctan curve)."""
+    lo = np.array([25.6, 25.6, 0.0, 5.0, -50.0, 50.0, 1.25, 20.0, 2.5, 0.5, 1.0, 1.0])
+    hi = np.array([38.4, 38.4, 360.0, 85.0, 50.0, 300.0, 5.0, 100.0, 7.5, 2.0, 1.0, 1.0])
+    return lo, hi
+
+
+C5_FREE = (1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 0, 0)
+
+
+def c5_galaxy(k: int) -> np.ndarray:
+    """Truth of galaxy k: drawn in the box, with PA kept 20 deg away from the
+    box ends so that no posterior straddles the 0/360 cut."""
+    rng = rng_for(5, k, 0)
+    lo, hi = c5_box()
+    p = lo + rng.random(NPAR) * (hi - lo)
+    p[PA] = rng.uniform(20.0, 340.0)
+    p[VSYS] = rng.uniform(-20.0, 20.0)
+    p[I0] = 1.0
+    return p
+
+
 # --------------------------------------------------------------------------
 # Observations from model maps computed by the caller
 # --------------------------------------------------------------------------

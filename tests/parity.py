@@ -21,15 +21,16 @@ def oracle_desc(O, grid: dict):
                   R=grid["R"], rc=grid["rc"])
 
 
-def bright(ref_m0: np.ndarray) -> np.ndarray:
+def bright(ref_m0: np.ndarray, frac: float = 1e-12) -> np.ndarray:
     mx = np.nanmax(ref_m0)
-    return ref_m0 >= 1e-12 * mx
+    return ref_m0 >= frac * mx
 
 
-def assert_maps_close(gpu: np.ndarray, ref: np.ndarray, what: str = ""):
-    """gpu, ref: [3][ny][nx]; ref is the FP64 oracle."""
+def assert_maps_close(gpu: np.ndarray, ref: np.ndarray, what: str = "", bright_frac: float = 1e-12):
+    """gpu, ref: [3][ny][nx]; ref is the FP64 oracle.  Parity is checked where
+    the oracle's flux is at least bright_frac of its maximum."""
     gpu = np.asarray(gpu, dtype=np.float64)
-    b = bright(ref[0])
+    b = bright(ref[0], bright_frac)
     assert np.isfinite(gpu).all(), f"{what}: non-finite GPU map values"
     d0 = np.abs(gpu[0] - ref[0])
     tol0 = M0_REL * np.abs(ref[0])
