@@ -428,6 +428,27 @@ gk_status gk_set_launch_mode(gk_model *model, int32_t mode);
 /* graph replays made by the model so far */
 gk_status gk_graph_launches(const gk_model *model, int64_t *count);
 
+/* ---- Launch-shape autotuner ------------------------------------------------
+ * Times every spatial-convolution configuration the model can run -- the FFT
+ * path and direct data tiles of 32x32, 64x32 (the register-blocked u = 1
+ * kernel when it applies), 32x16, 16x16, 32x8, 16x8, 8x8 and 64x16 -- on
+ * `batch` synthetic rows (a disc centred in the window; chi2 if the model
+ * has an observation, maps otherwise), best of three launches each after a
+ * warm-up, and keeps the fastest.  A model created with GK_CONV_DIRECT or
+ * GK_CONV_FFT only tries that path.  Frees the row scratch; blocks. */
+typedef struct {
+    int32_t conv_mode;      /* chosen: GK_CONV_DIRECT or GK_CONV_FFT */
+    int32_t tile_x, tile_y; /* chosen data tile of the direct path (0 for FFT) */
+    int32_t n_candidates;   /* configurations timed */
+    double ms_best;         /* its time per batch */
+    double ms[16];          /* per candidate in the order above, -1 if it did not fit */
+} gk_tune_result;
+gk_status gk_autotune(gk_model *model, int32_t batch, gk_tune_result *result);
+
+/* Forces a configuration (GK_CONV_DIRECT with a data tile from the list
+ * above, or GK_CONV_FFT with tile 0 x 0).  GK_EINVAL if it does not fit. */
+gk_status gk_set_conv_config(gk_model *model, int32_t conv_mode, int32_t tile_x, int32_t tile_y);
+
 /* The spatial convolution path the model runs: GK_CONV_DIRECT or GK_CONV_FFT. */
 gk_status gk_model_conv_path(const gk_model *model, int32_t *conv_mode);
 

@@ -177,7 +177,6 @@ bool setup_fft(gk_model *m, const std::vector<double> &kp, std::vector<double2> 
     }
     if (f.DC == 0) return false;
     f.ncb = (m->d.nx + f.DC - 1) / f.DC;
-    m->ntiles = f.ncb;  // chi-square partials per row
     // tw[k] = exp(-2 pi i k / P); spectrum of the circularly placed taps,
     // real because they are symmetric, scaled by 1/P, in bit-reversed order
     auto make = [&](int P, int logP, std::vector<double2> &tw, std::vector<double> &kb) {
@@ -478,20 +477,24 @@ gk_status gk_create_model(const gk_model_desc *desc, int device, gk_model **out)
     }
     choose_tile(m);
     const bool direct_ok = m->lds_bytes <= kMaxLds;
+    std::vector<double2> twx, twy;
+    std::vector<double> kbx, kby;
+    m->fft_ok = setup_fft(m, kp, twx, twy, kbx, kby);
     if (d.conv_mode == GK_CONV_DIRECT && !direct_ok) {
         delete m;
         return fail(GK_EINVAL, "PSF too wide for the direct convolution path");
     }
-    m->use_fft = d.conv_mode == GK_CONV_FFT ||
-                 (d.conv_mode == GK_CONV_AUTO && (!direct_ok || m->hp > kMaxFastHalo));
-    std::vector<double2> twx, twy;
-    std::vector<double> kbx, kby;
-    if (m->use_fft) {
-        if (!setup_fft(m, kp, twx, twy, kbx, kby)) {
-            delete m;
-            return fail(GK_EINVAL, "model grid too large for the FFT convolution path");
-        }
+    if (d.conv_mode == GK_CONV_FFT && !m->fft_ok) {
+        delete m;
+        return fail(GK_EINVAL, "model grid too large for the FFT convolution path");
     }
+    if (!direct_ok && !m->fft_ok) {
+        delete m;
+        return fail(GK_EINVAL, "model grid too large for both convolution paths");
+    }
+    m->use_fft = d.conv_mode == GK_CONV_FFT ||
+                 (d.conv_mode == GK_CONV_AUTO && m->fft_ok && (!direct_ok || m->hp > kMaxFastHalo));
+    if (m->use_fft) m->ntiles = m->fft.ncb;  // chi-square partials per row
 
     DeviceGuard g(device);
     hipError_t e = g.err;
@@ -501,7 +504,7 @@ gk_status gk_create_model(const gk_model_desc *desc, int device, gk_model **out)
         e = hipMemcpy(m->d_kp, kp.data(), kp.size() * sizeof(double), hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = hipMemcpy(m->d_wz, wz.data(), wz.size() * sizeof(double), hipMemcpyHostToDevice);
-    if (m->use_fft) {
+    if (m->fft_ok) {
         auto up = [&](auto **dst, const auto &v) {
             if (e == hipSuccess) e = dev_alloc(dst, v.size());
             if (e == hipSuccess)
@@ -682,3 +685,34 @@ gk_status gk_residual_batch(gk_model *m, const double *params, int32_t B, double
 }
 
 }  // extern "C"
+
+bool gbk::set_conv_config(gk_model *m, bool fft, int tx, int ty)
+{
+    if (fft) {
+        if (!m->fft_ok) return false;
+        m->use_fft = true;
+        m->ntiles = m->fft.ncb;
+    } else {
+        const int u = m->d.upsample;
+        const bool fast = u == 1 && ty == 32 && (tx == 32 || tx == 64) && m->hp <= kMaxFastHalo;
+        size_t lds;
+        if (fast) {
+            if (m->d.nx < tx || m->d.ny < 32) return false;
+            lds = psf_u1_lds_bytes(tx, m->hp);
+        } else {
+            if (tx < 1 || ty < 1 || tx * ty > 256 * kMaxPixPerThread) return false;
+            if (u == 1 && ty == 32 && (tx == 32 || tx == 64)) return false;  // the fast kernel's shapes
+            lds = psf_lds_bytes(tx, ty, u, m->hp);
+        }
+        if (lds > kMaxLds) return false;
+        m->use_fft = false;
+        m->TXd = tx;
+        m->TYd = ty;
+        m->ntx = (m->d.nx + tx - 1) / tx;
+        m->nty = (m->d.ny + ty - 1) / ty;
+        m->ntiles = m->ntx * m->nty;
+        m->lds_bytes = lds;
+    }
+    m->drop_scratch();
+    return true;
+}

@@ -77,7 +77,7 @@ struct gk_model {
     size_t lds_bytes = 0;
     double *d_kp = nullptr, *d_wz = nullptr;
     // FFT path of the spatial convolution (gbk_fft.hip)
-    bool use_fft = false;
+    bool use_fft = false, fft_ok = false;
     gbk::FftArgs fft{};  // sizes, twiddles and spectra; T/U set per chunk
     double2 *d_twx = nullptr, *d_twy = nullptr;
     double *d_kbx = nullptr, *d_kby = nullptr, *d_U = nullptr;
@@ -178,6 +178,23 @@ struct gk_model {
         return hipSuccess;
     }
 
+    // frees the row scratch (sizes depend on the convolution configuration)
+    void drop_scratch()
+    {
+        drop_graphs();
+        (void)hipDeviceSynchronize();
+        (void)hipFree(d_params);
+        (void)hipFree(d_consts);
+        (void)hipFree(d_T);
+        (void)hipFree(d_partial);
+        (void)hipFree(d_U);
+        (void)hipFree(d_count);
+        if (h_params) (void)hipHostFree(h_params);
+        d_params = d_consts = d_T = d_partial = h_params = d_U = nullptr;
+        d_count = nullptr;
+        cap = 0;
+    }
+
     void release()
     {
         (void)hipFree(d_kp);
@@ -216,5 +233,10 @@ namespace gbk {
 // float, resid [B][2][ny][nx] double, chi2 [B] / nvalid [B] (device).
 gk_status run_batch(gk_model *m, const double *params, int32_t B, float *maps, double *resid,
                     double *chi2, int64_t *nvalid, void *stream);
+
+// Switches the spatial convolution to the FFT path or to direct data tiles of
+// tx x ty; false (nothing changed) if the configuration does not fit.  Frees
+// the row scratch.
+bool set_conv_config(gk_model *m, bool fft, int tx, int ty);
 
 }  // namespace gbk

@@ -53,71 +53,110 @@ bool cholesky(std::vector<double> &M, int d)
 // Volume of the unit d-ball.
 double ball_volume(int d) { return std::pow(M_PI, 0.5 * d) / std::tgamma(0.5 * d + 1.0); }
 
-// Batch log-likelihood of n unit-cube points; floor is the lowest live
-// log-likelihood when the batch was drawn (candidates at or below it cannot
-// be accepted in this round).
-using BatchLogL = std::function<gk_status(const std::vector<double> &u, int n, double floor,
-                                          std::vector<double> &logl)>;
-
-struct Point {
-    std::vector<double> u;
-    double logl;
+// Sampling region of a round: the enlarged bounding ellipsoid of the live
+// points, x = mu + L z with |z| <= 1 (L lower triangular, row-major d x d),
+// or the whole unit cube when ell is false.
+struct Bound {
+    int ell;
+    int d;
+    double mu[GK_NP];
+    double L[GK_NP * GK_NP];
 };
 
-// Runs the sampler in the unit cube [0,1]^d; eval maps unit-cube points to
-// log-likelihoods.  Fills the posterior in unit-cube coordinates through
-// `post` (u, normalised weight) and the evidence fields of res.
-gk_status ns_run(int d, const BatchLogL &eval, const gk_ns_opts &o, gk_ns_result *res,
-                 std::vector<std::pair<std::vector<double>, double>> &post, bool &capped)
+// Draws n candidates from bnd (NULL: the first live points, uniform in the
+// cube), evaluates them and returns their unit-cube coordinates u [n][d] and
+// log-likelihoods; floor is the lowest live log-likelihood when the round
+// starts (candidates at or below it cannot be accepted in this round).
+using DrawEval = std::function<gk_status(const Bound *bnd, int n, int64_t round, double floor,
+                                         double *u, double *logl)>;
+
+// Candidates from bnd with a sequential Philox stream (host side): a
+// direction from d normals, a radius from U^(1/d), rejected until inside
+// the cube (after 10^5 rejections, uniform in the cube).
+void draw_host(const Bound *bnd, int n, int d, Rng &rng, double *ub)
+{
+    double z[GK_NP];
+    for (int c = 0; c < n; ++c) {
+        double *u = ub + (size_t)c * d;
+        for (int tries = 0;; ++tries) {
+            if (!bnd || !bnd->ell || tries > 100000) {
+                for (int a = 0; a < d; ++a) u[a] = rng.uniform();
+                break;
+            }
+            double nrm = 0.0;
+            for (int a = 0; a < d; ++a) {
+                z[a] = rng.normal();
+                nrm += z[a] * z[a];
+            }
+            const double rad = std::pow(rng.uniform(), 1.0 / d) / std::sqrt(nrm);
+            bool inside = true;
+            for (int a = 0; a < d; ++a) {
+                double s = bnd->mu[a];
+                for (int b = 0; b <= a; ++b) s += bnd->L[a * d + b] * z[b] * rad;
+                u[a] = s;
+                inside = inside && s > 0.0 && s < 1.0;
+            }
+            if (inside) break;
+        }
+    }
+}
+
+// Runs the sampler in the unit cube [0,1]^d.  Fills the evidence fields of
+// res, best[] in unit-cube coordinates, and the posterior samples post_u
+// [M][d] with normalised weights post_w [M].
+gk_status ns_run(int d, const DrawEval &draw_eval, const gk_ns_opts &o, gk_ns_result *res,
+                 std::vector<double> &post_u, std::vector<double> &post_w, bool &capped)
 {
     const int N = o.n_live, B = o.batch;
-    Rng rng(o.seed, 0x6e73u);
-    std::vector<Point> live(N);
-    std::vector<double> ub((size_t)std::max(N, B) * d), lb;
-    for (int i = 0; i < N; ++i)
-        for (int k = 0; k < d; ++k) ub[(size_t)i * d + k] = rng.uniform();
-    GK_TRY(eval(ub, N, -DBL_MAX, lb));
+    std::vector<double> live_u((size_t)N * d), live_l(N);
+    std::vector<double> ub((size_t)std::max(N, B) * d), lb(std::max(N, B));
+    GK_TRY(draw_eval(nullptr, N, 0, -DBL_MAX, live_u.data(), lb.data()));
     int64_t n_evals = N, n_launch = 1;
-    for (int i = 0; i < N; ++i) {
-        live[i].u.assign(ub.begin() + (size_t)i * d, ub.begin() + (size_t)(i + 1) * d);
-        live[i].logl = std::isfinite(lb[i]) ? lb[i] : -DBL_MAX;
-    }
-    std::vector<Point> dead;
-    std::vector<double> dead_logwt;
+    for (int i = 0; i < N; ++i) live_l[i] = std::isfinite(lb[i]) ? lb[i] : -DBL_MAX;
+    std::vector<double> dead_u, dead_l, dead_logwt;
     double logz = -INFINITY, max_logl = -INFINITY;
-    std::vector<double> best;
-    for (auto &p : live)
-        if (p.logl > max_logl) {
-            max_logl = p.logl;
-            best = p.u;
+    std::vector<double> best(d, 0.0);
+    for (int i = 0; i < N; ++i)
+        if (live_l[i] > max_logl) {
+            max_logl = live_l[i];
+            std::copy_n(&live_u[(size_t)i * d], d, best.begin());
         }
     // min-heap of (logl, index): the lowest live point, ties to the lowest index
     std::vector<std::pair<double, int>> heap(N);
-    for (int i = 0; i < N; ++i) heap[i] = {live[i].logl, i};
+    for (int i = 0; i < N; ++i) heap[i] = {live_l[i], i};
     std::make_heap(heap.begin(), heap.end(), std::greater<>());
     const double log_shrink = std::log1p(-std::exp(-1.0 / N));  // log(1 - e^{-1/N})
     int64_t k = 0;
     bool done = false;
     capped = false;
-    std::vector<double> mu(d), C((size_t)d * d), L((size_t)d * d), z(d);
+    Bound bnd{};
+    bnd.d = d;
+    double C[GK_NP * GK_NP], z[GK_NP];
     while (!done) {
         // bounding ellipsoid of the live points (unit-cube coordinates)
-        std::fill(mu.begin(), mu.end(), 0.0);
-        for (auto &p : live)
-            for (int a = 0; a < d; ++a) mu[a] += p.u[a] / N;
-        std::fill(C.begin(), C.end(), 0.0);
-        for (auto &p : live)
+        for (int a = 0; a < d; ++a) bnd.mu[a] = 0.0;
+        for (int i = 0; i < N; ++i)
+            for (int a = 0; a < d; ++a) bnd.mu[a] += live_u[(size_t)i * d + a];
+        for (int a = 0; a < d; ++a) bnd.mu[a] /= N;
+        std::fill(C, C + d * d, 0.0);
+        for (int i = 0; i < N; ++i) {
+            const double *u = &live_u[(size_t)i * d];
+            for (int a = 0; a < d; ++a) z[a] = u[a] - bnd.mu[a];
             for (int a = 0; a < d; ++a)
-                for (int b = 0; b < d; ++b) C[a * d + b] += (p.u[a] - mu[a]) * (p.u[b] - mu[b]) / N;
+                for (int b = 0; b <= a; ++b) C[a * d + b] += z[a] * z[b];
+        }
+        for (int a = 0; a < d; ++a)
+            for (int b = 0; b <= a; ++b) C[b * d + a] = C[a * d + b] = C[a * d + b] / N;
         for (int a = 0; a < d; ++a) C[a * d + a] += 1e-12;
-        L = C;
+        std::vector<double> L(C, C + d * d);
         bool ell = cholesky(L, d);
-        double kmax = 0.0;
         if (ell) {
-            for (auto &p : live) {  // Mahalanobis radius^2: solve L y = u - mu
+            double kmax = 0.0;
+            for (int i = 0; i < N; ++i) {  // Mahalanobis radius^2: solve L y = u - mu
+                const double *u = &live_u[(size_t)i * d];
                 double m2 = 0.0;
                 for (int a = 0; a < d; ++a) {
-                    double s = p.u[a] - mu[a];
+                    double s = u[a] - bnd.mu[a];
                     for (int b = 0; b < a; ++b) s -= L[a * d + b] * z[b];
                     z[a] = s / L[a * d + a];
                     m2 += z[a] * z[a];
@@ -129,52 +168,30 @@ gk_status ns_run(int d, const BatchLogL &eval, const gk_ns_opts &o, gk_ns_result
             for (int a = 0; a < d; ++a) logdet += std::log(L[a * d + a]);
             const double logvol = std::log(ball_volume(d)) + 0.5 * d * std::log(scale2) + logdet;
             if (logvol >= 0.0) ell = false;  // the ellipsoid is larger than the box
-            for (double &v : L) v *= std::sqrt(scale2);
+            for (int a = 0; a < d * d; ++a) bnd.L[a] = L[a] * std::sqrt(scale2);
         }
-        // candidates inside the ellipsoid and the unit cube
-        for (int c = 0; c < B; ++c) {
-            double *u = &ub[(size_t)c * d];
-            for (int tries = 0;; ++tries) {
-                if (!ell || tries > 100000) {
-                    for (int a = 0; a < d; ++a) u[a] = rng.uniform();
-                    break;
-                }
-                double nrm = 0.0;
-                for (int a = 0; a < d; ++a) {
-                    z[a] = rng.normal();
-                    nrm += z[a] * z[a];
-                }
-                const double rad = std::pow(rng.uniform(), 1.0 / d) / std::sqrt(nrm);
-                bool inside = true;
-                for (int a = 0; a < d; ++a) {
-                    double s = mu[a];
-                    for (int b = 0; b <= a; ++b) s += L[a * d + b] * z[b] * rad;
-                    u[a] = s;
-                    inside = inside && s > 0.0 && s < 1.0;
-                }
-                if (inside) break;
-            }
-        }
-        GK_TRY(eval(ub, B, heap.front().first, lb));
+        bnd.ell = ell;
+        GK_TRY(draw_eval(&bnd, B, n_launch, heap.front().first, ub.data(), lb.data()));
         n_evals += B;
         ++n_launch;
         for (int c = 0; c < B && !done; ++c) {
             const double lc = std::isfinite(lb[c]) ? lb[c] : -DBL_MAX;
             const int imin = heap.front().second;
-            if (!(lc > live[imin].logl)) continue;
+            if (!(lc > live_l[imin])) continue;
             std::pop_heap(heap.begin(), heap.end(), std::greater<>());
             heap.back() = {lc, imin};
             std::push_heap(heap.begin(), heap.end(), std::greater<>());
             ++k;
-            const double logwt = live[imin].logl + (-(double)(k - 1) / N + log_shrink);
+            const double logwt = live_l[imin] + (-(double)(k - 1) / N + log_shrink);
             logz = logaddexp(logz, logwt);
-            dead.push_back(live[imin]);
+            dead_u.insert(dead_u.end(), &live_u[(size_t)imin * d], &live_u[(size_t)imin * d] + d);
+            dead_l.push_back(live_l[imin]);
             dead_logwt.push_back(logwt);
-            live[imin].u.assign(ub.begin() + (size_t)c * d, ub.begin() + (size_t)(c + 1) * d);
-            live[imin].logl = lc;
+            std::copy_n(&ub[(size_t)c * d], d, &live_u[(size_t)imin * d]);
+            live_l[imin] = lc;
             if (lc > max_logl) {
                 max_logl = lc;
-                best = live[imin].u;
+                std::copy_n(&ub[(size_t)c * d], d, best.begin());
             }
             // the retired point is the lowest, so the live maximum is the running one
             if (logaddexp(logz, max_logl - (double)k / N) - logz < o.tol) done = true;
@@ -185,19 +202,20 @@ gk_status ns_run(int d, const BatchLogL &eval, const gk_ns_opts &o, gk_ns_result
         }
     }
     // final live points with weight X_k / N
-    for (auto &p : live) {
-        const double logwt = p.logl - (double)k / N - std::log((double)N);
+    for (int i = 0; i < N; ++i) {
+        const double logwt = live_l[i] - (double)k / N - std::log((double)N);
         logz = logaddexp(logz, logwt);
-        dead.push_back(p);
+        dead_u.insert(dead_u.end(), &live_u[(size_t)i * d], &live_u[(size_t)i * d] + d);
+        dead_l.push_back(live_l[i]);
         dead_logwt.push_back(logwt);
     }
     double H = 0.0;
-    post.clear();
-    post.reserve(dead.size());
-    for (size_t i = 0; i < dead.size(); ++i) {
+    post_u.swap(dead_u);
+    post_w.resize(dead_l.size());
+    for (size_t i = 0; i < dead_l.size(); ++i) {
         const double pw = std::exp(dead_logwt[i] - logz);
-        if (pw > 0.0 && dead[i].logl > -DBL_MAX) H += pw * (dead[i].logl - logz);
-        post.emplace_back(dead[i].u, pw);
+        if (pw > 0.0 && dead_l[i] > -DBL_MAX) H += pw * (dead_l[i] - logz);
+        post_w[i] = pw;
     }
     res->logz = logz;
     res->info_h = H;
@@ -206,22 +224,22 @@ gk_status ns_run(int d, const BatchLogL &eval, const gk_ns_opts &o, gk_ns_result
     res->n_iter = k;
     res->n_evals = n_evals;
     res->n_launches = n_launch;
-    for (int a = 0; a < d; ++a) res->best[a] = best.empty() ? 0.0 : best[a];
+    for (int a = 0; a < d; ++a) res->best[a] = best[a];
     return GK_OK;
 }
 
 // Weighted mean, sd and quantiles of coordinate a of the posterior.
-void posterior_stats(const std::vector<std::pair<std::vector<double>, double>> &post, int a,
+void posterior_stats(const std::vector<double> &pu, const std::vector<double> &pw, int d, int a,
                      double scale, double offset, gk_ns_result *res, int slot)
 {
     std::vector<std::pair<double, double>> v;
-    v.reserve(post.size());
+    v.reserve(pw.size());
     double m = 0.0, w = 0.0;
-    for (auto &p : post) {
-        const double x = offset + scale * p.first[a];
-        v.emplace_back(x, p.second);
-        m += p.second * x;
-        w += p.second;
+    for (size_t i = 0; i < pw.size(); ++i) {
+        const double x = offset + scale * pu[i * d + a];
+        v.emplace_back(x, pw[i]);
+        m += pw[i] * x;
+        w += pw[i];
     }
     m /= w;
     double var = 0.0;
@@ -289,30 +307,32 @@ extern "C" gk_status gk_nested_sample(int32_t dim, const double *lo, const doubl
     for (int a = 0; a < dim; ++a)
         if (!(hi[a] > lo[a])) return fail(GK_EINVAL, "empty prior range in dimension %d", a);
     std::vector<double> theta;
-    BatchLogL eval = [&](const std::vector<double> &u, int n, double, std::vector<double> &logl) -> gk_status {
+    Rng rng(o.seed, 0x6e73u);
+    DrawEval eval = [&](const Bound *bnd, int n, int64_t, double, double *u,
+                        double *logl) -> gk_status {
+        draw_host(bnd, n, dim, rng, u);
         theta.resize((size_t)n * dim);
         for (int i = 0; i < n; ++i)
             for (int a = 0; a < dim; ++a)
                 theta[(size_t)i * dim + a] = lo[a] + u[(size_t)i * dim + a] * (hi[a] - lo[a]);
-        logl.resize(n);
-        if (fn(theta.data(), n, dim, logl.data(), user) != 0)
+        if (fn(theta.data(), n, dim, logl, user) != 0)
             return fail(GK_EINVAL, "likelihood callback failed");
         return GK_OK;
     };
     std::memset(res, 0, sizeof *res);
-    std::vector<std::pair<std::vector<double>, double>> post;
+    std::vector<double> pu, pw;
     bool capped = false;
-    GK_TRY(ns_run(dim, eval, o, res, post, capped));
+    GK_TRY(ns_run(dim, eval, o, res, pu, pw, capped));
     for (int a = 0; a < dim; ++a) {
         res->best[a] = lo[a] + res->best[a] * (hi[a] - lo[a]);
-        posterior_stats(post, a, hi[a] - lo[a], lo[a], res, a);
+        posterior_stats(pu, pw, dim, a, hi[a] - lo[a], lo[a], res, a);
     }
     if (samples && n_samples) {
-        const int64_t n = std::min<int64_t>(cap, (int64_t)post.size());
+        const int64_t n = std::min<int64_t>(cap, (int64_t)pw.size());
         for (int64_t i = 0; i < n; ++i) {
             for (int a = 0; a < dim; ++a)
-                samples[i * (GK_NP + 1) + a] = lo[a] + post[i].first[a] * (hi[a] - lo[a]);
-            samples[i * (GK_NP + 1) + GK_NP] = post[i].second;
+                samples[i * (GK_NP + 1) + a] = lo[a] + pu[i * dim + a] * (hi[a] - lo[a]);
+            samples[i * (GK_NP + 1) + GK_NP] = pw[i];
         }
         *n_samples = n;
     }
@@ -327,7 +347,115 @@ gk_status fit_reserve_rows(gk_model *m, int rows, double **h_params, double **d_
 
 namespace {
 
-// Plain (s == NULL) or surrogate-screened nested sampling of a model.
+// ---------------------------------------------------------------------------
+// Device-side candidates of the model fits.  Candidate c of round r draws
+// from its own Philox4x32-10 stream: key = seed (high word xor a tag),
+// counter = (c, r, r >> 32, block); each block gives two 53-bit uniforms,
+// normals by Box-Muller (both outputs).  Same rule as draw_host: direction
+// from d normals, radius U^(1/d), rejected until inside the cube (after 10^4
+// rejections, uniform in the cube).
+// ---------------------------------------------------------------------------
+struct DrawArgs {
+    Bound bnd;
+    int n, round_valid;
+    uint64_t round;
+    uint32_t key0, key1;
+    int fr[GK_NP];
+    double lo[GK_NP], span[GK_NP], fixed[GK_NP];
+    double *u;     // [n][d]
+    double *rows;  // [n][GK_NP]
+};
+
+struct DevStream {
+    uint32_t ctr[4], key[2], buf[4];
+    int left;
+    __device__ uint32_t u32()
+    {
+        if (!left) {
+            philox4x32_10(ctr, key, buf);
+            ++ctr[3];
+            left = 4;
+        }
+        return buf[4 - left--];
+    }
+    __device__ double uniform()
+    {
+        const uint64_t a = u32(), b = u32();
+        return ((double)((a << 21) ^ (b >> 11)) + 0.5) * 0x1.0p-53;
+    }
+};
+
+__global__ __launch_bounds__(64) void k_ns_draw(DrawArgs g)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= g.n) return;
+    const int d = g.bnd.d;
+    DevStream rs;
+    rs.ctr[0] = (uint32_t)c;
+    rs.ctr[1] = (uint32_t)g.round;
+    rs.ctr[2] = (uint32_t)(g.round >> 32);
+    rs.ctr[3] = 0u;
+    rs.key[0] = g.key0;
+    rs.key[1] = g.key1;
+    rs.left = 0;
+    double x[GK_NP], z[GK_NP];
+    bool drawn = false;
+    if (g.round_valid && g.bnd.ell) {
+        for (int tries = 0; tries < 10000 && !drawn; ++tries) {
+            double nrm = 0.0;
+            for (int a = 0; a < d; a += 2) {
+                const double u1 = rs.uniform(), u2 = rs.uniform();
+                const double r = sqrt(-2.0 * log(u1)), t = 6.283185307179586 * u2;
+                z[a] = r * cos(t);
+                if (a + 1 < d) z[a + 1] = r * sin(t);
+            }
+            for (int a = 0; a < d; ++a) nrm += z[a] * z[a];
+            const double rad = pow(rs.uniform(), 1.0 / d) / sqrt(nrm);
+            bool inside = true;
+            for (int a = 0; a < d; ++a) {
+                double v = g.bnd.mu[a];
+                for (int b = 0; b <= a; ++b) v += g.bnd.L[a * d + b] * z[b] * rad;
+                x[a] = v;
+                inside = inside && v > 0.0 && v < 1.0;
+            }
+            drawn = inside;
+        }
+    }
+    if (!drawn)
+        for (int a = 0; a < d; ++a) x[a] = rs.uniform();
+    double *row = g.rows + (size_t)c * GK_NP;
+    for (int k = 0; k < GK_NP; ++k) row[k] = g.fixed[k];
+    for (int a = 0; a < d; ++a) {
+        g.u[(size_t)c * d + a] = x[a];
+        row[g.fr[a]] = g.lo[g.fr[a]] + x[a] * g.span[g.fr[a]];
+    }
+}
+
+// dst[i] = src[idx[i]] (parameter rows)
+__global__ void k_gather_rows(const double *__restrict__ src, const int *__restrict__ idx, int n,
+                              double *__restrict__ dst)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n * GK_NP) return;
+    const int r = i / GK_NP, k = i - r * GK_NP;
+    dst[i] = src[(size_t)idx[r] * GK_NP + k];
+}
+
+// Device buffers of one fit, freed on scope exit.
+struct NsBuffers {
+    double *d_u = nullptr, *d_rows2 = nullptr, *h_u = nullptr;
+    int *d_idx = nullptr, *h_idx = nullptr;
+    ~NsBuffers()
+    {
+        (void)hipFree(d_u);
+        (void)hipFree(d_rows2);
+        (void)hipFree(d_idx);
+        if (h_u) (void)hipHostFree(h_u);
+        if (h_idx) (void)hipHostFree(h_idx);
+    }
+};
+
+// Plain (sur == NULL) or surrogate-screened nested sampling of a model.
 gk_status fit_nested(gk_model *m, gk_surrogate *sur, const double *lo, const double *hi,
                      const uint8_t *free_mask, const double *fixed, const gk_ns_opts *o_in,
                      double margin, double audit, gk_ns_result *res, double *samples, int64_t cap,
@@ -345,70 +473,74 @@ gk_status fit_nested(gk_model *m, gk_surrogate *sur, const double *lo, const dou
         if (!surrogate_matches(sur, m)) return fail(GK_EINVAL, "model instrument differs from the surrogate's");
         if (surrogate_device(sur) != m->device) return fail(GK_EINVAL, "model and surrogate on different devices");
     }
-    std::vector<int> fr;
+    DrawArgs g{};
+    int d = 0;
     for (int k = 0; k < NPAR; ++k) {
+        g.fixed[k] = fixed[k];
+        g.lo[k] = lo[k];
+        g.span[k] = hi[k] - lo[k];
         if (!free_mask[k]) continue;
         if (!(hi[k] > lo[k])) return fail(GK_EINVAL, "empty prior range in slot %d", k);
-        fr.push_back(k);
+        g.fr[d++] = k;
     }
-    const int d = (int)fr.size();
     if (d == 0) return fail(GK_EINVAL, "no free parameter");
-    DeviceGuard g(m->device);
-    HIP_TRY(g.err);
+    g.key0 = (uint32_t)o.seed;
+    g.key1 = (uint32_t)(o.seed >> 32) ^ 0x6e736477u;
+    DeviceGuard dg(m->device);
+    HIP_TRY(dg.err);
     double *h_params, *d_params, *d_chi2, *h_chi2;
     hipStream_t stream;
     const int rows = std::max(o.n_live, o.batch);
     // chi2 rows, then (screened) surrogate chi2 rows
     GK_TRY(fit_reserve_rows(m, 2 * rows, &h_params, &d_params, &d_chi2, &h_chi2, &stream));
     double *d_chi2s = d_chi2 + rows, *h_chi2s = h_chi2 + rows;
+    NsBuffers nb;
+    HIP_TRY(hipMalloc((void **)&nb.d_u, sizeof(double) * rows * d));
+    HIP_TRY(hipHostMalloc((void **)&nb.h_u, sizeof(double) * rows * d, 0));
+    if (sur) {
+        HIP_TRY(hipMalloc((void **)&nb.d_rows2, sizeof(double) * rows * NPAR));
+        HIP_TRY(hipMalloc((void **)&nb.d_idx, sizeof(int) * rows));
+        HIP_TRY(hipHostMalloc((void **)&nb.h_idx, sizeof(int) * rows, 0));
+    }
     std::memset(res, 0, sizeof *res);
-    auto fill_rows = [&](const std::vector<double> &u, const std::vector<int> &idx) {
-        for (size_t i = 0; i < idx.size(); ++i) {
-            double *row = h_params + i * NPAR;
-            std::memcpy(row, fixed, sizeof(double) * NPAR);
-            for (int a = 0; a < d; ++a)
-                row[fr[a]] = lo[fr[a]] + u[(size_t)idx[i] * d + a] * (hi[fr[a]] - lo[fr[a]]);
-        }
-    };
-    // plain chi2 of the rows in h_params [0, n) into h_chi2
-    auto plain = [&](int n) -> gk_status {
-        if (n == 0) return GK_OK;
-        HIP_TRY(hipMemcpyAsync(d_params, h_params, sizeof(double) * NPAR * n, hipMemcpyHostToDevice,
-                               stream));
-        GK_TRY(run_batch(m, d_params, n, nullptr, nullptr, d_chi2, nullptr, stream));
-        HIP_TRY(hipMemcpyAsync(h_chi2, d_chi2, sizeof(double) * n, hipMemcpyDeviceToHost, stream));
-        HIP_TRY(hipStreamSynchronize(stream));
-        return GK_OK;
-    };
-    std::vector<int> all, keep;
     int64_t n_plain = 0;
     Rng audit_rng(o.seed, 0x617564u);
     std::vector<double> recent;  // surrogate-minus-plain chi2 of the latest plain evaluations
     size_t recent_pos = 0;
     double shift = 0.0;
-    BatchLogL eval = [&](const std::vector<double> &u, int n, double floor,
-                         std::vector<double> &logl) -> gk_status {
-        logl.assign(n, -INFINITY);
-        all.resize(n);
-        std::iota(all.begin(), all.end(), 0);
-        keep.clear();
+    std::vector<int> keep;
+    std::vector<char> audited;
+    DrawEval eval = [&](const Bound *bnd, int n, int64_t round, double floor, double *u,
+                        double *logl) -> gk_status {
+        g.n = n;
+        g.round = (uint64_t)round;
+        g.round_valid = bnd != nullptr;
+        if (bnd) g.bnd = *bnd;
+        g.bnd.d = d;
+        g.u = nb.d_u;
+        g.rows = d_params;
+        hipLaunchKernelGGL(k_ns_draw, dim3((n + 63) / 64), dim3(64), 0, stream, g);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipMemcpyAsync(nb.h_u, nb.d_u, sizeof(double) * n * d, hipMemcpyDeviceToHost, stream));
+        for (int i = 0; i < n; ++i) logl[i] = -INFINITY;
         if (!sur) {
-            fill_rows(u, all);
-            GK_TRY(plain(n));
+            GK_TRY(run_batch(m, d_params, n, nullptr, nullptr, d_chi2, nullptr, stream));
+            HIP_TRY(hipMemcpyAsync(h_chi2, d_chi2, sizeof(double) * n, hipMemcpyDeviceToHost, stream));
+            HIP_TRY(hipStreamSynchronize(stream));
+            std::memcpy(u, nb.h_u, sizeof(double) * n * d);
             n_plain += n;
             for (int i = 0; i < n; ++i) logl[i] = -0.5 * h_chi2[i];
             return GK_OK;
         }
-        // surrogate chi2 of every candidate
-        fill_rows(u, all);
-        HIP_TRY(hipMemcpyAsync(d_params, h_params, sizeof(double) * NPAR * n, hipMemcpyHostToDevice,
-                               stream));
+        // surrogate chi2 of every candidate, then the plain chi2 of the survivors
         GK_TRY(surrogate_chi2(sur, m, d_params, n, d_chi2s, stream));
         HIP_TRY(hipMemcpyAsync(h_chi2s, d_chi2s, sizeof(double) * n, hipMemcpyDeviceToHost, stream));
         HIP_TRY(hipStreamSynchronize(stream));
+        std::memcpy(u, nb.h_u, sizeof(double) * n * d);
         const double chi2_floor = floor > -DBL_MAX ? -2.0 * floor : INFINITY;
         const double cut = chi2_floor + shift + margin;
-        std::vector<char> audited(n, 0);
+        keep.clear();
+        audited.assign(n, 0);
         for (int i = 0; i < n; ++i) {
             const double a = audit_rng.uniform();  // one draw per candidate, used or not
             if (!(h_chi2s[i] > cut)) {
@@ -420,11 +552,20 @@ gk_status fit_nested(gk_model *m, gk_surrogate *sur, const double *lo, const dou
         }
         res->n_screened += n;
         res->n_rejected += n - (int64_t)keep.size();
-        fill_rows(u, keep);
-        GK_TRY(plain((int)keep.size()));
-        n_plain += (int64_t)keep.size();
+        const int nk = (int)keep.size();
+        if (nk > 0) {
+            std::memcpy(nb.h_idx, keep.data(), sizeof(int) * nk);
+            HIP_TRY(hipMemcpyAsync(nb.d_idx, nb.h_idx, sizeof(int) * nk, hipMemcpyHostToDevice, stream));
+            hipLaunchKernelGGL(k_gather_rows, dim3((nk * NPAR + 255) / 256), dim3(256), 0, stream,
+                               d_params, nb.d_idx, nk, nb.d_rows2);
+            HIP_TRY(hipGetLastError());
+            GK_TRY(run_batch(m, nb.d_rows2, nk, nullptr, nullptr, d_chi2, nullptr, stream));
+            HIP_TRY(hipMemcpyAsync(h_chi2, d_chi2, sizeof(double) * nk, hipMemcpyDeviceToHost, stream));
+            HIP_TRY(hipStreamSynchronize(stream));
+        }
+        n_plain += nk;
         const size_t window = (size_t)std::max(o.n_live, o.batch);
-        for (size_t j = 0; j < keep.size(); ++j) {
+        for (int j = 0; j < nk; ++j) {
             const int i = keep[j];
             const double c = h_chi2[j];
             logl[i] = -0.5 * c;
@@ -446,9 +587,9 @@ gk_status fit_nested(gk_model *m, gk_surrogate *sur, const double *lo, const dou
         for (double v : recent) shift = std::max(shift, v);
         return GK_OK;
     };
-    std::vector<std::pair<std::vector<double>, double>> post;
+    std::vector<double> pu, pw;
     bool capped = false;
-    GK_TRY(ns_run(d, eval, o, res, post, capped));
+    GK_TRY(ns_run(d, eval, o, res, pu, pw, capped));
     res->n_evals = n_plain;  // plain evaluations only
     double best_u[GK_NP];
     std::memcpy(best_u, res->best, sizeof best_u);
@@ -457,18 +598,18 @@ gk_status fit_nested(gk_model *m, gk_surrogate *sur, const double *lo, const dou
         res->sd[k] = 0.0;
     }
     for (int a = 0; a < d; ++a) {
-        const int k = fr[a];
+        const int k = g.fr[a];
         res->best[k] = lo[k] + best_u[a] * (hi[k] - lo[k]);
-        posterior_stats(post, a, hi[k] - lo[k], lo[k], res, k);
+        posterior_stats(pu, pw, d, a, hi[k] - lo[k], lo[k], res, k);
     }
     if (samples && n_samples) {
-        const int64_t n = std::min<int64_t>(cap, (int64_t)post.size());
+        const int64_t n = std::min<int64_t>(cap, (int64_t)pw.size());
         for (int64_t i = 0; i < n; ++i) {
             double *row = samples + i * (GK_NP + 1);
             std::memcpy(row, fixed, sizeof(double) * NPAR);
             for (int a = 0; a < d; ++a)
-                row[fr[a]] = lo[fr[a]] + post[i].first[a] * (hi[fr[a]] - lo[fr[a]]);
-            row[GK_NP] = post[i].second;
+                row[g.fr[a]] = lo[g.fr[a]] + pu[i * d + a] * (hi[g.fr[a]] - lo[g.fr[a]]);
+            row[GK_NP] = pw[i];
         }
         *n_samples = n;
     }

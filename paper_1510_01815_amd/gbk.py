@@ -32,7 +32,7 @@ SYMBOLS = (
     "gk_surrogate_train", "gk_surrogate_weight_count", "gk_surrogate_get_weights",
     "gk_surrogate_set_weights", "gk_surrogate_gradients", "gk_surrogate_predict",
     "gk_surrogate_chi2", "gk_fit_nested_screened", "gk_gemm_bf16", "gk_model_conv_path",
-    "gk_set_launch_mode", "gk_graph_launches",
+    "gk_set_launch_mode", "gk_graph_launches", "gk_autotune", "gk_set_conv_config",
 )
 LM_REASONS = {1: "ftol", 2: "xtol", 3: "lambda", 4: "maxiter"}
 GK_PROF_TIMING, GK_PROF_COUNT = 1, 2
@@ -82,6 +82,17 @@ class NSResult(ctypes.Structure):
                 ("n_launches", ctypes.c_int64)] + [
                 (n, ctypes.c_double * NPAR) for n in ("best", "mean", "sd", "median", "q16", "q84")] + [
                 (n, ctypes.c_int64) for n in ("n_screened", "n_rejected", "n_audited", "n_audit_miss")]
+
+
+class TuneResult(ctypes.Structure):
+    _fields_ = [("conv_mode", ctypes.c_int32), ("tile_x", ctypes.c_int32), ("tile_y", ctypes.c_int32),
+                ("n_candidates", ctypes.c_int32), ("ms_best", ctypes.c_double),
+                ("ms", ctypes.c_double * 16)]
+
+
+TUNE_CANDIDATES = (("fft", 0, 0), ("direct", 32, 32), ("direct", 64, 32), ("direct", 32, 16),
+                   ("direct", 16, 16), ("direct", 32, 8), ("direct", 16, 8), ("direct", 8, 8),
+                   ("direct", 64, 16))
 
 
 class SurrogateOpts(ctypes.Structure):
@@ -220,6 +231,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.gk_gemm_bf16.argtypes = [i32, i32, i32, i32, i32, vp, i32, vp, i32, vp, i32, vp]
     L.gk_model_conv_path.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
     L.gk_set_launch_mode.argtypes = [vp, ctypes.c_int32]
+    L.gk_autotune.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(TuneResult)]
+    L.gk_set_conv_config.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
     L.gk_graph_launches.argtypes = [vp, i64p]
     L.gk_last_error.restype = ctypes.c_char_p
     for name in SYMBOLS:
@@ -321,6 +334,17 @@ class Model:
         n = ctypes.c_int64()
         _check(load().gk_graph_launches(self._h, ctypes.byref(n)))
         return n.value
+
+    def autotune(self, batch: int) -> dict:
+        """Times the convolution configurations and keeps the fastest (gk_autotune)."""
+        r = TuneResult()
+        _check(load().gk_autotune(self._h, batch, ctypes.byref(r)))
+        return {"conv": {1: "direct", 2: "fft"}[r.conv_mode], "tile": (r.tile_x, r.tile_y),
+                "ms_best": r.ms_best, "n_candidates": r.n_candidates,
+                "ms": {c: r.ms[k] for k, c in enumerate(TUNE_CANDIDATES) if r.ms[k] >= 0}}
+
+    def set_conv_config(self, conv: str, tile_x: int = 0, tile_y: int = 0) -> None:
+        _check(load().gk_set_conv_config(self._h, CONV[conv], tile_x, tile_y))
 
     def conv_path(self) -> str:
         """"direct" or "fft": the spatial convolution the model runs."""
