@@ -9,7 +9,11 @@ sampler, drawn from the workload's generative ranges; every step uses a
 different batch, all resident in device memory before timing starts.
 
 Prints one JSON line: evals/s, the roofline of the dominant kernel (timed
-live with HIP events on the launch stream) and the CPU oracle baseline.
+live with HIP events on the launch stream) and the CPU oracle baseline, plus
+fits/hour of the surrogate workload (64 x 64 x 64 instrument): the network
+trained on 2 M rows streamed from the plain evaluation, then nested-sampling
+fits (1000 live points, 10 free parameters) of synthetic galaxies, plain and
+surrogate-screened, with the posterior medians compared.
 """
 import argparse
 import json
@@ -74,7 +78,52 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows-per-thread", type=int, default=40)
+    ap.add_argument("--fit-galaxies", type=int, default=6,
+                    help="galaxies of the surrogate workload fitted both ways (0: skip)")
+    ap.add_argument("--train-rows", type=int, default=2_000_000)
     return ap.parse_args()
+
+
+def fits_per_hour(gbk, I, torch, n_gal, train_rows):
+    """Surrogate workload: training, then plain and screened nested-sampling fits."""
+    grid = I.c5_grid()
+    m = gbk.Model.from_grid(grid)
+    lo, hi = I.c5_box()
+    free = list(I.C5_FREE)
+    dev = torch.device("cuda:0")
+    batch = 512
+    steps = max(1, train_rows // batch)
+    S = gbk.Surrogate(m, lo, hi, hidden=1024, layers=4, batch=batch, lr=1e-3, lr_final=1e-5, seed=1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    losses = S.train(steps)
+    t_train = time.perf_counter() - t0
+    out = {"workload": "64x64x64 instrument, 30 km/s channels, PSF FWHM 2.5 px, LSF sigma 30 km/s, "
+                       "noise 5 km/s; nested sampling with 1000 live points, 10 free parameters",
+           "train": {"rows": steps * batch, "seconds": round(t_train, 3),
+                     "rows_per_s": round(steps * batch / t_train, 1),
+                     "final_loss": float(np.mean(losses[-50:]))}}
+    fits = []
+    for k in range(n_gal):
+        truth = I.c5_galaxy(k + 1)
+        maps = m.evaluate(torch.tensor(truth[None], device=dev)).cpu().numpy()[0]
+        obs = I.make_observation(maps, 5.0, I.rng_for(5, k + 1, 1))
+        m.set_obs(obs)
+        pl = m.fit_nested(lo, hi, free, truth, n_live=1000, seed=100 + k)
+        sc = S.fit_nested(m, lo, hi, free, truth, margin=25.0, audit=0.02, n_live=1000, seed=100 + k)
+        sd = np.where(pl["sd"] > 0, pl["sd"], 1.0)
+        fits.append({"plain_s": pl["t_wall_s"], "screened_s": sc["t_wall_s"],
+                     "plain_evals": pl["n_evals"], "screened_plain_evals": sc["n_evals"],
+                     "surrogate_evals": sc["n_screened"], "audit_misses": sc["n_audit_miss"],
+                     "max_median_shift_sd": float(np.max(np.abs(sc["median"] - pl["median"]) / sd))})
+    if fits:
+        tp = sum(f["plain_s"] for f in fits)
+        ts = sum(f["screened_s"] for f in fits)
+        out.update({"galaxies": len(fits), "plain": round(3600 * len(fits) / tp, 1),
+                    "screened": round(3600 * len(fits) / ts, 1), "ratio": round(tp / ts, 3),
+                    "unit": "fits/hour", "fits": fits})
+    S.close()
+    return out
 
 
 def cpu_baseline(grid, first_row, obs, rows_per_thread):
@@ -106,6 +155,28 @@ def cpu_baseline(grid, first_row, obs, rows_per_thread):
             "chi2_first": res[0]}
 
 
+def oracle_rate_c5(I):
+    """The oracle's evals/s on the surrogate workload's instrument (2 rows per thread)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    from oracle import oracle as O
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from parity import oracle_desc
+    O.lib()
+    grid = I.c5_grid()
+    d = oracle_desc(O, grid.as_dict())
+    lo, hi = I.c5_box()
+    truth = I.c5_galaxy(1)
+    obs = I.make_observation(O.evaluate(d, truth), 5.0, I.rng_for(5, 1, 1))
+    threads = max(1, min(16, os.cpu_count() or 1))
+    rows = lo + I.rng_for(5, 0, 9).random((threads * 2, I.NPAR)) * (hi - lo)
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(threads) as ex:
+        list(ex.map(lambda r: O.eval_chi2(d, r, obs.vel, obs.sig, obs.evel, obs.esig, obs.mask,
+                                          obs.W), rows))
+    return len(rows) / (time.perf_counter() - t0), threads
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -129,6 +200,7 @@ def main():
     obs = I.make_observation(truth_maps, 3.0, I.rng_for(2, 0, 1))
     model.set_obs(obs)
 
+    tune = model.autotune(BATCH)  # launch shape of the PSF/moment stage, timed on this GPU
     K, W = args.steps, args.warmup
     rng = I.rng_for(2, 0, 2)
     batches = torch.tensor(I.c2_draw(rng, (K + W) * BATCH).reshape(K + W, BATCH, I.NPAR),
@@ -204,14 +276,26 @@ def main():
                                   "400 nested-sampling proposals per launch",
                       "nx": 128, "ny": 128, "nz": 48, "batch": BATCH,
                       "psf_fwhm_pix": grid.psf_fwhm, "lsf_sigma_kms": round(grid.lsf_sigma, 4),
-                      "rotation_curve": "exponential rise", "parallelism": "single GPU"},
+                      "rotation_curve": "exponential rise", "parallelism": "single GPU",
+                      "conv": tune["conv"], "tile": list(tune["tile"])},
            "roofline": roofline, "rooflines": rooflines, "kernel_ms_per_launch": per_kernel_ms}
+    if args.fit_galaxies > 0:
+        out["fits_per_hour"] = fits_per_hour(gbk, I, torch, args.fit_galaxies, args.train_rows)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(grid, batches[W, 0].cpu().numpy(), obs,
                                            args.cpu_rows_per_thread)
         gpu_first = float(chi2[W, 0].item())
         cb = out["cpu_baseline"].pop("chi2_first")
         out["cpu_baseline"]["chi2_rel_diff_first_row"] = abs(gpu_first - cb) / abs(cb)
+        fph = out.get("fits_per_hour", {})
+        if fph.get("fits"):
+            evals = float(np.mean([f["plain_evals"] for f in fph["fits"]]))
+            eps, threads = oracle_rate_c5(I)
+            out["cpu_baseline"]["surrogate_workload"] = {
+                "evals_per_s": round(eps, 2), "cores": threads,
+                "fits_per_hour": round(3600 * eps / evals, 4),
+                "kind": "extrapolated: oracle evals/s on the 64x64x64 instrument x the plain "
+                        "fitter's evaluations per fit"}
     print(json.dumps(out), flush=True)
 
 

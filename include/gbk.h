@@ -239,6 +239,8 @@ typedef struct {
     int64_t n_rejected;        /* of those, discarded without a plain evaluation */
     int64_t n_audited;         /* discarded ones evaluated anyway (audit draws) */
     int64_t n_audit_miss;      /* audited ones that the plain chi2 would have accepted */
+    double t_wall_s;           /* wall time of the call (model fits; 0 for gk_nested_sample) */
+    double t_wait_s;           /* of which blocked waiting for the device */
 } gk_ns_result;
 
 gk_status gk_ns_default_opts(gk_ns_opts *opts);

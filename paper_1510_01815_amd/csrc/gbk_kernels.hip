@@ -583,18 +583,34 @@ __device__ __forceinline__ void psf_u1_tile(const PsfArgs &a, const RowPtrs &r)
     }
 }
 
-// Row pointers of a single-model launch (row = blockIdx.y, tile = blockIdx.x).
+// Row pointers of a single-model launch, grid (ntiles, B).  Workgroups go to
+// the 8 XCDs round-robin by linear id; the ids are remapped so that all tiles
+// of one row run on one XCD and the halo each tile shares with its
+// neighbours is re-read from that XCD's L2 rather than from HBM: id L goes to
+// XCD L % 8, which takes rows b = L % 8 (mod 8) tile by tile (rows beyond the
+// last full group of 8 keep the plain order).
 __device__ __forceinline__ RowPtrs single_row(const PsfArgs &a)
 {
-    const int b = blockIdx.y;
+    const int ntiles = gridDim.x, L = blockIdx.x + blockIdx.y * ntiles;
+    const int full = gridDim.y >> 3, base = 8 * ntiles * full;
+    int b, tile;
+    if (L < base) {
+        const int s = L >> 3;
+        b = (L & 7) + 8 * (s / ntiles);
+        tile = s % ntiles;
+    } else {
+        const int rest = L - base;
+        b = 8 * full + rest / ntiles;
+        tile = rest % ntiles;
+    }
     const size_t npix = (size_t)a.nx * a.ny;
     RowPtrs r;
     r.T = a.T + (size_t)b * 3 * a.EX * a.EY;
     r.c = a.consts + (size_t)b * NCONST;
     r.maps = a.maps ? a.maps + (size_t)b * 3 * npix : nullptr;
     r.resid = a.resid ? a.resid + (size_t)b * 2 * npix : nullptr;
-    r.partial = a.partial ? a.partial + (size_t)b * a.ntiles + blockIdx.x : nullptr;
-    r.tile = blockIdx.x;
+    r.partial = a.partial ? a.partial + (size_t)b * a.ntiles + tile : nullptr;
+    r.tile = tile;
     return r;
 }
 

@@ -39,7 +39,7 @@ namespace {
 constexpr int kInPad = 32;
 constexpr float kVelScale = 300.0f, kSigScale = 100.0f;
 constexpr int kRedBlocks = 256;
-constexpr int GBK = 64, LDK = GBK + 8;  // K depth of a stage; LDS rows padded by 16 bytes
+// LDS rows of a stage are padded by 16 bytes (8 bf16) beyond its K depth
 
 enum Epi {
     EPI_F32 = 0,    // C (f32) = acc + bias
@@ -78,18 +78,18 @@ __device__ inline float gelu_grad(float z)
            z * expf(-0.5f * z * z) * 0.39894228040143268f;
 }
 
-// Global -> registers for one stage: the R x 64 block (rows r0.., k0..) of
+// Global -> registers for one stage: the R x BK block (rows r0.., k0..) of
 // X(row, k), X(row, k) = X[row * ldx + k] (TR false) or X[k * ldx + row] (TR
 // true), as uint4 chunks of 8 bf16; out-of-range elements are zero.
-template <int R, bool TR>
+template <int R, int BK, bool TR>
 __device__ inline void load_stage(const uint16_t *__restrict__ X, int ldx, int rows, int K, int r0,
-                                  int k0, uint4 (&reg)[R / 32], int tid)
+                                  int k0, uint4 (&reg)[R * BK / 2048], int tid)
 {
 #pragma unroll
-    for (int i = 0; i < R / 32; ++i) {
+    for (int i = 0; i < R * BK / 2048; ++i) {
         const int c = tid + i * 256;
         if (!TR) {  // chunk = 8 consecutive k of one row
-            const int row = c >> 3, kc = (c & 7) * 8;
+            const int row = c / (BK / 8), kc = (c % (BK / 8)) * 8;
             const bool ok = r0 + row < rows && k0 + kc < K;
             reg[i] = ok ? *reinterpret_cast<const uint4 *>(X + (size_t)(r0 + row) * ldx + k0 + kc)
                         : uint4{0u, 0u, 0u, 0u};
@@ -110,15 +110,16 @@ __device__ inline void load_stage(const uint16_t *__restrict__ X, int ldx, int r
     }
 }
 
-// registers -> LDS S[row][k] (row stride LDK)
-template <int R, bool TR>
-__device__ inline void store_stage(const uint4 (&reg)[R / 32], uint16_t *__restrict__ S, int tid)
+// registers -> LDS S[row][k] (row stride BK + 8)
+template <int R, int BK, bool TR>
+__device__ inline void store_stage(const uint4 (&reg)[R * BK / 2048], uint16_t *__restrict__ S, int tid)
 {
+    constexpr int LDK = BK + 8;
 #pragma unroll
-    for (int i = 0; i < R / 32; ++i) {
+    for (int i = 0; i < R * BK / 2048; ++i) {
         const int c = tid + i * 256;
         if (!TR) {
-            const int row = c >> 3, kc = (c & 7) * 8;
+            const int row = c / (BK / 8), kc = (c % (BK / 8)) * 8;
             *reinterpret_cast<uint4 *>(S + row * LDK + kc) = reg[i];
         } else {
             const int kk = c / (R / 8), rc = (c % (R / 8)) * 8;
@@ -132,10 +133,10 @@ __device__ inline void store_stage(const uint4 (&reg)[R / 32], uint16_t *__restr
 // C[M][N] = sum_k A(m, k) B(n, k) on BM x BN tiles, 4 waves of (BM/2) x (BN/2).
 // The MFMA takes the B fragment as its row operand, so a lane's four results
 // are four consecutive columns n of one row m (vector stores in the epilogue).
-template <int BM, int BN, bool TA, bool TB, int EPI>
+template <int BM, int BN, int BK, bool TA, bool TB, int EPI>
 __global__ __launch_bounds__(256) void k_gemm(GemmArgs g)
 {
-    constexpr int WM = BM / 2, WN = BN / 2, TM = WM / 16, TN = WN / 16;
+    constexpr int WM = BM / 2, WN = BN / 2, TM = WM / 16, TN = WN / 16, LDK = BK + 8;
     __shared__ __attribute__((aligned(16))) uint16_t As[BM * LDK];
     __shared__ __attribute__((aligned(16))) uint16_t Bs[BN * LDK];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -149,19 +150,19 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g)
 #pragma unroll
         for (int j = 0; j < TN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-    uint4 ra[BM / 32], rb[BN / 32];
-    load_stage<BM, TA>(A, g.lda, g.M, g.K, m0, 0, ra, tid);
-    load_stage<BN, TB>(B, g.ldb, g.N, g.K, n0, 0, rb, tid);
-    for (int k0 = 0; k0 < g.K; k0 += GBK) {
-        store_stage<BM, TA>(ra, As, tid);
-        store_stage<BN, TB>(rb, Bs, tid);
+    uint4 ra[BM * BK / 2048], rb[BN * BK / 2048];
+    load_stage<BM, BK, TA>(A, g.lda, g.M, g.K, m0, 0, ra, tid);
+    load_stage<BN, BK, TB>(B, g.ldb, g.N, g.K, n0, 0, rb, tid);
+    for (int k0 = 0; k0 < g.K; k0 += BK) {
+        store_stage<BM, BK, TA>(ra, As, tid);
+        store_stage<BN, BK, TB>(rb, Bs, tid);
         __syncthreads();
-        if (k0 + GBK < g.K) {  // the next stage's loads overlap this stage's products
-            load_stage<BM, TA>(A, g.lda, g.M, g.K, m0, k0 + GBK, ra, tid);
-            load_stage<BN, TB>(B, g.ldb, g.N, g.K, n0, k0 + GBK, rb, tid);
+        if (k0 + BK < g.K) {  // the next stage's loads overlap this stage's products
+            load_stage<BM, BK, TA>(A, g.lda, g.M, g.K, m0, k0 + BK, ra, tid);
+            load_stage<BN, BK, TB>(B, g.ldb, g.N, g.K, n0, k0 + BK, rb, tid);
         }
 #pragma unroll
-        for (int kk = 0; kk < GBK; kk += 32) {
+        for (int kk = 0; kk < BK; kk += 32) {
             bf16x8 af[TM], bfr[TN];
 #pragma unroll
             for (int i = 0; i < TM; ++i)
@@ -429,21 +430,25 @@ __global__ void k_to_bf16(const float *__restrict__ a, bf16 *__restrict__ b, siz
     if (i < n) b[i] = (bf16)a[i];
 }
 
-// chi2[m] = sum of the row's epilogue partials in a fixed order; +INF for rows
-// outside the parameter domain
-__global__ void k_chi2_finish(const double *__restrict__ partial, int nparts, int M,
-                              const double *__restrict__ params, int rc, double *__restrict__ chi2)
+// chi2[m] = sum of the row's epilogue partials in a fixed order (one wave
+// per row: lane sums, then a butterfly); +INF for rows outside the domain
+__global__ __launch_bounds__(256) void k_chi2_finish(const double *__restrict__ partial, int nparts,
+                                                     int M, const double *__restrict__ params,
+                                                     int rc, double *__restrict__ chi2)
 {
-    const int m = blockIdx.x * blockDim.x + threadIdx.x;
-    if (m >= M) return;
+    const int m = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (m >= M) return;  // wave-uniform
     double c = 0.0;
-    for (int j = 0; j < nparts; ++j) c += partial[(size_t)m * nparts + j];
-    const double *p = params + (size_t)m * NPAR;
-    bool ok = true;
-    for (int k = 0; k < NPAR; ++k) ok = ok && isfinite(p[k]);
-    ok = ok && p[P_INC] > 0.0 && p[P_INC] < 90.0 && p[P_SIG] > 0.0 && p[P_R0] > 0.0 &&
-         p[P_RT] > 0.0 && (rc != RC_EPINAT || p[P_G] > 0.0);
-    chi2[m] = ok ? c : __builtin_inf();
+    for (int j = lane; j < nparts; j += 64) c += partial[(size_t)m * nparts + j];
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+    if (lane == 0) {
+        const double *p = params + (size_t)m * NPAR;
+        bool ok = true;
+        for (int k = 0; k < NPAR; ++k) ok = ok && isfinite(p[k]);
+        ok = ok && p[P_INC] > 0.0 && p[P_INC] < 90.0 && p[P_SIG] > 0.0 && p[P_R0] > 0.0 &&
+             p[P_RT] > 0.0 && (rc != RC_EPINAT || p[P_G] > 0.0);
+        chi2[m] = ok ? c : __builtin_inf();
+    }
 }
 
 __global__ void k_scale_maps(const float *__restrict__ y, int npix, size_t n, float *__restrict__ maps)
@@ -456,8 +461,9 @@ __global__ void k_scale_maps(const float *__restrict__ y, int npix, size_t n, fl
 
 bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }  // NULL passes
 
-// Tile edge for an M x N product: 128 when that still gives two tiles per
-// compute unit, else 64 (more, smaller tiles for the narrow layers).
+// Tile edge for an M x N product: 128 (K stages of 64) when that still gives
+// two tiles per compute unit, else 64 (K stages of 128: more, smaller tiles
+// for the narrow layers, with as many products per stage).
 int gemm_tile(int M, int N)
 {
     const long t = (long)((M + 127) / 128) * ((N + 127) / 128);
@@ -480,9 +486,9 @@ template <bool TA, bool TB, int EPI> gk_status gemm(const GemmArgs &g, hipStream
     if (EPI == EPI_CHI2 && g.obs.nparts != 2 * (int)grid.x)
         return fail(GK_EINVAL, "chi2 partial count mismatch");
     if (T == 128)
-        hipLaunchKernelGGL((k_gemm<128, 128, TA, TB, EPI>), grid, dim3(256), 0, s, g);
+        hipLaunchKernelGGL((k_gemm<128, 128, 64, TA, TB, EPI>), grid, dim3(256), 0, s, g);
     else
-        hipLaunchKernelGGL((k_gemm<64, 64, TA, TB, EPI>), grid, dim3(256), 0, s, g);
+        hipLaunchKernelGGL((k_gemm<64, 64, 128, TA, TB, EPI>), grid, dim3(256), 0, s, g);
     HIP_TRY(hipGetLastError());
     return GK_OK;
 }
@@ -728,8 +734,8 @@ gk_status infer_chi2(gk_surrogate *s, gk_model *m, int B, double *chi2, hipStrea
                2 * ((s->nout + T - 1) / T)};
     GemmArgs g{s->H[L - 1], s->Wb[L], in, in, B, s->nout, in, s->b[L], nullptr, nullptr, nullptr, 0, ob};
     GK_TRY((gemm<false, false, EPI_CHI2>(g, st)));
-    hipLaunchKernelGGL(k_chi2_finish, dim3(blocks(B)), dim3(256), 0, st, s->d_cpart, ob.nparts, B,
-                       s->d_params, m->d.rc, chi2);
+    hipLaunchKernelGGL(k_chi2_finish, dim3((B + 3) / 4), dim3(256), 0, st, s->d_cpart, ob.nparts,
+                       B, s->d_params, m->d.rc, chi2);
     HIP_TRY(hipGetLastError());
     return GK_OK;
 }

@@ -9,6 +9,7 @@
 
 #include <algorithm>
 #include <cfloat>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <functional>
@@ -151,14 +152,15 @@ gk_status ns_run(int d, const DrawEval &draw_eval, const gk_ns_opts &o, gk_ns_re
         std::vector<double> L(C, C + d * d);
         bool ell = cholesky(L, d);
         if (ell) {
-            double kmax = 0.0;
+            double kmax = 0.0, inv_diag[GK_NP];
+            for (int a = 0; a < d; ++a) inv_diag[a] = 1.0 / L[a * d + a];
             for (int i = 0; i < N; ++i) {  // Mahalanobis radius^2: solve L y = u - mu
                 const double *u = &live_u[(size_t)i * d];
                 double m2 = 0.0;
                 for (int a = 0; a < d; ++a) {
                     double s = u[a] - bnd.mu[a];
                     for (int b = 0; b < a; ++b) s -= L[a * d + b] * z[b];
-                    z[a] = s / L[a * d + a];
+                    z[a] = s * inv_diag[a];
                     m2 += z[a] * z[a];
                 }
                 kmax = std::max(kmax, m2);
@@ -488,6 +490,15 @@ gk_status fit_nested(gk_model *m, gk_surrogate *sur, const double *lo, const dou
     g.key1 = (uint32_t)(o.seed >> 32) ^ 0x6e736477u;
     DeviceGuard dg(m->device);
     HIP_TRY(dg.err);
+    using clock = std::chrono::steady_clock;
+    const auto t_start = clock::now();
+    double t_wait = 0.0;
+    auto wait = [&](hipStream_t st) -> hipError_t {
+        const auto t0 = clock::now();
+        const hipError_t e = hipStreamSynchronize(st);
+        t_wait += std::chrono::duration<double>(clock::now() - t0).count();
+        return e;
+    };
     double *h_params, *d_params, *d_chi2, *h_chi2;
     hipStream_t stream;
     const int rows = std::max(o.n_live, o.batch);
@@ -526,7 +537,7 @@ gk_status fit_nested(gk_model *m, gk_surrogate *sur, const double *lo, const dou
         if (!sur) {
             GK_TRY(run_batch(m, d_params, n, nullptr, nullptr, d_chi2, nullptr, stream));
             HIP_TRY(hipMemcpyAsync(h_chi2, d_chi2, sizeof(double) * n, hipMemcpyDeviceToHost, stream));
-            HIP_TRY(hipStreamSynchronize(stream));
+            HIP_TRY(wait(stream));
             std::memcpy(u, nb.h_u, sizeof(double) * n * d);
             n_plain += n;
             for (int i = 0; i < n; ++i) logl[i] = -0.5 * h_chi2[i];
@@ -535,7 +546,7 @@ gk_status fit_nested(gk_model *m, gk_surrogate *sur, const double *lo, const dou
         // surrogate chi2 of every candidate, then the plain chi2 of the survivors
         GK_TRY(surrogate_chi2(sur, m, d_params, n, d_chi2s, stream));
         HIP_TRY(hipMemcpyAsync(h_chi2s, d_chi2s, sizeof(double) * n, hipMemcpyDeviceToHost, stream));
-        HIP_TRY(hipStreamSynchronize(stream));
+        HIP_TRY(wait(stream));
         std::memcpy(u, nb.h_u, sizeof(double) * n * d);
         const double chi2_floor = floor > -DBL_MAX ? -2.0 * floor : INFINITY;
         const double cut = chi2_floor + shift + margin;
@@ -561,7 +572,7 @@ gk_status fit_nested(gk_model *m, gk_surrogate *sur, const double *lo, const dou
             HIP_TRY(hipGetLastError());
             GK_TRY(run_batch(m, nb.d_rows2, nk, nullptr, nullptr, d_chi2, nullptr, stream));
             HIP_TRY(hipMemcpyAsync(h_chi2, d_chi2, sizeof(double) * nk, hipMemcpyDeviceToHost, stream));
-            HIP_TRY(hipStreamSynchronize(stream));
+            HIP_TRY(wait(stream));
         }
         n_plain += nk;
         const size_t window = (size_t)std::max(o.n_live, o.batch);
@@ -591,6 +602,8 @@ gk_status fit_nested(gk_model *m, gk_surrogate *sur, const double *lo, const dou
     bool capped = false;
     GK_TRY(ns_run(d, eval, o, res, pu, pw, capped));
     res->n_evals = n_plain;  // plain evaluations only
+    res->t_wall_s = std::chrono::duration<double>(clock::now() - t_start).count();
+    res->t_wait_s = t_wait;
     double best_u[GK_NP];
     std::memcpy(best_u, res->best, sizeof best_u);
     for (int k = 0; k < NPAR; ++k) {

@@ -81,7 +81,8 @@ class NSResult(ctypes.Structure):
                 ("n_iter", ctypes.c_int64), ("n_evals", ctypes.c_int64),
                 ("n_launches", ctypes.c_int64)] + [
                 (n, ctypes.c_double * NPAR) for n in ("best", "mean", "sd", "median", "q16", "q84")] + [
-                (n, ctypes.c_int64) for n in ("n_screened", "n_rejected", "n_audited", "n_audit_miss")]
+                (n, ctypes.c_int64) for n in ("n_screened", "n_rejected", "n_audited", "n_audit_miss")] + [
+                ("t_wall_s", ctypes.c_double), ("t_wait_s", ctypes.c_double)]
 
 
 class TuneResult(ctypes.Structure):
@@ -126,7 +127,7 @@ def _ns_dict(r: "NSResult", st: int, dim: int, samples=None) -> dict:
     out = {"logz": r.logz, "logz_err": r.logz_err, "info_h": r.info_h, "max_logl": r.max_logl,
            "n_iter": r.n_iter, "n_evals": r.n_evals, "n_launches": r.n_launches, "status": st,
            "n_screened": r.n_screened, "n_rejected": r.n_rejected, "n_audited": r.n_audited,
-           "n_audit_miss": r.n_audit_miss}
+           "n_audit_miss": r.n_audit_miss, "t_wall_s": r.t_wall_s, "t_wait_s": r.t_wait_s}
     for n in ("best", "mean", "sd", "median", "q16", "q84"):
         out[n] = np.array(getattr(r, n)[:dim])
     if samples is not None:
