@@ -205,15 +205,27 @@ gk_status gk_fit_lm(gk_model *model, double *p_inout, const uint8_t *free_mask, 
                     const double *hi, const gk_lm_opts *opts, gk_lm_result *result);
 
 /* ---- Nested sampling (Sec. 2.3.2) -----------------------------------------
- * Single-ellipsoid nested sampling (Skilling 2004; ellipsoidal bound as in
- * Mukherjee et al. 2006) over a uniform prior box.  N live points; L =
- * exp(-chi2/2).  Each round fits the bounding ellipsoid of the live points
- * (covariance scaled to enclose them all, volume enlarged by `enlarge`),
- * draws `batch` candidates uniformly inside it and inside the box, evaluates
- * them in one launch, and consumes them in draw order: a candidate whose L
+ * Nested sampling (Skilling 2004) over a uniform prior box with an
+ * ellipsoidal bound (Mukherjee et al. 2006; several ellipsoids as in
+ * MultiNest, Feroz et al. 2009).  N live points; L = exp(-chi2/2).  Each round
+ * bounds the live points by an ellipsoid (covariance scaled to enclose them
+ * all, volume enlarged by `enlarge`), split recursively in two by 2-means
+ * while the two children's volumes sum to under half the parent's (each child
+ * keeping >= 2 (d + 1) points, at most max_ell ellipsoids, none smaller than
+ * the prior volume n_e X_k / N of its points), rebuilt after every N/20
+ * retired points (an older bound still encloses the shrinking constrained
+ * region); draws a batch of candidates
+ * uniformly over the union inside the box, evaluates them in one launch, and
+ * consumes them in draw order: a candidate whose L
  * exceeds the current lowest live L replaces that point, which is retired with
  * prior-volume weight X_{k-1} - X_k, X_k = exp(-k/N).  Stops when
  * log(Z + L_max X_k) - log Z < tol, then adds the live points with weight X_k/N.
+ * Batch: `batch` candidates per round, or, with batch_max > batch, as many
+ * as should give about N/10 acceptances at the acceptance rate of the last
+ * two rounds, within [batch, batch_max] (fewer, larger launches when the
+ * bound fits the constrained region poorly; the candidates of a round are
+ * still drawn from a bound that encloses the region, so the sampler's
+ * statistics are those of the fixed batch).
  * Random numbers: Philox4x32-10 (Salmon et al. 2011) keyed by `seed`. */
 typedef struct {
     int32_t n_live;      /* default 400 */
@@ -222,6 +234,8 @@ typedef struct {
     double enlarge;      /* ellipsoid volume factor; default 1.25 (= 1/e with e = 0.8) */
     double tol;          /* evidence tolerance; default 0.5 */
     uint64_t seed;       /* default 1 */
+    int32_t max_ell;     /* ellipsoids of the bound, 1..8; default 8 (1: one ellipsoid) */
+    int32_t batch_max;   /* adaptive batch ceiling (>= batch; 0: fixed batch); default 0 */
 } gk_ns_opts;
 
 typedef struct {

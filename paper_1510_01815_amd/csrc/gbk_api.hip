@@ -167,8 +167,8 @@ bool setup_fft(gk_model *m, const std::vector<double> &kp, std::vector<double2> 
     f.logPY = std::max(1, ceil_log2(m->EY));
     f.PX = 1 << f.logPX;
     f.PY = 1 << f.logPY;
-    if ((size_t)f.PX * sizeof(double2) > kMaxLds) return false;
     f.NLX = std::max<int>(1, (int)(32768 / (sizeof(double2) * f.PX)));
+    if (fft_x_lds_bytes(f) > kMaxLds) return false;
     f.DC = 0;
     for (int dc = 8; dc >= 1; dc /= 2) {
         f.DC = dc;

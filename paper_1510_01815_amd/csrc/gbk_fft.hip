@@ -25,9 +25,19 @@ __device__ inline double2 cmul(double2 a, double2 b)
     return double2{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
 }
 
-// In-place convolution of NL complex lines of length P = 2^logP in LDS.
-__device__ void fft_convolve(double2 *x, int NL, int P, int logP, const double2 *__restrict__ tw,
-                             const double *__restrict__ kbr)
+// Copies the twiddles (P/2) and the spectrum (P) of a line length into LDS
+// (tw_s, kb_s); the caller synchronises before use.
+__device__ inline void stage_tables(int P, const double2 *__restrict__ tw, const double *__restrict__ kbr,
+                                    double2 *tw_s, double *kb_s)
+{
+    for (int i = threadIdx.x; i < P / 2; i += blockDim.x) tw_s[i] = tw[i];
+    for (int i = threadIdx.x; i < P; i += blockDim.x) kb_s[i] = kbr[i];
+}
+
+// In-place convolution of NL complex lines of length P = 2^logP in LDS, with
+// the twiddles and the spectrum also in LDS.
+__device__ void fft_convolve(double2 *x, int NL, int P, int logP, const double2 *tw,
+                             const double *kbr)
 {
     const int hP = P >> 1, nb = NL * hP;
     for (int len = P, stride = 1; len >= 2; len >>= 1, stride <<= 1) {
@@ -68,6 +78,9 @@ __device__ void fft_convolve(double2 *x, int NL, int P, int logP, const double2 
 __global__ __launch_bounds__(256) void k_fft_x(FftArgs f)
 {
     extern __shared__ double2 sx[];
+    double2 *tw_s = sx + (size_t)f.NLX * f.PX;
+    double *kb_s = reinterpret_cast<double *>(tw_s + f.PX / 2);
+    stage_tables(f.PX, f.twx, f.kbx, tw_s, kb_s);
     const int b = blockIdx.y, nreal = 3 * f.EY;
     const int q0 = blockIdx.x * f.NLX;
     const int NL = min(f.NLX, (nreal + 1) / 2 - q0);
@@ -84,7 +97,7 @@ __global__ __launch_bounds__(256) void k_fft_x(FftArgs f)
         sx[i] = double2{re, im};
     }
     __syncthreads();
-    fft_convolve(sx, NL, f.PX, f.logPX, f.twx, f.kbx);
+    fft_convolve(sx, NL, f.PX, f.logPX, tw_s, kb_s);
     for (int i = threadIdx.x; i < NL * f.NXF; i += blockDim.x) {
         const int ql = i / f.NXF, X = i - ql * f.NXF;
         const int l0 = 2 * (q0 + ql), l1 = l0 + 1;
@@ -102,6 +115,9 @@ __global__ __launch_bounds__(256) void k_fft_y_moments(FftArgs f, PsfArgs a)
     extern __shared__ double2 sy[];
     const int b = blockIdx.y, cb = blockIdx.x, u = a.u;
     const int CW = u * f.DC, nreal = 3 * CW, nlc = (nreal + 1) / 2;
+    double2 *tw_s = sy + (size_t)nlc * f.PY;
+    double *kb_s = reinterpret_cast<double *>(tw_s + f.PY / 2);
+    stage_tables(f.PY, f.twy, f.kby, tw_s, kb_s);
     const int xd0 = cb * f.DC, X0 = xd0 * u;
     const double *U = f.U + (size_t)b * 3 * f.EY * f.NXF;
     const double *cbp = a.consts + (size_t)b * NCONST;
@@ -118,7 +134,7 @@ __global__ __launch_bounds__(256) void k_fft_y_moments(FftArgs f, PsfArgs a)
         sr[2 * ((L >> 1) * f.PY + y) + (L & 1)] = v;
     }
     __syncthreads();
-    fft_convolve(sy, nlc, f.PY, f.logPY, f.twy, f.kby);
+    fft_convolve(sy, nlc, f.PY, f.logPY, tw_s, kb_s);
 
     double acc = 0.0;
     const double inv_uu = 1.0 / ((double)u * u);
@@ -183,11 +199,16 @@ __global__ __launch_bounds__(256) void k_fft_y_moments(FftArgs f, PsfArgs a)
 
 }  // namespace
 
-size_t fft_x_lds_bytes(const FftArgs &f) { return sizeof(double2) * (size_t)f.NLX * f.PX; }
+// lines, then P/2 twiddles and P spectrum values
+size_t fft_x_lds_bytes(const FftArgs &f)
+{
+    return sizeof(double2) * ((size_t)f.NLX * f.PX + f.PX / 2) + sizeof(double) * f.PX;
+}
 
 size_t fft_y_lds_bytes(const FftArgs &f, int u)
 {
-    return sizeof(double2) * (size_t)((3 * u * f.DC + 1) / 2) * f.PY;
+    return sizeof(double2) * ((size_t)((3 * u * f.DC + 1) / 2) * f.PY + f.PY / 2) +
+           sizeof(double) * f.PY;
 }
 
 hipError_t launch_fft_x(const FftArgs &f, int B, hipStream_t s)

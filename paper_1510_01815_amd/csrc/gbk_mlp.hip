@@ -150,17 +150,16 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g)
 #pragma unroll
         for (int j = 0; j < TN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-    uint4 ra[BM * BK / 2048], rb[BN * BK / 2048];
-    load_stage<BM, BK, TA>(A, g.lda, g.M, g.K, m0, 0, ra, tid);
-    load_stage<BN, BK, TB>(B, g.ldb, g.N, g.K, n0, 0, rb, tid);
-    for (int k0 = 0; k0 < g.K; k0 += BK) {
-        store_stage<BM, BK, TA>(ra, As, tid);
-        store_stage<BN, BK, TB>(rb, Bs, tid);
-        __syncthreads();
-        if (k0 + BK < g.K) {  // the next stage's loads overlap this stage's products
-            load_stage<BM, BK, TA>(A, g.lda, g.M, g.K, m0, k0 + BK, ra, tid);
-            load_stage<BN, BK, TB>(B, g.ldb, g.N, g.K, n0, k0 + BK, rb, tid);
+    // two register sets: stage s + 2 is loaded while stage s is multiplied
+    constexpr int RA = BM * BK / 2048, RB = BN * BK / 2048;
+    uint4 ra0[RA], rb0[RB], ra1[RA], rb1[RB];
+    auto load = [&](int k0, uint4(&ra)[RA], uint4(&rb)[RB]) {
+        if (k0 < g.K) {
+            load_stage<BM, BK, TA>(A, g.lda, g.M, g.K, m0, k0, ra, tid);
+            load_stage<BN, BK, TB>(B, g.ldb, g.N, g.K, n0, k0, rb, tid);
         }
+    };
+    auto multiply = [&]() {
 #pragma unroll
         for (int kk = 0; kk < BK; kk += 32) {
             bf16x8 af[TM], bfr[TN];
@@ -178,7 +177,24 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g)
                 for (int j = 0; j < TN; ++j)
                     acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bfr[j], af[i], acc[i][j], 0, 0, 0);
         }
+    };
+    load(0, ra0, rb0);
+    load(BK, ra1, rb1);
+    for (int k0 = 0; k0 < g.K; k0 += 2 * BK) {
+        store_stage<BM, BK, TA>(ra0, As, tid);
+        store_stage<BN, BK, TB>(rb0, Bs, tid);
         __syncthreads();
+        load(k0 + 2 * BK, ra0, rb0);
+        multiply();
+        __syncthreads();
+        if (k0 + BK < g.K) {  // uniform
+            store_stage<BM, BK, TA>(ra1, As, tid);
+            store_stage<BN, BK, TB>(rb1, Bs, tid);
+            __syncthreads();
+            load(k0 + 3 * BK, ra1, rb1);
+            multiply();
+            __syncthreads();
+        }
     }
 
     // lane: row m = ... + lane % 16, columns n = ... + 4 (lane / 16) + r

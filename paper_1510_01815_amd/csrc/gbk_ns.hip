@@ -54,15 +54,169 @@ bool cholesky(std::vector<double> &M, int d)
 // Volume of the unit d-ball.
 double ball_volume(int d) { return std::pow(M_PI, 0.5 * d) / std::tgamma(0.5 * d + 1.0); }
 
-// Sampling region of a round: the enlarged bounding ellipsoid of the live
-// points, x = mu + L z with |z| <= 1 (L lower triangular, row-major d x d),
-// or the whole unit cube when ell is false.
+// Sampling region of a round: the union of up to kMaxEll ellipsoids
+// x = mu_e + L_e z, |z| <= 1 (L_e lower triangular, row-major d x d), drawn
+// from in proportion to their volumes (cum = cumulative volume fractions),
+// or the whole unit cube when n_ell is 0.
+constexpr int kMaxEll = 8;
 struct Bound {
-    int ell;
+    int n_ell;
     int d;
-    double mu[GK_NP];
-    double L[GK_NP * GK_NP];
+    double cum[kMaxEll];
+    double mu[kMaxEll][GK_NP];
+    double L[kMaxEll][GK_NP * GK_NP];
+    double inv_diag[kMaxEll][GK_NP];
 };
+
+// Enclosing ellipsoid of the points idx[0..n) of U [.][d]: covariance of the
+// points scaled to enclose them all, volume enlarged by `enlarge` and raised
+// to at least exp(min_logvol).  False if the covariance is not positive
+// definite.
+bool fit_ellipsoid(const double *U, const int *idx, int n, int d, double enlarge,
+                   double min_logvol, double *mu, double *L, double *inv_diag, double &logvol)
+{
+    double C[GK_NP * GK_NP] = {}, z[GK_NP];
+    for (int a = 0; a < d; ++a) mu[a] = 0.0;
+    for (int i = 0; i < n; ++i)
+        for (int a = 0; a < d; ++a) mu[a] += U[(size_t)idx[i] * d + a];
+    for (int a = 0; a < d; ++a) mu[a] /= n;
+    for (int i = 0; i < n; ++i) {
+        const double *u = &U[(size_t)idx[i] * d];
+        for (int a = 0; a < d; ++a) z[a] = u[a] - mu[a];
+        for (int a = 0; a < d; ++a)
+            for (int b = 0; b <= a; ++b) C[a * d + b] += z[a] * z[b];
+    }
+    for (int a = 0; a < d; ++a)
+        for (int b = 0; b <= a; ++b) C[b * d + a] = C[a * d + b] = C[a * d + b] / n;
+    for (int a = 0; a < d; ++a) C[a * d + a] += 1e-12;
+    std::vector<double> M(C, C + d * d);
+    if (!cholesky(M, d)) return false;
+    double invd[GK_NP], kmax = 0.0;
+    for (int a = 0; a < d; ++a) invd[a] = 1.0 / M[a * d + a];
+    for (int i = 0; i < n; ++i) {  // Mahalanobis radius^2: solve M y = u - mu
+        const double *u = &U[(size_t)idx[i] * d];
+        double m2 = 0.0;
+        for (int a = 0; a < d; ++a) {
+            double s = u[a] - mu[a];
+            for (int b = 0; b < a; ++b) s -= M[a * d + b] * z[b];
+            z[a] = s * invd[a];
+            m2 += z[a] * z[a];
+        }
+        kmax = std::max(kmax, m2);
+    }
+    double logdet = 0.0;
+    for (int a = 0; a < d; ++a) logdet += std::log(M[a * d + a]);
+    double scale2 = kmax * std::pow(enlarge, 2.0 / d);
+    logvol = std::log(ball_volume(d)) + 0.5 * d * std::log(scale2) + logdet;
+    if (logvol < min_logvol) {  // expand to the expected prior volume of its points
+        scale2 *= std::exp(2.0 * (min_logvol - logvol) / d);
+        logvol = min_logvol;
+    }
+    const double sc = std::sqrt(scale2);
+    for (int k = 0; k < d * d; ++k) L[k] = M[k] * sc;
+    for (int a = 0; a < d; ++a) inv_diag[a] = 1.0 / L[a * d + a];
+    return true;
+}
+
+// Region of the live points U [N][d] at prior volume exp(logX): one
+// enclosing ellipsoid, split recursively in two (2-means in unit-cube
+// coordinates) while the two children's volumes sum to less than half the
+// parent's and each child keeps at least 2 (d + 1) points, up to max_ell
+// ellipsoids (MultiNest's decomposition, simplified).  An ellipsoid is never
+// smaller than the prior volume its points stand for, n_e X / N.
+void build_bound(const double *U, int N, int d, double enlarge, double logX, int max_ell, Bound &bnd)
+{
+    bnd.d = d;
+    bnd.n_ell = 0;
+    struct Node {
+        std::vector<int> idx;
+        double mu[GK_NP], L[GK_NP * GK_NP], invd[GK_NP], logvol;
+    };
+    auto min_vol = [&](int n) { return logX + std::log((double)n / N); };
+    std::vector<Node> done, todo(1);
+    todo[0].idx.resize(N);
+    std::iota(todo[0].idx.begin(), todo[0].idx.end(), 0);
+    if (!fit_ellipsoid(U, todo[0].idx.data(), N, d, enlarge, min_vol(N), todo[0].mu, todo[0].L,
+                       todo[0].invd, todo[0].logvol))
+        return;  // degenerate: the whole cube
+    std::vector<double> w;
+    while (!todo.empty()) {
+        Node nd = std::move(todo.back());
+        todo.pop_back();
+        const int n = (int)nd.idx.size();
+        bool split = false;
+        if (max_ell > 1 && (int)(done.size() + todo.size()) + 2 <= max_ell && n >= 4 * (d + 1)) {
+            // the node's points relative to its centre (unit-cube coordinates, where
+            // every parameter is scaled by its prior range)
+            w.assign((size_t)n * d, 0.0);
+            for (int i = 0; i < n; ++i)
+                for (int a = 0; a < d; ++a)
+                    w[(size_t)i * d + a] = U[(size_t)nd.idx[i] * d + a] - nd.mu[a];
+            auto dist2 = [&](const double *x, const double *c) {
+                double s = 0.0;
+                for (int a = 0; a < d; ++a) s += (x[a] - c[a]) * (x[a] - c[a]);
+                return s;
+            };
+            // 2-means: start from the point farthest from the centre and the one farthest from it
+            double c0[GK_NP], c1[GK_NP], zero[GK_NP] = {};
+            int f0 = 0, f1 = 0;
+            for (int i = 1; i < n; ++i)
+                if (dist2(&w[(size_t)i * d], zero) > dist2(&w[(size_t)f0 * d], zero)) f0 = i;
+            for (int i = 1; i < n; ++i)
+                if (dist2(&w[(size_t)i * d], &w[(size_t)f0 * d]) > dist2(&w[(size_t)f1 * d], &w[(size_t)f0 * d])) f1 = i;
+            std::copy_n(&w[(size_t)f0 * d], d, c0);
+            std::copy_n(&w[(size_t)f1 * d], d, c1);
+            std::vector<char> lab(n, 0);
+            for (int it = 0; it < 20; ++it) {
+                bool changed = false;
+                double s0[GK_NP] = {}, s1[GK_NP] = {};
+                int n0 = 0, n1 = 0;
+                for (int i = 0; i < n; ++i) {
+                    const double *y = &w[(size_t)i * d];
+                    const char l = dist2(y, c1) < dist2(y, c0) ? 1 : 0;
+                    changed = changed || l != lab[i];
+                    lab[i] = l;
+                    double *acc = l ? s1 : s0;
+                    for (int a = 0; a < d; ++a) acc[a] += y[a];
+                    (l ? n1 : n0) += 1;
+                }
+                if (n0 == 0 || n1 == 0) break;
+                for (int a = 0; a < d; ++a) {
+                    c0[a] = s0[a] / n0;
+                    c1[a] = s1[a] / n1;
+                }
+                if (!changed && it > 0) break;
+            }
+            Node ch[2];
+            for (int i = 0; i < n; ++i) ch[(int)lab[i]].idx.push_back(nd.idx[i]);
+            const int n0 = (int)ch[0].idx.size(), n1 = (int)ch[1].idx.size();
+            if (n0 >= 2 * (d + 1) && n1 >= 2 * (d + 1) &&
+                fit_ellipsoid(U, ch[0].idx.data(), n0, d, enlarge, min_vol(n0), ch[0].mu, ch[0].L,
+                              ch[0].invd, ch[0].logvol) &&
+                fit_ellipsoid(U, ch[1].idx.data(), n1, d, enlarge, min_vol(n1), ch[1].mu, ch[1].L,
+                              ch[1].invd, ch[1].logvol) &&
+                logaddexp(ch[0].logvol, ch[1].logvol) < nd.logvol + std::log(0.5)) {
+                todo.push_back(std::move(ch[0]));
+                todo.push_back(std::move(ch[1]));
+                split = true;
+            }
+        }
+        if (!split) done.push_back(std::move(nd));
+    }
+    double logtot = -INFINITY;
+    for (auto &e : done) logtot = logaddexp(logtot, e.logvol);
+    if (logtot >= 0.0) return;  // the union is larger than the box: the whole cube
+    bnd.n_ell = (int)done.size();
+    double c = 0.0;
+    for (int e = 0; e < bnd.n_ell; ++e) {
+        c += std::exp(done[e].logvol - logtot);
+        bnd.cum[e] = c;
+        std::copy_n(done[e].mu, d, bnd.mu[e]);
+        std::copy_n(done[e].L, d * d, bnd.L[e]);
+        std::copy_n(done[e].invd, d, bnd.inv_diag[e]);
+    }
+    bnd.cum[bnd.n_ell - 1] = 1.0;
+}
 
 // Draws n candidates from bnd (NULL: the first live points, uniform in the
 // cube), evaluates them and returns their unit-cube coordinates u [n][d] and
@@ -71,18 +225,39 @@ struct Bound {
 using DrawEval = std::function<gk_status(const Bound *bnd, int n, int64_t round, double floor,
                                          double *u, double *logl)>;
 
-// Candidates from bnd with a sequential Philox stream (host side): a
-// direction from d normals, a radius from U^(1/d), rejected until inside
-// the cube (after 10^5 rejections, uniform in the cube).
+// True if x lies in ellipsoid e of bnd.
+__host__ __device__ inline bool in_ellipsoid(const Bound &bnd, int e, const double *x)
+{
+    const int d = bnd.d;
+    double y[GK_NP], m2 = 0.0;
+    for (int a = 0; a < d; ++a) {
+        double t = x[a] - bnd.mu[e][a];
+        for (int b = 0; b < a; ++b) t -= bnd.L[e][a * d + b] * y[b];
+        y[a] = t * bnd.inv_diag[e][a];
+        m2 += y[a] * y[a];
+    }
+    return m2 <= 1.0;
+}
+
+// Candidates from bnd with a sequential Philox stream (host side): pick an
+// ellipsoid by volume, a direction from d normals and a radius U^(1/d);
+// reject outside the cube, and keep a point lying in q ellipsoids with
+// probability 1/q (uniform over the union).  After 10^5 rejections, uniform
+// in the cube.
 void draw_host(const Bound *bnd, int n, int d, Rng &rng, double *ub)
 {
     double z[GK_NP];
     for (int c = 0; c < n; ++c) {
         double *u = ub + (size_t)c * d;
         for (int tries = 0;; ++tries) {
-            if (!bnd || !bnd->ell || tries > 100000) {
+            if (!bnd || bnd->n_ell == 0 || tries > 100000) {
                 for (int a = 0; a < d; ++a) u[a] = rng.uniform();
                 break;
+            }
+            int e = 0;
+            if (bnd->n_ell > 1) {
+                const double pick = rng.uniform();
+                while (e < bnd->n_ell - 1 && bnd->cum[e] < pick) ++e;
             }
             double nrm = 0.0;
             for (int a = 0; a < d; ++a) {
@@ -92,12 +267,18 @@ void draw_host(const Bound *bnd, int n, int d, Rng &rng, double *ub)
             const double rad = std::pow(rng.uniform(), 1.0 / d) / std::sqrt(nrm);
             bool inside = true;
             for (int a = 0; a < d; ++a) {
-                double s = bnd->mu[a];
-                for (int b = 0; b <= a; ++b) s += bnd->L[a * d + b] * z[b] * rad;
+                double s = bnd->mu[e][a];
+                for (int b = 0; b <= a; ++b) s += bnd->L[e][a * d + b] * z[b] * rad;
                 u[a] = s;
                 inside = inside && s > 0.0 && s < 1.0;
             }
-            if (inside) break;
+            if (!inside) continue;
+            if (bnd->n_ell > 1) {
+                int q = 1;
+                for (int f = 0; f < bnd->n_ell; ++f) q += f != e && in_ellipsoid(*bnd, f, u);
+                if (q > 1 && !(rng.uniform() * q < 1.0)) continue;
+            }
+            break;
         }
     }
 }
@@ -108,9 +289,11 @@ void draw_host(const Bound *bnd, int n, int d, Rng &rng, double *ub)
 gk_status ns_run(int d, const DrawEval &draw_eval, const gk_ns_opts &o, gk_ns_result *res,
                  std::vector<double> &post_u, std::vector<double> &post_w, bool &capped)
 {
-    const int N = o.n_live, B = o.batch;
+    const int N = o.n_live, Bmax = std::max(o.batch, o.batch_max);
     std::vector<double> live_u((size_t)N * d), live_l(N);
-    std::vector<double> ub((size_t)std::max(N, B) * d), lb(std::max(N, B));
+    std::vector<double> ub((size_t)std::max(N, Bmax) * d), lb(std::max(N, Bmax));
+    int B = o.batch;
+    double acc_prev = -1.0, cand_prev = 0.0;  // acceptances and candidates of the last round
     GK_TRY(draw_eval(nullptr, N, 0, -DBL_MAX, live_u.data(), lb.data()));
     int64_t n_evals = N, n_launch = 1;
     for (int i = 0; i < N; ++i) live_l[i] = std::isfinite(lb[i]) ? lb[i] : -DBL_MAX;
@@ -131,51 +314,20 @@ gk_status ns_run(int d, const DrawEval &draw_eval, const gk_ns_opts &o, gk_ns_re
     bool done = false;
     capped = false;
     Bound bnd{};
-    bnd.d = d;
-    double C[GK_NP * GK_NP], z[GK_NP];
+    // The bound is rebuilt after every N/20 retired points (and at the start):
+    // an older bound still contains the current, smaller constrained region,
+    // so it stays valid, only less tight.
+    const int64_t rebuild = std::max(1, N / 20);
+    int64_t k_built = -rebuild;
     while (!done) {
-        // bounding ellipsoid of the live points (unit-cube coordinates)
-        for (int a = 0; a < d; ++a) bnd.mu[a] = 0.0;
-        for (int i = 0; i < N; ++i)
-            for (int a = 0; a < d; ++a) bnd.mu[a] += live_u[(size_t)i * d + a];
-        for (int a = 0; a < d; ++a) bnd.mu[a] /= N;
-        std::fill(C, C + d * d, 0.0);
-        for (int i = 0; i < N; ++i) {
-            const double *u = &live_u[(size_t)i * d];
-            for (int a = 0; a < d; ++a) z[a] = u[a] - bnd.mu[a];
-            for (int a = 0; a < d; ++a)
-                for (int b = 0; b <= a; ++b) C[a * d + b] += z[a] * z[b];
+        if (k - k_built >= rebuild) {
+            build_bound(live_u.data(), N, d, o.enlarge, -(double)k / N, o.max_ell, bnd);
+            k_built = k;
         }
-        for (int a = 0; a < d; ++a)
-            for (int b = 0; b <= a; ++b) C[b * d + a] = C[a * d + b] = C[a * d + b] / N;
-        for (int a = 0; a < d; ++a) C[a * d + a] += 1e-12;
-        std::vector<double> L(C, C + d * d);
-        bool ell = cholesky(L, d);
-        if (ell) {
-            double kmax = 0.0, inv_diag[GK_NP];
-            for (int a = 0; a < d; ++a) inv_diag[a] = 1.0 / L[a * d + a];
-            for (int i = 0; i < N; ++i) {  // Mahalanobis radius^2: solve L y = u - mu
-                const double *u = &live_u[(size_t)i * d];
-                double m2 = 0.0;
-                for (int a = 0; a < d; ++a) {
-                    double s = u[a] - bnd.mu[a];
-                    for (int b = 0; b < a; ++b) s -= L[a * d + b] * z[b];
-                    z[a] = s * inv_diag[a];
-                    m2 += z[a] * z[a];
-                }
-                kmax = std::max(kmax, m2);
-            }
-            const double scale2 = kmax * std::pow(o.enlarge, 2.0 / d);
-            double logdet = 0.0;
-            for (int a = 0; a < d; ++a) logdet += std::log(L[a * d + a]);
-            const double logvol = std::log(ball_volume(d)) + 0.5 * d * std::log(scale2) + logdet;
-            if (logvol >= 0.0) ell = false;  // the ellipsoid is larger than the box
-            for (int a = 0; a < d * d; ++a) bnd.L[a] = L[a] * std::sqrt(scale2);
-        }
-        bnd.ell = ell;
         GK_TRY(draw_eval(&bnd, B, n_launch, heap.front().first, ub.data(), lb.data()));
         n_evals += B;
         ++n_launch;
+        const int64_t k_round = k;
         for (int c = 0; c < B && !done; ++c) {
             const double lc = std::isfinite(lb[c]) ? lb[c] : -DBL_MAX;
             const int imin = heap.front().second;
@@ -201,6 +353,14 @@ gk_status ns_run(int d, const DrawEval &draw_eval, const gk_ns_opts &o, gk_ns_re
                 done = true;
                 capped = true;
             }
+        }
+        if (Bmax > o.batch) {  // next batch from the acceptance rate of the last two rounds
+            const double acc = (double)(k - k_round), cand = B;
+            const double rate = acc_prev < 0.0 ? acc / cand : (acc + acc_prev) / (cand + cand_prev);
+            acc_prev = acc;
+            cand_prev = cand;
+            const double want = rate > 0.0 ? std::ceil(std::max(1, N / 10) / rate) : (double)Bmax;
+            B = (int)std::min<double>(Bmax, std::max<double>(o.batch, want));
         }
     }
     // final live points with weight X_k / N
@@ -269,7 +429,8 @@ void posterior_stats(const std::vector<double> &pu, const std::vector<double> &p
 
 gk_status check_opts(const gk_ns_opts &o)
 {
-    if (o.n_live < 2 || o.batch < 1 || o.max_iter < 1 || !(o.enlarge >= 1.0) || !(o.tol > 0.0))
+    if (o.n_live < 2 || o.batch < 1 || o.max_iter < 1 || !(o.enlarge >= 1.0) || !(o.tol > 0.0) ||
+        o.max_ell < 1 || o.max_ell > kMaxEll || (o.batch_max != 0 && o.batch_max < o.batch))
         return fail(GK_EINVAL, "invalid nested-sampling options");
     return GK_OK;
 }
@@ -292,6 +453,8 @@ extern "C" gk_status gk_ns_default_opts(gk_ns_opts *o)
     o->enlarge = 1.25;
     o->tol = 0.5;
     o->seed = 1;
+    o->max_ell = 8;
+    o->batch_max = 0;
     return GK_OK;
 }
 
@@ -358,8 +521,8 @@ namespace {
 // rejections, uniform in the cube).
 // ---------------------------------------------------------------------------
 struct DrawArgs {
-    Bound bnd;
-    int n, round_valid;
+    const Bound *bnd;  // device copy of the round's region
+    int d, n, round_valid;
     uint64_t round;
     uint32_t key0, key1;
     int fr[GK_NP];
@@ -391,7 +554,7 @@ __global__ __launch_bounds__(64) void k_ns_draw(DrawArgs g)
 {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= g.n) return;
-    const int d = g.bnd.d;
+    const int d = g.d;
     DevStream rs;
     rs.ctr[0] = (uint32_t)c;
     rs.ctr[1] = (uint32_t)g.round;
@@ -402,8 +565,14 @@ __global__ __launch_bounds__(64) void k_ns_draw(DrawArgs g)
     rs.left = 0;
     double x[GK_NP], z[GK_NP];
     bool drawn = false;
-    if (g.round_valid && g.bnd.ell) {
+    if (g.round_valid && g.bnd->n_ell > 0) {
+        const Bound &bnd = *g.bnd;
         for (int tries = 0; tries < 10000 && !drawn; ++tries) {
+            int e = 0;
+            if (bnd.n_ell > 1) {
+                const double pick = rs.uniform();
+                while (e < bnd.n_ell - 1 && bnd.cum[e] < pick) ++e;
+            }
             double nrm = 0.0;
             for (int a = 0; a < d; a += 2) {
                 const double u1 = rs.uniform(), u2 = rs.uniform();
@@ -415,12 +584,18 @@ __global__ __launch_bounds__(64) void k_ns_draw(DrawArgs g)
             const double rad = pow(rs.uniform(), 1.0 / d) / sqrt(nrm);
             bool inside = true;
             for (int a = 0; a < d; ++a) {
-                double v = g.bnd.mu[a];
-                for (int b = 0; b <= a; ++b) v += g.bnd.L[a * d + b] * z[b] * rad;
+                double v = bnd.mu[e][a];
+                for (int b = 0; b <= a; ++b) v += bnd.L[e][a * d + b] * z[b] * rad;
                 x[a] = v;
                 inside = inside && v > 0.0 && v < 1.0;
             }
-            drawn = inside;
+            if (!inside) continue;
+            if (bnd.n_ell > 1) {
+                int q = 1;
+                for (int f = 0; f < bnd.n_ell; ++f) q += f != e && in_ellipsoid(bnd, f, x);
+                if (q > 1 && !(rs.uniform() * q < 1.0)) continue;
+            }
+            drawn = true;
         }
     }
     if (!drawn)
@@ -447,8 +622,11 @@ __global__ void k_gather_rows(const double *__restrict__ src, const int *__restr
 struct NsBuffers {
     double *d_u = nullptr, *d_rows2 = nullptr, *h_u = nullptr;
     int *d_idx = nullptr, *h_idx = nullptr;
+    Bound *d_bnd = nullptr, *h_bnd = nullptr;
     ~NsBuffers()
     {
+        (void)hipFree(d_bnd);
+        if (h_bnd) (void)hipHostFree(h_bnd);
         (void)hipFree(d_u);
         (void)hipFree(d_rows2);
         (void)hipFree(d_idx);
@@ -501,12 +679,14 @@ gk_status fit_nested(gk_model *m, gk_surrogate *sur, const double *lo, const dou
     };
     double *h_params, *d_params, *d_chi2, *h_chi2;
     hipStream_t stream;
-    const int rows = std::max(o.n_live, o.batch);
+    const int rows = std::max({o.n_live, o.batch, o.batch_max});
     // chi2 rows, then (screened) surrogate chi2 rows
     GK_TRY(fit_reserve_rows(m, 2 * rows, &h_params, &d_params, &d_chi2, &h_chi2, &stream));
     double *d_chi2s = d_chi2 + rows, *h_chi2s = h_chi2 + rows;
     NsBuffers nb;
     HIP_TRY(hipMalloc((void **)&nb.d_u, sizeof(double) * rows * d));
+    HIP_TRY(hipMalloc((void **)&nb.d_bnd, sizeof(Bound)));
+    HIP_TRY(hipHostMalloc((void **)&nb.h_bnd, sizeof(Bound), 0));
     HIP_TRY(hipHostMalloc((void **)&nb.h_u, sizeof(double) * rows * d, 0));
     if (sur) {
         HIP_TRY(hipMalloc((void **)&nb.d_rows2, sizeof(double) * rows * NPAR));
@@ -524,10 +704,15 @@ gk_status fit_nested(gk_model *m, gk_surrogate *sur, const double *lo, const dou
     DrawEval eval = [&](const Bound *bnd, int n, int64_t round, double floor, double *u,
                         double *logl) -> gk_status {
         g.n = n;
+        g.d = d;
         g.round = (uint64_t)round;
         g.round_valid = bnd != nullptr;
-        if (bnd) g.bnd = *bnd;
-        g.bnd.d = d;
+        if (bnd) {
+            // the pinned copy is free: every earlier round ended with a stream synchronisation
+            std::memcpy(nb.h_bnd, bnd, sizeof(Bound));
+            HIP_TRY(hipMemcpyAsync(nb.d_bnd, nb.h_bnd, sizeof(Bound), hipMemcpyHostToDevice, stream));
+        }
+        g.bnd = nb.d_bnd;
         g.u = nb.d_u;
         g.rows = d_params;
         hipLaunchKernelGGL(k_ns_draw, dim3((n + 63) / 64), dim3(64), 0, stream, g);
@@ -575,7 +760,7 @@ gk_status fit_nested(gk_model *m, gk_surrogate *sur, const double *lo, const dou
             HIP_TRY(wait(stream));
         }
         n_plain += nk;
-        const size_t window = (size_t)std::max(o.n_live, o.batch);
+        const size_t window = (size_t)std::max(o.n_live, o.batch);  // recent plain evaluations
         for (int j = 0; j < nk; ++j) {
             const int i = keep[j];
             const double c = h_chi2[j];

@@ -84,3 +84,67 @@ def test_ns_callback_failure_is_an_error():
         raise RuntimeError("boom")
     with pytest.raises(gbk.GkError):
         gbk.nested_sample(bad, [0.0], [1.0], n_live=10)
+
+
+def test_ns_two_modes_split_bound():
+    """Two separated Gaussian modes of equal mass: the evidence is analytic,
+    each mode carries half the posterior, and the multi-ellipsoid bound needs
+    far fewer evaluations than one ellipsoid."""
+    from paper_1510_01815_amd import gbk
+
+    def f(th):
+        a = np.sum((th - np.array([-3.0, 0.0])) ** 2, axis=1)
+        b = np.sum((th - np.array([3.0, 0.0])) ** 2, axis=1)
+        return np.logaddexp(-a / 0.18, -b / 0.18)  # sigma = 0.3
+    lo, hi = np.array([-6.0, -6.0]), np.array([6.0, 6.0])
+    true = math.log(2 * 2 * math.pi * 0.09 / 144)
+    multi = gbk.nested_sample(f, lo, hi, want_samples=100000, n_live=400, seed=3)
+    single = gbk.nested_sample(f, lo, hi, n_live=400, seed=3, max_ell=1)
+    for r in (multi, single):
+        assert abs(r["logz"] - true) < 3 * r["logz_err"] + 0.1
+    w, x = multi["samples"][:, -1], multi["samples"][:, 0]
+    assert abs(w[x < 0].sum() - 0.5) < 0.1
+    assert multi["n_evals"] < 0.6 * single["n_evals"]
+
+
+def test_ns_curved_posterior():
+    """Banana likelihood exp(-x^2/2 - (y - x^2)^2 / (2 0.1^2)): Z, the
+    moments of x ~ N(0, 1) and of y = x^2 + N(0, 0.01) (mean 1, variance
+    2.01) are analytic; the split bound follows the curve with several times
+    fewer evaluations."""
+    from paper_1510_01815_amd import gbk
+
+    def f(th):
+        x, y = th[:, 0], th[:, 1]
+        return -x ** 2 / 2 - (y - x ** 2) ** 2 / 0.02
+    lo, hi = np.array([-5.0, -2.0]), np.array([5.0, 28.0])
+    true = math.log(2 * math.pi * 0.1 / 300)
+    multi = gbk.nested_sample(f, lo, hi, n_live=400, seed=5)
+    single = gbk.nested_sample(f, lo, hi, n_live=400, seed=5, max_ell=1)
+    for r in (multi, single):
+        assert abs(r["logz"] - true) < 3 * r["logz_err"] + 0.1
+        assert abs(r["mean"][0]) < 0.1 and abs(r["sd"][0] - 1.0) < 0.1
+        assert abs(r["mean"][1] - 1.0) < 0.15 and abs(r["sd"][1] - math.sqrt(2.01)) < 0.15
+    assert multi["n_evals"] < 0.4 * single["n_evals"]
+
+
+def test_ns_adaptive_batch_keeps_the_statistics():
+    """Where the bound fits poorly (one ellipsoid on the curved likelihood) a
+    batch that grows with falling acceptance needs far fewer rounds, and the
+    evidence and posterior moments stay within their errors."""
+    from paper_1510_01815_amd import gbk
+
+    def f(th):
+        x, y = th[:, 0], th[:, 1]
+        return -x ** 2 / 2 - (y - x ** 2) ** 2 / 0.02
+    lo, hi = np.array([-5.0, -2.0]), np.array([5.0, 28.0])
+    true = math.log(2 * math.pi * 0.1 / 300)
+    fixed = gbk.nested_sample(f, lo, hi, n_live=400, seed=5, max_ell=1)
+    grow = gbk.nested_sample(f, lo, hi, n_live=400, seed=5, max_ell=1, batch_max=6400)
+    assert grow["n_launches"] < 0.5 * fixed["n_launches"]
+    for r in (fixed, grow):
+        assert abs(r["logz"] - true) < 3 * r["logz_err"] + 0.1
+        assert abs(r["mean"][0]) < 0.1 and abs(r["sd"][0] - 1.0) < 0.1
+        assert abs(r["mean"][1] - 1.0) < 0.15 and abs(r["sd"][1] - math.sqrt(2.01)) < 0.15
+    with pytest.raises(gbk.GkError):
+        gbk.nested_sample(f, lo, hi, n_live=400, batch=400, batch_max=100)
