@@ -727,8 +727,9 @@ gk_status stage_params(gk_surrogate *s, const double *params, int B, hipStream_t
     return GK_OK;
 }
 
-// inference chunk: rows per pass through the network
-int infer_chunk(const gk_surrogate *s) { return std::max(s->o.batch, 2048); }
+// inference chunk: rows per pass through the network (large passes keep
+// the narrow hidden-layer products busy on every compute unit)
+int infer_chunk(const gk_surrogate *s) { return std::max(s->o.batch, 8192); }
 
 gk_status encode_rows(gk_surrogate *s, int B, hipStream_t st)
 {
