@@ -49,7 +49,8 @@ enum Epi {
 };
 
 // observation terms of the fused chi2 epilogue: column n < npix is the velocity
-// map at pixel n, n >= npix the dispersion map at pixel n - npix
+// map at pixel n, n >= npix the dispersion map at pixel n - npix (mask NULL:
+// every pixel counts)
 struct ObsArgs {
     const uint8_t *mask;
     const float *vo, *so;
@@ -266,7 +267,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g)
                     if (n >= g.N) continue;
                     const bool vel = n < g.obs.npix;
                     const int p = vel ? n : n - g.obs.npix;
-                    if (!g.obs.mask[p]) continue;
+                    if (g.obs.mask && !g.obs.mask[p]) continue;
                     const float y = v[r] * (vel ? kVelScale : kSigScale);
                     const double d = ((double)y - (vel ? g.obs.vo[p] : g.obs.so[p])) *
                                      (vel ? g.obs.iev[p] : g.obs.ies[p]);
@@ -475,6 +476,34 @@ __global__ void k_scale_maps(const float *__restrict__ y, int npix, size_t n, fl
     maps[i] = y[i] * (r < (size_t)npix ? kVelScale : kSigScale);
 }
 
+// Rows of the compact output layer: row j < nv is velocity pixel idx[j], row
+// nv + j dispersion pixel idx[j]; one block per row.
+__global__ void k_compact_rows(const bf16 *__restrict__ W, const float *__restrict__ bias, int hidden,
+                               int npix, const int *__restrict__ idx, int nv, bf16 *__restrict__ Wc,
+                               float *__restrict__ bc)
+{
+    const int j = blockIdx.x;
+    const int src = j < nv ? idx[j] : npix + idx[j - nv];
+    for (int k = threadIdx.x; k < hidden; k += blockDim.x)
+        Wc[(size_t)j * hidden + k] = W[(size_t)src * hidden + k];
+    if (threadIdx.x == 0) bc[j] = bias[src];
+}
+
+__global__ void k_compact_obs(const float *__restrict__ vo, const float *__restrict__ so,
+                              const double *__restrict__ iev, const double *__restrict__ ies,
+                              const int *__restrict__ idx, int nv, float *__restrict__ cvo,
+                              float *__restrict__ cso, double *__restrict__ ciev,
+                              double *__restrict__ cies)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= nv) return;
+    const int p = idx[j];
+    cvo[j] = vo[p];
+    cso[j] = so[p];
+    ciev[j] = iev[p];
+    cies[j] = ies[p];
+}
+
 bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }  // NULL passes
 
 // Tile edge for an M x N product: 128 (K stages of 64) when that still gives
@@ -519,6 +548,17 @@ unsigned blocks(size_t n, unsigned t = 256) { return (unsigned)((n + t - 1) / t)
 struct gk_surrogate {
     gk_model *model = nullptr;  // the instrument whose plain evaluation trains the network
     int device = 0;
+    uint64_t wver = 0;          // bumped whenever the weights change
+    // output layer restricted to the unmasked pixels of one observation (the
+    // chi2 needs no other outputs): rows of W_o and b_o for the velocity, then
+    // the dispersion, of each unmasked pixel, and that pixel's observation
+    const gk_model *c_model = nullptr;
+    uint64_t c_gen = 0, c_wver = 0;
+    int c_nv = -1;
+    bf16 *c_W = nullptr;
+    float *c_b = nullptr, *c_vo = nullptr, *c_so = nullptr;
+    double *c_iev = nullptr, *c_ies = nullptr;
+    int *c_idx = nullptr;
     gk_surrogate_opts o{};
     int npix = 0, nout = 0, layers = 0;
     double lo[NPAR]{}, hi[NPAR]{};
@@ -576,6 +616,18 @@ struct gk_surrogate {
         d_params = h_params = d_partial = d_cpart = nullptr;
         cap = 0;
     }
+    void free_compact()
+    {
+        for (void *p : {(void *)c_W, (void *)c_b, (void *)c_vo, (void *)c_so, (void *)c_iev,
+                        (void *)c_ies, (void *)c_idx})
+            if (p) (void)hipFree(p);
+        c_W = nullptr;
+        c_b = c_vo = c_so = nullptr;
+        c_iev = c_ies = nullptr;
+        c_idx = nullptr;
+        c_model = nullptr;
+        c_nv = -1;
+    }
     void release()
     {
         if (stream) (void)hipStreamSynchronize(stream);
@@ -586,6 +638,7 @@ struct gk_surrogate {
         (void)hipFree(d_lo);
         (void)hipFree(d_hi);
         (void)hipFree(d_loss);
+        free_compact();
         if (ev_staged) (void)hipEventDestroy(ev_staged);
         if (stream) (void)hipStreamDestroy(stream);
     }
@@ -694,6 +747,7 @@ gk_status loss_and_grads(gk_surrogate *s, int M, float *loss_dev, hipStream_t st
 gk_status adam(gk_surrogate *s, double lr, hipStream_t st)
 {
     s->step += 1;
+    s->wver += 1;
     const double t = (double)s->step;
     const float c1 = (float)(1.0 / (1.0 - std::pow(0.9, t)));
     const float c2 = (float)(1.0 / (1.0 - std::pow(0.999, t)));
@@ -741,18 +795,61 @@ gk_status encode_rows(gk_surrogate *s, int B, hipStream_t st)
 
 // surrogate chi2 of the B rows in s->d_params against m's observation: the
 // output layer reduces its own residuals, so the maps never reach memory
+// The compact output layer for m's current observation and the current weights.
+gk_status compact_output(gk_surrogate *s, gk_model *m, hipStream_t st)
+{
+    if (s->c_model == m && s->c_gen == m->gen && s->c_wver == s->wver && s->c_nv >= 0)
+        return GK_OK;
+    std::vector<uint8_t> mask(s->npix);
+    HIP_TRY(hipStreamSynchronize(st));
+    HIP_TRY(hipMemcpy(mask.data(), m->d_mask, s->npix, hipMemcpyDeviceToHost));
+    std::vector<int> idx;
+    for (int p = 0; p < s->npix; ++p)
+        if (mask[p]) idx.push_back(p);
+    s->free_compact();
+    const int nv = (int)idx.size(), hid = s->o.hidden;
+    if (nv > 0) {
+        HIP_TRY(hipMalloc((void **)&s->c_W, (size_t)2 * nv * hid * sizeof(bf16)));
+        HIP_TRY(hipMalloc((void **)&s->c_b, (size_t)2 * nv * sizeof(float)));
+        HIP_TRY(hipMalloc((void **)&s->c_vo, (size_t)nv * sizeof(float)));
+        HIP_TRY(hipMalloc((void **)&s->c_so, (size_t)nv * sizeof(float)));
+        HIP_TRY(hipMalloc((void **)&s->c_iev, (size_t)nv * sizeof(double)));
+        HIP_TRY(hipMalloc((void **)&s->c_ies, (size_t)nv * sizeof(double)));
+        HIP_TRY(hipMalloc((void **)&s->c_idx, (size_t)nv * sizeof(int)));
+        HIP_TRY(hipMemcpy(s->c_idx, idx.data(), (size_t)nv * sizeof(int), hipMemcpyHostToDevice));
+        const int L = s->layers;
+        hipLaunchKernelGGL(k_compact_rows, dim3(2 * nv), dim3(256), 0, st, s->Wb[L], s->b[L], hid,
+                           s->npix, s->c_idx, nv, s->c_W, s->c_b);
+        hipLaunchKernelGGL(k_compact_obs, dim3(blocks(nv)), dim3(256), 0, st, m->d_vo, m->d_so,
+                           m->d_iev, m->d_ies, s->c_idx, nv, s->c_vo, s->c_so, s->c_iev, s->c_ies);
+        HIP_TRY(hipGetLastError());
+    }
+    s->c_nv = nv;
+    s->c_model = m;
+    s->c_gen = m->gen;
+    s->c_wver = s->wver;
+    return GK_OK;
+}
+
+// surrogate chi2 of the B rows in s->d_params against m's observation: the
+// output layer, restricted to the unmasked pixels, reduces its own
+// residuals, so the maps never reach memory
 gk_status infer_chi2(gk_surrogate *s, gk_model *m, int B, double *chi2, hipStream_t st)
 {
+    GK_TRY(compact_output(s, m, st));
     GK_TRY(encode_rows(s, B, st));
     GK_TRY(hidden_layers(s, B, false, st));
-    const int L = s->layers, in = s->o.hidden;
-    const int T = gemm_tile(B, s->nout);
-    ObsArgs ob{m->d_mask, m->d_vo, m->d_so, m->d_iev, m->d_ies, s->npix, s->d_cpart,
-               2 * ((s->nout + T - 1) / T)};
-    GemmArgs g{s->H[L - 1], s->Wb[L], in, in, B, s->nout, in, s->b[L], nullptr, nullptr, nullptr, 0, ob};
-    GK_TRY((gemm<false, false, EPI_CHI2>(g, st)));
-    hipLaunchKernelGGL(k_chi2_finish, dim3((B + 3) / 4), dim3(256), 0, st, s->d_cpart, ob.nparts,
-                       B, s->d_params, m->d.rc, chi2);
+    const int L = s->layers, in = s->o.hidden, nc = 2 * s->c_nv;
+    int nparts = 0;
+    if (nc > 0) {
+        const int T = gemm_tile(B, nc);
+        nparts = 2 * ((nc + T - 1) / T);
+        ObsArgs ob{nullptr, s->c_vo, s->c_so, s->c_iev, s->c_ies, s->c_nv, s->d_cpart, nparts};
+        GemmArgs g{s->H[L - 1], s->c_W, in, in, B, nc, in, s->c_b, nullptr, nullptr, nullptr, 0, ob};
+        GK_TRY((gemm<false, false, EPI_CHI2>(g, st)));
+    }
+    hipLaunchKernelGGL(k_chi2_finish, dim3((B + 3) / 4), dim3(256), 0, st, s->d_cpart, nparts, B,
+                       s->d_params, m->d.rc, chi2);
     HIP_TRY(hipGetLastError());
     return GK_OK;
 }
@@ -941,6 +1038,7 @@ gk_status gk_surrogate_set_weights(gk_surrogate *s, const float *w, int64_t n)
         HIP_TRY(hipMemsetAsync(s->vb[l], 0, nb * sizeof(float), s->stream));
     }
     s->step = 0;
+    s->wver += 1;
     HIP_TRY(hipStreamSynchronize(s->stream));
     return GK_OK;
 }

@@ -172,6 +172,21 @@ def test_surrogate_chi2_matches_oracle_chi2_of_predicted_maps(O, gbk):
             continue
         ref, n = O.chi2(maps[b, 0], maps[b, 1], obs.vel, obs.sig, obs.evel, obs.esig, obs.mask, 0.7)
         assert abs(c[b] - ref) <= 1e-9 * ref, (b, c[b], ref)
+    # a new observation (another mask) and further training: the restricted
+    # output layer follows both
+    obs2 = I.make_observation(O.evaluate(d, rows[3]), 3.0, I.rng_for(70, 1, 0), random_mask=0.3, W=1.0)
+    m.set_obs(obs2)
+    S.train(5)
+    maps = S.predict(rows).cpu().numpy().astype(np.float64)
+    c = S.chi2(m, rows).cpu().numpy()
+    for b in (0, 1, 2, 20, 49):
+        ref, n = O.chi2(maps[b, 0], maps[b, 1], obs2.vel, obs2.sig, obs2.evel, obs2.esig, obs2.mask, 1.0)
+        assert abs(c[b] - ref) <= 1e-9 * ref, (b, c[b], ref)
+    # all pixels masked: chi2 = 0 for rows in the domain
+    obs2.mask[:] = 0
+    m.set_obs(obs2)
+    c = S.chi2(m, rows).cpu().numpy()
+    assert c[7] == np.inf and np.all(c[np.arange(50) != 7] == 0.0)
     S.close()
 
 
