@@ -97,10 +97,6 @@ size_t psf_lds_bytes(int TXd, int TYd, int u, int hp)
     return sizeof(double) * (LY * LX + LY * TX + (size_t)(2 * hp + 1));
 }
 
-// Picks the data-pixel tile of the PSF/moment kernel.  u = 1 with an image
-// of at least 32 x 32 takes the register-blocked 32 x 32 kernel; otherwise
-// the tile is as large as the thread budget and the LDS limit allow, and no
-// wider than the image.
 // LDS of the register-blocked u = 1 kernel: padded rows, see k_psf_moments_u1
 size_t psf_u1_lds_bytes(int TX, int hp)
 {
@@ -109,9 +105,16 @@ size_t psf_u1_lds_bytes(int TX, int hp)
     return sizeof(double) * (LY * pad(TX + 2 * hp) + LY * pad(TX));
 }
 
+// Picks the data-pixel tile of the PSF/moment kernel.  u = 1 with an image
+// of at least 16 x 16 takes the register-blocked 32 x 32 kernel; otherwise
+// the tile is as large as the thread budget and the LDS limit allow, and no
+// wider than the image.
 void choose_tile(gk_model *m)
 {
-    if (m->d.upsample == 1 && m->d.nx >= 32 && m->d.ny >= 32 && m->hp <= kMaxFastHalo) {
+    // the register-blocked kernel takes ragged 32 x 32 tiles (loads beyond the
+    // window are zero, outputs beyond it skipped); below 16 pixels a side most
+    // of such a tile would be idle, and the generic tile fits the image
+    if (m->d.upsample == 1 && m->d.nx >= 16 && m->d.ny >= 16 && m->hp <= kMaxFastHalo) {
         const int tx = 32;
         if (psf_u1_lds_bytes(tx, m->hp) <= kMaxLds) {
             m->TXd = tx;
@@ -697,7 +700,7 @@ bool gbk::set_conv_config(gk_model *m, bool fft, int tx, int ty)
         const bool fast = u == 1 && ty == 32 && (tx == 32 || tx == 64) && m->hp <= kMaxFastHalo;
         size_t lds;
         if (fast) {
-            if (m->d.nx < tx || m->d.ny < 32) return false;
+            if (m->d.nx < tx / 2 || m->d.ny < 16) return false;
             lds = psf_u1_lds_bytes(tx, m->hp);
         } else {
             if (tx < 1 || ty < 1 || tx * ty > 256 * kMaxPixPerThread) return false;

@@ -416,13 +416,26 @@ __global__ __launch_bounds__(256) void k_loss_finish(const double *__restrict__ 
     if (threadIdx.x == 0) *loss = (float)(ws[0] / (double)(wc[0] > 0 ? wc[0] : 1));
 }
 
-// db[n] = sum_m d[m][n]
-__global__ void k_colsum(const bf16 *__restrict__ d, int M, int N, float *__restrict__ db)
+// db[n] = sum_m d[m][n] in two fixed-order passes: grid (ceil(N/256), kColChunks)
+// sums chunk c of the rows into part[c][n]; k_colsum_finish adds the chunks.
+constexpr int kColChunks = 32;
+__global__ void k_colsum(const bf16 *__restrict__ d, int M, int N, float *__restrict__ part)
+{
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    const int rows = (M + kColChunks - 1) / kColChunks, m0 = blockIdx.y * rows;
+    const int m1 = min(M, m0 + rows);
+    float s = 0.0f;
+    for (int m = m0; m < m1; ++m) s += (float)d[(size_t)m * N + n];
+    part[(size_t)blockIdx.y * N + n] = s;
+}
+
+__global__ void k_colsum_finish(const float *__restrict__ part, int N, float *__restrict__ db)
 {
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= N) return;
     float s = 0.0f;
-    for (int m = 0; m < M; ++m) s += (float)d[(size_t)m * N + n];
+    for (int c = 0; c < kColChunks; ++c) s += part[(size_t)c * N + n];
     db[n] = s;
 }
 
@@ -578,6 +591,7 @@ struct gk_surrogate {
     unsigned *cnt = nullptr;
     double *d_params = nullptr, *h_params = nullptr, *d_partial = nullptr;
     double *d_cpart = nullptr;  // [cap][2 ceil(nout / 64)] chi2 partials of the output layer
+    float *d_colpart = nullptr;  // [kColChunks][max(hidden, nout)] bias-gradient partials
     hipEvent_t ev_staged = nullptr;  // recorded after the last copy out of h_params
     int loss_cap = 0;
 
@@ -606,6 +620,7 @@ struct gk_surrogate {
         F(d_params);
         F(d_partial);
         F(d_cpart);
+        F(d_colpart);
         if (h_params) {
             if (ev_staged) (void)hipEventSynchronize(ev_staged);
             (void)hipHostFree(h_params);
@@ -614,6 +629,7 @@ struct gk_surrogate {
         Y = T = Mask = maps = nullptr;
         cnt = nullptr;
         d_params = h_params = d_partial = d_cpart = nullptr;
+        d_colpart = nullptr;
         cap = 0;
     }
     void free_compact()
@@ -675,6 +691,8 @@ gk_status reserve_rows(gk_surrogate *s, int rows)
     HIP_TRY(hipHostMalloc((void **)&s->h_params, R * NPAR * sizeof(double), 0));
     HIP_TRY(hipMalloc((void **)&s->d_partial, kRedBlocks * sizeof(double)));
     HIP_TRY(hipMalloc((void **)&s->d_cpart, R * 2 * ((no + 63) / 64) * sizeof(double)));
+    HIP_TRY(hipMalloc((void **)&s->d_colpart,
+                      (size_t)kColChunks * std::max<size_t>(hid, no) * sizeof(float)));
     s->cap = rows;
     return GK_OK;
 }
@@ -733,7 +751,10 @@ gk_status loss_and_grads(gk_surrogate *s, int M, float *loss_dev, hipStream_t st
         // gW_l[o][i] = sum_b d[b][o] hin[b][i]
         GemmArgs gw{d, hin, out, in, out, in, M, nullptr, s->gW[l], nullptr, nullptr, in};
         GK_TRY((gemm<true, true, EPI_F32>(gw, st)));
-        hipLaunchKernelGGL(k_colsum, dim3(blocks(out)), dim3(256), 0, st, d, M, out, s->gb[l]);
+        hipLaunchKernelGGL(k_colsum, dim3(blocks(out), kColChunks), dim3(256), 0, st, d, M, out,
+                           s->d_colpart);
+        hipLaunchKernelGGL(k_colsum_finish, dim3(blocks(out)), dim3(256), 0, st, s->d_colpart, out,
+                           s->gb[l]);
         HIP_TRY(hipGetLastError());
         if (l == 0) break;
         // d_{l-1}[b][i] = (sum_o d[b][o] W_l[o][i]) gelu'(Z_{l-1}[b][i])

@@ -548,6 +548,10 @@ struct DevStream {
         const uint64_t a = u32(), b = u32();
         return ((double)((a << 21) ^ (b >> 11)) + 0.5) * 0x1.0p-53;
     }
+    __device__ float uniformf()  // 24 random bits, never 0 or 1
+    {
+        return ((float)(u32() >> 8) + 0.5f) * 0x1.0p-24f;
+    }
 };
 
 __global__ __launch_bounds__(64) void k_ns_draw(DrawArgs g)
@@ -573,15 +577,18 @@ __global__ __launch_bounds__(64) void k_ns_draw(DrawArgs g)
                 const double pick = rs.uniform();
                 while (e < bnd.n_ell - 1 && bnd.cum[e] < pick) ++e;
             }
-            double nrm = 0.0;
+            // direction and radius in FP32 (only their distribution matters;
+            // the point itself is formed in FP64)
+            float nrm = 0.0f;
             for (int a = 0; a < d; a += 2) {
-                const double u1 = rs.uniform(), u2 = rs.uniform();
-                const double r = sqrt(-2.0 * log(u1)), t = 6.283185307179586 * u2;
-                z[a] = r * cos(t);
-                if (a + 1 < d) z[a + 1] = r * sin(t);
+                const float r = sqrtf(-2.0f * logf(rs.uniformf()));
+                float sn, cs;
+                sincosf(6.28318531f * rs.uniformf(), &sn, &cs);
+                z[a] = r * cs;
+                if (a + 1 < d) z[a + 1] = r * sn;
             }
-            for (int a = 0; a < d; ++a) nrm += z[a] * z[a];
-            const double rad = pow(rs.uniform(), 1.0 / d) / sqrt(nrm);
+            for (int a = 0; a < d; ++a) nrm += (float)(z[a] * z[a]);
+            const double rad = (double)(exp2f(log2f(rs.uniformf()) / (float)d) / sqrtf(nrm));
             bool inside = true;
             for (int a = 0; a < d; ++a) {
                 double v = bnd.mu[e][a];
