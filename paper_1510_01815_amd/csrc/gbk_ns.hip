@@ -513,12 +513,11 @@ gk_status fit_reserve_rows(gk_model *m, int rows, double **h_params, double **d_
 namespace {
 
 // ---------------------------------------------------------------------------
-// Device-side candidates of the model fits.  Candidate c of round r draws
-// from its own Philox4x32-10 stream: key = seed (high word xor a tag),
-// counter = (c, r, r >> 32, block); each block gives two 53-bit uniforms,
-// normals by Box-Muller (both outputs).  Same rule as draw_host: direction
-// from d normals, radius U^(1/d), rejected until inside the cube (after 10^4
-// rejections, uniform in the cube).
+// Device-side candidates of the model fits: Philox4x32-10 streams keyed by
+// the seed (high word xor a tag), one per (candidate, round, trial); normals
+// by Box-Muller (both outputs).  Same rule as draw_host: ellipsoid by volume,
+// direction from d normals, radius U^(1/d), rejected outside the cube and
+// kept with probability 1/q where q ellipsoids overlap.
 // ---------------------------------------------------------------------------
 struct DrawArgs {
     const Bound *bnd;  // device copy of the round's region
@@ -554,24 +553,34 @@ struct DevStream {
     }
 };
 
-__global__ __launch_bounds__(64) void k_ns_draw(DrawArgs g)
+// One wave per candidate: the 64 lanes make independent trials (lane l of
+// attempt t uses counter (c, r, l + 256 t, block)) and the lowest lane whose
+// trial is accepted supplies the candidate -- the first success of trials
+// taken in lane order, so the candidate is uniform over the region.  After
+// 156 attempts (~10^4 trials) lane 0 draws uniformly in the cube.
+__global__ __launch_bounds__(256) void k_ns_draw(DrawArgs g)
 {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= g.n) return;
+    const int c = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (c >= g.n) return;  // whole waves
     const int d = g.d;
-    DevStream rs;
-    rs.ctr[0] = (uint32_t)c;
-    rs.ctr[1] = (uint32_t)g.round;
-    rs.ctr[2] = (uint32_t)(g.round >> 32);
-    rs.ctr[3] = 0u;
-    rs.key[0] = g.key0;
-    rs.key[1] = g.key1;
-    rs.left = 0;
     double x[GK_NP], z[GK_NP];
     bool drawn = false;
+    int attempt = 0;
+    auto stream = [&](int t) {
+        DevStream rs;
+        rs.ctr[0] = (uint32_t)c;
+        rs.ctr[1] = (uint32_t)g.round;
+        rs.ctr[2] = (uint32_t)(lane + 256 * t);
+        rs.ctr[3] = 0u;
+        rs.key[0] = g.key0;
+        rs.key[1] = g.key1;
+        rs.left = 0;
+        return rs;
+    };
     if (g.round_valid && g.bnd->n_ell > 0) {
         const Bound &bnd = *g.bnd;
-        for (int tries = 0; tries < 10000 && !drawn; ++tries) {
+        for (; attempt < 156; ++attempt) {
+            DevStream rs = stream(attempt);
             int e = 0;
             if (bnd.n_ell > 1) {
                 const double pick = rs.uniform();
@@ -589,24 +598,31 @@ __global__ __launch_bounds__(64) void k_ns_draw(DrawArgs g)
             }
             for (int a = 0; a < d; ++a) nrm += (float)(z[a] * z[a]);
             const double rad = (double)(exp2f(log2f(rs.uniformf()) / (float)d) / sqrtf(nrm));
-            bool inside = true;
+            bool ok = true;
             for (int a = 0; a < d; ++a) {
                 double v = bnd.mu[e][a];
                 for (int b = 0; b <= a; ++b) v += bnd.L[e][a * d + b] * z[b] * rad;
                 x[a] = v;
-                inside = inside && v > 0.0 && v < 1.0;
+                ok = ok && v > 0.0 && v < 1.0;
             }
-            if (!inside) continue;
-            if (bnd.n_ell > 1) {
+            if (ok && bnd.n_ell > 1) {
                 int q = 1;
                 for (int f = 0; f < bnd.n_ell; ++f) q += f != e && in_ellipsoid(bnd, f, x);
-                if (q > 1 && !(rs.uniform() * q < 1.0)) continue;
+                ok = q == 1 || rs.uniform() * q < 1.0;
             }
-            drawn = true;
+            const unsigned long long hits = __ballot(ok);
+            if (hits) {  // uniform over the wave
+                drawn = lane == __ffsll((long long)hits) - 1;
+                if (!drawn) return;
+                break;
+            }
         }
     }
-    if (!drawn)
+    if (!drawn) {
+        if (lane != 0) return;
+        DevStream rs = stream(attempt);
         for (int a = 0; a < d; ++a) x[a] = rs.uniform();
+    }
     double *row = g.rows + (size_t)c * GK_NP;
     for (int k = 0; k < GK_NP; ++k) row[k] = g.fixed[k];
     for (int a = 0; a < d; ++a) {
@@ -722,7 +738,7 @@ gk_status fit_nested(gk_model *m, gk_surrogate *sur, const double *lo, const dou
         g.bnd = nb.d_bnd;
         g.u = nb.d_u;
         g.rows = d_params;
-        hipLaunchKernelGGL(k_ns_draw, dim3((n + 63) / 64), dim3(64), 0, stream, g);
+        hipLaunchKernelGGL(k_ns_draw, dim3((n + 3) / 4), dim3(256), 0, stream, g);
         HIP_TRY(hipGetLastError());
         HIP_TRY(hipMemcpyAsync(nb.h_u, nb.d_u, sizeof(double) * n * d, hipMemcpyDeviceToHost, stream));
         for (int i = 0; i < n; ++i) logl[i] = -INFINITY;
