@@ -47,11 +47,17 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_1510_01815_amd", "csrc", f)
 
 
 def kernel_source_hash() -> str:
+    """SHA-256 of the kernel sources' code: // comments, trailing blanks and
+    blank lines are dropped, so that edits to comments keep the counters valid."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(f, "rb") as fh:
-            h.update(fh.read())
+        with open(f, encoding="utf-8") as fh:
+            for line in fh:
+                code = re.sub(r"//.*", "", line).rstrip()
+                if code:
+                    h.update(code.encode() + b"\n")
     return h.hexdigest()
 
 

@@ -97,12 +97,22 @@ size_t psf_lds_bytes(int TXd, int TYd, int u, int hp)
     return sizeof(double) * (LY * LX + LY * TX + (size_t)(2 * hp + 1));
 }
 
-// LDS of the register-blocked u = 1 kernel: padded rows, see k_psf_moments_u1
+// LDS of the register-blocked u = 1 kernels (padded rows): the 32 x 32 tile
+// keeps the y-pass rows of one plane, the 64 x 32 tile one plane of T plus its
+// x-pass rows
 size_t psf_u1_lds_bytes(int TX, int hp)
 {
     auto pad = [](int n) { return n + ((1 - n) % 4 + 4) % 4; };
+    if (TX == 32) return sizeof(double) * 32 * pad(32 + 2 * hp);
     const size_t LY = 32 + 2 * hp;
     return sizeof(double) * (LY * pad(TX + 2 * hp) + LY * pad(TX));
+}
+
+// The 32 x 32 register-blocked kernel addresses a T plane with 32-bit byte
+// offsets.
+bool fast_plane_ok(const gk_model *m)
+{
+    return sizeof(double) * (size_t)m->EX * (size_t)m->EY < ((size_t)1 << 31);
 }
 
 // Picks the data-pixel tile of the PSF/moment kernel.  u = 1 with an image
@@ -114,7 +124,8 @@ void choose_tile(gk_model *m)
     // the register-blocked kernel takes ragged 32 x 32 tiles (loads beyond the
     // window are zero, outputs beyond it skipped); below 16 pixels a side most
     // of such a tile would be idle, and the generic tile fits the image
-    if (m->d.upsample == 1 && m->d.nx >= 16 && m->d.ny >= 16 && m->hp <= kMaxFastHalo) {
+    if (m->d.upsample == 1 && m->d.nx >= 16 && m->d.ny >= 16 && m->hp <= kMaxFastHalo &&
+        fast_plane_ok(m)) {
         const int tx = 32;
         if (psf_u1_lds_bytes(tx, m->hp) <= kMaxLds) {
             m->TXd = tx;
@@ -701,6 +712,7 @@ bool gbk::set_conv_config(gk_model *m, bool fft, int tx, int ty)
         size_t lds;
         if (fast) {
             if (m->d.nx < tx / 2 || m->d.ny < 16) return false;
+            if (tx == 32 && !fast_plane_ok(m)) return false;
             lds = psf_u1_lds_bytes(tx, m->hp);
         } else {
             if (tx < 1 || ty < 1 || tx * ty > 256 * kMaxPixPerThread) return false;

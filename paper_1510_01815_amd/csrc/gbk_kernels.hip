@@ -29,7 +29,8 @@
 //                  (eqs. 1-4), rotation curve (eqs. 6-7), velocity (eq. 8),
 //                  brightness (eq. 5), then T_j over the channels; the weight
 //                  table wz is [NZE][4] = {W0, W1, W2, 0} per fine channel
-//   k_psf_moments  per (evaluation, tile): PSF x then y pass on T_j in LDS,
+//   k_psf_moments  per (evaluation, tile): PSF x and y passes on T_j (LDS
+//                  staged, or y first from HBM for 32 x 32 tiles at u = 1),
 //                  u x u block sum, moments, masked chi-square terms (eq. 11)
 //   k_reduce_chi2  per evaluation: fixed-order sum of the tile partials
 #include <hip/hip_runtime.h>
@@ -249,14 +250,20 @@ __device__ __forceinline__ void line_sums_tile(const double *__restrict__ c,
         double g = exp2_wide(lamp - e0 * e0);
         double rt = exp2_wide(-(2.0 * e0 + sqk) * sqk);
         const double qq = c[C_Q];
+        // the next channel's weights are requested one step ahead, which
+        // lets the scalar loads of two channels merge into one
+        if (zlo <= zhi) {
+            double4 wk = w[zlo];
 #pragma unroll 2
-        for (int z = zlo; z <= zhi; ++z) {
-            const double4 wk = w[z];
-            t0 = fma(g, wk.x, t0);
-            t1 = fma(g, wk.y, t1);
-            t2 = fma(g, wk.z, t2);
-            g *= rt;
-            rt *= qq;
+            for (int z = zlo; z <= zhi; ++z) {
+                const double4 wn = w[z < zhi ? z + 1 : z];
+                t0 = fma(g, wk.x, t0);
+                t1 = fma(g, wk.y, t1);
+                t2 = fma(g, wk.z, t2);
+                g *= rt;
+                rt *= qq;
+                wk = wn;
+            }
         }
     } else {
         double e = e0;
@@ -435,8 +442,9 @@ __device__ __forceinline__ void psf_generic_tile(const PsfArgs &a, const RowPtrs
 }
 
 // ---------------------------------------------------------------------------
-// k_psf_moments_u1<HP, TX>: the u = 1 case with TX x 32 data-pixel tiles
-// (TX = 32 or 64) and a compile-time PSF half-width HP (0..kMaxFastHalo).
+// psf_u1_tile<HP, TX>: the u = 1 case with TX x 32 data-pixel tiles (used for
+// TX = 64; 32 x 32 tiles take psf_yx_tile below) and a compile-time PSF
+// half-width HP (0..kMaxFastHalo).
 // Each plane j: T tile + halo -> LDS (sT), x pass -> sX, y pass -> registers.
 // Both passes are register-blocked along the pass direction (a thread makes
 // 4 or RPT consecutive outputs from one window of LDS values) with the taps
@@ -583,6 +591,209 @@ __device__ __forceinline__ void psf_u1_tile(const PsfArgs &a, const RowPtrs &r)
     }
 }
 
+// ---------------------------------------------------------------------------
+// psf_yx_tile<HP>: the u = 1 case with 32 x 32 data-pixel tiles, y pass first.
+// Wave w owns output rows 8w..8w+7 of the tile and lane l the T column
+// tx0 + l (l < 32 + 2 HP <= 64).  Each lane loads its column's 8 + 2 HP
+// values straight from global memory (a wave reads contiguous row segments)
+// and makes the 8 y-pass outputs in registers; the y-pass rows go to LDS once
+// per plane, and the x pass reads them back register-blocked (a lane makes 4
+// consecutive outputs of one row from a window of 4 + 2 HP values).  The LDS
+// rows a wave reads in the x pass are the rows it wrote itself, so the passes
+// and the planes (which reuse the rows) are ordered by wave-level fences only,
+// and the waves of a tile run independently until the chi-square sum.
+// Row stride of sY = 1 (mod 4) doubles, which spreads the x-pass lanes of a
+// wave (8 rows x 8 windows) over all LDS banks.
+// ---------------------------------------------------------------------------
+// Word 3 of a raw buffer descriptor on gfx9-family chips (32-bit data format;
+// no swizzle, no index stride).
+constexpr int kBufferDword3 = 0x00020000;
+
+// Orders a wave's LDS accesses before and after this point (the hardware runs
+// one wave's LDS instructions in order; this keeps the compiler from moving
+// them across).
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int HP>
+__device__ __forceinline__ void psf_yx_tile(const PsfArgs &a, const RowPtrs &r)
+{
+    extern __shared__ double lds[];
+    constexpr int TT = 32, K = 2 * HP + 1, LX = TT + 2 * HP;
+    constexpr int RW = 8, NW = RW + 2 * HP;  // y-pass outputs and window per lane
+    constexpr int SY = pad_stride(LX);
+    static_assert(LX <= 64, "one lane per T column");
+    const int tile = r.tile, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int tx0 = (tile % a.ntx) * TT, ty0 = (tile / a.ntx) * TT;
+    const double *cb = r.c;
+    const bool valid = cb[C_VALID] != 0.0;
+    double kp[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) kp[k] = a.kp[k];
+    // x pass: lane -> row ry of the tile (inside this wave's 8 rows) and
+    // columns x0 .. x0 + 3
+    const int ry = tid >> 3, x0 = (tid & 7) * 4;
+
+    double S[3][4];
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+#pragma unroll
+        for (int o = 0; o < 4; ++o) S[j][o] = 0.0;
+
+    if (valid) {
+        // Loads go through one buffer descriptor per plane whose range is the
+        // plane: a row beyond EY reads 0 from the hardware's range check, and a
+        // lane beyond the tile's columns or EX gets an offset beyond every
+        // plane (the host keeps a plane under 2^31 bytes for this kernel).
+        const uint32_t plane_bytes = (uint32_t)(sizeof(double) * a.EX * a.EY);
+        const int gx = tx0 + lane, gy0 = ty0 + RW * wave;
+        const bool colok = lane < LX && gx < a.EX;
+        const uint32_t off0 = colok ? (uint32_t)(sizeof(double) * ((size_t)gy0 * a.EX + gx))
+                                    : 0x80000000u;
+        const uint32_t step = colok ? (uint32_t)(sizeof(double) * a.EX) : 0u;
+        auto load_plane = [&](int j, double *dst) {
+            const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+                (void *)(r.T + (size_t)j * a.EX * a.EY), 0, (int)plane_bytes, kBufferDword3);
+#pragma unroll
+            for (int w = 0; w < NW; ++w)
+                dst[w] = __builtin_bit_cast(
+                    double, __builtin_amdgcn_raw_buffer_load_b64(rs, off0 + (uint32_t)w * step, 0, 0));
+        };
+        double *sw = lds + (size_t)RW * wave * SY;  // this wave's rows
+        double v[NW], vn[NW];
+        load_plane(0, v);
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            if (j < 2) load_plane(j + 1, vn);
+            double y[RW];
+#pragma unroll
+            for (int o = 0; o < RW; ++o) {
+                double acc = 0.0;
+                // output o = sum_k K[k] v[o + 2HP - k]
+#pragma unroll
+                for (int k = 0; k < K; ++k) acc = fma(kp[k], v[o + 2 * HP - k], acc);
+                y[o] = acc;
+            }
+            // the x pass of the previous plane has read these rows
+            wave_sync();
+            if (lane < LX) {
+                double *dst = sw + lane;
+#pragma unroll
+                for (int o = 0; o < RW; ++o) dst[o * SY] = y[o];
+            }
+            wave_sync();
+            window<HP, 4>(lds + (size_t)ry * SY + x0, 1, kp, S[j]);
+            if (j < 2) {
+#pragma unroll
+                for (int w = 0; w < NW; ++w) v[w] = vn[w];
+            }
+        }
+    }
+
+    // moments and chi-square terms of the lane's 4 pixels (xd0 .. xd0 + 3, yd);
+    // with nx = 0 (mod 4) they are inside the image and 16-byte aligned, and
+    // the observation is read and the outputs written as vectors
+    double acc = 0.0;
+    const int yd = ty0 + ry, xd0 = tx0 + x0;
+    const size_t npix = (size_t)a.nx * a.ny;
+    if (yd < a.ny && xd0 < a.nx) {
+        double m0[4], m1[4], m2[4];
+#pragma unroll
+        for (int o = 0; o < 4; ++o) {
+            if (!valid) {
+                m0[o] = m1[o] = m2[o] = __builtin_nan("");
+            } else if (S[0][o] > 0.0) {
+                const double inv = 1.0 / S[0][o];
+                const double mr = S[1][o] * inv;
+                m0[o] = a.dv * S[0][o];
+                m1[o] = a.vref + mr;
+                m2[o] = sqrt(fmax(S[2][o] * inv - mr * mr, 0.0));
+            } else {
+                m0[o] = 0.0;
+                m1[o] = cb[C_VSYS];
+                m2[o] = 0.0;
+            }
+        }
+        const size_t p0 = (size_t)yd * a.nx + xd0;
+        double rv[4], rs[4];
+        if ((a.nx & 3) == 0) {
+            if (r.maps) {
+                float *mb = r.maps + p0;
+                *reinterpret_cast<float4 *>(mb) =
+                    make_float4((float)m0[0], (float)m0[1], (float)m0[2], (float)m0[3]);
+                *reinterpret_cast<float4 *>(mb + npix) =
+                    make_float4((float)m1[0], (float)m1[1], (float)m1[2], (float)m1[3]);
+                *reinterpret_cast<float4 *>(mb + 2 * npix) =
+                    make_float4((float)m2[0], (float)m2[1], (float)m2[2], (float)m2[3]);
+            }
+            if (a.mask) {
+                const uchar4 mk = *reinterpret_cast<const uchar4 *>(a.mask + p0);
+                const float4 vo = *reinterpret_cast<const float4 *>(a.vo + p0);
+                const float4 so = *reinterpret_cast<const float4 *>(a.so + p0);
+                const double2 ev0 = *reinterpret_cast<const double2 *>(a.iev + p0);
+                const double2 ev1 = *reinterpret_cast<const double2 *>(a.iev + p0 + 2);
+                const double2 es0 = *reinterpret_cast<const double2 *>(a.ies + p0);
+                const double2 es1 = *reinterpret_cast<const double2 *>(a.ies + p0 + 2);
+                const bool use[4] = {mk.x != 0, mk.y != 0, mk.z != 0, mk.w != 0};
+                const float vof[4] = {vo.x, vo.y, vo.z, vo.w}, sof[4] = {so.x, so.y, so.z, so.w};
+                const double iev[4] = {ev0.x, ev0.y, ev1.x, ev1.y};
+                const double ies[4] = {es0.x, es0.y, es1.x, es1.y};
+#pragma unroll
+                for (int o = 0; o < 4; ++o) {
+                    rv[o] = use[o] ? (m1[o] - (double)vof[o]) * iev[o] : 0.0;
+                    rs[o] = use[o] ? (m2[o] - (double)sof[o]) * ies[o] : 0.0;
+                    if (use[o]) acc += rv[o] * rv[o] + rs[o] * rs[o];
+                }
+                if (r.resid) {
+                    double *rb = r.resid + p0;
+                    if (!valid)
+#pragma unroll
+                        for (int o = 0; o < 4; ++o) rv[o] = rs[o] = __builtin_nan("");
+                    *reinterpret_cast<double2 *>(rb) = make_double2(rv[0], rv[1]);
+                    *reinterpret_cast<double2 *>(rb + 2) = make_double2(rv[2], rv[3]);
+                    *reinterpret_cast<double2 *>(rb + npix) = make_double2(rs[0], rs[1]);
+                    *reinterpret_cast<double2 *>(rb + npix + 2) = make_double2(rs[2], rs[3]);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int o = 0; o < 4; ++o) {
+                if (xd0 + o >= a.nx) break;
+                const size_t p = p0 + o;
+                if (r.maps) {
+                    float *mb = r.maps;
+                    mb[p] = (float)m0[o];
+                    mb[npix + p] = (float)m1[o];
+                    mb[2 * npix + p] = (float)m2[o];
+                }
+                if (a.mask) {
+                    const bool use = a.mask[p] != 0;
+                    rv[o] = use ? (m1[o] - (double)a.vo[p]) * a.iev[p] : 0.0;
+                    rs[o] = use ? (m2[o] - (double)a.so[p]) * a.ies[p] : 0.0;
+                    if (use) acc += rv[o] * rv[o] + rs[o] * rs[o];
+                    if (r.resid) {
+                        double *rb = r.resid;
+                        rb[p] = valid ? rv[o] : __builtin_nan("");
+                        rb[npix + p] = valid ? rs[o] : __builtin_nan("");
+                    }
+                }
+            }
+        }
+    }
+    if (r.partial) {
+        for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+        __shared__ double wsum[4];
+        if (lane == 0) wsum[wave] = acc;
+        __syncthreads();
+        if (tid == 0)
+            *r.partial = ((wsum[0] + wsum[1]) + wsum[2]) + wsum[3];
+    }
+}
+
 // Row pointers of a single-model launch, grid (ntiles, B).  Workgroups go to
 // the 8 XCDs round-robin by linear id; the ids are remapped so that all tiles
 // of one row run on one XCD and the halo each tile shares with its
@@ -619,7 +830,10 @@ __global__ __launch_bounds__(256) void k_psf_moments(PsfArgs a) { psf_generic_ti
 template <int HP, int TX>
 __global__ __launch_bounds__(256) void k_psf_moments_u1(PsfArgs a)
 {
-    psf_u1_tile<HP, TX>(a, single_row(a));
+    if constexpr (TX == 32)
+        psf_yx_tile<HP>(a, single_row(a));
+    else
+        psf_u1_tile<HP, TX>(a, single_row(a));
 }
 
 // Row pointers of a ragged multi-model launch over one bucket of rows.
@@ -658,7 +872,7 @@ __global__ __launch_bounds__(256) void k_psf_u1_multi(const ModelDev *md, RowMap
 {
     PsfArgs a;
     const RowPtrs r = multi_row(md, rm, bk, T, consts, resid, partial, a);
-    psf_u1_tile<HP, 32>(a, r);
+    psf_yx_tile<HP>(a, r);
 }
 
 template <int HP, int TX> void launch_u1(const PsfArgs &a, dim3 grid, size_t lds, hipStream_t s)
