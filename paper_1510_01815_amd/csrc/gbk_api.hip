@@ -230,18 +230,20 @@ gk_status enqueue_batch(gk_model *m, const double *params, PtrKind pk, int32_t B
     const bool timing = m->prof_flags & GK_PROF_TIMING;
     unsigned long long *counter = (m->prof_flags & GK_PROF_COUNT) ? m->d_count : nullptr;
     if (timing) m->prof_events.emplace_back();
-    // launches kernel `k` through `fn`, bracketed by events when timing
+    // launches stage `k` through `fn`; when timing, its launches carry a
+    // start and a stop event (the stage's first dispatch starts, its last ends)
     auto timed = [&](int k, auto fn) -> hipError_t {
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (timing) {
-            hipError_t e = hipEventCreate(&e0);
-            if (e == hipSuccess) e = hipEventCreate(&e1);
-            if (e == hipSuccess) e = hipEventRecord(e0, s);
+            // device-scope timestamps: no system-memory fence around the dispatch
+            hipError_t e = hipEventCreateWithFlags(&e0, hipEventDisableSystemFence);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&e1, hipEventDisableSystemFence);
             if (e != hipSuccess) return e;
+            launch_events() = {e0, e1};
         }
         hipError_t e = fn();
         if (timing) {
-            if (e == hipSuccess) e = hipEventRecord(e1, s);
+            launch_events() = {};
             m->prof_events.back().push_back({k, {e0, e1}});
         }
         return e;

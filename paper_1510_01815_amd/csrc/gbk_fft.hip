@@ -215,14 +215,14 @@ hipError_t launch_fft_x(const FftArgs &f, int B, hipStream_t s)
 {
     const int nlc = (3 * f.EY + 1) / 2;
     dim3 grid((nlc + f.NLX - 1) / f.NLX, B);
-    hipLaunchKernelGGL(k_fft_x, grid, dim3(256), fft_x_lds_bytes(f), s, f);
+    launch(k_fft_x, grid, dim3(256), fft_x_lds_bytes(f), s, f);
     return hipGetLastError();
 }
 
 hipError_t launch_fft_y_moments(const FftArgs &f, const PsfArgs &a, int B, hipStream_t s)
 {
     dim3 grid(f.ncb, B);
-    hipLaunchKernelGGL(k_fft_y_moments, grid, dim3(256), fft_y_lds_bytes(f, a.u), s, f, a);
+    launch(k_fft_y_moments, grid, dim3(256), fft_y_lds_bytes(f, a.u), s, f, a);
     return hipGetLastError();
 }
 

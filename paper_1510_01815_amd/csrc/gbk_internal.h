@@ -1,10 +1,37 @@
 // gbk_internal.h -- private declarations shared by the kernels and the
 // runtime of libgbk.so (not part of the C ABI).
 #pragma once
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 namespace gbk {
+
+// Timing of the launches made through launch(): while events are set, each
+// launch carries them itself (the start event takes the time its dispatch
+// begins, the stop event the time it ends), so no marker packets sit between
+// the kernels of a timed chain.  A launch consumes the start event; the stop
+// event stays set, so the last launch of a multi-kernel stage ends it.
+struct LaunchEvents {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
+inline LaunchEvents &launch_events()
+{
+    static thread_local LaunchEvents ev;
+    return ev;
+}
+
+template <typename F, typename... A>
+inline void launch(F kernel, dim3 grid, dim3 block, size_t lds, hipStream_t s, A... args)
+{
+    LaunchEvents &ev = launch_events();
+    if (ev.start || ev.stop) {
+        hipExtLaunchKernelGGL(kernel, grid, block, (uint32_t)lds, s, ev.start, ev.stop, 0u, args...);
+        ev.start = nullptr;
+    } else {
+        hipLaunchKernelGGL(kernel, grid, block, lds, s, args...);
+    }
+}
 
 // parameter slots of a row (same order as the public enum)
 enum { P_XO = 0, P_YO, P_PA, P_INC, P_VSYS, P_VT, P_RT, P_SIG, P_R0, P_I0, P_A, P_G, NPAR };

@@ -877,7 +877,7 @@ __global__ __launch_bounds__(256) void k_psf_u1_multi(const ModelDev *md, RowMap
 
 template <int HP, int TX> void launch_u1(const PsfArgs &a, dim3 grid, size_t lds, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_psf_moments_u1<HP, TX>), grid, dim3(256), lds, s, a);
+    launch(k_psf_moments_u1<HP, TX>, grid, dim3(256), lds, s, a);
 }
 
 using LaunchFn = void (*)(const PsfArgs &, dim3, size_t, hipStream_t);
@@ -977,7 +977,7 @@ hipError_t launch_reduce_multi(const double *partial, const ModelDev *md, const 
 hipError_t launch_prep(const double *params, int B, int rc, double dvf, int hp, int u,
                        double *consts, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_prep, dim3((B + 63) / 64), dim3(64), 0, s, params, B, rc, dvf, hp, u,
+    launch(k_prep, dim3((B + 63) / 64), dim3(64), 0, s, params, B, rc, dvf, hp, u,
                        consts);
     return hipGetLastError();
 }
@@ -987,7 +987,7 @@ hipError_t launch_line_sums(const double *consts, const double *wz, int NZE, int
                             unsigned long long *support_count, int B, hipStream_t s)
 {
     dim3 grid((EX + 15) / 16, (EY + 15) / 16, B);
-    hipLaunchKernelGGL(k_line_sums, grid, dim3(256), 0, s, consts, wz, NZE, EX, EY, hp, u, rc, vf0,
+    launch(k_line_sums, grid, dim3(256), 0, s, consts, wz, NZE, EX, EY, hp, u, rc, vf0,
                        inv_dvf, T, support_count);
     return hipGetLastError();
 }
@@ -1000,7 +1000,7 @@ hipError_t launch_psf_moments(const PsfArgs &a, int B, size_t lds_bytes, hipStre
     else if (a.u == 1 && a.TXd == 32 && a.TYd == 32 && a.hp <= kMaxFastHalo)
         kU1Table32[a.hp](a, grid, lds_bytes, s);
     else
-        hipLaunchKernelGGL(k_psf_moments, grid, dim3(256), lds_bytes, s, a);
+        launch(k_psf_moments, grid, dim3(256), lds_bytes, s, a);
     return hipGetLastError();
 }
 
@@ -1008,7 +1008,7 @@ hipError_t launch_reduce_chi2(const double *partial, int ntiles, const double *c
                               int64_t nvalid_obs, double *chi2, int64_t *nvalid, int B,
                               hipStream_t s)
 {
-    hipLaunchKernelGGL(k_reduce_chi2, dim3(B), dim3(64), 0, s, partial, ntiles, consts, nvalid_obs,
+    launch(k_reduce_chi2, dim3(B), dim3(64), 0, s, partial, ntiles, consts, nvalid_obs,
                        chi2, nvalid);
     return hipGetLastError();
 }

@@ -1,4 +1,4 @@
-// gbk_ns.hip -- batched single-ellipsoid nested sampling (Sec. 2.3.2) and the
+// gbk_ns.hip -- batched nested sampling with an ellipsoidal bound (Sec. 2.3.2) and the
 // Philox4x32-10 counter-based generator it draws from.
 //
 // The driver is generic over a batch log-likelihood; gk_fit_nested plugs in
@@ -11,9 +11,12 @@
 #include <cfloat>
 #include <chrono>
 #include <cmath>
+#include <condition_variable>
 #include <cstring>
 #include <functional>
+#include <mutex>
 #include <numeric>
+#include <thread>
 #include <vector>
 
 #include "gbk_model.h"
@@ -59,6 +62,7 @@ double ball_volume(int d) { return std::pow(M_PI, 0.5 * d) / std::tgamma(0.5 * d
 // from in proportion to their volumes (cum = cumulative volume fractions),
 // or the whole unit cube when n_ell is 0.
 constexpr int kMaxEll = 8;
+constexpr int kMeansPoints = 256;  // points of the 2-means iterations of a split
 struct Bound {
     int n_ell;
     int d;
@@ -166,13 +170,16 @@ void build_bound(const double *U, int N, int d, double enlarge, double logX, int
                 if (dist2(&w[(size_t)i * d], &w[(size_t)f0 * d]) > dist2(&w[(size_t)f1 * d], &w[(size_t)f0 * d])) f1 = i;
             std::copy_n(&w[(size_t)f0 * d], d, c0);
             std::copy_n(&w[(size_t)f1 * d], d, c1);
-            std::vector<char> lab(n, 0);
+            // Lloyd iterations on an evenly strided subset of at most
+            // kMeansPoints points, then every point goes to its nearer centre
+            const int stride = (n + kMeansPoints - 1) / kMeansPoints, ns = (n + stride - 1) / stride;
+            std::vector<char> lab(ns, 0);
             for (int it = 0; it < 20; ++it) {
                 bool changed = false;
                 double s0[GK_NP] = {}, s1[GK_NP] = {};
                 int n0 = 0, n1 = 0;
-                for (int i = 0; i < n; ++i) {
-                    const double *y = &w[(size_t)i * d];
+                for (int i = 0; i < ns; ++i) {
+                    const double *y = &w[(size_t)i * stride * d];
                     const char l = dist2(y, c1) < dist2(y, c0) ? 1 : 0;
                     changed = changed || l != lab[i];
                     lab[i] = l;
@@ -188,7 +195,10 @@ void build_bound(const double *U, int N, int d, double enlarge, double logX, int
                 if (!changed && it > 0) break;
             }
             Node ch[2];
-            for (int i = 0; i < n; ++i) ch[(int)lab[i]].idx.push_back(nd.idx[i]);
+            for (int i = 0; i < n; ++i) {
+                const double *y = &w[(size_t)i * d];
+                ch[dist2(y, c1) < dist2(y, c0) ? 1 : 0].idx.push_back(nd.idx[i]);
+            }
             const int n0 = (int)ch[0].idx.size(), n1 = (int)ch[1].idx.size();
             if (n0 >= 2 * (d + 1) && n1 >= 2 * (d + 1) &&
                 fit_ellipsoid(U, ch[0].idx.data(), n0, d, enlarge, min_vol(n0), ch[0].mu, ch[0].L,
@@ -283,6 +293,58 @@ void draw_host(const Bound *bnd, int n, int d, Rng &rng, double *ub)
     }
 }
 
+// One host thread that runs a job (the next bound) while the caller's thread
+// draws and evaluates a round.
+class Worker {
+  public:
+    Worker() : th_([this] { loop(); }) {}
+    ~Worker()
+    {
+        {
+            std::lock_guard<std::mutex> l(mu_);
+            quit_ = true;
+        }
+        cv_.notify_all();
+        th_.join();
+    }
+    void submit(std::function<void()> job)
+    {
+        {
+            std::lock_guard<std::mutex> l(mu_);
+            job_ = std::move(job);
+            pending_ = true;
+        }
+        cv_.notify_all();
+    }
+    void wait()
+    {
+        std::unique_lock<std::mutex> l(mu_);
+        cv_.wait(l, [&] { return !pending_; });
+    }
+
+  private:
+    void loop()
+    {
+        std::unique_lock<std::mutex> l(mu_);
+        for (;;) {
+            cv_.wait(l, [&] { return (pending_ && job_) || quit_; });
+            if (quit_) return;
+            std::function<void()> job = std::move(job_);
+            job_ = nullptr;
+            l.unlock();
+            job();
+            l.lock();
+            pending_ = false;
+            cv_.notify_all();
+        }
+    }
+    std::mutex mu_;
+    std::condition_variable cv_;
+    std::function<void()> job_;
+    bool pending_ = false, quit_ = false;
+    std::thread th_;
+};
+
 // Runs the sampler in the unit cube [0,1]^d.  Fills the evidence fields of
 // res, best[] in unit-cube coordinates, and the posterior samples post_u
 // [M][d] with normalised weights post_w [M].
@@ -313,18 +375,32 @@ gk_status ns_run(int d, const DrawEval &draw_eval, const gk_ns_opts &o, gk_ns_re
     int64_t k = 0;
     bool done = false;
     capped = false;
-    Bound bnd{};
-    // The bound is rebuilt after every N/20 retired points (and at the start):
-    // an older bound still contains the current, smaller constrained region,
-    // so it stays valid, only less tight.
+    // The bound is rebuilt after every N/20 retired points.  The first one is
+    // built before the first round; later ones are built on a worker thread
+    // from the live points at the start of a round, while that round is drawn
+    // and evaluated, and are used from the next round on.  A bound one round
+    // old still contains the current, smaller constrained region, so it stays
+    // valid, only less tight.
     const int64_t rebuild = std::max(1, N / 20);
-    int64_t k_built = -rebuild;
+    Bound bnd{}, next{};
+    build_bound(live_u.data(), N, d, o.enlarge, 0.0, o.max_ell, bnd);
+    int64_t k_built = 0;
+    Worker worker;
     while (!done) {
-        if (k - k_built >= rebuild) {
-            build_bound(live_u.data(), N, d, o.enlarge, -(double)k / N, o.max_ell, bnd);
+        const bool building = k - k_built >= rebuild;
+        if (building) {
+            const double logX = -(double)k / N;
+            worker.submit([&, logX] {
+                build_bound(live_u.data(), N, d, o.enlarge, logX, o.max_ell, next);
+            });
+        }
+        const gk_status st = draw_eval(&bnd, B, n_launch, heap.front().first, ub.data(), lb.data());
+        if (building) {  // the live points change below: the build must be over
+            worker.wait();
+            bnd = next;
             k_built = k;
         }
-        GK_TRY(draw_eval(&bnd, B, n_launch, heap.front().first, ub.data(), lb.data()));
+        GK_TRY(st);
         n_evals += B;
         ++n_launch;
         const int64_t k_round = k;
