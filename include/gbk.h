@@ -403,11 +403,12 @@ gk_status gk_surrogate_chi2(gk_surrogate *s, gk_model *model, const double *para
 /* Nested sampling as gk_fit_nested, with every round's candidates screened by
  * the surrogate.  With chi2_floor the plain chi2 of the lowest live point at
  * the start of the round and `shift` the largest surrogate-minus-plain chi2
- * seen on the previous round's plainly evaluated candidates (0 before the
- * first), a candidate whose surrogate chi2 exceeds chi2_floor + shift +
- * margin is discarded, except that a Philox draw keeps it with probability
- * audit (the audit sample measures the screen); every other candidate gets
- * the plain chi2, which alone decides acceptance, posterior and evidence.
+ * among the latest max(n_live, batch) plainly evaluated candidates (0 before
+ * the first), a candidate whose surrogate chi2 exceeds chi2_floor + shift +
+ * margin is discarded, except that a Philox draw (counter: candidate, round)
+ * keeps it with probability audit (the audit sample measures the screen);
+ * every other candidate gets the plain chi2, which alone decides acceptance,
+ * posterior and evidence.
  * With a useless surrogate the screen passes everything and the run is the
  * plain one.  margin >= 0, 0 <= audit <= 1.  Blocks. */
 gk_status gk_fit_nested_screened(gk_model *model, gk_surrogate *s, const double *lo,

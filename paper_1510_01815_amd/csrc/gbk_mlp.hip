@@ -582,8 +582,10 @@ struct gk_surrogate {
     std::vector<int> fin, fout;
     std::vector<float *> W, b, gW, gb, mW, vW, mb, vb;
     std::vector<bf16 *> Wb;
-    // per-row buffers for cap rows
-    int cap = 0;
+    // per-row buffers: the inference set (X, H, d_params, h_params, d_cpart)
+    // for cap rows, the training and full-output set (Z, dH, Y, T, Mask, dY,
+    // maps, cnt, d_partial, d_colpart) for tcap rows
+    int cap = 0, tcap = 0;
     bf16 *X = nullptr, *dY = nullptr;
     std::vector<bf16 *> H, dH;
     std::vector<float *> Z;
@@ -601,15 +603,28 @@ struct gk_surrogate {
         for (int l = 0; l <= layers; ++l) n += (size_t)fout[l] * fin[l] + fout[l];
         return n;
     }
-    void free_rows()
+    void free_infer()
     {
         auto F = [](void *p) { if (p) (void)hipFree(p); };
         F(X);
-        F(dY);
         for (bf16 *p : H) F(p);
+        H.clear();
+        F(d_params);
+        F(d_cpart);
+        if (h_params) {
+            if (ev_staged) (void)hipEventSynchronize(ev_staged);
+            (void)hipHostFree(h_params);
+        }
+        X = nullptr;
+        d_params = h_params = d_cpart = nullptr;
+        cap = 0;
+    }
+    void free_full()
+    {
+        auto F = [](void *p) { if (p) (void)hipFree(p); };
+        F(dY);
         for (bf16 *p : dH) F(p);
         for (float *p : Z) F(p);
-        H.clear();
         dH.clear();
         Z.clear();
         F(Y);
@@ -617,20 +632,19 @@ struct gk_surrogate {
         F(Mask);
         F(maps);
         F(cnt);
-        F(d_params);
         F(d_partial);
-        F(d_cpart);
         F(d_colpart);
-        if (h_params) {
-            if (ev_staged) (void)hipEventSynchronize(ev_staged);
-            (void)hipHostFree(h_params);
-        }
-        X = dY = nullptr;
+        dY = nullptr;
         Y = T = Mask = maps = nullptr;
         cnt = nullptr;
-        d_params = h_params = d_partial = d_cpart = nullptr;
+        d_partial = nullptr;
         d_colpart = nullptr;
-        cap = 0;
+        tcap = 0;
+    }
+    void free_rows()
+    {
+        free_infer();
+        free_full();
     }
     void free_compact()
     {
@@ -662,38 +676,54 @@ struct gk_surrogate {
 
 namespace {
 
-gk_status reserve_rows(gk_surrogate *s, int rows)
+// Buffers for `rows` rows: the inference set always, the training and
+// full-output set when `full`.  Capacities grow at least twofold, so a
+// sampler whose batches grow round by round reallocates a few times only.
+gk_status reserve_rows(gk_surrogate *s, int rows, bool full)
 {
-    if (rows <= s->cap) return GK_OK;
-    HIP_TRY(hipStreamSynchronize(s->stream));
-    s->free_rows();
-    rows = (rows + 31) / 32 * 32;
-    const size_t R = (size_t)rows, hid = (size_t)s->o.hidden;
-    HIP_TRY(hipMalloc((void **)&s->X, R * kInPad * sizeof(bf16)));
-    for (int l = 0; l < s->layers; ++l) {
-        bf16 *h, *dh;
-        float *z;
-        HIP_TRY(hipMalloc((void **)&h, R * hid * sizeof(bf16)));
-        s->H.push_back(h);
-        HIP_TRY(hipMalloc((void **)&dh, R * hid * sizeof(bf16)));
-        s->dH.push_back(dh);
-        HIP_TRY(hipMalloc((void **)&z, R * hid * sizeof(float)));
-        s->Z.push_back(z);
+    auto grown = [](int need, int have) {
+        return (std::max(need, 2 * have) + 31) / 32 * 32;
+    };
+    const size_t hid = (size_t)s->o.hidden, no = (size_t)s->nout;
+    if (rows > s->cap) {
+        HIP_TRY(hipStreamSynchronize(s->stream));
+        const int rc = grown(rows, s->cap);
+        s->free_infer();
+        const size_t R = (size_t)rc;
+        HIP_TRY(hipMalloc((void **)&s->X, R * kInPad * sizeof(bf16)));
+        for (int l = 0; l < s->layers; ++l) {
+            bf16 *h;
+            HIP_TRY(hipMalloc((void **)&h, R * hid * sizeof(bf16)));
+            s->H.push_back(h);
+        }
+        HIP_TRY(hipMalloc((void **)&s->d_params, R * NPAR * sizeof(double)));
+        HIP_TRY(hipHostMalloc((void **)&s->h_params, R * NPAR * sizeof(double), 0));
+        HIP_TRY(hipMalloc((void **)&s->d_cpart, R * 2 * ((no + 63) / 64) * sizeof(double)));
+        s->cap = rc;
     }
-    const size_t no = (size_t)s->nout;
-    HIP_TRY(hipMalloc((void **)&s->Y, R * no * sizeof(float)));
-    HIP_TRY(hipMalloc((void **)&s->T, R * no * sizeof(float)));
-    HIP_TRY(hipMalloc((void **)&s->Mask, R * no * sizeof(float)));
-    HIP_TRY(hipMalloc((void **)&s->dY, R * no * sizeof(bf16)));
-    HIP_TRY(hipMalloc((void **)&s->maps, R * 3 * s->npix * sizeof(float)));
-    HIP_TRY(hipMalloc((void **)&s->cnt, R * sizeof(unsigned)));
-    HIP_TRY(hipMalloc((void **)&s->d_params, R * NPAR * sizeof(double)));
-    HIP_TRY(hipHostMalloc((void **)&s->h_params, R * NPAR * sizeof(double), 0));
-    HIP_TRY(hipMalloc((void **)&s->d_partial, kRedBlocks * sizeof(double)));
-    HIP_TRY(hipMalloc((void **)&s->d_cpart, R * 2 * ((no + 63) / 64) * sizeof(double)));
-    HIP_TRY(hipMalloc((void **)&s->d_colpart,
-                      (size_t)kColChunks * std::max<size_t>(hid, no) * sizeof(float)));
-    s->cap = rows;
+    if (full && rows > s->tcap) {
+        HIP_TRY(hipStreamSynchronize(s->stream));
+        const int rt = grown(rows, s->tcap);
+        s->free_full();
+        const size_t R = (size_t)rt;
+        for (int l = 0; l < s->layers; ++l) {
+            bf16 *dh;
+            float *z;
+            HIP_TRY(hipMalloc((void **)&dh, R * hid * sizeof(bf16)));
+            s->dH.push_back(dh);
+            HIP_TRY(hipMalloc((void **)&z, R * hid * sizeof(float)));
+            s->Z.push_back(z);
+        }
+        HIP_TRY(hipMalloc((void **)&s->Y, R * no * sizeof(float)));
+        HIP_TRY(hipMalloc((void **)&s->T, R * no * sizeof(float)));
+        HIP_TRY(hipMalloc((void **)&s->Mask, R * no * sizeof(float)));
+        HIP_TRY(hipMalloc((void **)&s->dY, R * no * sizeof(bf16)));
+        HIP_TRY(hipMalloc((void **)&s->maps, R * 3 * s->npix * sizeof(float)));
+        HIP_TRY(hipMalloc((void **)&s->cnt, R * sizeof(unsigned)));
+        HIP_TRY(hipMalloc((void **)&s->d_partial, kRedBlocks * sizeof(double)));
+        HIP_TRY(hipMalloc((void **)&s->d_colpart, (size_t)kColChunks * std::max(hid, no) * sizeof(float)));
+        s->tcap = rt;
+    }
     return GK_OK;
 }
 
@@ -783,12 +813,13 @@ gk_status adam(gk_surrogate *s, double lr, hipStream_t st)
     return GK_OK;
 }
 
-// rows (host or device) -> s->d_params (on st)
-gk_status stage_params(gk_surrogate *s, const double *params, int B, hipStream_t st)
+// rows (host or device) -> s->d_params (on st); `full`: the caller needs the
+// training and full-output buffers too
+gk_status stage_params(gk_surrogate *s, const double *params, int B, bool full, hipStream_t st)
 {
     const PtrKind pk = pointer_kind(params);
     if (pk == PTR_BAD) return fail(GK_EINVAL, "params pointer of unknown kind");
-    GK_TRY(reserve_rows(s, B));
+    GK_TRY(reserve_rows(s, B, full));
     if (pk == PTR_DEVICE) {
         HIP_TRY(hipMemcpyAsync(s->d_params, params, sizeof(double) * NPAR * B,
                                hipMemcpyDeviceToDevice, st));
@@ -885,7 +916,7 @@ gk_status gbk::surrogate_chi2(gk_surrogate *s, gk_model *obs, const double *d_pa
 {
     for (int r0 = 0; r0 < B; r0 += infer_chunk(s)) {
         const int n = std::min(infer_chunk(s), B - r0);
-        GK_TRY(stage_params(s, d_params + (size_t)r0 * NPAR, n, st));
+        GK_TRY(stage_params(s, d_params + (size_t)r0 * NPAR, n, false, st));
         GK_TRY(infer_chi2(s, obs, n, d_chi2 + r0, st));
     }
     return GK_OK;
@@ -998,7 +1029,7 @@ gk_status gk_surrogate_create(gk_model *m, const double *lo, const double *hi,
             hipLaunchKernelGGL(k_to_bf16, dim3(blocks(nw)), dim3(256), 0, s->stream, s->W[l], pb, nw);
             HIP_TRY(hipGetLastError());
         }
-        GK_TRY(reserve_rows(s, o.batch));
+        GK_TRY(reserve_rows(s, o.batch, true));
         HIP_TRY(hipStreamSynchronize(s->stream));
         return GK_OK;
     };
@@ -1072,7 +1103,7 @@ gk_status gk_surrogate_train(gk_surrogate *s, int64_t steps, float *losses)
     DeviceGuard g(s->device);
     HIP_TRY(g.err);
     hipStream_t st = s->stream;
-    GK_TRY(reserve_rows(s, s->o.batch));
+    GK_TRY(reserve_rows(s, s->o.batch, true));
     const int64_t chunk = 4096;  // losses are gathered per chunk of steps
     if (s->loss_cap < chunk) {
         HIP_TRY(hipStreamSynchronize(st));
@@ -1111,7 +1142,7 @@ gk_status gk_surrogate_gradients(gk_surrogate *s, const double *params, int32_t 
     DeviceGuard g(s->device);
     HIP_TRY(g.err);
     hipStream_t st = s->stream;
-    GK_TRY(stage_params(s, params, B, st));
+    GK_TRY(stage_params(s, params, B, true, st));
     if (!s->d_loss) {
         HIP_TRY(hipMalloc((void **)&s->d_loss, 4096 * sizeof(float)));
         s->loss_cap = 4096;
@@ -1143,7 +1174,7 @@ gk_status gk_surrogate_predict(gk_surrogate *s, const double *params, int32_t B,
     hipStream_t st = (hipStream_t)stream;
     for (int r0 = 0; r0 < B; r0 += infer_chunk(s)) {
         const int n = std::min(infer_chunk(s), B - r0);
-        GK_TRY(stage_params(s, params + (size_t)r0 * NPAR, n, st));
+        GK_TRY(stage_params(s, params + (size_t)r0 * NPAR, n, true, st));
         GK_TRY(encode_rows(s, n, st));
         GK_TRY(forward(s, n, false, st));
         const size_t ne = (size_t)n * s->nout;
@@ -1170,7 +1201,7 @@ gk_status gk_surrogate_chi2(gk_surrogate *s, gk_model *m, const double *params, 
     hipStream_t st = (hipStream_t)stream;
     for (int r0 = 0; r0 < B; r0 += infer_chunk(s)) {
         const int n = std::min(infer_chunk(s), B - r0);
-        GK_TRY(stage_params(s, params + (size_t)r0 * NPAR, n, st));
+        GK_TRY(stage_params(s, params + (size_t)r0 * NPAR, n, false, st));
         GK_TRY(infer_chi2(s, m, n, chi2 + r0, st));
     }
     return GK_OK;

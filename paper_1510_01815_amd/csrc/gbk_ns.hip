@@ -794,7 +794,7 @@ gk_status fit_nested(gk_model *m, gk_surrogate *sur, const double *lo, const dou
     }
     std::memset(res, 0, sizeof *res);
     int64_t n_plain = 0;
-    Rng audit_rng(o.seed, 0x617564u);
+    const uint32_t audit_key[2] = {(uint32_t)o.seed, (uint32_t)(o.seed >> 32) ^ 0x61756474u};
     std::vector<double> recent;  // surrogate-minus-plain chi2 of the latest plain evaluations
     size_t recent_pos = 0;
     double shift = 0.0;
@@ -836,11 +836,23 @@ gk_status fit_nested(gk_model *m, gk_surrogate *sur, const double *lo, const dou
         const double cut = chi2_floor + shift + margin;
         keep.clear();
         audited.assign(n, 0);
+        // the audit draw of candidate i is 32-bit word i % 4 of the Philox block
+        // (i / 4, round) under the fit's audit key, made only for candidates
+        // the screen discards
+        uint32_t blk[4];
+        int blk_id = -1;
         for (int i = 0; i < n; ++i) {
-            const double a = audit_rng.uniform();  // one draw per candidate, used or not
             if (!(h_chi2s[i] > cut)) {
                 keep.push_back(i);
-            } else if (a < audit) {
+                continue;
+            }
+            if (!(audit > 0.0)) continue;
+            if (i / 4 != blk_id) {
+                blk_id = i / 4;
+                const uint32_t ctr[4] = {(uint32_t)blk_id, (uint32_t)round, 0x617564u, 0u};
+                philox4x32_10(ctr, audit_key, blk);
+            }
+            if (((double)blk[i % 4] + 0.5) * 0x1.0p-32 < audit) {
                 keep.push_back(i);
                 audited[i] = 1;
             }
