@@ -47,6 +47,9 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_1510_01815_amd", "csrc", f)
 
 
 TIME_EVERY = 10  # one step in TIME_EVERY of the timed region is timed kernel by kernel
+# acceptances per nested-sampling round (adaptive batch) of the surrogate
+# workload's fits, plain and screened alike: N/5 for N = 1000 live points
+ACCEPT_TARGET = 200
 
 
 def kernel_source_hash() -> str:
@@ -192,7 +195,8 @@ def fits_per_hour(gbk, I, torch, n_gal, train_rows):
     t_train = time.perf_counter() - t0
     log(f"surrogate trained on {steps * batch} rows in {t_train:.1f} s")
     out = {"workload": "64x64x64 instrument, 30 km/s channels, PSF FWHM 2.5 px, LSF sigma 30 km/s, "
-                       "noise 5 km/s; nested sampling with 1000 live points, 10 free parameters",
+                       "noise 5 km/s; nested sampling with 1000 live points, 10 free parameters, "
+                       f"adaptive batch (1000-16000 candidates, ~{ACCEPT_TARGET} acceptances per round)",
            "train": {"rows": steps * batch, "seconds": round(t_train, 3),
                      "rows_per_s": round(steps * batch / t_train, 1),
                      "final_loss": float(np.mean(losses[-50:]))}}
@@ -211,9 +215,10 @@ def fits_per_hour(gbk, I, torch, n_gal, train_rows):
         maps = m.evaluate(torch.tensor(truth[None], device=dev)).cpu().numpy()[0]
         obs = I.make_observation(maps, 5.0, I.rng_for(5, k, 1))
         m.set_obs(obs)
-        pl = m.fit_nested(lo, hi, free, truth, n_live=1000, batch_max=16000, seed=100 + k)
+        pl = m.fit_nested(lo, hi, free, truth, n_live=1000, batch_max=16000,
+                          accept_target=ACCEPT_TARGET, seed=100 + k)
         sc = S.fit_nested(m, lo, hi, free, truth, margin=25.0, audit=0.02, n_live=1000,
-                          batch_max=16000, seed=100 + k)
+                          batch_max=16000, accept_target=ACCEPT_TARGET, seed=100 + k)
         log(f"surrogate workload galaxy {k}: plain {pl['t_wall_s']:.2f} s, screened {sc['t_wall_s']:.2f} s")
         sd = np.where(pl["sd"] > 0, pl["sd"], 1.0)
         fits.append({"galaxy": k, "plain_s": pl["t_wall_s"], "screened_s": sc["t_wall_s"],

@@ -213,7 +213,8 @@ gk_status gk_fit_lm(gk_model *model, double *p_inout, const uint8_t *free_mask, 
  * while the two children's volumes sum to under half the parent's (each child
  * keeping >= 2 (d + 1) points, at most max_ell ellipsoids, none smaller than
  * the prior volume n_e X_k / N of its points), rebuilt after every N/20
- * retired points (an older bound still encloses the shrinking constrained
+ * retired points from the live points at the start of a round and used from
+ * the next round on (an older bound still encloses the shrinking constrained
  * region); draws a batch of candidates
  * uniformly over the union inside the box, evaluates them in one launch, and
  * consumes them in draw order: a candidate whose L
@@ -221,8 +222,9 @@ gk_status gk_fit_lm(gk_model *model, double *p_inout, const uint8_t *free_mask, 
  * prior-volume weight X_{k-1} - X_k, X_k = exp(-k/N).  Stops when
  * log(Z + L_max X_k) - log Z < tol, then adds the live points with weight X_k/N.
  * Batch: `batch` candidates per round, or, with batch_max > batch, as many
- * as should give about N/10 acceptances at the acceptance rate of the last
- * two rounds, within [batch, batch_max] (fewer, larger launches when the
+ * as should give about accept_target (default N/10) acceptances at the
+ * acceptance rate of the last two rounds, within [batch, batch_max] (fewer,
+ * larger launches when the
  * bound fits the constrained region poorly; the candidates of a round are
  * still drawn from a bound that encloses the region, so the sampler's
  * statistics are those of the fixed batch).
@@ -236,6 +238,8 @@ typedef struct {
     uint64_t seed;       /* default 1 */
     int32_t max_ell;     /* ellipsoids of the bound, 1..8; default 8 (1: one ellipsoid) */
     int32_t batch_max;   /* adaptive batch ceiling (>= batch; 0: fixed batch); default 0 */
+    int32_t accept_target; /* acceptances per round the adaptive batch aims at (>= 0;
+                              0: N/10); default 0 */
 } gk_ns_opts;
 
 typedef struct {

@@ -435,7 +435,8 @@ gk_status ns_run(int d, const DrawEval &draw_eval, const gk_ns_opts &o, gk_ns_re
             const double rate = acc_prev < 0.0 ? acc / cand : (acc + acc_prev) / (cand + cand_prev);
             acc_prev = acc;
             cand_prev = cand;
-            const double want = rate > 0.0 ? std::ceil(std::max(1, N / 10) / rate) : (double)Bmax;
+            const int target = o.accept_target > 0 ? o.accept_target : std::max(1, N / 10);
+            const double want = rate > 0.0 ? std::ceil(target / rate) : (double)Bmax;
             B = (int)std::min<double>(Bmax, std::max<double>(o.batch, want));
         }
     }
@@ -506,7 +507,8 @@ void posterior_stats(const std::vector<double> &pu, const std::vector<double> &p
 gk_status check_opts(const gk_ns_opts &o)
 {
     if (o.n_live < 2 || o.batch < 1 || o.max_iter < 1 || !(o.enlarge >= 1.0) || !(o.tol > 0.0) ||
-        o.max_ell < 1 || o.max_ell > kMaxEll || (o.batch_max != 0 && o.batch_max < o.batch))
+        o.max_ell < 1 || o.max_ell > kMaxEll || (o.batch_max != 0 && o.batch_max < o.batch) ||
+        o.accept_target < 0)
         return fail(GK_EINVAL, "invalid nested-sampling options");
     return GK_OK;
 }
@@ -531,6 +533,7 @@ extern "C" gk_status gk_ns_default_opts(gk_ns_opts *o)
     o->seed = 1;
     o->max_ell = 8;
     o->batch_max = 0;
+    o->accept_target = 0;
     return GK_OK;
 }
 

@@ -148,3 +148,26 @@ def test_ns_adaptive_batch_keeps_the_statistics():
         assert abs(r["mean"][1] - 1.0) < 0.15 and abs(r["sd"][1] - math.sqrt(2.01)) < 0.15
     with pytest.raises(gbk.GkError):
         gbk.nested_sample(f, lo, hi, n_live=400, batch=400, batch_max=100)
+
+
+def test_ns_accept_target_sets_the_round_size():
+    """A larger acceptance target per round (adaptive batch) takes fewer
+    rounds; evidence and moments stay within their errors; a negative target
+    is rejected."""
+    from paper_1510_01815_amd import gbk
+
+    def f(th):
+        x, y = th[:, 0], th[:, 1]
+        return -x ** 2 / 2 - (y - x ** 2) ** 2 / 0.02
+    lo, hi = np.array([-5.0, -2.0]), np.array([5.0, 28.0])
+    true = math.log(2 * math.pi * 0.1 / 300)
+    small = gbk.nested_sample(f, lo, hi, n_live=400, seed=7, batch=100, batch_max=6400)
+    large = gbk.nested_sample(f, lo, hi, n_live=400, seed=7, batch=100, batch_max=6400,
+                              accept_target=100)
+    assert large["n_launches"] < 0.7 * small["n_launches"]
+    for r in (small, large):
+        assert abs(r["logz"] - true) < 3 * r["logz_err"] + 0.1
+        assert abs(r["mean"][0]) < 0.1 and abs(r["sd"][0] - 1.0) < 0.1
+        assert abs(r["mean"][1] - 1.0) < 0.15 and abs(r["sd"][1] - math.sqrt(2.01)) < 0.15
+    with pytest.raises(gbk.GkError):
+        gbk.nested_sample(f, lo, hi, n_live=400, accept_target=-1)
