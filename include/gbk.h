@@ -240,6 +240,14 @@ typedef struct {
     int32_t batch_max;   /* adaptive batch ceiling (>= batch; 0: fixed batch); default 0 */
     int32_t accept_target; /* acceptances per round the adaptive batch aims at (>= 0;
                               0: N/10); default 0 */
+    /* gk_fit_nested_screened only: a round of n candidates skips the screen
+     * (every candidate gets the plain chi2) unless (1 - f) n > screen_cost n +
+     * screen_rows, f = the pass fraction of the last screened round; every
+     * 8th round is screened regardless.  screen_cost = cost of a surrogate
+     * row in plain rows, screen_rows = the screen's fixed cost per round in
+     * plain rows; default 0 and 0 (every round screened). */
+    double screen_cost;
+    int32_t screen_rows;
 } gk_ns_opts;
 
 typedef struct {

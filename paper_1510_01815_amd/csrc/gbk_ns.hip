@@ -508,7 +508,7 @@ gk_status check_opts(const gk_ns_opts &o)
 {
     if (o.n_live < 2 || o.batch < 1 || o.max_iter < 1 || !(o.enlarge >= 1.0) || !(o.tol > 0.0) ||
         o.max_ell < 1 || o.max_ell > kMaxEll || (o.batch_max != 0 && o.batch_max < o.batch) ||
-        o.accept_target < 0)
+        o.accept_target < 0 || !(o.screen_cost >= 0.0) || o.screen_rows < 0)
         return fail(GK_EINVAL, "invalid nested-sampling options");
     return GK_OK;
 }
@@ -534,6 +534,8 @@ extern "C" gk_status gk_ns_default_opts(gk_ns_opts *o)
     o->max_ell = 8;
     o->batch_max = 0;
     o->accept_target = 0;
+    o->screen_cost = 0.0;
+    o->screen_rows = 0;
     return GK_OK;
 }
 
@@ -803,6 +805,8 @@ gk_status fit_nested(gk_model *m, gk_surrogate *sur, const double *lo, const dou
     double shift = 0.0;
     std::vector<int> keep;
     std::vector<char> audited;
+    double pass_frac = 0.0;  // of the last screened round
+    int since_screen = 8;    // rounds since the last screened one (the first is screened)
     DrawEval eval = [&](const Bound *bnd, int n, int64_t round, double floor, double *u,
                         double *logl) -> gk_status {
         g.n = n;
@@ -821,7 +825,13 @@ gk_status fit_nested(gk_model *m, gk_surrogate *sur, const double *lo, const dou
         HIP_TRY(hipGetLastError());
         HIP_TRY(hipMemcpyAsync(nb.h_u, nb.d_u, sizeof(double) * n * d, hipMemcpyDeviceToHost, stream));
         for (int i = 0; i < n; ++i) logl[i] = -INFINITY;
-        if (!sur) {
+        // screen this round only where the plain evaluations it saves (at the
+        // last screened round's pass fraction) outweigh its own cost
+        const bool adaptive = o.screen_cost > 0.0 || o.screen_rows > 0;
+        const bool screen = sur && (!adaptive || since_screen >= 8 ||
+                                    (1.0 - pass_frac) * n > o.screen_cost * n + o.screen_rows);
+        if (!screen) {
+            ++since_screen;
             GK_TRY(run_batch(m, d_params, n, nullptr, nullptr, d_chi2, nullptr, stream));
             HIP_TRY(hipMemcpyAsync(h_chi2, d_chi2, sizeof(double) * n, hipMemcpyDeviceToHost, stream));
             HIP_TRY(wait(stream));
@@ -863,6 +873,8 @@ gk_status fit_nested(gk_model *m, gk_surrogate *sur, const double *lo, const dou
         res->n_screened += n;
         res->n_rejected += n - (int64_t)keep.size();
         const int nk = (int)keep.size();
+        pass_frac = (double)nk / n;
+        since_screen = 0;
         if (nk > 0) {
             std::memcpy(nb.h_idx, keep.data(), sizeof(int) * nk);
             HIP_TRY(hipMemcpyAsync(nb.d_idx, nb.h_idx, sizeof(int) * nk, hipMemcpyHostToDevice, stream));

@@ -74,7 +74,8 @@ class NSOpts(ctypes.Structure):
     _fields_ = [("n_live", ctypes.c_int32), ("batch", ctypes.c_int32), ("max_iter", ctypes.c_int64),
                 ("enlarge", ctypes.c_double), ("tol", ctypes.c_double), ("seed", ctypes.c_uint64),
                 ("max_ell", ctypes.c_int32), ("batch_max", ctypes.c_int32),
-                ("accept_target", ctypes.c_int32)]
+                ("accept_target", ctypes.c_int32), ("screen_cost", ctypes.c_double),
+                ("screen_rows", ctypes.c_int32)]
 
 
 class NSResult(ctypes.Structure):

@@ -248,6 +248,26 @@ def test_screened_nested_sampling_matches_plain_with_fewer_evaluations(gbk, trai
     assert scr["n_evals"] < 0.5 * plain["n_evals"]
 
 
+def test_screened_nested_sampling_skips_unprofitable_rounds(gbk, trained):
+    """With the screen priced above a plain evaluation (screen_cost 2) a round
+    is screened only every 8th time: far fewer candidates reach the network,
+    and the posterior still matches the plain sampler's."""
+    m, truth, lo, hi, free, S = trained
+    plain = m.fit_nested(lo, hi, free, truth, n_live=200, seed=11)
+    always = S.fit_nested(m, lo, hi, free, truth, margin=25.0, audit=0.02, n_live=200, seed=11)
+    rare = S.fit_nested(m, lo, hi, free, truth, margin=25.0, audit=0.02, n_live=200, seed=11,
+                        screen_cost=2.0)
+    total = rare["n_evals"] + rare["n_rejected"]  # every candidate of the run
+    print("screened", rare["n_screened"], "of", total, "(always:", always["n_screened"], ")")
+    assert rare["status"] == 0
+    assert 0 < rare["n_screened"] < 0.3 * total
+    assert always["n_screened"] == always["n_evals"] + always["n_rejected"]
+    for k in range(12):
+        if free[k]:
+            assert abs(rare["median"][k] - plain["median"][k]) <= 0.1 * plain["sd"][k], k
+    assert abs(rare["logz"] - plain["logz"]) < 3 * plain["logz_err"]
+
+
 def test_surrogate_rejects_bad_arguments(O, gbk):
     grid, lo, hi, opts = small_setup(O)
     m = gbk.Model.from_grid(grid)

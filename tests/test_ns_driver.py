@@ -171,3 +171,6 @@ def test_ns_accept_target_sets_the_round_size():
         assert abs(r["mean"][1] - 1.0) < 0.15 and abs(r["sd"][1] - math.sqrt(2.01)) < 0.15
     with pytest.raises(gbk.GkError):
         gbk.nested_sample(f, lo, hi, n_live=400, accept_target=-1)
+    for bad in ({"screen_cost": -1.0}, {"screen_rows": -1}, {"screen_cost": float("nan")}):
+        with pytest.raises(gbk.GkError):
+            gbk.nested_sample(f, lo, hi, n_live=400, **bad)
