@@ -395,6 +395,16 @@ int64_t gk_surrogate_weight_count(const gk_surrogate *s);
 gk_status gk_surrogate_get_weights(gk_surrogate *s, float *w, int64_t n);
 gk_status gk_surrogate_set_weights(gk_surrogate *s, const float *w, int64_t n);
 
+/* Saves the surrogate to a file: options, box and instrument description
+ * (the fields of gk_model_desc that define the grid, PSF, LSF and rotation
+ * curve) and the FP32 master weights, little-endian, after the 8-byte tag
+ * "GKSURR01".  Load creates a surrogate for `instrument` from such a file and
+ * sets its weights (fresh Adam state); the instrument must match the saved
+ * description.  Both block.  Errors: GK_EINVAL (unreadable or truncated file,
+ * wrong tag, instrument mismatch), GK_ENOMEM, GK_EDEVICE. */
+gk_status gk_surrogate_save(gk_surrogate *s, const char *path);
+gk_status gk_surrogate_load(gk_model *instrument, const char *path, gk_surrogate **out);
+
 /* Loss and its gradient (host, weight-vector layout) on the rows params
  * [B][GK_NP] (host or device; B a multiple of 32), targets from the plain
  * evaluation; no update.  Blocks. */

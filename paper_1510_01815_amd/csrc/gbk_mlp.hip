@@ -20,6 +20,7 @@
 
 #include <cfloat>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -1130,6 +1131,123 @@ gk_status gk_surrogate_train(gk_surrogate *s, int64_t steps, float *losses)
             HIP_TRY(hipMemcpyAsync(losses + t0, s->d_loss, n * sizeof(float), hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
     }
+    return GK_OK;
+}
+
+namespace {
+
+constexpr char kSurrogateTag[8] = {'G', 'K', 'S', 'U', 'R', 'R', '0', '1'};
+
+// The instrument fields a saved surrogate depends on, in file order (no
+// padding: six doubles, then six 32-bit integers, the last always 0).
+struct SavedInstrument {
+    double dv, v0, crpix, psf, lsf, R;
+    int32_t nx, ny, nz, upsample, rc, zero;
+};
+static_assert(sizeof(SavedInstrument) == 72, "unpadded layout");
+
+SavedInstrument instrument_of(const gk_model_desc &d)
+{
+    return {d.dv_kms, d.v0_kms, d.crpix, d.psf_fwhm_pix, d.lsf_sigma_kms, d.kernel_radius_sigma,
+            d.nx, d.ny, d.nz, d.upsample, d.rc, 0};
+}
+
+bool same_instrument(const SavedInstrument &a, const SavedInstrument &b)
+{
+    return a.dv == b.dv && a.v0 == b.v0 && a.crpix == b.crpix && a.psf == b.psf && a.lsf == b.lsf &&
+           a.R == b.R && a.nx == b.nx && a.ny == b.ny && a.nz == b.nz && a.upsample == b.upsample &&
+           a.rc == b.rc;
+}
+
+struct File {
+    FILE *f = nullptr;
+    ~File()
+    {
+        if (f) std::fclose(f);
+    }
+};
+
+}  // namespace
+
+gk_status gk_surrogate_save(gk_surrogate *s, const char *path)
+{
+    if (!s || !path) return fail(GK_EINVAL, "NULL argument");
+    std::vector<float> w(s->weight_count());
+    GK_TRY(gk_surrogate_get_weights(s, w.data(), (int64_t)w.size()));
+    File f;
+    f.f = std::fopen(path, "wb");
+    if (!f.f) return fail(GK_EINVAL, "cannot open %s for writing", path);
+    const SavedInstrument ins = instrument_of(s->model->d);
+    const int32_t ints[3] = {s->o.hidden, s->o.layers, s->o.batch};
+    const double lrs[2] = {s->o.lr, s->o.lr_final};
+    const int64_t n = (int64_t)w.size();
+    bool ok = std::fwrite(kSurrogateTag, 1, 8, f.f) == 8;
+    ok = ok && std::fwrite(ints, sizeof ints, 1, f.f) == 1;
+    ok = ok && std::fwrite(lrs, sizeof lrs, 1, f.f) == 1;
+    ok = ok && std::fwrite(&s->o.seed, sizeof s->o.seed, 1, f.f) == 1;
+    ok = ok && std::fwrite(s->lo, sizeof s->lo, 1, f.f) == 1;
+    ok = ok && std::fwrite(s->hi, sizeof s->hi, 1, f.f) == 1;
+    ok = ok && std::fwrite(&ins, sizeof ins, 1, f.f) == 1;
+    ok = ok && std::fwrite(&n, sizeof n, 1, f.f) == 1;
+    ok = ok && std::fwrite(w.data(), sizeof(float), w.size(), f.f) == w.size();
+    ok = std::fclose(f.f) == 0 && ok;
+    f.f = nullptr;
+    if (!ok) return fail(GK_EINVAL, "writing %s failed", path);
+    return GK_OK;
+}
+
+gk_status gk_surrogate_load(gk_model *m, const char *path, gk_surrogate **out)
+{
+    if (!m || !path || !out) return fail(GK_EINVAL, "NULL argument");
+    *out = nullptr;
+    File f;
+    f.f = std::fopen(path, "rb");
+    if (!f.f) return fail(GK_EINVAL, "cannot open %s", path);
+    char tag[8];
+    int32_t ints[3];
+    double lrs[2], lo[NPAR], hi[NPAR];
+    uint64_t seed;
+    SavedInstrument ins;
+    int64_t n = 0;
+    bool ok = std::fread(tag, 1, 8, f.f) == 8 && std::memcmp(tag, kSurrogateTag, 8) == 0;
+    ok = ok && std::fread(ints, sizeof ints, 1, f.f) == 1;
+    ok = ok && std::fread(lrs, sizeof lrs, 1, f.f) == 1;
+    ok = ok && std::fread(&seed, sizeof seed, 1, f.f) == 1;
+    ok = ok && std::fread(lo, sizeof lo, 1, f.f) == 1;
+    ok = ok && std::fread(hi, sizeof hi, 1, f.f) == 1;
+    ok = ok && std::fread(&ins, sizeof ins, 1, f.f) == 1;
+    ok = ok && std::fread(&n, sizeof n, 1, f.f) == 1;
+    if (!ok) return fail(GK_EINVAL, "%s is not a saved surrogate or is truncated", path);
+    const SavedInstrument mine = instrument_of(m->d);
+    if (!same_instrument(ins, mine))
+        return fail(GK_EINVAL, "%s was saved for another instrument", path);
+    gk_surrogate_opts o;
+    gk_surrogate_default_opts(&o);
+    o.hidden = ints[0];
+    o.layers = ints[1];
+    o.batch = ints[2];
+    o.lr = lrs[0];
+    o.lr_final = lrs[1];
+    o.seed = seed;
+    gk_surrogate *s = nullptr;
+    GK_TRY(gk_surrogate_create(m, lo, hi, &o, &s));
+    std::vector<float> w;
+    gk_status st = GK_OK;
+    if (n != gk_surrogate_weight_count(s)) {
+        st = fail(GK_EINVAL, "%s holds %lld weights, the network has %lld", path, (long long)n,
+                  (long long)gk_surrogate_weight_count(s));
+    } else {
+        w.resize((size_t)n);
+        if (std::fread(w.data(), sizeof(float), w.size(), f.f) != w.size())
+            st = fail(GK_EINVAL, "%s is truncated", path);
+        else
+            st = gk_surrogate_set_weights(s, w.data(), n);
+    }
+    if (st != GK_OK) {
+        gk_surrogate_destroy(s);
+        return st;
+    }
+    *out = s;
     return GK_OK;
 }
 

@@ -30,7 +30,8 @@ SYMBOLS = (
     "gk_create_survey", "gk_destroy_survey", "gk_survey_chi2", "gk_fit_lm_survey",
     "gk_surrogate_default_opts", "gk_surrogate_create", "gk_surrogate_destroy",
     "gk_surrogate_train", "gk_surrogate_weight_count", "gk_surrogate_get_weights",
-    "gk_surrogate_set_weights", "gk_surrogate_gradients", "gk_surrogate_predict",
+    "gk_surrogate_set_weights", "gk_surrogate_save", "gk_surrogate_load",
+    "gk_surrogate_gradients", "gk_surrogate_predict",
     "gk_surrogate_chi2", "gk_fit_nested_screened", "gk_gemm_bf16", "gk_model_conv_path",
     "gk_set_launch_mode", "gk_graph_launches", "gk_autotune", "gk_set_conv_config",
 )
@@ -227,6 +228,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.gk_surrogate_weight_count.argtypes = [vp]
     L.gk_surrogate_get_weights.argtypes = [vp, vp, ctypes.c_int64]
     L.gk_surrogate_set_weights.argtypes = [vp, vp, ctypes.c_int64]
+    L.gk_surrogate_save.argtypes = [vp, ctypes.c_char_p]
+    L.gk_surrogate_load.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(vp)]
     L.gk_surrogate_gradients.argtypes = [vp, vp, i32, vp, ctypes.POINTER(ctypes.c_double)]
     L.gk_surrogate_predict.argtypes = [vp, vp, i32, vp, vp]
     L.gk_surrogate_chi2.argtypes = [vp, vp, vp, i32, vp, vp]
@@ -555,6 +558,25 @@ class Surrogate:
         self._h = h
         self.device = model.device
         self.nx, self.ny = model.nx, model.ny
+
+    def save(self, path: str) -> None:
+        """Writes options, box, instrument and weights to `path` (gk_surrogate_save)."""
+        _check(load().gk_surrogate_save(self._h, os.fsencode(path)))
+
+    @classmethod
+    def load(cls, model: "Model", path: str) -> "Surrogate":
+        """A surrogate for `model`'s instrument from a file written by save()."""
+        L = load()
+        h = ctypes.c_void_p()
+        _check(L.gk_surrogate_load(model._h, os.fsencode(path), ctypes.byref(h)))
+        self = cls.__new__(cls)
+        self._h = h
+        self.model = model  # the model must outlive the surrogate
+        self.device = model.device
+        self.nx, self.ny = model.nx, model.ny
+        self.opts = None
+        self.lo = self.hi = None
+        return self
 
     def close(self):
         if getattr(self, "_h", None):

@@ -268,6 +268,32 @@ def test_screened_nested_sampling_skips_unprofitable_rounds(gbk, trained):
     assert abs(rare["logz"] - plain["logz"]) < 3 * plain["logz_err"]
 
 
+def test_surrogate_save_and_load_round_trip(O, gbk, tmp_path):
+    """A saved surrogate loads with the same weights and predicts the same maps;
+    another instrument, a foreign file and a missing file are refused."""
+    grid, lo, hi, opts = small_setup(O)
+    m = gbk.Model.from_grid(grid)
+    S = gbk.Surrogate(m, lo, hi, **opts)
+    S.train(20)
+    path = str(tmp_path / "net.gks")
+    S.save(path)
+    T = gbk.Surrogate.load(m, path)
+    np.testing.assert_array_equal(S.get_weights(), T.get_weights())
+    rows = draw_rows(np.random.default_rng(5), lo, hi, 64)
+    np.testing.assert_array_equal(S.predict(rows).cpu().numpy(), T.predict(rows).cpu().numpy())
+    other = gbk.Model.from_grid(I.Grid(16, 16, 32, 25.0, psf_fwhm=2.0, lsf_sigma=30.0))
+    with pytest.raises(gbk.GkError):
+        gbk.Surrogate.load(other, path)                               # other channel width
+    bad = tmp_path / "bad.gks"
+    bad.write_bytes(b"GKSURR01" + bytes(16))
+    with pytest.raises(gbk.GkError):
+        gbk.Surrogate.load(m, str(bad))                               # truncated
+    with pytest.raises(gbk.GkError):
+        gbk.Surrogate.load(m, str(tmp_path / "missing.gks"))
+    T.close()
+    S.close()
+
+
 def test_surrogate_rejects_bad_arguments(O, gbk):
     grid, lo, hi, opts = small_setup(O)
     m = gbk.Model.from_grid(grid)
