@@ -15,6 +15,7 @@
 #include <cstring>
 #include <functional>
 #include <mutex>
+#include <new>
 #include <numeric>
 #include <thread>
 #include <vector>
@@ -388,10 +389,15 @@ gk_status ns_run(int d, const DrawEval &draw_eval, const gk_ns_opts &o, gk_ns_re
     Worker worker;
     while (!done) {
         const bool building = k - k_built >= rebuild;
+        bool build_failed = false;
         if (building) {
             const double logX = -(double)k / N;
             worker.submit([&, logX] {
-                build_bound(live_u.data(), N, d, o.enlarge, logX, o.max_ell, next);
+                try {
+                    build_bound(live_u.data(), N, d, o.enlarge, logX, o.max_ell, next);
+                } catch (const std::bad_alloc &) {
+                    build_failed = true;
+                }
             });
         }
         const gk_status st = draw_eval(&bnd, B, n_launch, heap.front().first, ub.data(), lb.data());
@@ -401,6 +407,7 @@ gk_status ns_run(int d, const DrawEval &draw_eval, const gk_ns_opts &o, gk_ns_re
             k_built = k;
         }
         GK_TRY(st);
+        if (build_failed) return fail(GK_ENOMEM, "out of host memory building the bound");
         n_evals += B;
         ++n_launch;
         const int64_t k_round = k;
