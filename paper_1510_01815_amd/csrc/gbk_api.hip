@@ -237,8 +237,12 @@ gk_status enqueue_batch(gk_model *m, const double *params, PtrKind pk, int32_t B
         if (timing) {
             // device-scope timestamps: no system-memory fence around the dispatch
             hipError_t e = hipEventCreateWithFlags(&e0, hipEventDisableSystemFence);
-            if (e == hipSuccess) e = hipEventCreateWithFlags(&e1, hipEventDisableSystemFence);
             if (e != hipSuccess) return e;
+            e = hipEventCreateWithFlags(&e1, hipEventDisableSystemFence);
+            if (e != hipSuccess) {
+                (void)hipEventDestroy(e0);
+                return e;
+            }
             launch_events() = {e0, e1};
         }
         hipError_t e = fn();
