@@ -191,3 +191,28 @@ def test_c2_full_batch_sampled(O, gbk):
         assert_maps_close(maps[b], ref[k], f"c2 row {b}")
         assert_chi2_close(c[b], rc[k], rn[k], f"c2 row {b}")
         print("c2 row", b, max_map_errors(maps[b], ref[k]))
+
+
+def test_c5_instrument_largest_batch_sampled(O, gbk):
+    """64 x 64 x 64 (the surrogate workload's instrument), 16,000 rows per
+    launch, the largest batch its nested-sampling fits draw; three rows are
+    checked whole against the oracle (maps and chi-square)."""
+    import torch
+    grid = I.c5_grid()
+    lo, hi = I.c5_box()
+    rows = lo + np.random.default_rng(17).random((16000, I.NPAR)) * (hi - lo)
+    obs = make_obs(O, grid, I.c5_galaxy(2), 19, noise=5.0)
+    m = gbk.Model.from_grid(grid)
+    m.set_obs(obs)
+    dev_rows = torch.tensor(rows, device="cuda")
+    maps = m.evaluate(dev_rows).cpu().numpy()
+    c, n = m.chi2(dev_rows)
+    c = c.cpu().numpy()
+    sample = [0, 8191, 15999]
+    ref = oracle_maps(O, grid, rows[sample])
+    rc, rn = oracle_chi2(O, grid, rows[sample], obs)
+    for k, b in enumerate(sample):
+        assert_maps_close(maps[b], ref[k], f"c5 row {b}")
+        assert_chi2_close(c[b], rc[k], rn[k], f"c5 row {b}")
+        print("c5 row", b, max_map_errors(maps[b], ref[k]))
+
