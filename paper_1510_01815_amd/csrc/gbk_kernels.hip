@@ -154,6 +154,14 @@ __device__ inline void wave_min2(int a, int b, int &amin, int &bmin)
     bmin = (int)hi;
 }
 
+// 1/sqrt(r2) in FP64 (r2 >= 0; ~1e15 at r2 = 0): the FP32 estimate refined
+// by one Newton step (relative error ~1e-14)
+__device__ inline double y0_refine(double r2)
+{
+    const double y0 = (double)__builtin_amdgcn_rsqf(fmaxf((float)r2, 1e-30f));
+    return y0 * fma(-0.5 * r2 * y0, y0, 1.5);
+}
+
 // 2^x for x in roughly [-1070, 1000] in FP64 with FP32 relative accuracy:
 // x = n + f, f in [0, 1), 2^x = ldexp(2^f, n).
 __device__ inline double exp2_wide(double x)
@@ -202,24 +210,33 @@ __device__ __forceinline__ void line_sums_tile(const double *__restrict__ c,
     const double xe = fma(fx, c[C_XEX], fma(fy, c[C_XEY], c[C_XE0]));
     const double ye = fma(fx, c[C_YEX], fma(fy, c[C_YEY], c[C_YE0]));
     const double r2 = fma(xe, xe, ye * ye);
-    const double y0 = (double)__builtin_amdgcn_rsqf(fmaxf((float)r2, 1e-30f));
-    const double rd = r2 * (y0 * fma(-0.5 * r2 * y0, y0, 1.5));
+    const double yr = y0_refine(r2);  // 1/r, FP64
+    const double rd = r2 * yr;
     const float r = (float)rd;
-    const float costh = r > 0.0f ? (float)xe * __builtin_amdgcn_rcpf(r) : 0.0f;
 
-    // rotation curve (eqs. 6-7 or exponential rise), FP32
-    const float q = r * (float)c[C_IRT];
-    float shape;
-    if (rc == RC_ARCTAN) {
-        shape = (float)(2.0 / kPi) * atanf(q);
-    } else if (rc == RC_EPINAT) {
-        shape = q > 0.0f ? powf(q, (float)c[C_G]) / (1.0f + powf(q, (float)c[C_A])) : 0.0f;
+    // rotation curve (eqs. 6-7 or exponential rise) and eq. 8.  The bounded
+    // curves (arctan, exponential rise: |V_rot| <= V_t) run in FP32, and the
+    // product is added to Vsys in FP64.  The Epinat curve rises without bound
+    // when g > a (Sec. 2.1.3), where FP32 would leave ~3e-7 of a velocity of
+    // thousands of km/s in the line centre, and a line centred outside the
+    // band then changes its in-band wing by ~1e-5; that curve runs in FP64.
+    double vlos;
+    if (rc == RC_EPINAT) {
+        const double lq = log2(rd * c[C_IRT]);  // -inf at r = 0: shape 0
+        const double shape = exp2(c[C_G] * lq) / (1.0 + exp2(c[C_A] * lq));
+        vlos = c[C_VSYS] + c[C_VTSINI] * shape * (r2 > 0.0 ? xe * yr : 0.0);
     } else {
-        // 1 - e^-q; absolute error ~1e-7, i.e. ~1e-5 km/s on the velocity
-        shape = 1.0f - __builtin_amdgcn_exp2f(-q * (float)kLog2e);
+        const float costh = r > 0.0f ? (float)xe * __builtin_amdgcn_rcpf(r) : 0.0f;
+        const float q = r * (float)c[C_IRT];
+        float shape;
+        if (rc == RC_ARCTAN) {
+            shape = (float)(2.0 / kPi) * atanf(q);
+        } else {
+            // 1 - e^-q; absolute error ~1e-7, i.e. ~1e-5 km/s on the velocity
+            shape = 1.0f - __builtin_amdgcn_exp2f(-q * (float)kLog2e);
+        }
+        vlos = c[C_VSYS] + (double)((float)c[C_VTSINI] * shape * costh);
     }
-    // eq. 8 (the FP32 product is added to Vsys in FP64)
-    const double vlos = c[C_VSYS] + (double)((float)c[C_VTSINI] * shape * costh);
 
     // line centre in fine halo-channel units and its significant range
     const double zc = (vlos - vf0) * inv_dvf;

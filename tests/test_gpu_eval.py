@@ -7,6 +7,7 @@ degenerate shapes, and the 128 x 128 x 48 workload at its full batch of 400
 rows (the launch configuration of the benchmark), sampled.
 """
 import math
+import zlib
 
 import numpy as np
 import pytest
@@ -59,7 +60,7 @@ def oracle_maps(O, grid, rows):
 def test_maps_match_oracle(O, gbk, name):
     import torch
     grid = GRIDS[name]
-    rows = rows_for(grid, 6, hash(name) % 1000)
+    rows = rows_for(grid, 6, zlib.crc32(name.encode()) % 1000)  # same rows in every process
     m = gbk.Model.from_grid(grid)
     ref = oracle_maps(O, grid, rows)
     # host-given rows
