@@ -14,8 +14,9 @@
  * with the separable PSF/LSF kernel of eq. 9 (Sec. 2.2.3, done as three 1-D
  * passes z, x, y), average down by the upsampling factor (Sec. 2.2.4), take
  * the zeroth/first/second moments of every spectrum (Sec. 2.2.5) and form the
- * masked chi-square of eq. 11 (Sec. 2.2.6).  No blocking, fusion or
- * reordering.  The fitters at the end (Levenberg-Marquardt, Sec. 2.3.1; nested
+ * masked chi-square of eq. 11 (Sec. 2.2.6).  The velocity-field strategy
+ * (Sec. 2.2.1) evaluates eq. 8 per data pixel and goes straight to eq. 11.
+ * No blocking, fusion or reordering.  The fitters at the end (Levenberg-Marquardt, Sec. 2.3.1; nested
  * grids, Sec. 2.3.3) call the evaluation exactly as written here.
  *
  * Readings of points the paper leaves open (all listed in the design doc):
@@ -363,6 +364,55 @@ int go_eval_chi2(const go_desc *d, const double *p, const double *vo, const doub
     }
     if (rc == 0)
         go_chi2((int)npix, maps + npix, maps + 2 * npix, vo, so, ev, es, mask, W, chi2, nvalid);
+    free(maps);
+    return rc;
+}
+
+/* ---- velocity-field modelling strategy (Sec. 2.2.1) --------------------- */
+
+/* The second strategy: the kinematic model evaluated straight on the data
+ * grid, one value per pixel centre (x, y) = (i, j), with no cube, no PSF or
+ * LSF, no down-sampling and no moments; the residual step (eq. 11) follows.
+ * maps[3][ny][nx] = surface brightness (eq. 5), line-of-sight velocity
+ * (eq. 8) and the intrinsic dispersion sigma, which is the model's
+ * dispersion map when no beam smearing acts.  Only nx and ny of the
+ * descriptor (and its rotation curve) are used.  Out-of-domain parameters
+ * give NaN maps and -1. */
+int go_vfield(const go_desc *d, const double *p, double *maps)
+{
+    size_t npix = (size_t)d->nx * d->ny;
+    if (!go_params_valid(d, p)) {
+        for (size_t i = 0; i < 3 * npix; ++i) maps[i] = NAN;
+        return -1;
+    }
+    for (int y = 0; y < d->ny; ++y)
+        for (int x = 0; x < d->nx; ++x) {
+            size_t i = (size_t)y * d->nx + x;
+            double vlos, inten;
+            go_sky_point(d->rc, p, (double)x, (double)y, &vlos, &inten);
+            maps[i] = inten;
+            maps[npix + i] = vlos;
+            maps[2 * npix + i] = p[P_SIG];
+        }
+    return 0;
+}
+
+/* Velocity field then chi2 (eq. 11; the dispersion term only when W != 0);
+ * chi2 = +inf for an out-of-domain row. */
+int go_vfield_chi2(const go_desc *d, const double *p, const double *vo, const double *so,
+                   const double *ev, const double *es, const uint8_t *mask, double W,
+                   double *chi2, int64_t *nvalid)
+{
+    size_t npix = (size_t)d->nx * d->ny;
+    double *maps = (double *)malloc(sizeof(double) * 3 * npix);
+    if (!maps) return -2;
+    int rc = go_vfield(d, p, maps);
+    if (rc == -1) {
+        *chi2 = INFINITY;
+        if (nvalid) *nvalid = 0;
+    } else {
+        go_chi2((int)npix, maps + npix, maps + 2 * npix, vo, so, ev, es, mask, W, chi2, nvalid);
+    }
     free(maps);
     return rc;
 }

@@ -8,7 +8,8 @@ every signature are declared independently.
 Each function follows a step of the paper's evaluation (Bekiaris et al. 2016):
 model cube (Sec. 2.1, eqs. 1-8; Sec. 2.2.2), PSF/LSF convolution (eq. 9,
 Sec. 2.2.3), down-sampling (Sec. 2.2.4), moments (Sec. 2.2.5), chi-square
-(eq. 11, Sec. 2.2.6).
+(eq. 11, Sec. 2.2.6); the velocity-field strategy (Sec. 2.2.1) evaluates eq. 8
+per data pixel and skips the cube, convolution and moment steps.
 """
 from __future__ import annotations
 
@@ -103,6 +104,9 @@ def lib():
                               ctypes.POINTER(ctypes.c_int64)]
         L.go_eval_chi2.argtypes = [P, D, D, D, D, D, U8, ctypes.c_double, D,
                                    ctypes.POINTER(ctypes.c_int64)]
+        L.go_vfield.argtypes = [P, D, D]
+        L.go_vfield_chi2.argtypes = [P, D, D, D, D, D, U8, ctypes.c_double, D,
+                                     ctypes.POINTER(ctypes.c_int64)]
         _lib = L
     return _lib
 
@@ -209,6 +213,30 @@ def eval_chi2(d: Desc, p, vo, so, ev, es, mask, W: float):
     rc = lib().go_eval_chi2(ctypes.byref(d.c()), _ptr(p), _ptr(vo), _ptr(so), _ptr(ev),
                             _ptr(es), mask.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
                             W, ctypes.byref(c), ctypes.byref(n))
+    if rc == -2:
+        raise MemoryError("oracle allocation failed")
+    return c.value, n.value
+
+
+def vfield(d: Desc, p) -> np.ndarray:
+    """Velocity-field strategy (Sec. 2.2.1): maps[3][ny][nx] = (surface
+    brightness, eq. 8 velocity, sigma) at the data pixel centres; NaN maps for
+    out-of-domain parameters.  Only nx, ny and rc of the descriptor are used."""
+    out = np.zeros((3, d.ny, d.nx))
+    p = _f64(p)
+    lib().go_vfield(ctypes.byref(d.c()), _ptr(p), _ptr(out))
+    return out
+
+
+def vfield_chi2(d: Desc, p, vo, so, ev, es, mask, W: float):
+    """(chi2, n_valid) of the velocity-field strategy; chi2 = +inf out of domain."""
+    vo, so, ev, es = (_f64(a).ravel() for a in (vo, so, ev, es))
+    mask = np.ascontiguousarray(mask, dtype=np.uint8).ravel()
+    p = _f64(p)
+    c, n = ctypes.c_double(), ctypes.c_int64()
+    rc = lib().go_vfield_chi2(ctypes.byref(d.c()), _ptr(p), _ptr(vo), _ptr(so), _ptr(ev),
+                              _ptr(es), mask.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                              W, ctypes.byref(c), ctypes.byref(n))
     if rc == -2:
         raise MemoryError("oracle allocation failed")
     return c.value, n.value
