@@ -13,7 +13,10 @@ live with HIP events on the launch stream) and the CPU oracle baseline, plus
 fits/hour of the surrogate workload (64 x 64 x 64 instrument): the network
 trained on 2 M rows streamed from the plain evaluation, then nested-sampling
 fits (1000 live points, 10 free parameters) of synthetic galaxies, plain and
-surrogate-screened, with the posterior medians compared.
+surrogate-screened, with the posterior medians compared; and the
+velocity-field strategy (Sec. 2.2.1) on GHASP-shaped 256^2 and 512^2 maps:
+evals/s of 1024-row launches, its kernel's roofline, LM fits and the oracle's
+rate.
 """
 import argparse
 import json
@@ -54,6 +57,17 @@ ACCEPT_TARGET = 200
 # ~0.24 plain rows on the 64x64x64 instrument and the screen ~500 plain rows per
 # round (measured on MI355X); 0.3 and 300 fitted best over the six galaxies
 SCREEN_COST, SCREEN_ROWS = 0.3, 300
+
+# Velocity-field strategy (Sec. 2.2.1) on GHASP-shaped maps: batch of the
+# timed launches, and the kernel's executed FP64 FLOP and VALU instructions per
+# pixel on the Epinat curve, from the SQ_INSTS_VALU_{FMA,ADD,MUL,TRANS}_F64 and
+# SQ_INSTS_VALU counters of the 512 x 512 x 1024-row launches (FMA = 2 FLOP; the
+# FP64 elementary functions' polynomial evaluations included)
+VF_BATCH = 1024
+VF_FLOP_PER_PIXEL = 167.3
+VF_VALU_PER_PIXEL = 182.6
+# wave64 VALU issue peak: 256 CUs x 4 SIMDs x 2.4 GHz, one wave instruction per 4 cycles
+VALU_ISSUE_PER_S = 256 * 4 * 2.4e9 / 4
 
 
 def kernel_source_hash() -> str:
@@ -101,6 +115,8 @@ def parse():
                     help="galaxies of the uneven-survey LM workload (0: skip)")
     ap.add_argument("--grid-galaxies", type=int, default=2,
                     help="galaxies of the nested-grid workload (0: skip)")
+    ap.add_argument("--vfield-galaxies", type=int, default=4,
+                    help="LM fits of the velocity-field workload (-1: skip the workload)")
     return ap.parse_args()
 
 
@@ -175,6 +191,99 @@ def other_workloads(gbk, I, torch, n_survey, n_grid):
                                        "fits_per_hour": round(3600 * n_grid / sum(ts), 1),
                                        "evals_per_s": round(ev / sum(ts), 1),
                                        "evals_per_fit": ev / n_grid}
+    return out
+
+
+def velocity_field_workload(gbk, I, torch, n_fit, cpu):
+    """The velocity-field strategy on GHASP-shaped maps (Epinat curve,
+    velocity only): evals/s of 1024-row chi-square launches at 256^2 and 512^2,
+    the kernel's roofline, LM fits of 512^2 galaxies, and the oracle's rate."""
+    dev = torch.device("cuda:0")
+    out = {"workload": "GHASP-shaped velocity fields (Fabry-Perot, Sec. 4.2): Epinat curve, "
+                       "velocity only (W = 0), coverage to ~3 disc scale lengths with 30% holes, "
+                       f"noise 5 km/s, {VF_BATCH} rows per launch"}
+    for side in (256, 512):
+        grid = I.ghasp_grid(side)
+        m = gbk.Model.from_grid(grid)
+        rows = I.ghasp_draw(I.rng_for(6, side, 0), 21 * VF_BATCH, side)
+        mp = m.evaluate(torch.tensor(rows[:1], device=dev)).cpu().numpy()[0]
+        m.set_obs(I.make_observation(mp, 5.0, I.rng_for(6, side, 1), flux_frac=I.GHASP_FLUX_FRAC,
+                                     random_mask=I.GHASP_HOLES, W=0.0))
+        batches = torch.tensor(rows.reshape(21, VF_BATCH, I.NPAR), device=dev)
+        c2 = torch.empty((21, VF_BATCH), dtype=torch.float64, device=dev)
+        nv = torch.empty((21, VF_BATCH), dtype=torch.int64, device=dev)
+        stream = torch.cuda.current_stream()
+        for k in range(3):
+            m.chi2(batches[k], out=c2[k], n_valid=nv[k], stream=stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(1, 21):
+            m.chi2(batches[k], out=c2[k], n_valid=nv[k], stream=stream)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / 20
+        m.set_profiling(gbk.GK_PROF_TIMING)
+        for k in range(1, 11):
+            m.chi2(batches[k], out=c2[k], n_valid=nv[k], stream=stream)
+        prof = m.read_profile()
+        m.set_profiling(0)
+        kms = prof["kernel_ms"]["k_line_sums"] / max(prof["launches"]["k_line_sums"], 1)
+        px = VF_BATCH * side * side
+        entry = {"evals_per_s": round(VF_BATCH / dt, 1), "ms_per_launch": round(1e3 * dt, 4),
+                 "k_vfield_ms": round(kms, 5)}
+        if side == 512:
+            tf = px * VF_FLOP_PER_PIXEL / (kms * 1e-3) / 1e12
+            issue = px * VF_VALU_PER_PIXEL / 64 / (kms * 1e-3)
+            entry["roofline"] = {"bound": "alu", "kernel": "k_vfield", "achieved": round(tf, 3),
+                                 "peak": round(PEAK_TFLOPS, 1), "unit": "TFLOP/s",
+                                 "frac": round(tf / PEAK_TFLOPS, 4), "traffic": None,
+                                 "flop_per_pixel": VF_FLOP_PER_PIXEL,
+                                 "valu_issue_frac": round(issue / VALU_ISSUE_PER_S, 4)}
+            assert np.isfinite(c2.cpu().numpy()).all()
+        out[f"{side}x{side}"] = entry
+        log(f"velocity field {side}^2: {VF_BATCH / dt:.0f} evals/s")
+    if n_fit > 0:
+        side = 512
+        grid = I.ghasp_grid(side)
+        lo, hi = I.ghasp_box(side)
+        ts, ev, it = [], [], []
+        for k in range(n_fit):
+            truth = I.ghasp_draw(I.rng_for(6, 100 + k, 0), 1, side)[0]
+            m = gbk.Model.from_grid(grid)
+            mp = m.evaluate(torch.tensor(truth[None], device=dev)).cpu().numpy()[0]
+            m.set_obs(I.make_observation(mp, 5.0, I.rng_for(6, 100 + k, 1),
+                                         flux_frac=I.GHASP_FLUX_FRAC, random_mask=I.GHASP_HOLES,
+                                         W=0.0))
+            p0 = I.ghasp_start(I.rng_for(6, 100 + k, 2), truth, side)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = m.fit_lm(p0, I.GHASP_FREE, lo, hi)
+            ts.append(time.perf_counter() - t0)
+            ev.append(r["n_evals"])
+            it.append(r["iterations"])
+        out["lm_512x512"] = {"fits": n_fit, "free": 7, "s_per_fit": round(float(np.mean(ts)), 4),
+                             "fits_per_hour": round(3600 * n_fit / sum(ts), 1),
+                             "evals_per_fit": float(np.mean(ev)),
+                             "iterations_per_fit": float(np.mean(it))}
+        log(f"velocity-field LM fits: {np.mean(ts):.3f} s each")
+    if cpu:
+        from concurrent.futures import ThreadPoolExecutor
+
+        from oracle import oracle as O
+        O.lib()
+        side = 512
+        d = O.Desc(side, side, 1, rc=I.RC_EPINAT)
+        threads = max(1, min(16, os.cpu_count() or 1))
+        rows = I.ghasp_draw(I.rng_for(6, side, 0), 64 * threads, side)
+        ob = I.make_observation(O.vfield(d, rows[0]), 5.0, I.rng_for(6, side, 1),
+                                flux_frac=I.GHASP_FLUX_FRAC, random_mask=I.GHASP_HOLES, W=0.0)
+        t0 = time.perf_counter()
+        with ThreadPoolExecutor(threads) as ex:
+            list(ex.map(lambda r: O.vfield_chi2(d, r, ob.vel, ob.sig, ob.evel, ob.esig, ob.mask,
+                                                0.0), rows))
+        dt = time.perf_counter() - t0
+        out["cpu_oracle_512x512"] = {"value": round(len(rows) / dt, 2), "unit": "evals/s",
+                                     "cores": threads, "kind": "oracle",
+                                     "sample": f"{len(rows)} rows, {dt:.2f} s wall"}
     return out
 
 
@@ -407,6 +516,9 @@ def main():
         out["fits_per_hour"] = fits_per_hour(gbk, I, torch, args.fit_galaxies, args.train_rows)
     if args.survey_galaxies > 0 or args.grid_galaxies > 0:
         out["workloads"] = other_workloads(gbk, I, torch, args.survey_galaxies, args.grid_galaxies)
+    if args.vfield_galaxies >= 0:
+        out["velocity_field"] = velocity_field_workload(gbk, I, torch, args.vfield_galaxies,
+                                                        not args.no_cpu_baseline)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(grid, batches[W, 0].cpu().numpy(), obs,
                                            args.cpu_rows_per_thread)

@@ -85,6 +85,7 @@ typedef struct {
     double kernel_radius_sigma;  /* R > 0 (4 is the usual choice) */
     int32_t rc;                  /* GK_RC_* */
     int32_t conv_mode;           /* GK_CONV_*: how the spatial PSF convolution runs */
+    int32_t strategy;            /* GK_STRATEGY_*: 0 (zero-initialised) = the cube strategy */
 } gk_model_desc;
 
 /* Spatial PSF convolution: AUTO takes the direct LDS-tiled passes while the
@@ -95,6 +96,25 @@ typedef struct {
  * two >= the padded extent (eq. 10) in FP64; its results equal the direct
  * path's up to rounding of order log2(P) * 1e-16 of the largest plane value. */
 enum { GK_CONV_AUTO = 0, GK_CONV_DIRECT = 1, GK_CONV_FFT = 2 };
+
+/* Modelling strategy (Sec. 2.2).  GK_STRATEGY_CUBE is the chain described at
+ * the top of this header.  GK_STRATEGY_VFIELD is the velocity-field strategy
+ * of Sec. 2.2.1: the model of eq. 8 is evaluated at every data pixel centre
+ * (x, y) = (i, j), and the cube, convolution, down-sampling and moment steps
+ * are skipped, so the evaluation goes straight to eq. 11.  Its maps are
+ * [3][ny][nx] = surface brightness I(r) (eq. 5), line-of-sight velocity
+ * (eq. 8) and the intrinsic dispersion sigma (the dispersion map of a disc
+ * without beam smearing), FP64 inside and stored as FP32; its residuals and
+ * chi-square are those of eq. 11 with these maps in place of m1 and m2 (an
+ * observation set with W = 0 compares the velocity field alone).  It needs
+ * upsample = 1 and no PSF or LSF; nz, dv_kms, v0_kms, crpix,
+ * kernel_radius_sigma and conv_mode are not used.  Parameter rows and their
+ * domain are the same as for the cube strategy.  The evaluation calls, the
+ * fitters (LM, nested sampling, nested grids), graphs and profiling (kernel
+ * index 1 = the velocity-field kernel; no voxel count) accept such models;
+ * gk_create_survey, gk_surrogate_create, gk_autotune, gk_set_conv_config and
+ * gk_model_conv_path return GK_EINVAL for them. */
+enum { GK_STRATEGY_CUBE = 0, GK_STRATEGY_VFIELD = 1 };
 
 /* Creates a model for one instrument grid on HIP device `device`.
  * Errors: GK_EINVAL (bad descriptor), GK_ENOMEM, GK_EDEVICE. */

@@ -266,6 +266,39 @@ gk_status enqueue_batch(gk_model *m, const double *params, PtrKind pk, int32_t B
             HIP_TRY(hipEventRecord(m->ev_staged, s));
             prow = m->d_params;
         }
+        if (m->vfield) {
+            // Sec. 2.2.1: constants at u = 1 with no halo, then eq. 8 and the
+            // chi-square terms per pixel (the channel width only enters
+            // constants this path does not read)
+            HIP_TRY(timed(0, [&] { return launch_prep(prow, nb, m->d.rc, 1.0, 0, 1, m->d_consts, s); }));
+            VfArgs v{};
+            v.params = prow;
+            v.consts = m->d_consts;
+            v.rc = m->d.rc;
+            v.nx = m->d.nx;
+            v.ny = m->d.ny;
+            v.B = nb;
+            v.ntiles = m->ntiles;
+            v.rows_per_block = vfield_rows_per_block(m->ntiles, nb);
+            v.use_sig = m->obs_sig;
+            if (resid || chi2) {
+                v.mask = m->d_mask;
+                v.vo = m->d_vo;
+                v.so = m->d_so;
+                v.iev = m->d_iev;
+                v.ies = m->d_ies;
+            }
+            v.maps = maps ? maps + (size_t)b0 * 3 * npix : nullptr;
+            v.resid = resid ? resid + (size_t)b0 * 2 * npix : nullptr;
+            v.partial = chi2 ? m->d_partial : nullptr;
+            HIP_TRY(timed(1, [&] { return launch_vfield(v, s); }));
+            if (chi2)
+                HIP_TRY(timed(3, [&] {
+                    return launch_reduce_chi2(m->d_partial, m->ntiles, m->d_consts, m->nvalid,
+                                              chi2 + b0, nvalid ? nvalid + b0 : nullptr, nb, s);
+                }));
+            continue;
+        }
         HIP_TRY(timed(0, [&] {
             return launch_prep(prow, nb, m->d.rc, m->dvf, m->hp, m->d.upsample, m->d_consts, s);
         }));
@@ -425,7 +458,34 @@ gk_status gk_graph_launches(const gk_model *m, int64_t *count)
 gk_status gk_model_conv_path(const gk_model *m, int32_t *conv_mode)
 {
     if (!m || !conv_mode) return fail(GK_EINVAL, "NULL argument");
+    if (m->vfield) return fail(GK_EINVAL, "a velocity-field model has no convolution");
     *conv_mode = m->use_fft ? GK_CONV_FFT : GK_CONV_DIRECT;
+    return GK_OK;
+}
+
+// The velocity-field strategy (Sec. 2.2.1): the data grid only, no kernel
+// tables, no convolution path.
+static gk_status create_vfield_model(const gk_model_desc &d, int device, gk_model **out)
+{
+    if (d.nx < 1 || d.ny < 1) return fail(GK_EINVAL, "grid sizes must be >= 1");
+    if ((double)d.nx * d.ny >= 2.0e9) return fail(GK_EINVAL, "velocity field too large");
+    if (d.upsample != 1) return fail(GK_EINVAL, "the velocity-field strategy needs upsample = 1");
+    if (d.psf_fwhm_pix != 0.0 || d.lsf_sigma_kms != 0.0)
+        return fail(GK_EINVAL, "the velocity-field strategy has no PSF or LSF (both must be 0)");
+    if (d.rc < GK_RC_ARCTAN || d.rc > GK_RC_BOISSIER) return fail(GK_EINVAL, "unknown rotation curve");
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
+        return fail(GK_EINVAL, "no HIP device %d", device);
+    gk_model *m = new (std::nothrow) gk_model();
+    if (!m) return fail(GK_ENOMEM, "host allocation failed");
+    m->d = d;
+    m->device = device;
+    m->vfield = true;
+    m->NX = m->EX = d.nx;
+    m->NY = m->EY = d.ny;
+    m->NZ = m->NZE = 1;
+    m->ntiles = (int)(((int64_t)d.nx * d.ny + kVfTile - 1) / kVfTile);
+    *out = m;
     return GK_OK;
 }
 
@@ -434,6 +494,8 @@ gk_status gk_create_model(const gk_model_desc *desc, int device, gk_model **out)
     if (!desc || !out) return fail(GK_EINVAL, "desc and out must not be NULL");
     *out = nullptr;
     const gk_model_desc &d = *desc;
+    if (d.strategy == GK_STRATEGY_VFIELD) return create_vfield_model(d, device, out);
+    if (d.strategy != GK_STRATEGY_CUBE) return fail(GK_EINVAL, "unknown strategy %d", d.strategy);
     if (d.nx < 1 || d.ny < 1 || d.nz < 1) return fail(GK_EINVAL, "grid sizes must be >= 1");
     if (d.upsample < 1 || d.upsample > 8) return fail(GK_EINVAL, "upsample must be in 1..8");
     if (!(d.dv_kms > 0.0) || !std::isfinite(d.dv_kms)) return fail(GK_EINVAL, "dv must be > 0");
@@ -567,7 +629,7 @@ gk_status gk_set_profiling(gk_model *m, int flags)
     if (flags & ~(GK_PROF_TIMING | GK_PROF_COUNT)) return fail(GK_EINVAL, "unknown profiling flag");
     DeviceGuard g(m->device);
     HIP_TRY(g.err);
-    if ((flags & GK_PROF_COUNT) && !m->d_count) {
+    if ((flags & GK_PROF_COUNT) && !m->d_count && !m->vfield) {
         // one counter per (row, wave) of the largest chunk
         const size_t n = m->count_slots();
         HIP_TRY(hipMalloc((void **)&m->d_count, n * sizeof(unsigned long long)));
@@ -670,6 +732,7 @@ gk_status gk_set_observation(gk_model *m, const float *vel, const float *sig, co
     HIP_TRY(hipMemcpy(m->d_ies, ies.data(), n * sizeof(double), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(m->d_mask, mk.data(), n, hipMemcpyHostToDevice));
     m->nvalid = nv;
+    m->obs_sig = W > 0.0;
     m->has_obs = true;
     m->drop_graphs();  // recorded chains hold the observation's pointers and count
     return GK_OK;

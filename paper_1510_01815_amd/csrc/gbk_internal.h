@@ -149,4 +149,29 @@ hipError_t launch_reduce_chi2(const double *partial, int ntiles, const double *c
                               int64_t nvalid_obs, double *chi2, int64_t *nvalid, int B,
                               hipStream_t s);
 
+// Velocity-field strategy (gbk_vfield.hip): eq. 8 per data pixel and the
+// chi-square terms of eq. 11, no cube.  A block covers kVfTile consecutive
+// pixels (kVfPixPerThread per thread) for up to kVfMaxRowsPerBlock rows.
+constexpr int kVfPixPerThread = 4;
+constexpr int kVfTile = 256 * kVfPixPerThread;
+constexpr int kVfMaxRowsPerBlock = 64;
+struct VfArgs {
+    const double *params;  // [B][NPAR] (device)
+    const double *consts;  // [B][NCONST] from k_prep with u = 1, hp = 0
+    int rc, nx, ny, B;
+    int ntiles;            // ceil(nx * ny / kVfTile)
+    int rows_per_block;    // 1..kVfMaxRowsPerBlock
+    bool use_sig;          // the observation has a dispersion term (W > 0)
+    // observation (mask == nullptr: none)
+    const uint8_t *mask;
+    const float *vo, *so;
+    const double *iev, *ies;
+    // outputs (nullable)
+    float *maps;      // [B][3][ny][nx]: brightness, velocity, dispersion
+    double *resid;    // [B][2][ny][nx]
+    double *partial;  // [B][ntiles]
+};
+int vfield_rows_per_block(int ntiles, int B);
+hipError_t launch_vfield(const VfArgs &a, hipStream_t s);
+
 }  // namespace gbk

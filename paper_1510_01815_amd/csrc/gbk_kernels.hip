@@ -222,8 +222,9 @@ __device__ __forceinline__ void line_sums_tile(const double *__restrict__ c,
     // band then changes its in-band wing by ~1e-5; that curve runs in FP64.
     double vlos;
     if (rc == RC_EPINAT) {
-        const double lq = log2(rd * c[C_IRT]);  // -inf at r = 0: shape 0
-        const double shape = exp2(c[C_G] * lq) / (1.0 + exp2(c[C_A] * lq));
+        // shape 0 at r = 0, where a = 0 would give exp2(0 * -inf) = NaN
+        const double lq = log2(rd * c[C_IRT]);
+        const double shape = r2 > 0.0 ? exp2(c[C_G] * lq) / (1.0 + exp2(c[C_A] * lq)) : 0.0;
         vlos = c[C_VSYS] + c[C_VTSINI] * shape * (r2 > 0.0 ? xe * yr : 0.0);
     } else {
         const float costh = r > 0.0f ? (float)xe * __builtin_amdgcn_rcpf(r) : 0.0f;

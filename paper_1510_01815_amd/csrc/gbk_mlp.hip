@@ -957,6 +957,7 @@ gk_status gk_surrogate_create(gk_model *m, const double *lo, const double *hi,
 {
     if (!m || !lo || !hi || !out) return fail(GK_EINVAL, "NULL argument");
     *out = nullptr;
+    if (m->vfield) return fail(GK_EINVAL, "the surrogate learns cube-strategy maps");
     gk_surrogate_opts o;
     gk_surrogate_default_opts(&o);
     if (o_in) o = *o_in;

@@ -74,6 +74,8 @@ struct gk_model {
     int hp = 0, hl = 0, NX = 0, NY = 0, NZ = 0, EX = 0, EY = 0, NZE = 0;
     double vf0 = 0, dvf = 0, inv_dvf = 0, vref = 0;
     int TXd = 0, TYd = 0, ntx = 0, nty = 0, ntiles = 0;
+    // velocity-field strategy (Sec. 2.2.1): no cube, ntiles = pixel tiles of k_vfield
+    bool vfield = false;
     size_t lds_bytes = 0;
     double *d_kp = nullptr, *d_wz = nullptr;
     // FFT path of the spatial convolution (gbk_fft.hip)
@@ -83,6 +85,7 @@ struct gk_model {
     double *d_kbx = nullptr, *d_kby = nullptr, *d_U = nullptr;
     // observation
     bool has_obs = false;
+    bool obs_sig = false;  // the observation's dispersion weight W > 0
     int64_t nvalid = 0;
     float *d_vo = nullptr, *d_so = nullptr;
     double *d_iev = nullptr, *d_ies = nullptr;
@@ -138,6 +141,7 @@ struct gk_model {
 
     int chunk_rows() const
     {
+        if (vfield) return 65535;  // per-row scratch: constants and tile partials only
         size_t per = (size_t)3 * EX * EY * sizeof(double);
         if (use_fft) per += (size_t)3 * EY * NX * sizeof(double);
         size_t n = std::max<size_t>(1, gbk::kScratchBudget / per);
@@ -171,7 +175,8 @@ struct gk_model {
             return e;
         if ((e = gbk::dev_alloc(&d_params, (size_t)rows * gbk::NPAR)) != hipSuccess) return e;
         if ((e = gbk::dev_alloc(&d_consts, (size_t)rows * gbk::NCONST)) != hipSuccess) return e;
-        if ((e = gbk::dev_alloc(&d_T, (size_t)rows * 3 * EX * EY)) != hipSuccess) return e;
+        if (!vfield && (e = gbk::dev_alloc(&d_T, (size_t)rows * 3 * EX * EY)) != hipSuccess)
+            return e;
         if ((e = gbk::dev_alloc(&d_partial, (size_t)rows * ntiles)) != hipSuccess) return e;
         if (use_fft && (e = gbk::dev_alloc(&d_U, (size_t)rows * 3 * EY * NX)) != hipSuccess) return e;
         cap = rows;

@@ -308,6 +308,8 @@ extern "C" gk_status gk_create_survey(gk_model *const *models, int32_t n, gk_sur
     *out = nullptr;
     for (int i = 0; i < n; ++i) {
         if (!models[i]) return fail(GK_EINVAL, "model %d is NULL", i);
+        if (models[i]->vfield)
+            return fail(GK_EINVAL, "model %d uses the velocity-field strategy; surveys take cube models", i);
         if (models[i]->use_fft)
             return fail(GK_EINVAL, "model %d uses the FFT convolution path; surveys take direct-path models", i);
         if (models[i]->device != models[0]->device)

@@ -58,6 +58,7 @@ std::vector<double> tune_rows(const gk_model *m, int B)
 extern "C" gk_status gk_set_conv_config(gk_model *m, int32_t conv_mode, int32_t tile_x, int32_t tile_y)
 {
     if (!m) return fail(GK_EINVAL, "model is NULL");
+    if (m->vfield) return fail(GK_EINVAL, "a velocity-field model has no convolution");
     if (conv_mode != GK_CONV_DIRECT && conv_mode != GK_CONV_FFT)
         return fail(GK_EINVAL, "conv_mode must be GK_CONV_DIRECT or GK_CONV_FFT");
     if (m->prof_flags) return fail(GK_ESTATE, "profiling is on");
@@ -71,6 +72,7 @@ extern "C" gk_status gk_set_conv_config(gk_model *m, int32_t conv_mode, int32_t 
 extern "C" gk_status gk_autotune(gk_model *m, int32_t B, gk_tune_result *res)
 {
     if (!m || !res) return fail(GK_EINVAL, "NULL argument");
+    if (m->vfield) return fail(GK_EINVAL, "a velocity-field model has no convolution to tune");
     if (B < 1 || B > 65535) return fail(GK_EINVAL, "batch must be in 1..65535");
     if (m->prof_flags) return fail(GK_ESTATE, "profiling is on");
     DeviceGuard g(m->device);

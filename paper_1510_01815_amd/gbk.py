@@ -20,6 +20,7 @@ GK_OK, GK_PARTIAL, GK_EINVAL, GK_ENOMEM, GK_EDEVICE, GK_ENOTCONV, GK_ESTATE = 0,
 NPAR = 12
 RC = {"arctan": 0, "epinat": 1, "boissier": 2}
 CONV = {"auto": 0, "direct": 1, "fft": 2}
+STRATEGY = {"cube": 0, "vfield": 1}
 
 # exported symbols, kept in step with include/gbk.h
 SYMBOLS = (
@@ -51,7 +52,7 @@ class ModelDesc(ctypes.Structure):
                 ("v0_kms", ctypes.c_double), ("crpix", ctypes.c_double),
                 ("psf_fwhm_pix", ctypes.c_double), ("lsf_sigma_kms", ctypes.c_double),
                 ("kernel_radius_sigma", ctypes.c_double), ("rc", ctypes.c_int32),
-                ("conv_mode", ctypes.c_int32)]
+                ("conv_mode", ctypes.c_int32), ("strategy", ctypes.c_int32)]
 
 
 class ProfileStats(ctypes.Structure):
@@ -284,14 +285,17 @@ class Model:
     """One instrument grid on one device; see gk_create_model."""
 
     def __init__(self, nx, ny, nz, dv, psf_fwhm=0.0, lsf_sigma=0.0, u=1, v0=0.0, crpix=None,
-                 R=4.0, rc=0, device=0, conv="auto"):
+                 R=4.0, rc=0, device=0, conv="auto", strategy=0):
         L = load()
         if isinstance(rc, str):
             rc = RC[rc]
         if isinstance(conv, str):
             conv = CONV[conv]
+        if isinstance(strategy, str):
+            strategy = STRATEGY[strategy]
         self.desc = ModelDesc(nx, ny, nz, u, dv, v0, nz / 2.0 if crpix is None else crpix,
-                              psf_fwhm, lsf_sigma, R, rc, conv)
+                              psf_fwhm, lsf_sigma, R, rc, conv, strategy)
+        self.strategy = strategy
         self.nx, self.ny, self.nz, self.device = nx, ny, nz, device
         h = ctypes.c_void_p()
         _check(L.gk_create_model(ctypes.byref(self.desc), device, ctypes.byref(h)))
@@ -301,7 +305,12 @@ class Model:
     def from_grid(cls, grid, device=0, conv="auto"):
         d = grid.as_dict() if hasattr(grid, "as_dict") else dict(grid)
         return cls(d["nx"], d["ny"], d["nz"], d["dv"], d["psf_fwhm"], d["lsf_sigma"], d["u"],
-                   d["v0"], d["crpix"], d["R"], d["rc"], device, conv)
+                   d["v0"], d["crpix"], d["R"], d["rc"], device, conv, d.get("strategy", 0))
+
+    @classmethod
+    def velocity_field(cls, nx, ny, rc=0, device=0):
+        """A velocity-field strategy model (Sec. 2.2.1) of an nx x ny map."""
+        return cls(nx, ny, 1, 1.0, rc=rc, device=device, strategy=STRATEGY["vfield"])
 
     def close(self):
         if getattr(self, "_h", None):

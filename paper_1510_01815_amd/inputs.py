@@ -40,12 +40,13 @@ class Grid:
     crpix: float | None = None
     R: float = 4.0
     rc: int = RC_ARCTAN
+    strategy: int = 0   # 0: intensity cube, 1: velocity field (no spectral axis used)
 
     def as_dict(self) -> dict:
         crpix = self.nz / 2.0 if self.crpix is None else self.crpix
         return dict(nx=self.nx, ny=self.ny, nz=self.nz, u=self.u, dv=self.dv, v0=self.v0,
                     crpix=crpix, psf_fwhm=self.psf_fwhm, lsf_sigma=self.lsf_sigma, R=self.R,
-                    rc=self.rc)
+                    rc=self.rc, strategy=self.strategy)
 
 
 def rng_for(config_id: int, galaxy: int = 0, purpose: int = 0) -> np.random.Generator:
@@ -212,6 +213,69 @@ def c5_galaxy(k: int) -> np.ndarray:
     p[VSYS] = rng.uniform(-20.0, 20.0)
     p[I0] = 1.0
     return p
+
+
+# --------------------------------------------------------------------------
+# Workload 6: velocity fields shaped like the GHASP Fabry-Perot sample
+# (Sec. 4.2 of the paper): side x side maps (256 or 512), Epinat curve,
+# velocity only, kinematic centre held fixed -> 7 free parameters
+# --------------------------------------------------------------------------
+
+STRATEGY_CUBE, STRATEGY_VFIELD = 0, 1
+GHASP_FREE = (0, 0, 1, 1, 1, 1, 1, 0, 0, 0, 1, 1)
+
+
+def ghasp_grid(side: int = 512) -> Grid:
+    return Grid(side, side, 1, 1.0, psf_fwhm=0.0, lsf_sigma=0.0, rc=RC_EPINAT,
+                strategy=STRATEGY_VFIELD)
+
+
+def ghasp_box(side: int = 512) -> tuple[np.ndarray, np.ndarray]:
+    """Fitting box of the velocity-field workload."""
+    lo = np.array([0.0, 0.0, -180.0, 5.0, 0.0, 10.0, 0.005 * side, 1.0, 0.01 * side, 0.1,
+                   0.2, 0.2])
+    hi = np.array([side, side, 540.0, 85.0, 10000.0, 600.0, 0.5 * side, 200.0, side, 10.0,
+                   4.0, 4.0])
+    return lo, hi
+
+
+def ghasp_draw(rng: np.random.Generator, n: int, side: int = 512) -> np.ndarray:
+    """Nearby discs filling much of the field: systemic velocities of a few
+    thousand km/s, turn-over radii of 3-15% of the field, inner slope g in
+    [0.8, 1.6] and outer slope a >= g so that the curve stays bounded."""
+    p = np.zeros((n, NPAR))
+    p[:, XO] = rng.uniform(0.45, 0.55, n) * side
+    p[:, YO] = rng.uniform(0.45, 0.55, n) * side
+    p[:, PA] = rng.uniform(0.0, 360.0, n)
+    p[:, INC] = rng.uniform(20.0, 75.0, n)
+    p[:, VSYS] = rng.uniform(300.0, 6000.0, n)
+    p[:, VT] = rng.uniform(80.0, 300.0, n)
+    p[:, RT] = rng.uniform(0.03, 0.15, n) * side
+    p[:, SIG] = 20.0
+    p[:, R0] = rng.uniform(0.08, 0.2, n) * side
+    p[:, I0] = 1.0
+    p[:, G] = rng.uniform(0.8, 1.6, n)
+    p[:, A] = p[:, G] + rng.uniform(0.0, 1.0, n)
+    return p
+
+
+def ghasp_start(rng: np.random.Generator, truth: np.ndarray, side: int = 512) -> np.ndarray:
+    """Start of a fit: the free parameters perturbed about the truth."""
+    p = truth.copy()
+    p[PA] += rng.uniform(-10.0, 10.0)
+    p[INC] = np.clip(p[INC] + rng.uniform(-10.0, 10.0), 10.0, 80.0)
+    p[VSYS] += rng.uniform(-20.0, 20.0)
+    p[VT] *= rng.uniform(0.8, 1.2)
+    p[RT] *= rng.uniform(0.8, 1.2)
+    p[A] *= rng.uniform(0.85, 1.15)
+    p[G] *= rng.uniform(0.85, 1.15)
+    return p
+
+
+# coverage of a Fabry-Perot map: the disc out to ~3 scale lengths, with a
+# patchy fraction of the pixels (no H-alpha) missing; velocity noise 3-10 km/s
+GHASP_FLUX_FRAC = math.exp(-3.0)
+GHASP_HOLES = 0.3
 
 
 # --------------------------------------------------------------------------

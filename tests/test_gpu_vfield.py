@@ -1,0 +1,261 @@
+"""GPU parity of the velocity-field strategy (Bekiaris et al. 2016, Sec. 2.2.1)
+against the FP64 oracle, through the C ABI, on seeded synthetic inputs.
+
+Maps, chi-square and residuals on grids of one to several 1024-pixel tiles
+with ragged tails, all three rotation curves, with and without a dispersion
+term; invalid rows; batch-size invariance; the GHASP-shaped 256 x 256 and
+512 x 512 workloads at the benchmark's batch of 1024 rows (sampled rows);
+fitters on such a model; and the entry points that refuse it.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1510_01815_amd import inputs as I
+from parity import assert_chi2_close, assert_maps_close
+
+pytestmark = pytest.mark.gpu
+
+GRIDS = {
+    "arctan_67x45": I.Grid(67, 45, 1, 1.0, 0.0, 0.0, rc=I.RC_ARCTAN, strategy=1),
+    "epinat_40x33": I.Grid(40, 33, 1, 1.0, 0.0, 0.0, rc=I.RC_EPINAT, strategy=1),
+    "boissier_32x32": I.Grid(32, 32, 1, 1.0, 0.0, 0.0, rc=I.RC_BOISSIER, strategy=1),
+    "single_pixel": I.Grid(1, 1, 1, 1.0, 0.0, 0.0, rc=I.RC_EPINAT, strategy=1),
+    "one_row_2500": I.Grid(2500, 1, 1, 1.0, 0.0, 0.0, rc=I.RC_ARCTAN, strategy=1),
+}
+SEEDS = {name: k for k, name in enumerate(sorted(GRIDS))}
+
+
+def vf_rows(grid: I.Grid, n: int, seed: int) -> np.ndarray:
+    """GHASP-like rows scaled to the grid, any rotation curve."""
+    side = max(min(grid.nx, grid.ny), 8)
+    p = I.ghasp_draw(I.rng_for(106, seed, 0), n, side)
+    p[:, I.XO] = I.rng_for(106, seed, 1).uniform(0.3, 0.7, n) * grid.nx
+    p[:, I.YO] = I.rng_for(106, seed, 2).uniform(0.3, 0.7, n) * grid.ny
+    p[:, I.SIG] = I.rng_for(106, seed, 3).uniform(10.0, 60.0, n)
+    p[:, I.I0] = I.rng_for(106, seed, 4).uniform(0.5, 2.0, n)
+    return p
+
+
+def odesc(O, grid):
+    return O.Desc(grid.nx, grid.ny, 1, rc=grid.rc)
+
+
+def vf_obs(O, grid, truth, seed, noise=5.0, random_mask=0.2, W=0.0):
+    maps = O.vfield(odesc(O, grid), truth)
+    ob = I.make_observation(maps, noise, I.rng_for(107, seed, 0), flux_frac=I.GHASP_FLUX_FRAC,
+                            random_mask=random_mask, W=W)
+    if ob.mask.sum() == 0:
+        ob.mask[:] = 1
+    return ob
+
+
+@pytest.mark.parametrize("name", sorted(GRIDS))
+def test_vfield_maps_match_oracle(O, gbk, name):
+    import torch
+    grid = GRIDS[name]
+    rows = vf_rows(grid, 6, SEEDS[name])
+    rows[3, I.INC] = 95.0  # out of the domain: NaN maps
+    m = gbk.Model.from_grid(grid)
+    out = m.evaluate(rows).cpu().numpy()
+    d = odesc(O, grid)
+    for b in range(len(rows)):
+        ref = O.vfield(d, rows[b])
+        if b == 3:
+            assert np.isnan(out[b]).all()
+            continue
+        assert_maps_close(out[b], ref, f"{name} row {b}", bright_frac=0.0)
+        np.testing.assert_array_equal(out[b, 2], np.float32(rows[b, I.SIG]))
+    out2 = m.evaluate(torch.tensor(rows, device="cuda")).cpu().numpy()
+    np.testing.assert_array_equal(out, out2)
+
+
+@pytest.mark.parametrize("name", sorted(GRIDS))
+@pytest.mark.parametrize("W", [0.0, 0.5])
+def test_vfield_chi2_matches_oracle(O, gbk, name, W):
+    grid = GRIDS[name]
+    rows = vf_rows(grid, 8, SEEDS[name] + 20)
+    obs = vf_obs(O, grid, rows[0], SEEDS[name], W=W)
+    rows[5, I.R0] = -1.0  # out of the domain: chi2 = +inf, n_valid = 0
+    m = gbk.Model.from_grid(grid)
+    m.set_obs(obs)
+    assert m.n_valid() == int(obs.mask.sum())
+    c, n = m.chi2(rows)
+    c, n = c.cpu().numpy(), n.cpu().numpy()
+    d = odesc(O, grid)
+    for b in range(len(rows)):
+        rc, rn = O.vfield_chi2(d, rows[b], obs.vel, obs.sig, obs.evel, obs.esig, obs.mask, W)
+        assert n[b] == rn, (b, n[b], rn)
+        if b == 5:
+            assert c[b] == math.inf
+            continue
+        assert_chi2_close(c[b], rc, rn, f"{name} W={W} row {b}")
+
+
+def test_vfield_residuals_match_oracle(O, gbk):
+    grid = GRIDS["arctan_67x45"]
+    rows = vf_rows(grid, 4, 31)
+    obs = vf_obs(O, grid, rows[1], 32, W=0.7)
+    m = gbk.Model.from_grid(grid)
+    m.set_obs(obs)
+    r = m.residuals(rows).cpu().numpy()
+    c, _ = m.chi2(rows)
+    d = odesc(O, grid)
+    mk = obs.mask.astype(bool)
+    for b in range(len(rows)):
+        ref = O.vfield(d, rows[b])
+        rv = np.where(mk, (ref[1] - obs.vel) / obs.evel, 0.0)
+        rs = np.where(mk, math.sqrt(0.7) * (ref[2] - obs.sig) / obs.esig, 0.0)
+        np.testing.assert_allclose(r[b, 0], rv, rtol=1e-9, atol=1e-9)
+        np.testing.assert_allclose(r[b, 1], rs, rtol=1e-9, atol=1e-9)
+        assert (r[b][:, ~mk] == 0).all()
+        ss = float(np.sum(r[b] ** 2))
+        assert abs(ss - float(c[b])) <= 1e-12 * max(ss, 1.0)
+
+
+def test_vfield_chi2_is_independent_of_the_batch(gbk, O):
+    """Rows per block change with the batch size; every row's tile sums and
+    their order do not, so chi2 is bit-identical."""
+    grid = GRIDS["epinat_40x33"]
+    rows = vf_rows(grid, 300, 41)
+    obs = vf_obs(O, grid, rows[0], 42)
+    m = gbk.Model.from_grid(grid)
+    m.set_obs(obs)
+    full = m.chi2(rows)[0].cpu().numpy()
+    part = np.concatenate([m.chi2(rows[:1])[0].cpu().numpy(), m.chi2(rows[1:8])[0].cpu().numpy(),
+                           m.chi2(rows[8:])[0].cpu().numpy()])
+    np.testing.assert_array_equal(full, part)
+
+
+def test_epinat_a0_centre_on_a_pixel(O, gbk):
+    """a = 0 with the centre exactly on a pixel centre: at r = 0 the curve is
+    0 (the oracle's pow(0, 0) = 1), in both strategies."""
+    p = np.array([10.0, 8.0, 30.0, 50.0, 100.0, 150.0, 4.0, 25.0, 5.0, 1.0, 0.0, 1.3])
+    gv = I.Grid(21, 17, 1, 1.0, 0.0, 0.0, rc=I.RC_EPINAT, strategy=1)
+    mv = gbk.Model.from_grid(gv).evaluate(p[None]).cpu().numpy()[0]
+    ref = O.vfield(odesc(O, gv), p)
+    assert np.isfinite(mv).all() and mv[1, 8, 10] == np.float32(100.0)
+    assert_maps_close(mv, ref, "vfield a=0", bright_frac=0.0)
+    gc = I.Grid(21, 17, 48, 20.0, psf_fwhm=2.0, lsf_sigma=15.0, rc=I.RC_EPINAT, v0=100.0,
+                crpix=23.5)
+    mc = gbk.Model.from_grid(gc).evaluate(p[None]).cpu().numpy()[0]
+    from parity import oracle_desc
+    refc = O.evaluate(oracle_desc(O, gc.as_dict()), p)
+    assert np.isfinite(mc).all()
+    assert_maps_close(mc, refc, "cube a=0")
+
+
+@pytest.mark.parametrize("side", [256, 512])
+def test_ghasp_full_batch_sampled(O, gbk, side):
+    """The GHASP-shaped workload at the benchmark's batch (1024 rows): every
+    row's chi2 on the GPU, sampled rows against the oracle; maps of the
+    sampled rows."""
+    import torch
+    grid = I.ghasp_grid(side)
+    rows = I.ghasp_draw(I.rng_for(6, side, 0), 1024, side)
+    obs = vf_obs(O, grid, rows[0], side, noise=5.0, random_mask=I.GHASP_HOLES)
+    m = gbk.Model.from_grid(grid)
+    m.set_obs(obs)
+    dev = torch.tensor(rows, device="cuda")
+    c, n = m.chi2(dev)
+    c, n = c.cpu().numpy(), n.cpu().numpy()
+    assert np.isfinite(c).all() and (n == int(obs.mask.sum())).all()
+    d = odesc(O, grid)
+    pick = [0, 1, 511, 1023]
+    maps = m.evaluate(rows[pick]).cpu().numpy()
+    for k, b in enumerate(pick):
+        rc, rn = O.vfield_chi2(d, rows[b], obs.vel, obs.sig, obs.evel, obs.esig, obs.mask, 0.0)
+        assert_chi2_close(c[b], rc, rn, f"{side} row {b}")
+        assert_maps_close(maps[k], O.vfield(d, rows[b]), f"{side} row {b}", bright_frac=0.0)
+
+
+def test_vfield_lm_recovers_a_noise_free_galaxy(O, gbk):
+    side = 128
+    grid = I.ghasp_grid(side)
+    truth = I.ghasp_draw(I.rng_for(6, 7, 0), 1, side)[0]
+    obs = vf_obs(O, grid, truth, 7, noise=0.0, random_mask=I.GHASP_HOLES)
+    m = gbk.Model.from_grid(grid)
+    m.set_obs(obs)
+    lo, hi = I.ghasp_box(side)
+    p0 = I.ghasp_start(I.rng_for(6, 7, 1), truth, side)
+    r = m.fit_lm(p0, I.GHASP_FREE, lo, hi, max_iter=200)
+    print("LM", r["iterations"], r["n_evals"], r["chi2"], r["reason"])
+    assert r["status"] >= 0
+    free = np.array(I.GHASP_FREE, dtype=bool)
+    np.testing.assert_allclose(r["p"][free], truth[free], rtol=2e-3, atol=1e-3)
+    np.testing.assert_array_equal(r["p"][~free], p0[~free])
+    c, _ = O.vfield_chi2(odesc(O, grid), r["p"], obs.vel, obs.sig, obs.evel, obs.esig,
+                         obs.mask, 0.0)
+    assert abs(c - r["chi2"]) <= 1e-6 * max(c, float(r["n_valid"]))
+
+
+def test_vfield_nested_sampling_brackets_the_truth(O, gbk):
+    side = 64
+    grid = I.ghasp_grid(side)
+    truth = I.ghasp_draw(I.rng_for(6, 8, 0), 1, side)[0]
+    truth[I.PA] = 120.0
+    obs = vf_obs(O, grid, truth, 8, noise=5.0, random_mask=I.GHASP_HOLES)
+    m = gbk.Model.from_grid(grid)
+    m.set_obs(obs)
+    lo, hi = truth.copy(), truth.copy()
+    free = [0, 0, 1, 1, 1, 1, 1, 0, 0, 0, 0, 0]
+    for k, w in ((I.PA, 30.0), (I.INC, 15.0), (I.VSYS, 30.0), (I.VT, 60.0), (I.RT, 3.0)):
+        lo[k], hi[k] = truth[k] - w, truth[k] + w
+    lo[I.INC], hi[I.INC] = max(lo[I.INC], 5.0), min(hi[I.INC], 85.0)
+    r = m.fit_nested(lo, hi, free, truth, n_live=200, seed=5)
+    print("NS", r["logz"], r["n_iter"], r["n_evals"], "median", r["median"][2:7],
+          "sd", r["sd"][2:7])
+    assert r["status"] == 0
+    for k in (I.PA, I.INC, I.VSYS, I.VT, I.RT):
+        assert abs(r["median"][k] - truth[k]) < 5 * r["sd"][k] + 1e-3, k
+
+
+def test_vfield_graph_replays_match_eager(O, gbk):
+    import torch
+    grid = GRIDS["arctan_67x45"]
+    rows = vf_rows(grid, 16, 51)
+    obs = vf_obs(O, grid, rows[0], 52)
+    m = gbk.Model.from_grid(grid)
+    m.set_obs(obs)
+    m.set_launch_mode("eager")
+    ref = m.chi2(rows)[0].cpu().numpy()
+    m.set_launch_mode("graph")
+    s = torch.cuda.Stream()
+    dev = torch.tensor(rows, device="cuda")
+    out = torch.empty(16, dtype=torch.float64, device="cuda")
+    nv = torch.empty(16, dtype=torch.int64, device="cuda")
+    for _ in range(4):
+        m.chi2(dev, out=out, n_valid=nv, stream=s)
+        s.synchronize()
+        np.testing.assert_array_equal(out.cpu().numpy(), ref)
+    assert m.graph_launches() >= 2
+
+
+def test_vfield_profiling_times_the_velocity_kernel(O, gbk):
+    grid = GRIDS["epinat_40x33"]
+    m = gbk.Model.from_grid(grid)
+    m.set_profiling(gbk.GK_PROF_TIMING | gbk.GK_PROF_COUNT)
+    m.evaluate(vf_rows(grid, 5, 61))
+    st = m.read_profile()
+    assert st["rows"] == 5 and st["support_voxels"] == 0
+    names = list(st["kernel_ms"])
+    assert st["launches"][names[0]] == 1 and st["launches"][names[1]] == 1
+    assert st["launches"][names[2]] == 0
+
+
+def test_vfield_refused_where_it_has_no_meaning(gbk):
+    g = I.Grid(32, 32, 1, 1.0, 0.0, 0.0, rc=I.RC_EPINAT, strategy=1)
+    m = gbk.Model.from_grid(g)
+    lo, hi = I.ghasp_box(32)
+    for call in (lambda: gbk.Survey([m]), lambda: gbk.Surrogate(m, lo, hi),
+                 lambda: m.autotune(8), lambda: m.conv_path(),
+                 lambda: m.set_conv_config("direct", 32, 32)):
+        with pytest.raises(gbk.GkError) as e:
+            call()
+        assert e.value.status == gbk.GK_EINVAL
+    for kw in (dict(psf_fwhm=2.0), dict(lsf_sigma=10.0), dict(u=2)):
+        with pytest.raises(gbk.GkError):
+            gbk.Model(16, 16, 1, 1.0, strategy="vfield", **kw)
+    with pytest.raises(gbk.GkError):
+        gbk.Model(16, 16, 1, 1.0, strategy=7)
