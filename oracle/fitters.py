@@ -8,6 +8,8 @@ this project's reading.
 
 levenberg_marquardt: Sec. 2.3.1 -- gradient/curvature local optimiser with box
 constraints and a finite-difference Jacobian of absolute step ~0.1 (Sec. 4).
+mc_errors: Monte-Carlo parameter errors by refits of simulated observations,
+shuffled residuals (Sec. 4.2) or perturbations by the error maps (Sec. 4.3).
 """
 from __future__ import annotations
 
@@ -144,6 +146,76 @@ def model_residuals(d: "O.Desc", obs):
         rs = sw * (m[2].ravel()[mk] - so) / es if obs.W > 0 else np.zeros_like(rv)
         return np.concatenate([rv, rs])
     return resid
+
+
+def vfield_residuals(d: "O.Desc", obs):
+    """r(p) of the velocity-field strategy (Sec. 2.2.1): the terms of eq. 11
+    with the eq. 8 velocity field and sigma in place of m1 and m2."""
+    mk = np.asarray(obs.mask).astype(bool).ravel()
+    vo = np.asarray(obs.vel, dtype=np.float64).ravel()[mk]
+    so = np.asarray(obs.sig, dtype=np.float64).ravel()[mk]
+    ev = np.asarray(obs.evel, dtype=np.float64).ravel()[mk]
+    es = np.asarray(obs.esig, dtype=np.float64).ravel()[mk]
+    sw = math.sqrt(obs.W)
+
+    def resid(p):
+        m = O.vfield(d, p)
+        rv = (m[1].ravel()[mk] - vo) / ev
+        rs = sw * (m[2].ravel()[mk] - so) / es if obs.W > 0 else np.zeros_like(rv)
+        return np.concatenate([rv, rs])
+    return resid
+
+
+def mc_simulations(best_maps: np.ndarray, obs, mode: str, perm=None, noise=None) -> list:
+    """Simulated observations of the Monte-Carlo error estimates.
+
+    shuffle (Sec. 4.2): the residual field of the best fit, observation minus
+    model over the unmasked pixels, has its pixel positions shuffled and is
+    added back to the best-fit model; the unmasked pixels are numbered in
+    row-major order and simulation s puts residual perm[s][k] on pixel k.
+    perturb (Sec. 4.3): each unmasked pixel of the observed maps is moved by
+    its measurement error times noise[s].  The dispersion map changes only
+    when the observation weighs it (W > 0).  Maps are returned as float32,
+    like every observation.
+    """
+    mk = np.asarray(obs.mask).astype(bool)
+    idx = np.flatnonzero(mk.ravel())
+    vo = np.asarray(obs.vel, dtype=np.float64).ravel()
+    so = np.asarray(obs.sig, dtype=np.float64).ravel()
+    out = []
+    n_sim = len(perm) if mode == "shuffle" else len(noise)
+    for s in range(n_sim):
+        v, g = vo.copy(), so.copy()
+        if mode == "shuffle":
+            bv = best_maps[1].ravel().astype(np.float64)
+            bs = best_maps[2].ravel().astype(np.float64)
+            src = idx[np.asarray(perm[s])]
+            v[idx] = bv[idx] + (vo[src] - bv[src])
+            if obs.W > 0:
+                g[idx] = bs[idx] + (so[src] - bs[src])
+        else:
+            n = np.asarray(noise[s], dtype=np.float64)
+            ev = np.asarray(obs.evel, dtype=np.float64).ravel()
+            es = np.asarray(obs.esig, dtype=np.float64).ravel()
+            v[idx] = vo[idx] + ev[idx] * n[0].ravel()[idx]
+            if obs.W > 0:
+                g[idx] = so[idx] + es[idx] * n[1].ravel()[idx]
+        out.append(type(obs)(v.reshape(mk.shape).astype(np.float32),
+                             g.reshape(mk.shape).astype(np.float32), obs.evel, obs.esig, obs.mask,
+                             obs.W))
+    return out
+
+
+def mc_errors(residuals_of, best, best_maps, obs, free, lo, hi, mode, perm=None, noise=None,
+              **lm):
+    """Monte-Carlo parameter errors: every simulation refitted by LM from
+    `best`; returns (fits [n_sim][12], sample SD of each free slot).
+    residuals_of(obs) -> r(p) of the strategy in use."""
+    sims = mc_simulations(best_maps, obs, mode, perm, noise)
+    fits = np.array([levenberg_marquardt(residuals_of(o), best, free, lo, hi, **lm).p
+                     for o in sims])
+    sd = np.where(np.asarray(free, dtype=bool), fits.std(axis=0, ddof=1), 0.0)
+    return fits, sd
 
 
 @dataclass

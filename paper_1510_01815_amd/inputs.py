@@ -279,6 +279,20 @@ GHASP_HOLES = 0.3
 
 
 # --------------------------------------------------------------------------
+# Random draws of the Monte-Carlo error estimates (Sec. 4.2, 4.3)
+# --------------------------------------------------------------------------
+
+def mc_permutations(rng: np.random.Generator, n_sim: int, n_valid: int) -> np.ndarray:
+    """One permutation of 0..n_valid-1 per simulation, int32 [n_sim][n_valid]."""
+    return np.stack([rng.permutation(n_valid) for _ in range(n_sim)]).astype(np.int32)
+
+
+def mc_normals(rng: np.random.Generator, n_sim: int, ny: int, nx: int) -> np.ndarray:
+    """Standard normal draws per simulation, map and pixel, float32 [n_sim][2][ny][nx]."""
+    return rng.standard_normal((n_sim, 2, ny, nx)).astype(np.float32)
+
+
+# --------------------------------------------------------------------------
 # Observations from model maps computed by the caller
 # --------------------------------------------------------------------------
 
