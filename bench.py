@@ -64,6 +64,7 @@ SCREEN_COST, SCREEN_ROWS = 0.3, 300
 # SQ_INSTS_VALU counters of the 512 x 512 x 1024-row launches (FMA = 2 FLOP; the
 # FP64 elementary functions' polynomial evaluations included)
 VF_BATCH = 1024
+MC_SIMS = 200  # simulated velocity fields per galaxy for the Monte-Carlo errors (Sec. 4.2)
 VF_FLOP_PER_PIXEL = 167.3
 VF_VALU_PER_PIXEL = 182.6
 # wave64 VALU issue peak: 256 CUs x 4 SIMDs x 2.4 GHz, one wave instruction per 4 cycles
@@ -265,6 +266,19 @@ def velocity_field_workload(gbk, I, torch, n_fit, cpu):
                              "evals_per_fit": float(np.mean(ev)),
                              "iterations_per_fit": float(np.mean(it))}
         log(f"velocity-field LM fits: {np.mean(ts):.3f} s each")
+        # Monte-Carlo errors of the last galaxy (Sec. 4.2): 200 shuffled residual
+        # fields about its fit, refitted in batched groups
+        best = r["p"]
+        perm = I.mc_permutations(I.rng_for(6, 199, 3), MC_SIMS, m.n_valid())
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        mc = m.mc_errors(best, I.GHASP_FREE, lo, hi, "shuffle", perm=perm)
+        dt = time.perf_counter() - t0
+        out["mc_errors_512x512"] = {"simulations": MC_SIMS, "seconds": round(dt, 4),
+                                    "refits_per_s": round(MC_SIMS / dt, 1),
+                                    "galaxies_per_hour": round(3600 / dt, 1),
+                                    "capped_fits": mc["n_capped"]}
+        log(f"Monte-Carlo errors, {MC_SIMS} refits: {dt:.3f} s")
     if cpu:
         from concurrent.futures import ThreadPoolExecutor
 

@@ -112,7 +112,8 @@ enum { GK_CONV_AUTO = 0, GK_CONV_DIRECT = 1, GK_CONV_FFT = 2 };
  * domain are the same as for the cube strategy.  The evaluation calls, the
  * fitters (LM, nested sampling, nested grids), graphs and profiling (kernel
  * index 1 = the velocity-field kernel; no voxel count) accept such models;
- * gk_create_survey, gk_surrogate_create, gk_autotune, gk_set_conv_config and
+ * surveys whose models all use this strategy, and gk_mc_errors accept such
+ * models; gk_surrogate_create, gk_autotune, gk_set_conv_config and
  * gk_model_conv_path return GK_EINVAL for them. */
 enum { GK_STRATEGY_CUBE = 0, GK_STRATEGY_VFIELD = 1 };
 
@@ -348,7 +349,9 @@ gk_status gk_fit_grid(gk_model *model, const double *lo, const double *hi,
 typedef struct gk_survey gk_survey;
 
 /* models [n] must stay alive (and on one device) while the survey is used;
- * their observations are read at each call.  Errors: GK_EINVAL. */
+ * their observations are read at each call.  All models of a survey use one
+ * strategy; cube models must run the direct convolution path.
+ * Errors: GK_EINVAL. */
 gk_status gk_create_survey(gk_model *const *models, int32_t n, gk_survey **out);
 gk_status gk_destroy_survey(gk_survey *survey);
 
@@ -458,6 +461,37 @@ gk_status gk_fit_nested_screened(gk_model *model, gk_surrogate *s, const double 
                                  const gk_ns_opts *opts, double margin, double audit,
                                  gk_ns_result *result, double *samples, int64_t cap,
                                  int64_t *n_samples);
+
+/* ---- Monte-Carlo parameter errors (Sec. 4.2, Sec. 4.3) --------------------
+ * Refits n_sim simulated observations of the model's instrument, each with
+ * the LM of gk_fit_lm_survey (same options and box, started from `best`), and
+ * returns every fit and the sample standard deviation over the simulations.
+ * The simulations are built on the device from the model's observation:
+ *  GK_MC_SHUFFLE (the GHASP errors, Sec. 4.2): residual field of `best`
+ *    re-dealt over the unmasked pixels: with the unmasked pixels numbered
+ *    0..n_valid-1 in row-major order, pixel k of simulation s gets
+ *    V_best(k) + (V_obs - V_best)(perm[s][k]), and likewise sigma when the
+ *    observation's W > 0; perm [n_sim][n_valid] (host) holds one
+ *    permutation of 0..n_valid-1 per simulation (checked);
+ *  GK_MC_PERTURB (the DYNAMO errors, Sec. 4.3): every unmasked pixel moves
+ *    by its error times a standard normal draw, V_obs + E_v noise[s][0] and,
+ *    when W > 0, sigma_obs + E_s noise[s][1]; noise [n_sim][2][ny][nx] (host).
+ * Masked pixels, errors, mask and W stay those of the observation; the
+ * random draws are inputs, so results are reproducible.  best [12], lo, hi
+ * [12] (NULL = unbounded), free_mask [12] and opts as for gk_fit_lm.
+ * fits [n_sim][12] (host) gets each simulation's fit, sd [12] the standard
+ * deviation (divisor n_sim - 1) of each free slot over the simulations, 0 for
+ * fixed ones; *n_capped (may be NULL) the fits that stopped at max_iter.
+ * Simulations run in groups as surveys of clones of the model (its
+ * observation memory each), with the LM residuals of a group kept under
+ * 4 GiB.  Cube models must run the direct convolution path.  Blocks.
+ * Errors: GK_EINVAL (arguments, a row of perm that is not a permutation),
+ * GK_ESTATE (no observation), GK_ENOMEM, GK_EDEVICE. */
+enum { GK_MC_SHUFFLE = 0, GK_MC_PERTURB = 1 };
+gk_status gk_mc_errors(gk_model *model, const double *best, const uint8_t *free_mask,
+                       const double *lo, const double *hi, const gk_lm_opts *opts, int32_t mode,
+                       int32_t n_sim, const int32_t *perm, const float *noise, double *fits,
+                       double *sd, int32_t *n_capped);
 
 /* BF16 GEMM of the surrogate: C [M][N] (f32, row stride ldc) = sum_k A(m, k)
  * B(n, k), A(m, k) = trans_a ? A[k lda + m] : A[m lda + k], B likewise; BF16

@@ -733,6 +733,7 @@ gk_status gk_set_observation(gk_model *m, const float *vel, const float *sig, co
     HIP_TRY(hipMemcpy(m->d_mask, mk.data(), n, hipMemcpyHostToDevice));
     m->nvalid = nv;
     m->obs_sig = W > 0.0;
+    m->obs_W = W;
     m->has_obs = true;
     m->drop_graphs();  // recorded chains hold the observation's pointers and count
     return GK_OK;

@@ -91,6 +91,8 @@ struct ModelDev {
     int64_t nvalid;         // unmasked pixels of the observation
     int fast_hp;            // >= 0: register-blocked u = 1 kernel with this half-width; -1: generic
     int lds_bytes;          // dynamic LDS of its PSF/moment kernel
+    int vfield;             // velocity-field strategy: psf.ntiles = k_vfield tiles, no T planes
+    int use_sig;            // its observation has a dispersion term
 };
 
 // Ragged rows of a multi-model launch (device arrays).
@@ -173,5 +175,11 @@ struct VfArgs {
 };
 int vfield_rows_per_block(int ntiles, int B);
 hipError_t launch_vfield(const VfArgs &a, hipStream_t s);
+// Ragged rows of velocity-field models (one row per workgroup): rm.ls_base
+// holds the prefix sums of the rows' tiles; chi2 partials at rm.part_off,
+// residuals at rm.resid_off (if resid != NULL).
+hipError_t launch_vfield_multi(const ModelDev *md, const RowMap &rm, int nblocks,
+                               const double *params, const double *consts, double *resid,
+                               double *partial, hipStream_t s);
 
 }  // namespace gbk

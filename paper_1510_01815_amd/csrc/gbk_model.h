@@ -86,6 +86,7 @@ struct gk_model {
     // observation
     bool has_obs = false;
     bool obs_sig = false;  // the observation's dispersion weight W > 0
+    double obs_W = 0.0;    // that weight
     int64_t nvalid = 0;
     float *d_vo = nullptr, *d_so = nullptr;
     double *d_iev = nullptr, *d_ies = nullptr;

@@ -121,10 +121,74 @@ gk_status refresh_models(gk_survey *s, hipStream_t st)
         d.fast_hp = (m->d.upsample == 1 && m->TXd == 32 && m->TYd == 32 && m->hp <= kMaxFastHalo)
                         ? m->hp : -1;
         d.lds_bytes = (int)m->lds_bytes;
+        d.vfield = m->vfield ? 1 : 0;
+        d.use_sig = m->obs_sig ? 1 : 0;
+        if (m->vfield) {  // constants at u = 1 without halo (Sec. 2.2.1)
+            d.hp = 0;
+            d.u = 1;
+            d.dvf = 1.0;
+            d.fast_hp = -1;
+        }
     }
     GK_TRY(s->md.need(n));
     HIP_TRY(hipMemcpyAsync(s->md.p, s->h_md.data(), sizeof(ModelDev) * n, hipMemcpyHostToDevice, st));
     HIP_TRY(hipStreamSynchronize(st));
+    return GK_OK;
+}
+
+// Velocity-field surveys (every model of the survey uses that strategy): per
+// row the constants, then one workgroup per (row, pixel tile), then the
+// fixed-order sum of the tile partials.  No T planes, so chunks are bounded
+// only by the 65,535 rows of a launch.
+gk_status survey_batch_vfield(gk_survey *s, const int32_t *midx, const double *d_params, int B,
+                              double *chi2, double *resid, const int64_t *resid_off, hipStream_t st)
+{
+    for (int b0 = 0; b0 < B; b0 += 65535) {
+        const int nb = std::min(B - b0, 65535);
+        std::vector<int> rmodel(nb), lsb(nb + 1);
+        std::vector<int64_t> poff(nb), roff(nb);
+        int64_t pt = 0;
+        lsb[0] = 0;
+        for (int i = 0; i < nb; ++i) {
+            const ModelDev &m = s->h_md[midx[b0 + i]];
+            rmodel[i] = midx[b0 + i];
+            if ((int64_t)lsb[i] + m.psf.ntiles > INT32_MAX) return fail(GK_EINVAL, "batch too large");
+            lsb[i + 1] = lsb[i] + m.psf.ntiles;
+            poff[i] = pt;
+            pt += m.psf.ntiles;
+            roff[i] = resid_off ? resid_off[b0 + i] : 0;
+        }
+        // staging: ints [rmodel | lsb], then int64 [poff | roff]
+        const size_t bytes = (size_t)(2 * nb + 1) * sizeof(int) + 8 + (size_t)2 * nb * sizeof(int64_t);
+        HIP_TRY(hipEventSynchronize(s->ev_staged));
+        GK_TRY(s->h_idx.need(bytes));
+        GK_TRY(s->idx.need(bytes));
+        char *h = s->h_idx.p;
+        size_t o = 0;
+        auto put = [&](const void *src, size_t n) { std::memcpy(h + o, src, n); o += n; };
+        const size_t o_rm = o; put(rmodel.data(), nb * sizeof(int));
+        const size_t o_ls = o; put(lsb.data(), (nb + 1) * sizeof(int));
+        o = (o + 7) & ~(size_t)7;
+        const size_t o_po = o; put(poff.data(), nb * sizeof(int64_t));
+        const size_t o_ro = o; put(roff.data(), nb * sizeof(int64_t));
+        GK_TRY(s->consts.need((size_t)nb * NCONST));
+        GK_TRY(s->partial.need((size_t)pt));
+        HIP_TRY(hipMemcpyAsync(s->idx.p, h, o, hipMemcpyHostToDevice, st));
+        HIP_TRY(hipEventRecord(s->ev_staged, st));
+        const char *d = s->idx.p;
+        RowMap rm{};
+        rm.row_model = (const int *)(d + o_rm);
+        rm.ls_base = (const int *)(d + o_ls);
+        rm.part_off = (const int64_t *)(d + o_po);
+        rm.resid_off = resid ? (const int64_t *)(d + o_ro) : nullptr;
+        rm.B = nb;
+        const double *prow = d_params + (size_t)b0 * NPAR;
+        HIP_TRY(launch_prep_multi(prow, nb, rm.row_model, s->md.p, s->consts.p, st));
+        HIP_TRY(launch_vfield_multi(s->md.p, rm, lsb[nb], prow, s->consts.p, resid,
+                                    chi2 ? s->partial.p : nullptr, st));
+        if (chi2)
+            HIP_TRY(launch_reduce_multi(s->partial.p, s->md.p, rm, s->consts.p, chi2 + b0, nb, st));
+    }
     return GK_OK;
 }
 
@@ -136,6 +200,7 @@ gk_status survey_batch(gk_survey *s, const int32_t *midx, const double *d_params
     const int nm = (int)s->models.size();
     for (int b = 0; b < B; ++b)
         if (midx[b] < 0 || midx[b] >= nm) return fail(GK_EINVAL, "row %d: model index %d", b, midx[b]);
+    if (s->models[0]->vfield) return survey_batch_vfield(s, midx, d_params, B, chi2, resid, resid_off, st);
     // chunk so that the T planes fit the scratch budget
     int b0 = 0;
     while (b0 < B) {
@@ -308,8 +373,8 @@ extern "C" gk_status gk_create_survey(gk_model *const *models, int32_t n, gk_sur
     *out = nullptr;
     for (int i = 0; i < n; ++i) {
         if (!models[i]) return fail(GK_EINVAL, "model %d is NULL", i);
-        if (models[i]->vfield)
-            return fail(GK_EINVAL, "model %d uses the velocity-field strategy; surveys take cube models", i);
+        if (models[i]->vfield != models[0]->vfield)
+            return fail(GK_EINVAL, "model %d: all models of a survey must use one strategy", i);
         if (models[i]->use_fft)
             return fail(GK_EINVAL, "model %d uses the FFT convolution path; surveys take direct-path models", i);
         if (models[i]->device != models[0]->device)

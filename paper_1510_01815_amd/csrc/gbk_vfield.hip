@@ -34,6 +34,46 @@ __device__ inline double rsqrt_refined(double r2)
     return y0 * fma(-0.5 * r2 * y0, y0, 1.5);
 }
 
+// Rotation-curve shape V_rot(r) / V_t at q = r / r_t (r2 = r^2 tells r = 0),
+// FP64: arctan (eq. 6), Epinat (eq. 7; 0 at r = 0, where a = 0 would give
+// 0 * -inf), exponential rise.
+template <int RC> __device__ inline double rc_shape(double qr, double r2, const double *c)
+{
+    if (RC == RC_ARCTAN) return kTwoOverPi * atan(qr);
+    if (RC == RC_EPINAT) {
+        const double lq = log2(qr);
+        return r2 > 0.0 ? exp2(c[C_G] * lq) / (1.0 + exp2(c[C_A] * lq)) : 0.0;
+    }
+    return -expm1(-qr);
+}
+
+__device__ inline double rc_shape_rt(int rc, double qr, double r2, const double *c)
+{
+    switch (rc) {
+    case RC_ARCTAN: return rc_shape<RC_ARCTAN>(qr, r2, c);
+    case RC_EPINAT: return rc_shape<RC_EPINAT>(qr, r2, c);
+    default: return rc_shape<RC_BOISSIER>(qr, r2, c);
+    }
+}
+
+// eqs. 1-4 and 8 at pixel (fx, fy) of a row with constants c: returns the
+// line-of-sight velocity and the deprojected radius r.  x_e and y_e / cos(i)
+// are affine in the pixel indices; cos(theta) = x_e / r, 0 at the centre.
+template <int RC> __device__ inline double vf_velocity(const double *c, double fx, double fy,
+                                                       int rc, double &r)
+{
+    const double xe = fma(fx, c[C_XEX], fma(fy, c[C_XEY], c[C_XE0]));
+    const double ye = fma(fx, c[C_YEX], fma(fy, c[C_YEY], c[C_YE0]));
+    const double r2 = fma(xe, xe, ye * ye);
+    const double yr = rsqrt_refined(r2);  // 1/r
+    r = r2 * yr;
+    const double qr = r * c[C_IRT];
+    double shape;
+    if constexpr (RC >= 0) shape = rc_shape<RC>(qr, r2, c);
+    else shape = rc_shape_rt(rc, qr, r2, c);
+    return c[C_VSYS] + c[C_VTSINI] * shape * (r2 > 0.0 ? xe * yr : 0.0);
+}
+
 template <int RC, bool MAPS, bool RESID, bool SIG>
 __global__ __launch_bounds__(256) void k_vfield(VfArgs a)
 {
@@ -76,25 +116,8 @@ __global__ __launch_bounds__(256) void k_vfield(VfArgs a)
             double inten = __builtin_nan(""), v = __builtin_nan(""), s = __builtin_nan("");
             double rv = __builtin_nan(""), rs = __builtin_nan("");
             if (valid) {
-                // eqs. 1-4: x_e and y_e / cos(i) are affine in the pixel indices
-                const double xe = fma(fx[q], c[C_XEX], fma(fy[q], c[C_XEY], c[C_XE0]));
-                const double ye = fma(fx[q], c[C_YEX], fma(fy[q], c[C_YEY], c[C_YE0]));
-                const double r2 = fma(xe, xe, ye * ye);
-                const double yr = rsqrt_refined(r2);  // 1/r
-                const double r = r2 * yr;
-                const double qr = r * c[C_IRT];
-                double shape;
-                if (RC == RC_ARCTAN) {
-                    shape = kTwoOverPi * atan(qr);                   // eq. 6
-                } else if (RC == RC_EPINAT) {
-                    // eq. 7; at r = 0 the shape is 0 (and a = 0 would give 0 * -inf)
-                    const double lq = log2(qr);
-                    shape = r2 > 0.0 ? exp2(c[C_G] * lq) / (1.0 + exp2(c[C_A] * lq)) : 0.0;
-                } else {
-                    shape = -expm1(-qr);                             // 1 - exp(-r/rt)
-                }
-                // eq. 8; cos(theta) = x_e / r, 0 at the centre
-                v = c[C_VSYS] + c[C_VTSINI] * shape * (r2 > 0.0 ? xe * yr : 0.0);
+                double r;
+                v = vf_velocity<RC>(c, fx[q], fy[q], RC, r);
                 s = sig;
                 if (MAPS) inten = prow[P_I0] * exp(-fmin(r * c[C_IR0], 60.0));  // eq. 5
                 rv = use[q] ? (v - vo[q]) * iev[q] : 0.0;
@@ -125,6 +148,67 @@ __global__ __launch_bounds__(256) void k_vfield(VfArgs a)
             const double *w = wsum[tid];
             a.partial[(size_t)b * a.ntiles + tile] = ((w[0] + w[1]) + w[2]) + w[3];
         }
+    }
+}
+
+// Row-model lookup of a ragged launch: the largest k with base[k] <= x
+__device__ inline int vf_find_row(const int *__restrict__ base, int n, int x)
+{
+    int lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (base[mid] <= x) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// One (row, tile) per workgroup over rows of different velocity-field models
+// (each with its own grid and observation); chi-square terms and residuals
+// only, the same per-pixel arithmetic and summation order as k_vfield.
+__global__ __launch_bounds__(256) void k_vfield_multi(const ModelDev *__restrict__ md, RowMap rm,
+                                                      const double *__restrict__ params,
+                                                      const double *__restrict__ consts,
+                                                      double *__restrict__ resid,
+                                                      double *__restrict__ partial)
+{
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int b = vf_find_row(rm.ls_base, rm.B, blockIdx.x);
+    const ModelDev &m = md[rm.row_model[b]];
+    const PsfArgs &a = m.psf;
+    const int tile = blockIdx.x - rm.ls_base[b];
+    const int npix = a.nx * a.ny;
+    const double *c = consts + (size_t)b * NCONST;
+    const bool valid = c[C_VALID] != 0.0;
+    const bool sig_term = m.use_sig != 0;
+    double acc = 0.0;
+#pragma unroll
+    for (int q = 0; q < kVfPixPerThread; ++q) {
+        const int p = tile * kVfTile + q * 256 + tid;
+        if (p >= npix) continue;
+        const int y = p / a.nx;
+        const bool use = a.mask && a.mask[p] != 0;
+        double rv = __builtin_nan(""), rs = __builtin_nan("");
+        if (valid) {
+            double r;
+            const double v = vf_velocity<-1>(c, (double)(p - y * a.nx), (double)y, m.rc, r);
+            const double s = params[(size_t)b * NPAR + P_SIG];
+            rv = use ? (v - (double)a.vo[p]) * a.iev[p] : 0.0;
+            rs = use && sig_term ? (s - (double)a.so[p]) * a.ies[p] : 0.0;
+            if (use) acc += rv * rv + rs * rs;
+        }
+        if (resid) {
+            double *rb = resid + rm.resid_off[b];
+            rb[p] = valid ? rv : __builtin_nan("");
+            rb[npix + p] = valid ? rs : __builtin_nan("");
+        }
+    }
+    if (partial) {
+        for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+        __shared__ double ws[4];
+        if (lane == 0) ws[wave] = acc;
+        __syncthreads();
+        if (tid == 0) partial[rm.part_off[b] + tile] = ((ws[0] + ws[1]) + ws[2]) + ws[3];
     }
 }
 
@@ -160,6 +244,15 @@ int vfield_rows_per_block(int ntiles, int B)
     long r = ((long)ntiles * B) / target;
     r = r < 1 ? 1 : (r > kVfMaxRowsPerBlock ? kVfMaxRowsPerBlock : r);
     return (int)r;
+}
+
+hipError_t launch_vfield_multi(const ModelDev *md, const RowMap &rm, int nblocks,
+                               const double *params, const double *consts, double *resid,
+                               double *partial, hipStream_t s)
+{
+    if (nblocks <= 0) return hipSuccess;
+    launch(k_vfield_multi, dim3(nblocks), dim3(256), 0, s, md, rm, params, consts, resid, partial);
+    return hipGetLastError();
 }
 
 hipError_t launch_vfield(const VfArgs &a, hipStream_t s)

@@ -35,7 +35,9 @@ SYMBOLS = (
     "gk_surrogate_gradients", "gk_surrogate_predict",
     "gk_surrogate_chi2", "gk_fit_nested_screened", "gk_gemm_bf16", "gk_model_conv_path",
     "gk_set_launch_mode", "gk_graph_launches", "gk_autotune", "gk_set_conv_config",
+    "gk_mc_errors",
 )
+MC = {"shuffle": 0, "perturb": 1}
 LM_REASONS = {1: "ftol", 2: "xtol", 3: "lambda", 4: "maxiter"}
 GK_PROF_TIMING, GK_PROF_COUNT = 1, 2
 
@@ -222,6 +224,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.gk_survey_chi2.argtypes = [vp, vp, vp, i32, vp, vp]
     L.gk_fit_lm_survey.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(LMOpts),
                                    ctypes.POINTER(LMResult)]
+    L.gk_mc_errors.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(LMOpts), ctypes.c_int32,
+                               ctypes.c_int32, vp, vp, vp, vp, ctypes.POINTER(ctypes.c_int32)]
     L.gk_surrogate_default_opts.argtypes = [ctypes.POINTER(SurrogateOpts)]
     L.gk_surrogate_create.argtypes = [vp, vp, vp, ctypes.POINTER(SurrogateOpts), ctypes.POINTER(vp)]
     L.gk_surrogate_destroy.argtypes = [vp]
@@ -427,6 +431,32 @@ class Model:
         return {"p": p, "chi2": r.chi2, "n_valid": r.n_valid, "iterations": r.iterations,
                 "reason": LM_REASONS.get(r.reason, str(r.reason)), "n_evals": r.n_evals,
                 "errors": np.array(r.errors[:]), "status": st}
+
+    def mc_errors(self, best, free, lo=None, hi=None, mode="shuffle", perm=None, noise=None,
+                  **opts) -> dict:
+        """Monte-Carlo parameter errors (gk_mc_errors): every simulation's fit and the
+        standard deviation over them."""
+        L = load()
+        o = LMOpts()
+        _check(L.gk_lm_default_opts(ctypes.byref(o)))
+        for k, v in opts.items():
+            setattr(o, k, v)
+        b = np.ascontiguousarray(best, dtype=np.float64)
+        fm = np.ascontiguousarray(free, dtype=np.uint8)
+        lo_a = None if lo is None else np.ascontiguousarray(lo, dtype=np.float64)
+        hi_a = None if hi is None else np.ascontiguousarray(hi, dtype=np.float64)
+        md = MC[mode] if isinstance(mode, str) else int(mode)
+        pa = None if perm is None else np.ascontiguousarray(perm, dtype=np.int32)
+        na = None if noise is None else np.ascontiguousarray(noise, dtype=np.float32)
+        n_sim = len(pa) if pa is not None else (len(na) if na is not None else 0)
+        fits = np.zeros((max(n_sim, 1), NPAR))
+        sd = np.zeros(NPAR)
+        capped = ctypes.c_int32(0)
+        ptr = lambda a: None if a is None else a.ctypes.data
+        _check(L.gk_mc_errors(self._h, b.ctypes.data, fm.ctypes.data, ptr(lo_a), ptr(hi_a),
+                              ctypes.byref(o), md, n_sim, ptr(pa), ptr(na), fits.ctypes.data,
+                              sd.ctypes.data, ctypes.byref(capped)))
+        return {"fits": fits[:n_sim], "sd": sd, "n_capped": capped.value}
 
     def fit_nested(self, lo, hi, free, fixed, want_samples=0, **opts) -> dict:
         """Nested sampling of the model's posterior (gk_fit_nested)."""

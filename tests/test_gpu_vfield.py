@@ -248,7 +248,7 @@ def test_vfield_refused_where_it_has_no_meaning(gbk):
     g = I.Grid(32, 32, 1, 1.0, 0.0, 0.0, rc=I.RC_EPINAT, strategy=1)
     m = gbk.Model.from_grid(g)
     lo, hi = I.ghasp_box(32)
-    for call in (lambda: gbk.Survey([m]), lambda: gbk.Surrogate(m, lo, hi),
+    for call in (lambda: gbk.Surrogate(m, lo, hi),
                  lambda: m.autotune(8), lambda: m.conv_path(),
                  lambda: m.set_conv_config("direct", 32, 32)):
         with pytest.raises(gbk.GkError) as e:
@@ -259,3 +259,8 @@ def test_vfield_refused_where_it_has_no_meaning(gbk):
             gbk.Model(16, 16, 1, 1.0, strategy="vfield", **kw)
     with pytest.raises(gbk.GkError):
         gbk.Model(16, 16, 1, 1.0, strategy=7)
+    # a survey takes models of one strategy
+    cube = gbk.Model(16, 16, 24, 25.0, psf_fwhm=2.0, lsf_sigma=20.0)
+    with pytest.raises(gbk.GkError) as e:
+        gbk.Survey([m, cube])
+    assert e.value.status == gbk.GK_EINVAL
