@@ -28,6 +28,9 @@ struct FitWork {
     double *d_chi2 = nullptr, *h_chi2 = nullptr;      // [rows_cap]
     double *d_resid = nullptr;                        // [resid_cap][2][npix]
     double *d_norm = nullptr, *h_norm = nullptr;
+    // normal equations: chunk partials, and {goff[2], scale[NPAR]} staged per evaluation
+    double *d_part = nullptr;
+    char *d_aux = nullptr, *h_aux = nullptr;
 };
 
 void fit_release(FitWork *w)
@@ -41,8 +44,141 @@ void fit_release(FitWork *w)
     (void)hipFree(w->d_resid);
     (void)hipFree(w->d_norm);
     (void)hipHostFree(w->h_norm);
+    (void)hipFree(w->d_part);
+    (void)hipFree(w->d_aux);
+    (void)hipHostFree(w->h_aux);
     if (w->stream) (void)hipStreamDestroy(w->stream);
     delete w;
+}
+
+template <int NF>
+__global__ __launch_bounds__(256) void k_lm_normal_chunks(const double *__restrict__ R,
+                                                          const int64_t *__restrict__ goff,
+                                                          const double *__restrict__ scale,
+                                                          int nchunk, double *__restrict__ partial)
+{
+    constexpr int NP = NF * (NF + 1) / 2, NB = NP + NF + 1;
+    const int g = blockIdx.y, ch = blockIdx.x, tid = threadIdx.x;
+    const int64_t base = goff[g];
+    const int64_t n = (goff[g + 1] - base) / (1 + 2 * NF);
+    const double *R0 = R + base;
+    double s[NF], acc[NB];
+#pragma unroll
+    for (int a = 0; a < NF; ++a) s[a] = scale[(size_t)g * NPAR + a];
+#pragma unroll
+    for (int k = 0; k < NB; ++k) acc[k] = 0.0;
+    const int clen = lm_chunk_len(n);
+    const int64_t i0 = (int64_t)ch * clen;
+    for (int q = 0; q < clen / 256; ++q) {
+        const int64_t i = i0 + q * 256 + tid;
+        if (i >= n) break;
+        const double r0 = R0[i];
+        double j[NF];
+#pragma unroll
+        for (int a = 0; a < NF; ++a)
+            j[a] = (R0[(size_t)(1 + 2 * a) * n + i] - R0[(size_t)(2 + 2 * a) * n + i]) * s[a];
+        int k = 0;
+#pragma unroll
+        for (int a = 0; a < NF; ++a)
+#pragma unroll
+            for (int b = a; b < NF; ++b) acc[k++] += j[a] * j[b];
+#pragma unroll
+        for (int a = 0; a < NF; ++a) acc[NP + a] += j[a] * r0;
+        acc[NB - 1] += r0 * r0;
+    }
+    __shared__ double ws[4][NB];
+    const int wave = tid >> 6, lane = tid & 63;
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+        double v = acc[k];
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        if (lane == 0) ws[wave][k] = v;
+    }
+    __syncthreads();
+    if (tid < NB)
+        partial[((size_t)g * nchunk + ch) * NB + tid] = ((ws[0][tid] + ws[1][tid]) + ws[2][tid]) + ws[3][tid];
+}
+
+// One workgroup per (fit, output) for fits whose rows form one chunk.
+__global__ __launch_bounds__(256) void k_lm_normal_rows(const double *__restrict__ R,
+                                                        const int64_t *__restrict__ goff,
+                                                        const double *__restrict__ scale, int nf,
+                                                        double *__restrict__ out)
+{
+    const int k = blockIdx.x, g = blockIdx.y, tid = threadIdx.x;
+    const int np = nf * (nf + 1) / 2, nblk = np + nf + 1;
+    const int64_t base = goff[g];
+    const int64_t n = (goff[g + 1] - base) / (1 + 2 * nf);
+    const double *R0 = R + base;
+    const double *s = scale + (size_t)g * NPAR;
+    double acc = 0.0;
+    if (k < np) {
+        int a = 0, r = k;
+        while (r >= nf - a) {  // pair index k -> (a, b), a <= b, in row order
+            r -= nf - a;
+            ++a;
+        }
+        const int b = a + r;
+        const double *pa = R0 + (size_t)(1 + 2 * a) * n, *ma = R0 + (size_t)(2 + 2 * a) * n;
+        const double *pb = R0 + (size_t)(1 + 2 * b) * n, *mb = R0 + (size_t)(2 + 2 * b) * n;
+        for (int64_t i = tid; i < n; i += 256) acc += ((pa[i] - ma[i]) * s[a]) * ((pb[i] - mb[i]) * s[b]);
+    } else if (k < np + nf) {
+        const int a = k - np;
+        const double *pa = R0 + (size_t)(1 + 2 * a) * n, *ma = R0 + (size_t)(2 + 2 * a) * n;
+        for (int64_t i = tid; i < n; i += 256) acc += ((pa[i] - ma[i]) * s[a]) * R0[i];
+    } else {
+        for (int64_t i = tid; i < n; i += 256) acc += R0[i] * R0[i];
+    }
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    __shared__ double ws[4];
+    if ((tid & 63) == 0) ws[tid >> 6] = acc;
+    __syncthreads();
+    if (tid == 0) out[(size_t)g * nblk + k] = 0.0 + (((ws[0] + ws[1]) + ws[2]) + ws[3]);
+}
+
+__global__ __launch_bounds__(128) void k_lm_normal_finish(const double *__restrict__ partial,
+                                                          const int64_t *__restrict__ goff,
+                                                          int rows, int nchunk, int nblk,
+                                                          double *__restrict__ out)
+{
+    const int g = blockIdx.x, k = threadIdx.x;
+    if (k >= nblk) return;
+    const int nc = lm_normal_chunks((goff[g + 1] - goff[g]) / rows);  // this fit's chunks
+    const double *p = partial + (size_t)g * nchunk * nblk + k;
+    double s = 0.0;
+    for (int c = 0; c < nc; ++c) s += p[(size_t)c * nblk];
+    out[(size_t)g * nblk + k] = s;
+}
+
+template <int NF>
+void launch_lm_chunks(const double *R, const int64_t *goff, const double *scale, int ng,
+                      int nchunk, double *partial, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_lm_normal_chunks<NF>, dim3(nchunk, ng), dim3(256), 0, s, R, goff, scale,
+                       nchunk, partial);
+}
+
+hipError_t launch_lm_normal(const double *R, const int64_t *goff, const double *scale, int ng,
+                            int nf, int nchunk, double *partial, double *out, hipStream_t s)
+{
+    using Fn = void (*)(const double *, const int64_t *, const double *, int, int, double *,
+                        hipStream_t);
+    static const Fn table[NPAR] = {launch_lm_chunks<1>, launch_lm_chunks<2>, launch_lm_chunks<3>,
+                                   launch_lm_chunks<4>, launch_lm_chunks<5>, launch_lm_chunks<6>,
+                                   launch_lm_chunks<7>, launch_lm_chunks<8>, launch_lm_chunks<9>,
+                                   launch_lm_chunks<10>, launch_lm_chunks<11>, launch_lm_chunks<12>};
+    if (nf < 1 || nf > NPAR || ng < 1 || ng > 65535 || nchunk < 1)
+        return hipErrorInvalidValue;
+    const int nblk = nf * (nf + 1) / 2 + nf + 1;
+    if (nchunk == 1) {
+        hipLaunchKernelGGL(k_lm_normal_rows, dim3(nblk, ng), dim3(256), 0, s, R, goff, scale, nf,
+                           out);
+        return hipGetLastError();
+    }
+    table[nf - 1](R, goff, scale, ng, nchunk, partial, s);
+    hipLaunchKernelGGL(k_lm_normal_finish, dim3(ng), dim3(128), 0, s, partial, goff, 1 + 2 * nf,
+                       nchunk, nblk, out);
+    return hipGetLastError();
 }
 
 }  // namespace gbk
@@ -52,6 +188,7 @@ namespace {
 constexpr int kMaxFree = NPAR;
 constexpr int kMaxPairs = kMaxFree * (kMaxFree + 1) / 2;
 constexpr int kNormSlots = kMaxPairs + kMaxFree + 1;
+constexpr size_t kAuxBytes = 2 * sizeof(int64_t) + NPAR * sizeof(double);
 
 // Grows the fitter workspace to `rows` parameter rows (and `resid_rows`
 // residual rows when > 0).
@@ -63,6 +200,10 @@ gk_status fit_reserve(gk_model *m, int rows, int resid_rows)
         HIP_TRY(hipStreamCreate(&m->fit->stream));
         HIP_TRY(hipMalloc((void **)&m->fit->d_norm, sizeof(double) * kNormSlots));
         HIP_TRY(hipHostMalloc((void **)&m->fit->h_norm, sizeof(double) * kNormSlots, 0));
+        const int nchunk = lm_normal_chunks((int64_t)2 * m->d.nx * m->d.ny);
+        HIP_TRY(hipMalloc((void **)&m->fit->d_part, sizeof(double) * kNormSlots * nchunk));
+        HIP_TRY(hipMalloc((void **)&m->fit->d_aux, kAuxBytes));
+        HIP_TRY(hipHostMalloc((void **)&m->fit->h_aux, kAuxBytes, 0));
     }
     FitWork *w = m->fit;
     if (rows > w->rows_cap) {
@@ -91,39 +232,13 @@ gk_status fit_reserve(gk_model *m, int rows, int resid_rows)
     return GK_OK;
 }
 
-// Row indices and scales of the Jacobian columns for k_lm_normal.
+// Row indices and scales of the Jacobian columns of the normal equations.
 struct LMIdx {
     int nf, npairs;
     int ip[kMaxFree], im[kMaxFree];
     double s[kMaxFree];
     unsigned char pa[kMaxPairs], pb[kMaxPairs];
 };
-
-// Block k: k < npairs -> (J^T J)[pa][pb]; k < npairs + nf -> (J^T r)[k - npairs];
-// last block -> chi2 of row 0.  J_a = (R[ip_a] - R[im_a]) s_a; fixed-order sums.
-__global__ __launch_bounds__(256) void k_lm_normal(const double *__restrict__ R, int n, LMIdx ix,
-                                                   double *__restrict__ out)
-{
-    const int k = blockIdx.x, tid = threadIdx.x;
-    double acc = 0.0;
-    if (k < ix.npairs) {
-        const int a = ix.pa[k], b = ix.pb[k];
-        const double *pa = R + (size_t)ix.ip[a] * n, *ma = R + (size_t)ix.im[a] * n;
-        const double *pb = R + (size_t)ix.ip[b] * n, *mb = R + (size_t)ix.im[b] * n;
-        for (int i = tid; i < n; i += 256) acc += ((pa[i] - ma[i]) * ix.s[a]) * ((pb[i] - mb[i]) * ix.s[b]);
-    } else if (k < ix.npairs + ix.nf) {
-        const int a = k - ix.npairs;
-        const double *pa = R + (size_t)ix.ip[a] * n, *ma = R + (size_t)ix.im[a] * n;
-        for (int i = tid; i < n; i += 256) acc += ((pa[i] - ma[i]) * ix.s[a]) * R[i];
-    } else {
-        for (int i = tid; i < n; i += 256) acc += R[i] * R[i];
-    }
-    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
-    __shared__ double ws[4];
-    if ((tid & 63) == 0) ws[tid >> 6] = acc;
-    __syncthreads();
-    if (tid == 0) out[k] = ((ws[0] + ws[1]) + ws[2]) + ws[3];
-}
 
 // Solves M x = b for symmetric positive definite M (n <= 12) by Cholesky;
 // false if M is not positive definite.
@@ -248,9 +363,14 @@ extern "C" gk_status gk_fit_lm(gk_model *m, double *p_io, const uint8_t *free_ma
         HIP_TRY(hipMemcpyAsync(w->d_params, hp, sizeof(double) * NPAR * rows, hipMemcpyHostToDevice,
                                w->stream));
         GK_TRY(run_batch(m, w->d_params, rows, nullptr, w->d_resid, nullptr, nullptr, w->stream));
-        hipLaunchKernelGGL(k_lm_normal, dim3(nblk), dim3(256), 0, w->stream, w->d_resid, n, ix,
-                           w->d_norm);
-        HIP_TRY(hipGetLastError());
+        int64_t *goff = (int64_t *)w->h_aux;
+        goff[0] = 0;
+        goff[1] = (int64_t)rows * n;
+        std::memcpy(w->h_aux + 2 * sizeof(int64_t), ix.s, sizeof(double) * nf);
+        HIP_TRY(hipMemcpyAsync(w->d_aux, w->h_aux, kAuxBytes, hipMemcpyHostToDevice, w->stream));
+        HIP_TRY(launch_lm_normal(w->d_resid, (const int64_t *)w->d_aux,
+                                 (const double *)(w->d_aux + 2 * sizeof(int64_t)), 1, nf,
+                                 lm_normal_chunks(n), w->d_part, w->d_norm, w->stream));
         HIP_TRY(hipMemcpyAsync(w->h_norm, w->d_norm, sizeof(double) * nblk, hipMemcpyDeviceToHost,
                                w->stream));
         HIP_TRY(hipStreamSynchronize(w->stream));

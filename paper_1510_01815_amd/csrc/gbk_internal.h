@@ -151,6 +151,33 @@ hipError_t launch_reduce_chi2(const double *partial, int ntiles, const double *c
                               int64_t nvalid_obs, double *chi2, int64_t *nvalid, int B,
                               hipStream_t s);
 
+// Normal equations of Levenberg-Marquardt over ng fits at once (gbk_fit.hip).
+// Fit g's residual rows start at goff[g] (device), all of one length n_g =
+// (goff[g+1] - goff[g]) / (1 + 2 nf): row 0 is the point's residual vector,
+// rows 1 + 2a and 2 + 2a its plus and minus rows for free slot a, and
+// J_a = (R[1 + 2a] - R[2 + 2a]) scale[g * NPAR + a] (device).  out [ng][nblk],
+// nblk = nf (nf + 1) / 2 + nf + 1: (J^T J)[a][b] for a <= b in row order,
+// then J^T r, then r.r.  Rows of up to 16384 entries form one chunk, longer
+// ones chunks of 4096.  When every fit of a launch has one chunk, one
+// workgroup per (fit, output) sums its products over the whole rows; otherwise
+// a first pass reads every residual row once, one workgroup per (fit, chunk)
+// forming all outputs, into partials [ng][nchunk][nblk], and a second pass
+// adds each fit's chunk partials in chunk order.  In both, thread t sums
+// entries t, t + 256, ... of a chunk in order, then the lanes by butterfly and
+// the four waves in order, so a fit's sums depend on its row length only, not
+// on the variant or on which fits share the launch.
+__host__ __device__ inline int lm_chunk_len(int64_t n)
+{
+    return n <= 16384 ? (int)(((n + 255) / 256) * 256 < 256 ? 256 : ((n + 255) / 256) * 256) : 4096;
+}
+__host__ __device__ inline int lm_normal_chunks(int64_t n)
+{
+    const int c = lm_chunk_len(n);
+    return (int)((n + c - 1) / c);
+}
+hipError_t launch_lm_normal(const double *R, const int64_t *goff, const double *scale, int ng,
+                            int nf, int nchunk, double *partial, double *out, hipStream_t s);
+
 // Velocity-field strategy (gbk_vfield.hip): eq. 8 per data pixel and the
 // chi-square terms of eq. 11, no cube.  A block covers kVfTile consecutive
 // pixels (kVfPixPerThread per thread) for up to kVfMaxRowsPerBlock rows.

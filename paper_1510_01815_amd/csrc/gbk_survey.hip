@@ -58,7 +58,7 @@ struct gk_survey {
     HBuf<char> h_idx;
     HBuf<double> h_params;
     // LM workspace
-    DBuf<double> resid, norm, scale;
+    DBuf<double> resid, norm, scale, npart;
     DBuf<int64_t> goff;
     HBuf<double> h_norm, h_scale;
     HBuf<int64_t> h_goff;
@@ -69,6 +69,7 @@ struct gk_survey {
         if (fit_stream) (void)hipStreamSynchronize(fit_stream);
         md.free(); params.free(); consts.free(); T.free(); partial.free(); idx.free();
         h_idx.free(); h_params.free(); resid.free(); norm.free(); scale.free(); goff.free();
+        npart.free();
         h_norm.free(); h_scale.free(); h_goff.free();
         if (ev_staged) (void)hipEventDestroy(ev_staged);
         if (fit_stream) (void)hipStreamDestroy(fit_stream);
@@ -298,45 +299,11 @@ gk_status survey_batch(gk_survey *s, const int32_t *midx, const double *d_params
     return GK_OK;
 }
 
-// Normal equations of G galaxies: block (g, k) as in the single-model LM;
-// rows of galaxy g start at row_base[g] (rows 1 + 2a and 2 + 2a are the
-// Jacobian pair of free slot a), its residuals at goff[g] with n = 2 npix.
+// Index of the normal-equation pairs (a <= b) in output order.
 struct NormIdx {
     int nf, npairs, nblk;
     unsigned char pa[NPAR * (NPAR + 1) / 2], pb[NPAR * (NPAR + 1) / 2];
 };
-
-__global__ __launch_bounds__(256) void k_lm_normal_multi(const double *__restrict__ R,
-                                                         const int64_t *__restrict__ goff,
-                                                         const double *__restrict__ scale,
-                                                         NormIdx ix, double *__restrict__ out)
-{
-    const int g = blockIdx.y, k = blockIdx.x, tid = threadIdx.x;
-    const int rows = 1 + 2 * ix.nf;
-    // residual row r of galaxy g starts at goff[g] + r * n, n = (goff[g+1] - goff[g]) / rows
-    const int64_t base = goff[g];
-    const int n = (int)((goff[g + 1] - base) / rows);
-    const double *R0 = R + base;
-    const double *s = scale + (size_t)g * NPAR;
-    double acc = 0.0;
-    if (k < ix.npairs) {
-        const int a = ix.pa[k], b = ix.pb[k];
-        const double *pa = R0 + (size_t)(1 + 2 * a) * n, *ma = pa + n;
-        const double *pb = R0 + (size_t)(1 + 2 * b) * n, *mb = pb + n;
-        for (int i = tid; i < n; i += 256) acc += ((pa[i] - ma[i]) * s[a]) * ((pb[i] - mb[i]) * s[b]);
-    } else if (k < ix.npairs + ix.nf) {
-        const int a = k - ix.npairs;
-        const double *pa = R0 + (size_t)(1 + 2 * a) * n, *ma = pa + n;
-        for (int i = tid; i < n; i += 256) acc += ((pa[i] - ma[i]) * s[a]) * R0[i];
-    } else {
-        for (int i = tid; i < n; i += 256) acc += R0[i] * R0[i];
-    }
-    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
-    __shared__ double ws[4];
-    if ((tid & 63) == 0) ws[tid >> 6] = acc;
-    __syncthreads();
-    if (tid == 0) out[(size_t)g * ix.nblk + k] = ((ws[0] + ws[1]) + ws[2]) + ws[3];
-}
 
 bool chol_solve(std::vector<double> M, int n, const double *b, double *x)
 {
@@ -504,6 +471,7 @@ extern "C" gk_status gk_fit_lm_survey(gk_survey *s, double *p_io, const uint8_t 
         const int B = ng * rows;
         std::vector<int32_t> midx(B);
         std::vector<int64_t> roff(B), goff(ng + 1);
+        int max_chunks = 1;
         HIP_TRY(hipStreamSynchronize(st));  // the staging buffers are free again
         GK_TRY(s->h_params.need((size_t)B * NPAR));
         GK_TRY(s->params.need((size_t)B * NPAR));
@@ -517,6 +485,7 @@ extern "C" gk_status gk_fit_lm_survey(gk_survey *s, double *p_io, const uint8_t 
         for (int i = 0; i < ng; ++i) {
             const int g = gal[i];
             const size_t n2 = (size_t)2 * s->models[g]->d.nx * s->models[g]->d.ny;
+            max_chunks = std::max(max_chunks, lm_normal_chunks((int64_t)n2));
             goff[i] = r;
             const double *qg = &q[(size_t)g * NPAR];
             double *row = s->h_params.p + (size_t)i * rows * NPAR;
@@ -538,6 +507,8 @@ extern "C" gk_status gk_fit_lm_survey(gk_survey *s, double *p_io, const uint8_t 
         }
         goff[ng] = r;
         GK_TRY(s->resid.need((size_t)r));
+        const int nchunk = max_chunks;
+        GK_TRY(s->npart.need((size_t)ng * nchunk * ix.nblk));
         std::memcpy(s->h_goff.p, goff.data(), sizeof(int64_t) * (ng + 1));
         HIP_TRY(hipMemcpyAsync(s->params.p, s->h_params.p, sizeof(double) * NPAR * B,
                                hipMemcpyHostToDevice, st));
@@ -546,9 +517,8 @@ extern "C" gk_status gk_fit_lm_survey(gk_survey *s, double *p_io, const uint8_t 
         HIP_TRY(hipMemcpyAsync(s->goff.p, s->h_goff.p, sizeof(int64_t) * (ng + 1),
                                hipMemcpyHostToDevice, st));
         GK_TRY(survey_batch(s, midx.data(), s->params.p, B, nullptr, s->resid.p, roff.data(), st));
-        hipLaunchKernelGGL(k_lm_normal_multi, dim3(ix.nblk, ng), dim3(256), 0, st, s->resid.p,
-                           s->goff.p, s->scale.p, ix, s->norm.p);
-        HIP_TRY(hipGetLastError());
+        HIP_TRY(launch_lm_normal(s->resid.p, s->goff.p, s->scale.p, ng, nf, nchunk, s->npart.p,
+                                 s->norm.p, st));
         HIP_TRY(hipMemcpyAsync(s->h_norm.p, s->norm.p, sizeof(double) * ng * ix.nblk,
                                hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
