@@ -65,8 +65,8 @@ SCREEN_COST, SCREEN_ROWS = 0.3, 300
 # FP64 elementary functions' polynomial evaluations included)
 VF_BATCH = 1024
 MC_SIMS = 200  # simulated velocity fields per galaxy for the Monte-Carlo errors (Sec. 4.2)
-VF_FLOP_PER_PIXEL = 167.3
-VF_VALU_PER_PIXEL = 182.6
+VF_FLOP_PER_PIXEL = 170.3
+VF_VALU_PER_PIXEL = 187.1
 # wave64 VALU issue peak: 256 CUs x 4 SIMDs x 2.4 GHz, one wave instruction per 4 cycles
 VALU_ISSUE_PER_S = 256 * 4 * 2.4e9 / 4
 
