@@ -493,6 +493,35 @@ gk_status gk_mc_errors(gk_model *model, const double *best, const uint8_t *free_
                        int32_t n_sim, const int32_t *perm, const float *noise, double *fits,
                        double *sd, int32_t *n_capped);
 
+/* ---- Gaussian line fitting of a cube (Sec. 2.2.5, Sec. 5.2) ---------------
+ * The alternative to moment maps: every spectrum of a data cube is fitted by
+ * A exp(-(v - mu)^2 / (2 s^2)) at the channel velocities
+ * v_k = v0_kms + (k - crpix) dv_kms, minimising the sum of squared residuals.
+ * Start: the moments of the spectrum clipped at zero (area S0 dv, centre,
+ * width; A = area / (s sqrt(2 pi))); S0 <= 0 or zero width means no line.
+ * Box: A >= 0, mu inside the band, s in [dv / 4, nz dv].  Steps: damped
+ * Gauss-Newton with the analytic Jacobian, (M + lambda diag M) d = -g by
+ * Cholesky (d = 0 if M is not positive definite), trial clipped to the box,
+ * accepted if chi2 drops (lambda /= 10; stop when the relative chi2 decrease
+ * <= ftol or the largest relative step <= xtol), else lambda *= 10 (stop above
+ * 1e10); at most max_iter trials.  All FP64, one lane per spectrum.
+ * cube: device float [nz][nspec] (channel-major: a [nz][ny][nx] cube is
+ * nspec = nx ny).  maps: device float [3][nspec] = line flux A s sqrt(2 pi)
+ * (0 without a line), centre mu and width s (NaN without a line).  status
+ * (device int32 [nspec], may be NULL): 0 no line, 1 converged, 2 damping
+ * limit, 3 iteration cap; iterations (device int32 [nspec], may be NULL): the
+ * trials made.  Enqueued on hip_stream. */
+typedef struct {
+    int32_t max_iter;   /* default 100 */
+    int32_t reserved;   /* must be 0 */
+    double lambda0;     /* default 1e-3 */
+    double ftol, xtol;  /* defaults 1e-12 */
+} gk_line_opts;
+gk_status gk_line_default_opts(gk_line_opts *opts);
+gk_status gk_fit_lines(const float *cube, int32_t nz, int64_t nspec, double v0_kms, double dv_kms,
+                       double crpix, const gk_line_opts *opts, float *maps, int32_t *status,
+                       int32_t *iterations, void *hip_stream);
+
 /* BF16 GEMM of the surrogate: C [M][N] (f32, row stride ldc) = sum_k A(m, k)
  * B(n, k), A(m, k) = trans_a ? A[k lda + m] : A[m lda + k], B likewise; BF16
  * operands as uint16 bit patterns; all device memory; K a multiple of 32,

@@ -35,7 +35,7 @@ SYMBOLS = (
     "gk_surrogate_gradients", "gk_surrogate_predict",
     "gk_surrogate_chi2", "gk_fit_nested_screened", "gk_gemm_bf16", "gk_model_conv_path",
     "gk_set_launch_mode", "gk_graph_launches", "gk_autotune", "gk_set_conv_config",
-    "gk_mc_errors",
+    "gk_mc_errors", "gk_line_default_opts", "gk_fit_lines",
 )
 MC = {"shuffle": 0, "perturb": 1}
 LM_REASONS = {1: "ftol", 2: "xtol", 3: "lambda", 4: "maxiter"}
@@ -66,6 +66,11 @@ class LMOpts(ctypes.Structure):
     _fields_ = [("max_iter", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("fd_step", ctypes.c_double), ("lambda0", ctypes.c_double),
                 ("ftol", ctypes.c_double), ("xtol", ctypes.c_double)]
+
+
+class LineOpts(ctypes.Structure):
+    _fields_ = [("max_iter", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("lambda0", ctypes.c_double), ("ftol", ctypes.c_double), ("xtol", ctypes.c_double)]
 
 
 class LMResult(ctypes.Structure):
@@ -224,6 +229,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.gk_survey_chi2.argtypes = [vp, vp, vp, i32, vp, vp]
     L.gk_fit_lm_survey.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(LMOpts),
                                    ctypes.POINTER(LMResult)]
+    L.gk_line_default_opts.argtypes = [ctypes.POINTER(LineOpts)]
+    L.gk_fit_lines.argtypes = [vp, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_double,
+                               ctypes.c_double, ctypes.POINTER(LineOpts), vp, vp, vp, vp]
     L.gk_mc_errors.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(LMOpts), ctypes.c_int32,
                                ctypes.c_int32, vp, vp, vp, vp, ctypes.POINTER(ctypes.c_int32)]
     L.gk_surrogate_default_opts.argtypes = [ctypes.POINTER(SurrogateOpts)]
@@ -500,6 +508,26 @@ class Model:
         self.last_status = _check(load().gk_residual_batch(self._h, p, B, out.data_ptr(),
                                                            _stream_ptr(stream)))
         return out
+
+
+def fit_lines(cube, v0, dv, crpix, stream=None, **opts):
+    """Gaussian fit of every spectrum of a channel-major float32 CUDA tensor
+    cube [nz, ...] (gk_fit_lines): (maps [3, ...] float32, status, iterations)."""
+    import torch
+    L = load()
+    o = LineOpts()
+    _check(L.gk_line_default_opts(ctypes.byref(o)))
+    for k, v in opts.items():
+        setattr(o, k, v)
+    assert cube.dtype == torch.float32 and cube.is_cuda and cube.is_contiguous()
+    nz = cube.shape[0]
+    nspec = cube.numel() // nz
+    maps = torch.empty((3,) + tuple(cube.shape[1:]), dtype=torch.float32, device=cube.device)
+    st = torch.empty(tuple(cube.shape[1:]), dtype=torch.int32, device=cube.device)
+    it = torch.empty(tuple(cube.shape[1:]), dtype=torch.int32, device=cube.device)
+    _check(L.gk_fit_lines(cube.data_ptr(), nz, nspec, v0, dv, crpix, ctypes.byref(o),
+                          maps.data_ptr(), st.data_ptr(), it.data_ptr(), _stream_ptr(stream)))
+    return maps, st, it
 
 
 class Survey:
