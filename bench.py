@@ -15,8 +15,8 @@ trained on 2 M rows streamed from the plain evaluation, then nested-sampling
 fits (1000 live points, 10 free parameters) of synthetic galaxies, plain and
 surrogate-screened, with the posterior medians compared; and the
 velocity-field strategy (Sec. 2.2.1) on GHASP-shaped 256^2 and 512^2 maps:
-evals/s of 1024-row launches, its kernel's roofline, LM fits and the oracle's
-rate.
+evals/s of 1024-row launches, its kernel's roofline, LM fits, Monte-Carlo
+errors and the oracle's rate; and Gaussian line fitting of 262,144 spectra.
 """
 import argparse
 import json
@@ -116,6 +116,7 @@ def parse():
                     help="galaxies of the uneven-survey LM workload (0: skip)")
     ap.add_argument("--grid-galaxies", type=int, default=2,
                     help="galaxies of the nested-grid workload (0: skip)")
+    ap.add_argument("--no-line-fit", action="store_true", help="skip the line-fitting workload")
     ap.add_argument("--vfield-galaxies", type=int, default=4,
                     help="LM fits of the velocity-field workload (-1: skip the workload)")
     return ap.parse_args()
@@ -298,6 +299,48 @@ def velocity_field_workload(gbk, I, torch, n_fit, cpu):
         out["cpu_oracle_512x512"] = {"value": round(len(rows) / dt, 2), "unit": "evals/s",
                                      "cores": threads, "kind": "oracle",
                                      "sample": f"{len(rows)} rows, {dt:.2f} s wall"}
+    return out
+
+
+def line_fit_workload(gbk, I, torch, cpu):
+    """Gaussian line fitting of every spectrum (gk_fit_lines): a 128 x 128 x 48
+    cube of 16 km/s channels stacked 16 times (262,144 spectra), lines of random
+    amplitude, centre and width plus noise; spectra/s and the oracle's rate."""
+    nz, dv, crpix, n = 48, 16.0, 24.0, 16 * 128 * 128
+    rng = I.rng_for(7, 0, 0)
+    amp = torch.tensor(rng.uniform(0.5, 2.0, n), device="cuda")
+    mu = torch.tensor(rng.uniform(-200.0, 200.0, n), device="cuda")
+    sig = torch.tensor(rng.uniform(15.0, 60.0, n), device="cuda")
+    v = (torch.arange(nz, device="cuda", dtype=torch.float64) - crpix) * dv
+    noise = torch.tensor(rng.standard_normal((nz, n)), device="cuda")
+    cube = (amp * torch.exp(-0.5 * ((v[:, None] - mu) / sig) ** 2) + 0.05 * noise).float().contiguous()
+    gbk.fit_lines(cube, 0.0, dv, crpix)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 5
+    e0.record()
+    for _ in range(reps):
+        maps, st, it = gbk.fit_lines(cube, 0.0, dv, crpix)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    st, it = st.cpu().numpy(), it.cpu().numpy()
+    out = {"workload": "Gaussian line fit of every spectrum: 128x128x48 cube (16 km/s channels) "
+                       "x 16, random lines + noise (S/N ~ 10-40)",
+           "spectra": n, "ms_per_cube_stack": round(ms, 4), "spectra_per_s": round(n / (ms * 1e-3), 1),
+           "mean_trials": round(float(it.mean()), 2),
+           "status_fraction": {str(k): round(float((st == k).mean()), 4) for k in range(4)}}
+    log(f"line fitting: {n / (ms * 1e-3):.3g} spectra/s")
+    if cpu:
+        from oracle import fitters as F
+        c = cube[:, :200].double().cpu().numpy()
+        vv = v.cpu().numpy()
+        t0 = time.perf_counter()
+        for j in range(c.shape[1]):
+            F.fit_gaussian_line(c[:, j], vv, dv)
+        dt = time.perf_counter() - t0
+        out["cpu_oracle"] = {"value": round(200 / dt, 1), "unit": "spectra/s", "cores": 1,
+                             "kind": "oracle", "sample": f"200 spectra, {dt:.2f} s"}
     return out
 
 
@@ -530,6 +573,8 @@ def main():
         out["fits_per_hour"] = fits_per_hour(gbk, I, torch, args.fit_galaxies, args.train_rows)
     if args.survey_galaxies > 0 or args.grid_galaxies > 0:
         out["workloads"] = other_workloads(gbk, I, torch, args.survey_galaxies, args.grid_galaxies)
+    if not args.no_line_fit:
+        out["line_fitting"] = line_fit_workload(gbk, I, torch, not args.no_cpu_baseline)
     if args.vfield_galaxies >= 0:
         out["velocity_field"] = velocity_field_workload(gbk, I, torch, args.vfield_galaxies,
                                                         not args.no_cpu_baseline)
