@@ -117,6 +117,7 @@ def parse():
     ap.add_argument("--grid-galaxies", type=int, default=2,
                     help="galaxies of the nested-grid workload (0: skip)")
     ap.add_argument("--no-line-fit", action="store_true", help="skip the line-fitting workload")
+    ap.add_argument("--no-large-cubes", action="store_true", help="skip the survey/high-res shapes")
     ap.add_argument("--vfield-galaxies", type=int, default=4,
                     help="LM fits of the velocity-field workload (-1: skip the workload)")
     return ap.parse_args()
@@ -341,6 +342,47 @@ def line_fit_workload(gbk, I, torch, cpu):
         dt = time.perf_counter() - t0
         out["cpu_oracle"] = {"value": round(200 / dt, 1), "unit": "spectra/s", "cores": 1,
                              "kind": "oracle", "sample": f"200 spectra, {dt:.2f} s"}
+    return out
+
+
+def large_cube_workload(gbk, I, torch):
+    """evals/s on the survey shapes of Sec. 6.5 (SAMI, MaNGA's largest IFU, u = 2)
+    and the 700 x 700 high-resolution mock of Sec. 5.3 (u = 1, 15 km/s)."""
+    shapes = {
+        "sami_32x32x128_u2": (I.Grid(32, 32, 128, 33.5, psf_fwhm=4.2,
+                                     lsf_sigma=67.0 / I.FWHM_PER_SIGMA, u=2), 400),
+        "manga_64x64x64_u2": (I.Grid(64, 64, 64, 60.0, psf_fwhm=5.0,
+                                     lsf_sigma=120.0 / I.FWHM_PER_SIGMA, u=2), 400),
+        "hires_700x700x64": (I.Grid(700, 700, 64, 15.0, psf_fwhm=3.0,
+                                    lsf_sigma=15.0 / I.FWHM_PER_SIGMA), 200),
+    }
+    out = {}
+    for name, (grid, B) in shapes.items():
+        side = min(grid.nx, grid.ny)
+        rng = I.rng_for(8, 0, len(out))
+        rows = I.c1_box_draw(rng, B, side, grid.psf_fwhm)
+        rows[:, I.XO] = rng.uniform(0.45, 0.55, B) * grid.nx
+        rows[:, I.YO] = rng.uniform(0.45, 0.55, B) * grid.ny
+        rows[:, I.R0] = rng.uniform(0.1, 0.2, B) * side
+        rows[:, I.RT] = rng.uniform(0.05, 0.15, B) * side
+        m = gbk.Model.from_grid(grid)
+        dev = torch.tensor(rows, device="cuda")
+        mp = m.evaluate(dev[:1]).cpu().numpy()[0]
+        m.set_obs(I.make_observation(mp, 5.0, I.rng_for(8, 1, len(out)), W=0.2))
+        c2 = torch.empty(B, dtype=torch.float64, device="cuda")
+        nv = torch.empty(B, dtype=torch.int64, device="cuda")
+        s = torch.cuda.current_stream()
+        for _ in range(2):
+            m.chi2(dev, out=c2, n_valid=nv, stream=s)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            m.chi2(dev, out=c2, n_valid=nv, stream=s)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / 5
+        out[name] = {"batch": B, "ms_per_launch": round(1e3 * dt, 3), "evals_per_s": round(B / dt, 1),
+                     "conv": m.conv_path()}
+        log(f"{name}: {B / dt:.0f} evals/s")
     return out
 
 
@@ -573,6 +615,8 @@ def main():
         out["fits_per_hour"] = fits_per_hour(gbk, I, torch, args.fit_galaxies, args.train_rows)
     if args.survey_galaxies > 0 or args.grid_galaxies > 0:
         out["workloads"] = other_workloads(gbk, I, torch, args.survey_galaxies, args.grid_galaxies)
+    if not args.no_large_cubes:
+        out["large_cubes"] = large_cube_workload(gbk, I, torch)
     if not args.no_line_fit:
         out["line_fitting"] = line_fit_workload(gbk, I, torch, not args.no_cpu_baseline)
     if args.vfield_galaxies >= 0:

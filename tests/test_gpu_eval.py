@@ -217,3 +217,49 @@ def test_c5_instrument_largest_batch_sampled(O, gbk):
         assert_chi2_close(c[b], rc[k], rn[k], f"c5 row {b}")
         print("c5 row", b, max_map_errors(maps[b], ref[k]))
 
+
+
+# Survey shapes of Sec. 6.5 (u = 2 in all three dimensions) and the
+# high-resolution 700 x 700 mock of Sec. 5.3 (u = 1, 15 km/s channels): the
+# evaluation keeps per row only the three T planes of the fine spaxels, never
+# the fine cube, so these run without any memory-saving mode.
+LARGE = {
+    # SAMI: 0.5"/px over ~15", PSF FWHM 2.1" = 4.2 px, 67 km/s resolution
+    "sami_32x32x128_u2": I.Grid(32, 32, 128, 33.5, psf_fwhm=4.2, lsf_sigma=67.0 / I.FWHM_PER_SIGMA,
+                                u=2),
+    # MaNGA, largest IFU: 32" / 0.5" = 64 px, PSF 2.5" = 5 px, 120 km/s
+    "manga_64x64x64_u2": I.Grid(64, 64, 64, 60.0, psf_fwhm=5.0, lsf_sigma=120.0 / I.FWHM_PER_SIGMA,
+                                u=2),
+    "hires_700x700x64": I.Grid(700, 700, 64, 15.0, psf_fwhm=3.0, lsf_sigma=15.0 / I.FWHM_PER_SIGMA),
+}
+
+
+@pytest.mark.parametrize("name", sorted(LARGE))
+def test_large_cube_shapes_sampled(O, gbk, name):
+    """Batches of the survey and high-resolution shapes (the 700 x 700 one in
+    several scratch chunks); the first and last rows against the oracle."""
+    import torch
+    grid = LARGE[name]
+    side = min(grid.nx, grid.ny)
+    rng = I.rng_for(108, zlib.crc32(name.encode()) % 1000, 0)
+    B = 200 if grid.nx >= 700 else 64
+    rows = I.c1_box_draw(rng, B, side, grid.psf_fwhm)
+    rows[:, I.XO] = rng.uniform(0.45, 0.55, B) * grid.nx
+    rows[:, I.YO] = rng.uniform(0.45, 0.55, B) * grid.ny
+    rows[:, I.R0] = rng.uniform(0.1, 0.2, B) * side
+    rows[:, I.RT] = rng.uniform(0.05, 0.15, B) * side
+    obs = make_obs(O, grid, rows[0], 23, noise=5.0, W=0.2)
+    m = gbk.Model.from_grid(grid)
+    m.set_obs(obs)
+    dev = torch.tensor(rows, device="cuda")
+    c, n = m.chi2(dev)
+    c = c.cpu().numpy()
+    assert np.isfinite(c).all()
+    sample = [0, B - 1]
+    maps = m.evaluate(dev[sample]).cpu().numpy()
+    ref = oracle_maps(O, grid, rows[sample])
+    rc, rn = oracle_chi2(O, grid, rows[sample], obs)
+    for k, b in enumerate(sample):
+        assert_maps_close(maps[k], ref[k], f"{name} row {b}")
+        assert_chi2_close(c[b], rc[k], rn[k], f"{name} row {b}")
+        print(name, "row", b, max_map_errors(maps[k], ref[k]))
