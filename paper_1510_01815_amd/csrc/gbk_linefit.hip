@@ -3,9 +3,9 @@
 // the paper ran with mpfit on the CPU and left to a GPU Levenberg-Marquardt as
 // future work (Sec. 5.2, Sec. 6).
 //
-// k_line_fit: one lane per spectrum, the whole fit in registers.  The cube is
-// channel-major ([nz][nspec]), so at every channel the lanes of a wave read
-// consecutive spectra (coalesced).  Per spectrum: start from the moments of
+// k_line_fit: one lane per spectrum, the whole fit in registers (the spectrum
+// in LDS, up to 64 channels).  The cube is channel-major ([nz][nspec]), so at
+// every channel the lanes of a wave read consecutive spectra (coalesced).  Per spectrum: start from the moments of
 // the spectrum clipped at zero, then damped Gauss-Newton on
 // A exp(-(v - mu)^2 / (2 s^2)) with the analytic Jacobian; each trial is one
 // pass over the channels forming chi2, J^T J (6) and J^T r (3) at the trial
@@ -35,15 +35,33 @@ struct Sys {
     double chi2, m[6], g[3];  // m: (00, 01, 02, 11, 12, 22)
 };
 
-__device__ inline void line_system(const LineArgs &a, const float *spec, double A, double mu,
-                                   double s, Sys &y)
+// Spectra of at most kLdsChannels channels are copied once into LDS (the
+// workgroup's 256 spectra as [channel][lane], conflict-free); longer ones are
+// read from the cube at every pass.  Both visit the channels in the same order
+// with the same arithmetic, so they give identical fits.
+constexpr int kLdsChannels = 64;
+
+// Calls f(k, D_k) for the lane's channels in order.
+template <bool LDS, class F>
+__device__ __forceinline__ void for_channels(const LineArgs &a, const float *spec, const float *lds,
+                                             F f)
+{
+    if constexpr (LDS) {
+        for (int k = 0; k < a.nz; ++k) f(k, (double)lds[k * 256]);
+    } else {
+        for (int k = 0; k < a.nz; ++k) f(k, (double)spec[(size_t)k * a.nspec]);
+    }
+}
+
+template <bool LDS>
+__device__ inline void line_system(const LineArgs &a, const float *spec, const float *lds, double A,
+                                   double mu, double s, Sys &y)
 {
     double c = 0.0, m0 = 0.0, m1 = 0.0, m2 = 0.0, m3 = 0.0, m4 = 0.0, m5 = 0.0;
     double g0 = 0.0, g1 = 0.0, g2 = 0.0;
     const double is = 1.0 / s;
-    for (int k = 0; k < a.nz; ++k) {
+    for_channels<LDS>(a, spec, lds, [&](int k, double d) {
         const double v = a.v0 + (k - a.crpix) * a.dv;
-        const double d = (double)spec[(size_t)k * a.nspec];
         const double t = (v - mu) * is;
         const double e = exp(-0.5 * t * t);
         const double r = A * e - d;
@@ -58,7 +76,7 @@ __device__ inline void line_system(const LineArgs &a, const float *spec, double 
         g0 += j0 * r;
         g1 += j1 * r;
         g2 += j2 * r;
-    }
+    });
     y.chi2 = c;
     y.m[0] = m0; y.m[1] = m1; y.m[2] = m2; y.m[3] = m3; y.m[4] = m4; y.m[5] = m5;
     y.g[0] = g0; y.g[1] = g1; y.g[2] = g2;
@@ -87,30 +105,36 @@ __device__ inline bool solve3(const double *m, const double *g, double lam, doub
     return true;
 }
 
+template <bool LDS>
 __global__ __launch_bounds__(256) void k_line_fit(LineArgs a)
 {
+    extern __shared__ float lds_all[];
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= a.nspec) return;
+    if (p >= a.nspec) return;  // no barrier below: each lane reads only its own column
     const float *spec = a.cube + p;
     const int64_t ns = a.nspec;
+    float *lds = lds_all + threadIdx.x;
+    if constexpr (LDS) {
+        for (int k = 0; k < a.nz; ++k) lds[k * 256] = spec[(size_t)k * a.nspec];
+    }
     // start: moments of the spectrum clipped at zero
     double s0 = 0.0, s1 = 0.0;
-    for (int k = 0; k < a.nz; ++k) {
+    for_channels<LDS>(a, spec, lds, [&](int k, double d) {
         const double v = a.v0 + (k - a.crpix) * a.dv;
-        const double d = fmax((double)spec[(size_t)k * a.nspec], 0.0);
+        d = fmax(d, 0.0);
         s0 += d;
         s1 += d * v;
-    }
+    });
     int status = 0, it = 0;
     double A = 0.0, mu = __builtin_nan(""), s = __builtin_nan("");
     if (s0 > 0.0) {
         const double m = s1 / s0;
         double s2 = 0.0;
-        for (int k = 0; k < a.nz; ++k) {
+        for_channels<LDS>(a, spec, lds, [&](int k, double d) {
             const double v = a.v0 + (k - a.crpix) * a.dv;
-            const double d = fmax((double)spec[(size_t)k * a.nspec], 0.0);
+            d = fmax(d, 0.0);
             s2 += d * (v - m) * (v - m);
-        }
+        });
         const double var = s2 / s0;
         if (var > 0.0) {
             const double vfirst = a.v0 - a.crpix * a.dv, vlast = a.v0 + (a.nz - 1 - a.crpix) * a.dv;
@@ -120,7 +144,7 @@ __global__ __launch_bounds__(256) void k_line_fit(LineArgs a)
             double q[3] = {s0 * a.dv / (w * 2.5066282746310002), m, w};  // sqrt(2 pi)
             for (int i = 0; i < 3; ++i) q[i] = fmin(fmax(q[i], lo[i]), hi[i]);
             Sys cur, tri;
-            line_system(a, spec, q[0], q[1], q[2], cur);
+            line_system<LDS>(a, spec, lds, q[0], q[1], q[2], cur);
             double lam = a.lam0;
             status = 3;
             while (it < a.max_iter) {
@@ -129,7 +153,7 @@ __global__ __launch_bounds__(256) void k_line_fit(LineArgs a)
                 if (!solve3(cur.m, cur.g, lam, dlt)) dlt[0] = dlt[1] = dlt[2] = 0.0;
                 double qt[3];
                 for (int i = 0; i < 3; ++i) qt[i] = fmin(fmax(q[i] + dlt[i], lo[i]), hi[i]);
-                line_system(a, spec, qt[0], qt[1], qt[2], tri);
+                line_system<LDS>(a, spec, lds, qt[0], qt[1], qt[2], tri);
                 if (tri.chi2 < cur.chi2) {
                     double step = 0.0;
                     for (int i = 0; i < 3; ++i) step = fmax(step, fabs(qt[i] - q[i]) / (fabs(q[i]) + 1e-10));
@@ -208,7 +232,11 @@ extern "C" gk_status gk_fit_lines(const float *cube, int32_t nz, int64_t nspec, 
     a.iters = iterations;
     const int64_t blocks = (nspec + 255) / 256;
     if (blocks > 0x7fffffff) return fail(GK_EINVAL, "too many spectra");
-    launch(k_line_fit, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, a);
+    if (nz <= kLdsChannels)
+        launch(k_line_fit<true>, dim3((unsigned)blocks), dim3(256), sizeof(float) * 256 * nz,
+               (hipStream_t)stream, a);
+    else
+        launch(k_line_fit<false>, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, a);
     HIP_TRY(hipGetLastError());
     return GK_OK;
 }

@@ -4,8 +4,9 @@ per-spectrum LM, through the C ABI.
 
 Cubes: the oracle's convolved, down-sampled model cube plus seeded noise (a
 ragged number of spectra), noise-free Gaussian lines, a 128 x 128 x 48 cube
-stacked 16 times (sampled spectra), and the degenerate cases (empty spectra,
-a single channel, a single spectrum).
+stacked 16 times (sampled spectra), spectra longer than the 64 channels
+staged in LDS, and the degenerate cases (empty spectra, a single channel, a
+single spectrum).
 """
 import math
 
@@ -153,3 +154,20 @@ def test_line_fit_refuses_bad_arguments(gbk):
         assert e.value.status == gbk.GK_EINVAL
     with pytest.raises(gbk.GkError):
         gbk.fit_lines(cube, 0.0, 10.0, 5.0, max_iter=0)
+
+
+def test_long_spectra_read_from_the_cube(gbk):
+    """More than 64 channels: the spectra are read from the cube at every pass
+    instead of being staged in LDS; noisy lines against the oracle."""
+    import torch
+    nz, dv, crpix = 96, 10.0, 47.5
+    v = velocities(nz, 0.0, dv, crpix)
+    rng = I.rng_for(97, 3, 0)
+    n = 300
+    amp = rng.uniform(0.5, 3.0, n)
+    mu = rng.uniform(-250.0, 250.0, n)
+    sig = rng.uniform(15.0, 80.0, n)
+    cube = (amp * np.exp(-0.5 * ((v[:, None] - mu) / sig) ** 2)
+            + 0.05 * rng.standard_normal((nz, n))).astype(np.float32)
+    maps, st, it = gbk.fit_lines(torch.tensor(cube, device="cuda"), 0.0, dv, crpix)
+    check_against_oracle(maps.cpu().numpy(), st.cpu().numpy(), cube, v, dv, range(n))
