@@ -1,15 +1,17 @@
 """Reference optimisers of the oracle (Sec. 2.3), plain FP64 numpy.
 
 TEST INFRASTRUCTURE ONLY (see oracle.py): used by tests/ to check the GPU
-library's fitters.  Each follows the step-by-step specification shared with
-the library (written out in the design doc); the paper names the algorithms but
-uses third-party implementations (mpfit, MultiNest), so the details below are
-this project's reading.
+library's fitters.  Each follows a step-by-step rule that the library's
+fitters follow too, stated in each function's docstring; the paper names the
+algorithms but uses third-party implementations (mpfit, MultiNest), so the
+details below are this project's reading.
 
 levenberg_marquardt: Sec. 2.3.1 -- gradient/curvature local optimiser with box
 constraints and a finite-difference Jacobian of absolute step ~0.1 (Sec. 4).
 mc_errors: Monte-Carlo parameter errors by refits of simulated observations,
 shuffled residuals (Sec. 4.2) or perturbations by the error maps (Sec. 4.3).
+fit_gaussian_line(s): Gaussian fit of each spectrum of a cube, the alternative
+to moments (Sec. 2.2.5, Sec. 5.2).
 """
 from __future__ import annotations
 
