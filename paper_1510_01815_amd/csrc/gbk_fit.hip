@@ -54,13 +54,15 @@ void fit_release(FitWork *w)
 template <int NF>
 __global__ __launch_bounds__(256) void k_lm_normal_chunks(const double *__restrict__ R,
                                                           const int64_t *__restrict__ goff,
+                                                          const int64_t *__restrict__ nused,
                                                           const double *__restrict__ scale,
                                                           int nchunk, double *__restrict__ partial)
 {
     constexpr int NP = NF * (NF + 1) / 2, NB = NP + NF + 1;
     const int g = blockIdx.y, ch = blockIdx.x, tid = threadIdx.x;
     const int64_t base = goff[g];
-    const int64_t n = (goff[g + 1] - base) / (1 + 2 * NF);
+    const int64_t stride = (goff[g + 1] - base) / (1 + 2 * NF);
+    const int64_t n = nused ? nused[g] : stride;
     const double *R0 = R + base;
     double s[NF], acc[NB];
 #pragma unroll
@@ -76,7 +78,7 @@ __global__ __launch_bounds__(256) void k_lm_normal_chunks(const double *__restri
         double j[NF];
 #pragma unroll
         for (int a = 0; a < NF; ++a)
-            j[a] = (R0[(size_t)(1 + 2 * a) * n + i] - R0[(size_t)(2 + 2 * a) * n + i]) * s[a];
+            j[a] = (R0[(size_t)(1 + 2 * a) * stride + i] - R0[(size_t)(2 + 2 * a) * stride + i]) * s[a];
         int k = 0;
 #pragma unroll
         for (int a = 0; a < NF; ++a)
@@ -102,13 +104,15 @@ __global__ __launch_bounds__(256) void k_lm_normal_chunks(const double *__restri
 // One workgroup per (fit, output) for fits whose rows form one chunk.
 __global__ __launch_bounds__(256) void k_lm_normal_rows(const double *__restrict__ R,
                                                         const int64_t *__restrict__ goff,
+                                                        const int64_t *__restrict__ nused,
                                                         const double *__restrict__ scale, int nf,
                                                         double *__restrict__ out)
 {
     const int k = blockIdx.x, g = blockIdx.y, tid = threadIdx.x;
     const int np = nf * (nf + 1) / 2, nblk = np + nf + 1;
     const int64_t base = goff[g];
-    const int64_t n = (goff[g + 1] - base) / (1 + 2 * nf);
+    const int64_t stride = (goff[g + 1] - base) / (1 + 2 * nf);
+    const int64_t n = nused ? nused[g] : stride;
     const double *R0 = R + base;
     const double *s = scale + (size_t)g * NPAR;
     double acc = 0.0;
@@ -119,12 +123,12 @@ __global__ __launch_bounds__(256) void k_lm_normal_rows(const double *__restrict
             ++a;
         }
         const int b = a + r;
-        const double *pa = R0 + (size_t)(1 + 2 * a) * n, *ma = R0 + (size_t)(2 + 2 * a) * n;
-        const double *pb = R0 + (size_t)(1 + 2 * b) * n, *mb = R0 + (size_t)(2 + 2 * b) * n;
+        const double *pa = R0 + (size_t)(1 + 2 * a) * stride, *ma = R0 + (size_t)(2 + 2 * a) * stride;
+        const double *pb = R0 + (size_t)(1 + 2 * b) * stride, *mb = R0 + (size_t)(2 + 2 * b) * stride;
         for (int64_t i = tid; i < n; i += 256) acc += ((pa[i] - ma[i]) * s[a]) * ((pb[i] - mb[i]) * s[b]);
     } else if (k < np + nf) {
         const int a = k - np;
-        const double *pa = R0 + (size_t)(1 + 2 * a) * n, *ma = R0 + (size_t)(2 + 2 * a) * n;
+        const double *pa = R0 + (size_t)(1 + 2 * a) * stride, *ma = R0 + (size_t)(2 + 2 * a) * stride;
         for (int64_t i = tid; i < n; i += 256) acc += ((pa[i] - ma[i]) * s[a]) * R0[i];
     } else {
         for (int64_t i = tid; i < n; i += 256) acc += R0[i] * R0[i];
@@ -138,12 +142,13 @@ __global__ __launch_bounds__(256) void k_lm_normal_rows(const double *__restrict
 
 __global__ __launch_bounds__(128) void k_lm_normal_finish(const double *__restrict__ partial,
                                                           const int64_t *__restrict__ goff,
+                                                          const int64_t *__restrict__ nused,
                                                           int rows, int nchunk, int nblk,
                                                           double *__restrict__ out)
 {
     const int g = blockIdx.x, k = threadIdx.x;
     if (k >= nblk) return;
-    const int nc = lm_normal_chunks((goff[g + 1] - goff[g]) / rows);  // this fit's chunks
+    const int nc = lm_normal_chunks(nused ? nused[g] : (goff[g + 1] - goff[g]) / rows);
     const double *p = partial + (size_t)g * nchunk * nblk + k;
     double s = 0.0;
     for (int c = 0; c < nc; ++c) s += p[(size_t)c * nblk];
@@ -151,18 +156,19 @@ __global__ __launch_bounds__(128) void k_lm_normal_finish(const double *__restri
 }
 
 template <int NF>
-void launch_lm_chunks(const double *R, const int64_t *goff, const double *scale, int ng,
-                      int nchunk, double *partial, hipStream_t s)
+void launch_lm_chunks(const double *R, const int64_t *goff, const int64_t *nused,
+                      const double *scale, int ng, int nchunk, double *partial, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_lm_normal_chunks<NF>, dim3(nchunk, ng), dim3(256), 0, s, R, goff, scale,
-                       nchunk, partial);
+    hipLaunchKernelGGL(k_lm_normal_chunks<NF>, dim3(nchunk, ng), dim3(256), 0, s, R, goff, nused,
+                       scale, nchunk, partial);
 }
 
-hipError_t launch_lm_normal(const double *R, const int64_t *goff, const double *scale, int ng,
-                            int nf, int nchunk, double *partial, double *out, hipStream_t s)
+hipError_t launch_lm_normal(const double *R, const int64_t *goff, const int64_t *nused,
+                            const double *scale, int ng, int nf, int nchunk, double *partial,
+                            double *out, hipStream_t s)
 {
-    using Fn = void (*)(const double *, const int64_t *, const double *, int, int, double *,
-                        hipStream_t);
+    using Fn = void (*)(const double *, const int64_t *, const int64_t *, const double *, int, int,
+                        double *, hipStream_t);
     static const Fn table[NPAR] = {launch_lm_chunks<1>, launch_lm_chunks<2>, launch_lm_chunks<3>,
                                    launch_lm_chunks<4>, launch_lm_chunks<5>, launch_lm_chunks<6>,
                                    launch_lm_chunks<7>, launch_lm_chunks<8>, launch_lm_chunks<9>,
@@ -171,13 +177,13 @@ hipError_t launch_lm_normal(const double *R, const int64_t *goff, const double *
         return hipErrorInvalidValue;
     const int nblk = nf * (nf + 1) / 2 + nf + 1;
     if (nchunk == 1) {
-        hipLaunchKernelGGL(k_lm_normal_rows, dim3(nblk, ng), dim3(256), 0, s, R, goff, scale, nf,
-                           out);
+        hipLaunchKernelGGL(k_lm_normal_rows, dim3(nblk, ng), dim3(256), 0, s, R, goff, nused, scale,
+                           nf, out);
         return hipGetLastError();
     }
-    table[nf - 1](R, goff, scale, ng, nchunk, partial, s);
-    hipLaunchKernelGGL(k_lm_normal_finish, dim3(ng), dim3(128), 0, s, partial, goff, 1 + 2 * nf,
-                       nchunk, nblk, out);
+    table[nf - 1](R, goff, nused, scale, ng, nchunk, partial, s);
+    hipLaunchKernelGGL(k_lm_normal_finish, dim3(ng), dim3(128), 0, s, partial, goff, nused,
+                       1 + 2 * nf, nchunk, nblk, out);
     return hipGetLastError();
 }
 
@@ -188,7 +194,7 @@ namespace {
 constexpr int kMaxFree = NPAR;
 constexpr int kMaxPairs = kMaxFree * (kMaxFree + 1) / 2;
 constexpr int kNormSlots = kMaxPairs + kMaxFree + 1;
-constexpr size_t kAuxBytes = 2 * sizeof(int64_t) + NPAR * sizeof(double);
+constexpr size_t kAuxBytes = 4 * sizeof(int64_t) + NPAR * sizeof(double);  // goff[2], nused, pad, scale
 
 // Grows the fitter workspace to `rows` parameter rows (and `resid_rows`
 // residual rows when > 0).
@@ -363,14 +369,19 @@ extern "C" gk_status gk_fit_lm(gk_model *m, double *p_io, const uint8_t *free_ma
         HIP_TRY(hipMemcpyAsync(w->d_params, hp, sizeof(double) * NPAR * rows, hipMemcpyHostToDevice,
                                w->stream));
         GK_TRY(run_batch(m, w->d_params, rows, nullptr, w->d_resid, nullptr, nullptr, w->stream));
+        // without a weighted dispersion term the second map of each row is 0
+        const int64_t used = m->obs_sig ? n : n / 2;
         int64_t *goff = (int64_t *)w->h_aux;
         goff[0] = 0;
         goff[1] = (int64_t)rows * n;
-        std::memcpy(w->h_aux + 2 * sizeof(int64_t), ix.s, sizeof(double) * nf);
+        goff[2] = used;
+        goff[3] = 0;
+        std::memcpy(w->h_aux + 4 * sizeof(int64_t), ix.s, sizeof(double) * nf);
         HIP_TRY(hipMemcpyAsync(w->d_aux, w->h_aux, kAuxBytes, hipMemcpyHostToDevice, w->stream));
         HIP_TRY(launch_lm_normal(w->d_resid, (const int64_t *)w->d_aux,
-                                 (const double *)(w->d_aux + 2 * sizeof(int64_t)), 1, nf,
-                                 lm_normal_chunks(n), w->d_part, w->d_norm, w->stream));
+                                 (const int64_t *)w->d_aux + 2,
+                                 (const double *)(w->d_aux + 4 * sizeof(int64_t)), 1, nf,
+                                 lm_normal_chunks(used), w->d_part, w->d_norm, w->stream));
         HIP_TRY(hipMemcpyAsync(w->h_norm, w->d_norm, sizeof(double) * nblk, hipMemcpyDeviceToHost,
                                w->stream));
         HIP_TRY(hipStreamSynchronize(w->stream));

@@ -152,8 +152,10 @@ hipError_t launch_reduce_chi2(const double *partial, int ntiles, const double *c
                               hipStream_t s);
 
 // Normal equations of Levenberg-Marquardt over ng fits at once (gbk_fit.hip).
-// Fit g's residual rows start at goff[g] (device), all of one length n_g =
-// (goff[g+1] - goff[g]) / (1 + 2 nf): row 0 is the point's residual vector,
+// Fit g's residual rows start at goff[g] (device), all of one stride
+// (goff[g+1] - goff[g]) / (1 + 2 nf), of which the first n_g = nused[g] entries
+// enter the sums (nused NULL: the whole stride; the fitters leave out the
+// dispersion half when the observation does not weigh it): row 0 is the point's residual vector,
 // rows 1 + 2a and 2 + 2a its plus and minus rows for free slot a, and
 // J_a = (R[1 + 2a] - R[2 + 2a]) scale[g * NPAR + a] (device).  out [ng][nblk],
 // nblk = nf (nf + 1) / 2 + nf + 1: (J^T J)[a][b] for a <= b in row order,
@@ -175,8 +177,9 @@ __host__ __device__ inline int lm_normal_chunks(int64_t n)
     const int c = lm_chunk_len(n);
     return (int)((n + c - 1) / c);
 }
-hipError_t launch_lm_normal(const double *R, const int64_t *goff, const double *scale, int ng,
-                            int nf, int nchunk, double *partial, double *out, hipStream_t s);
+hipError_t launch_lm_normal(const double *R, const int64_t *goff, const int64_t *nused,
+                            const double *scale, int ng, int nf, int nchunk, double *partial,
+                            double *out, hipStream_t s);
 
 // Velocity-field strategy (gbk_vfield.hip): eq. 8 per data pixel and the
 // chi-square terms of eq. 11, no cube.  A block covers kVfTile consecutive
@@ -204,7 +207,8 @@ int vfield_rows_per_block(int ntiles, int B);
 hipError_t launch_vfield(const VfArgs &a, hipStream_t s);
 // Ragged rows of velocity-field models (one row per workgroup): rm.ls_base
 // holds the prefix sums of the rows' tiles; chi2 partials at rm.part_off,
-// residuals at rm.resid_off (if resid != NULL).
+// residuals at rm.resid_off (if resid != NULL; the dispersion map only for
+// models whose observation weighs it, the fitters' use).
 hipError_t launch_vfield_multi(const ModelDev *md, const RowMap &rm, int nblocks,
                                const double *params, const double *consts, double *resid,
                                double *partial, hipStream_t s);

@@ -477,15 +477,20 @@ extern "C" gk_status gk_fit_lm_survey(gk_survey *s, double *p_io, const uint8_t 
         GK_TRY(s->params.need((size_t)B * NPAR));
         GK_TRY(s->h_scale.need((size_t)ng * NPAR));
         GK_TRY(s->scale.need((size_t)ng * NPAR));
-        GK_TRY(s->h_goff.need((size_t)ng + 1));
-        GK_TRY(s->goff.need((size_t)ng + 1));
+        // [goff (ng + 1) | used entries per row (ng)]
+        GK_TRY(s->h_goff.need((size_t)2 * ng + 1));
+        GK_TRY(s->goff.need((size_t)2 * ng + 1));
+        std::vector<int64_t> nused(ng);
         GK_TRY(s->norm.need((size_t)ng * ix.nblk));
         GK_TRY(s->h_norm.need((size_t)ng * ix.nblk));
         int64_t r = 0;
         for (int i = 0; i < ng; ++i) {
             const int g = gal[i];
             const size_t n2 = (size_t)2 * s->models[g]->d.nx * s->models[g]->d.ny;
-            max_chunks = std::max(max_chunks, lm_normal_chunks((int64_t)n2));
+            // without a weighted dispersion term the second map of each row is 0
+            // (and velocity-field rows leave it unwritten)
+            nused[i] = s->models[g]->obs_sig ? (int64_t)n2 : (int64_t)n2 / 2;
+            max_chunks = std::max(max_chunks, lm_normal_chunks(nused[i]));
             goff[i] = r;
             const double *qg = &q[(size_t)g * NPAR];
             double *row = s->h_params.p + (size_t)i * rows * NPAR;
@@ -510,14 +515,16 @@ extern "C" gk_status gk_fit_lm_survey(gk_survey *s, double *p_io, const uint8_t 
         const int nchunk = max_chunks;
         GK_TRY(s->npart.need((size_t)ng * nchunk * ix.nblk));
         std::memcpy(s->h_goff.p, goff.data(), sizeof(int64_t) * (ng + 1));
+        std::memcpy(s->h_goff.p + ng + 1, nused.data(), sizeof(int64_t) * ng);
         HIP_TRY(hipMemcpyAsync(s->params.p, s->h_params.p, sizeof(double) * NPAR * B,
                                hipMemcpyHostToDevice, st));
         HIP_TRY(hipMemcpyAsync(s->scale.p, s->h_scale.p, sizeof(double) * NPAR * ng,
                                hipMemcpyHostToDevice, st));
-        HIP_TRY(hipMemcpyAsync(s->goff.p, s->h_goff.p, sizeof(int64_t) * (ng + 1),
+        HIP_TRY(hipMemcpyAsync(s->goff.p, s->h_goff.p, sizeof(int64_t) * (2 * ng + 1),
                                hipMemcpyHostToDevice, st));
         GK_TRY(survey_batch(s, midx.data(), s->params.p, B, nullptr, s->resid.p, roff.data(), st));
-        HIP_TRY(launch_lm_normal(s->resid.p, s->goff.p, s->scale.p, ng, nf, nchunk, s->npart.p,
+        HIP_TRY(launch_lm_normal(s->resid.p, s->goff.p, s->goff.p + ng + 1, s->scale.p, ng, nf,
+                                 nchunk, s->npart.p,
                                  s->norm.p, st));
         HIP_TRY(hipMemcpyAsync(s->h_norm.p, s->norm.p, sizeof(double) * ng * ix.nblk,
                                hipMemcpyDeviceToHost, st));

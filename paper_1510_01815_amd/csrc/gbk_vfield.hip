@@ -197,10 +197,10 @@ __global__ __launch_bounds__(256) void k_vfield_multi(const ModelDev *__restrict
             rs = use && sig_term ? (s - (double)a.so[p]) * a.ies[p] : 0.0;
             if (use) acc += rv * rv + rs * rs;
         }
-        if (resid) {
+        if (resid) {  // the fitters do not read the dispersion map unless it is weighted
             double *rb = resid + rm.resid_off[b];
             rb[p] = valid ? rv : __builtin_nan("");
-            rb[npix + p] = valid ? rs : __builtin_nan("");
+            if (sig_term) rb[npix + p] = valid ? rs : __builtin_nan("");
         }
     }
     if (partial) {
