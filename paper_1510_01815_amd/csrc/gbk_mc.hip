@@ -166,25 +166,27 @@ extern "C" gk_status gk_mc_errors(gk_model *m, const double *best, const uint8_t
     }
     std::vector<gk_lm_result> res(G);
     int capped = 0;
+    // one set of clones and one survey serve every group (the last, shorter
+    // group gets a survey of the first clones)
+    Clones cl;
+    for (int i = 0; i < G; ++i) {
+        gk_model *c = nullptr;
+        const gk_status st = clone_model(m, &c);
+        if (c) cl.v.push_back(c);
+        GK_TRY(st);
+    }
+    GK_TRY(gk_create_survey(cl.v.data(), G, &cl.s));
+    if (mode == GK_MC_SHUFFLE) HIP_TRY(hipMalloc(&d_perm.p, sizeof(int32_t) * (size_t)G * nv));
+    else HIP_TRY(hipMalloc(&d_noise.p, sizeof(float) * (size_t)G * 2 * npix));
+    const int sig = m->obs_sig ? 1 : 0;
     for (int s0 = 0; s0 < n_sim; s0 += G) {
         const int ng = std::min(G, n_sim - s0);
-        Clones cl;
-        for (int i = 0; i < ng; ++i) {
-            gk_model *c = nullptr;
-            const gk_status st = clone_model(m, &c);
-            if (c) cl.v.push_back(c);
-            GK_TRY(st);
-        }
-        if (mode == GK_MC_SHUFFLE) {
-            HIP_TRY(hipMalloc(&d_perm.p, sizeof(int32_t) * (size_t)ng * nv));
+        if (mode == GK_MC_SHUFFLE)
             HIP_TRY(hipMemcpy(d_perm.p, perm + (size_t)s0 * nv, sizeof(int32_t) * (size_t)ng * nv,
                               hipMemcpyHostToDevice));
-        } else {
-            HIP_TRY(hipMalloc(&d_noise.p, sizeof(float) * (size_t)ng * 2 * npix));
+        else
             HIP_TRY(hipMemcpy(d_noise.p, noise + (size_t)s0 * 2 * npix,
                               sizeof(float) * (size_t)ng * 2 * npix, hipMemcpyHostToDevice));
-        }
-        const int sig = m->obs_sig ? 1 : 0;
         for (int i = 0; i < ng; ++i) {
             gk_model *c = cl.v[i];
             if (mode == GK_MC_SHUFFLE)
@@ -201,13 +203,12 @@ extern "C" gk_status gk_mc_errors(gk_model *m, const double *best, const uint8_t
             HIP_TRY(hipGetLastError());
         }
         HIP_TRY(hipDeviceSynchronize());
-        (void)hipFree(d_perm.p);
-        (void)hipFree(d_noise.p);
-        d_perm.p = d_noise.p = nullptr;
-        GK_TRY(gk_create_survey(cl.v.data(), ng, &cl.s));
+        Clones tail;  // holds only the shorter group's survey
+        if (ng < G) GK_TRY(gk_create_survey(cl.v.data(), ng, &tail.s));
         for (int i = 0; i < ng; ++i) std::memcpy(&p_io[(size_t)i * NPAR], best, sizeof(double) * NPAR);
-        const gk_status st = gk_fit_lm_survey(cl.s, p_io.data(), free_mask, lo ? lo_g.data() : nullptr,
-                                              hi ? hi_g.data() : nullptr, opts, res.data());
+        const gk_status st = gk_fit_lm_survey(ng < G ? tail.s : cl.s, p_io.data(), free_mask,
+                                              lo ? lo_g.data() : nullptr, hi ? hi_g.data() : nullptr,
+                                              opts, res.data());
         if (st < 0 && st != GK_ENOTCONV) return st;
         for (int i = 0; i < ng; ++i) {
             std::memcpy(fits + (size_t)(s0 + i) * NPAR, &p_io[(size_t)i * NPAR], sizeof(double) * NPAR);
