@@ -15,8 +15,9 @@ trained on 2 M rows streamed from the plain evaluation, then nested-sampling
 fits (1000 live points, 10 free parameters) of synthetic galaxies, plain and
 surrogate-screened, with the posterior medians compared; and the
 velocity-field strategy (Sec. 2.2.1) on GHASP-shaped 256^2 and 512^2 maps:
-evals/s of 1024-row launches, its kernel's roofline, LM fits, Monte-Carlo
-errors and the oracle's rate; and Gaussian line fitting of 262,144 spectra.
+evals/s of 1024-row launches, its kernel's roofline, LM and nested-sampling
+fits, Monte-Carlo errors and the oracle's rate; the survey-shaped and 700^2
+cubes; and Gaussian line fitting of 262,144 spectra.
 """
 import argparse
 import json
@@ -268,6 +269,32 @@ def velocity_field_workload(gbk, I, torch, n_fit, cpu):
                              "evals_per_fit": float(np.mean(ev)),
                              "iterations_per_fit": float(np.mean(it))}
         log(f"velocity-field LM fits: {np.mean(ts):.3f} s each")
+        # nested sampling of the same galaxies (the paper's settings, Sec. 4: 50 live
+        # points, tolerance 0.5), 7 free parameters in a box about the truth
+        ts_ns, ev_ns = [], []
+        for k in range(n_fit):
+            truth = I.ghasp_draw(I.rng_for(6, 100 + k, 0), 1, side)[0]
+            mk = gbk.Model.from_grid(grid)
+            mp = mk.evaluate(torch.tensor(truth[None], device=dev)).cpu().numpy()[0]
+            mk.set_obs(I.make_observation(mp, 5.0, I.rng_for(6, 100 + k, 1),
+                                          flux_frac=I.GHASP_FLUX_FRAC, random_mask=I.GHASP_HOLES,
+                                          W=0.0))
+            blo, bhi = truth.copy(), truth.copy()
+            for slot, w in ((I.PA, 20.0), (I.INC, 10.0), (I.VSYS, 30.0), (I.VT, 60.0),
+                            (I.RT, 0.3 * truth[I.RT]), (I.A, 0.3), (I.G, 0.3)):
+                blo[slot], bhi[slot] = truth[slot] - w, truth[slot] + w
+            blo[I.INC], bhi[I.INC] = max(blo[I.INC], 5.0), min(bhi[I.INC], 85.0)
+            blo[I.G] = max(blo[I.G], 0.05)
+            blo[I.A] = max(blo[I.A], 0.0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rn = mk.fit_nested(blo, bhi, I.GHASP_FREE, truth, n_live=50, tol=0.5, seed=k + 1)
+            ts_ns.append(time.perf_counter() - t0)
+            ev_ns.append(rn["n_evals"])
+        out["ns_512x512"] = {"fits": n_fit, "free": 7, "n_live": 50, "s_per_fit": round(float(np.mean(ts_ns)), 4),
+                             "fits_per_hour": round(3600 * n_fit / sum(ts_ns), 1),
+                             "evals_per_fit": float(np.mean(ev_ns))}
+        log(f"velocity-field NS fits: {np.mean(ts_ns):.3f} s each")
         # Monte-Carlo errors of the last galaxy (Sec. 4.2): 200 shuffled residual
         # fields about its fit, refitted in batched groups
         best = r["p"]
