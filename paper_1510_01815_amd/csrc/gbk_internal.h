@@ -208,8 +208,9 @@ hipError_t launch_vfield(const VfArgs &a, hipStream_t s);
 // Ragged rows of velocity-field models (one row per workgroup): rm.ls_base
 // holds the prefix sums of the rows' tiles; chi2 partials at rm.part_off,
 // residuals at rm.resid_off (if resid != NULL; the dispersion map only for
-// models whose observation weighs it, the fitters' use).
-hipError_t launch_vfield_multi(const ModelDev *md, const RowMap &rm, int nblocks,
+// models whose observation weighs it, the fitters' use).  rc: the rotation
+// curve shared by every row's model, -1 if they differ.
+hipError_t launch_vfield_multi(const ModelDev *md, const RowMap &rm, int nblocks, int rc,
                                const double *params, const double *consts, double *resid,
                                double *partial, hipStream_t s);
 

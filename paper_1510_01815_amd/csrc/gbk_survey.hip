@@ -150,9 +150,11 @@ gk_status survey_batch_vfield(gk_survey *s, const int32_t *midx, const double *d
         std::vector<int64_t> poff(nb), roff(nb);
         int64_t pt = 0;
         lsb[0] = 0;
+        int rc = s->h_md[midx[b0]].rc;
         for (int i = 0; i < nb; ++i) {
             const ModelDev &m = s->h_md[midx[b0 + i]];
             rmodel[i] = midx[b0 + i];
+            if (m.rc != rc) rc = -1;
             if ((int64_t)lsb[i] + m.psf.ntiles > INT32_MAX) return fail(GK_EINVAL, "batch too large");
             lsb[i + 1] = lsb[i] + m.psf.ntiles;
             poff[i] = pt;
@@ -185,7 +187,7 @@ gk_status survey_batch_vfield(gk_survey *s, const int32_t *midx, const double *d
         rm.B = nb;
         const double *prow = d_params + (size_t)b0 * NPAR;
         HIP_TRY(launch_prep_multi(prow, nb, rm.row_model, s->md.p, s->consts.p, st));
-        HIP_TRY(launch_vfield_multi(s->md.p, rm, lsb[nb], prow, s->consts.p, resid,
+        HIP_TRY(launch_vfield_multi(s->md.p, rm, lsb[nb], rc, prow, s->consts.p, resid,
                                     chi2 ? s->partial.p : nullptr, st));
         if (chi2)
             HIP_TRY(launch_reduce_multi(s->partial.p, s->md.p, rm, s->consts.p, chi2 + b0, nb, st));

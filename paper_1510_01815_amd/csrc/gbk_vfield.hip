@@ -165,7 +165,9 @@ __device__ inline int vf_find_row(const int *__restrict__ base, int n, int x)
 
 // One (row, tile) per workgroup over rows of different velocity-field models
 // (each with its own grid and observation); chi-square terms and residuals
-// only, the same per-pixel arithmetic and summation order as k_vfield.
+// only, the same per-pixel arithmetic and summation order as k_vfield.  RC is
+// the rotation curve when every row's model shares it, -1 to read it per row.
+template <int RC>
 __global__ __launch_bounds__(256) void k_vfield_multi(const ModelDev *__restrict__ md, RowMap rm,
                                                       const double *__restrict__ params,
                                                       const double *__restrict__ consts,
@@ -191,7 +193,7 @@ __global__ __launch_bounds__(256) void k_vfield_multi(const ModelDev *__restrict
         double rv = __builtin_nan(""), rs = __builtin_nan("");
         if (valid) {
             double r;
-            const double v = vf_velocity<-1>(c, (double)(p - y * a.nx), (double)y, m.rc, r);
+            const double v = vf_velocity<RC>(c, (double)(p - y * a.nx), (double)y, m.rc, r);
             const double s = params[(size_t)b * NPAR + P_SIG];
             rv = use ? (v - (double)a.vo[p]) * a.iev[p] : 0.0;
             rs = use && sig_term ? (s - (double)a.so[p]) * a.ies[p] : 0.0;
@@ -246,12 +248,18 @@ int vfield_rows_per_block(int ntiles, int B)
     return (int)r;
 }
 
-hipError_t launch_vfield_multi(const ModelDev *md, const RowMap &rm, int nblocks,
+hipError_t launch_vfield_multi(const ModelDev *md, const RowMap &rm, int nblocks, int rc,
                                const double *params, const double *consts, double *resid,
                                double *partial, hipStream_t s)
 {
     if (nblocks <= 0) return hipSuccess;
-    launch(k_vfield_multi, dim3(nblocks), dim3(256), 0, s, md, rm, params, consts, resid, partial);
+    const dim3 g(nblocks), b(256);
+    switch (rc) {
+    case RC_ARCTAN: launch(k_vfield_multi<RC_ARCTAN>, g, b, 0, s, md, rm, params, consts, resid, partial); break;
+    case RC_EPINAT: launch(k_vfield_multi<RC_EPINAT>, g, b, 0, s, md, rm, params, consts, resid, partial); break;
+    case RC_BOISSIER: launch(k_vfield_multi<RC_BOISSIER>, g, b, 0, s, md, rm, params, consts, resid, partial); break;
+    default: launch(k_vfield_multi<-1>, g, b, 0, s, md, rm, params, consts, resid, partial); break;
+    }
     return hipGetLastError();
 }
 
