@@ -530,9 +530,17 @@ gk_status gk_create_model(const gk_model_desc *desc, int device, gk_model **out)
     m->EX = m->NX + 2 * m->hp;
     m->EY = m->NY + 2 * m->hp;
     m->NZE = m->NZ + 2 * m->hl;
-    if ((double)m->EX * m->EY >= 2.0e9 || m->NZE > (1 << 20)) {
+    if ((double)m->EX * m->EY >= 2.0e9) {
         delete m;
         return fail(GK_EINVAL, "model grid too large");
+    }
+    // the line-sum kernel packs a wave's channel range into two 16-bit fields
+    // holding values up to NZE + 1
+    if (m->NZE > kMaxFineChannels) {
+        const int nze = m->NZE;
+        delete m;
+        return fail(GK_EINVAL, "%d fine channels with the LSF halo (nz u + 2 h_lsf); at most %d",
+                    nze, kMaxFineChannels);
     }
     m->dvf = d.dv_kms / u;
     m->inv_dvf = u / d.dv_kms;
@@ -800,4 +808,33 @@ bool gbk::set_conv_config(gk_model *m, bool fft, int tx, int ty)
     }
     m->drop_scratch();
     return true;
+}
+
+void gbk::survey_tile(const gk_model *m, SurveyTile *t)
+{
+    t->TXd = m->TXd;
+    t->TYd = m->TYd;
+    t->ntx = m->ntx;
+    t->nty = m->nty;
+    t->ntiles = m->ntiles;
+    t->lds_bytes = m->lds_bytes;
+    if (m->use_fft || m->TXd * m->TYd <= 256 * kMaxPixPerThread) return;
+    // the 64 x 32 register-blocked tile: the survey kernels take 32 x 32
+    // register-blocked tiles or generic tiles of at most 1024 pixels
+    if (fast_plane_ok(m) && psf_u1_lds_bytes(32, m->hp) <= kMaxLds) {
+        t->TXd = t->TYd = 32;
+        t->lds_bytes = psf_u1_lds_bytes(32, m->hp);
+    } else {
+        int tx = 32, ty = 16;
+        while (psf_lds_bytes(tx, ty, m->d.upsample, m->hp) > kMaxLds && (tx > 1 || ty > 1)) {
+            if (tx >= ty && tx > 1) tx /= 2;
+            else ty /= 2;
+        }
+        t->TXd = tx;
+        t->TYd = ty;
+        t->lds_bytes = psf_lds_bytes(tx, ty, m->d.upsample, m->hp);
+    }
+    t->ntx = (m->d.nx + t->TXd - 1) / t->TXd;
+    t->nty = (m->d.ny + t->TYd - 1) / t->TYd;
+    t->ntiles = t->ntx * t->nty;
 }

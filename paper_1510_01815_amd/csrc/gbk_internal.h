@@ -54,6 +54,9 @@ constexpr int kMaxPixPerThread = 4;
 
 // largest PSF half-width (fine pixels) of the register-blocked u = 1 kernel
 constexpr int kMaxFastHalo = 16;
+// Fine channels with the LSF halo (NZE) a model may have: the line-sum kernel
+// packs a wave's channel range into two 16-bit fields of values up to NZE + 1.
+constexpr int kMaxFineChannels = 65534;
 
 struct PsfArgs {
     const double *T;       // [B][3][EY][EX]

@@ -240,6 +240,15 @@ namespace gbk {
 gk_status run_batch(gk_model *m, const double *params, int32_t B, float *maps, double *resid,
                     double *chi2, int64_t *nvalid, void *stream);
 
+// Data tile of a model inside a survey: the model's own, except that the
+// 64 x 32 register-blocked tile (which the survey kernels do not run) becomes
+// the 32 x 32 one, or a generic tile where that does not apply.
+struct SurveyTile {
+    int TXd, TYd, ntx, nty, ntiles;
+    size_t lds_bytes;
+};
+void survey_tile(const gk_model *m, SurveyTile *t);
+
 // Switches the spatial convolution to the FFT path or to direct data tiles of
 // tx x ty; false (nothing changed) if the configuration does not fit.  Frees
 // the row scratch.

@@ -95,10 +95,12 @@ gk_status refresh_models(gk_survey *s, hipStream_t st)
         a.ny = m->d.ny;
         a.EX = m->EX;
         a.EY = m->EY;
-        a.TXd = m->TXd;
-        a.TYd = m->TYd;
-        a.ntx = m->ntx;
-        a.ntiles = m->ntiles;
+        SurveyTile tile;
+        survey_tile(m, &tile);
+        a.TXd = tile.TXd;
+        a.TYd = tile.TYd;
+        a.ntx = tile.ntx;
+        a.ntiles = tile.ntiles;
         a.dv = m->d.dv_kms;
         a.vref = m->vref;
         if (m->has_obs) {
@@ -119,9 +121,9 @@ gk_status refresh_models(gk_survey *s, hipStream_t st)
         d.inv_dvf = m->inv_dvf;
         d.vf0 = m->vf0;
         d.nvalid = m->nvalid;
-        d.fast_hp = (m->d.upsample == 1 && m->TXd == 32 && m->TYd == 32 && m->hp <= kMaxFastHalo)
-                        ? m->hp : -1;
-        d.lds_bytes = (int)m->lds_bytes;
+        d.fast_hp = (m->d.upsample == 1 && tile.TXd == 32 && tile.TYd == 32 &&
+                     m->hp <= kMaxFastHalo) ? m->hp : -1;
+        d.lds_bytes = (int)tile.lds_bytes;
         d.vfield = m->vfield ? 1 : 0;
         d.use_sig = m->obs_sig ? 1 : 0;
         if (m->vfield) {  // constants at u = 1 without halo (Sec. 2.2.1)

@@ -70,7 +70,7 @@ def test_fft_chi2_and_residuals_match_oracle(O, gbk, name, W, rmask):
     rc, rn = oracle_chi2(O, grid, rows, obs)
     np.testing.assert_array_equal(n, rn)
     for b in range(len(rows)):
-        assert_chi2_close(c[b], rc[b], rn[b], f"{name} row {b}")
+        assert_chi2_close(c[b], rc[b], rn[b], f"{name} row {b}", obs=obs)
     r = m.residuals(rows[:2]).cpu().numpy()
     assert np.isfinite(r[:, :, obs.mask.astype(bool)]).all()
 

@@ -55,7 +55,7 @@ def test_survey_chi2_bit_identical_to_single_model(O, gbk):
         g, ob = grids[midx[b]], obs[midx[b]]
         v, n = O.eval_chi2(oracle_desc(O, g.as_dict()), rows[b], ob.vel, ob.sig, ob.evel,
                            ob.esig, ob.mask, ob.W)
-        assert_chi2_close(c[b], v, n, f"row {b}")
+        assert_chi2_close(c[b], v, n, f"row {b}", obs=ob)
 
 
 def test_survey_lm_equals_per_galaxy_lm(O, gbk):
@@ -78,3 +78,46 @@ def test_survey_lm_equals_per_galaxy_lm(O, gbk):
         one = m.fit_lm(starts[k], free, lo[k], hi[k], max_iter=60)
         np.testing.assert_array_equal(r["p"][k], one["p"])
         assert r["chi2"][k] == one["chi2"] and r["iterations"][k] == one["iterations"]
+
+
+def test_survey_retiles_64x32_models(O, gbk):
+    """A u = 1 model forced to the 64 x 32 register-blocked tile (which the
+    survey kernels do not run) takes the 32 x 32 tile inside a survey: its
+    survey chi2 equals, bit for bit, the single-model chi2 with the 32 x 32
+    tile, agrees with the 64 x 32 single-model chi2 to summation rounding,
+    and matches the oracle."""
+    import torch
+    g = I.Grid(96, 80, 40, 30.0, psf_fwhm=2.5, lsf_sigma=30.0)
+    rng = np.random.default_rng(12)
+    truth = I.c1_box_draw(rng, 1, 80, 2.5)[0]
+    truth[I.XO], truth[I.YO] = 47.5, 40.2
+    d = oracle_desc(O, g.as_dict())
+    ob = I.make_observation(O.evaluate(d, truth), 5.0, rng, random_mask=0.1)
+    m = gbk.Model.from_grid(g)
+    m.set_obs(ob)
+    m.set_conv_config("direct", 64, 32)
+    other = gbk.Model.from_grid(I.Grid(40, 40, 32, 30.0, psf_fwhm=2.0, lsf_sigma=30.0))
+    ob2 = I.make_observation(O.evaluate(oracle_desc(O, I.Grid(40, 40, 32, 30.0, psf_fwhm=2.0,
+                                                                lsf_sigma=30.0).as_dict()),
+                                        np.array([20.0, 19.5, 30, 50, 0, 180, 3, 40, 5, 1, 1, 1.0])),
+                             5.0, rng)
+    other.set_obs(ob2)
+    sv = gbk.Survey([m, other])
+    rows = np.stack([truth] * 6)
+    rows[:, I.PA] += np.linspace(-10, 10, 6)
+    midx = np.array([0, 0, 1, 0, 0, 0])
+    rows[2] = np.array([20.0, 19.5, 35, 55, 2, 170, 3, 40, 5, 1, 1, 1.0])
+    c = sv.chi2(midx, rows).cpu().numpy()
+    sel = np.where(midx == 0)[0]
+    wide, _ = m.chi2(rows[sel])
+    wide = wide.cpu().numpy()
+    m.set_conv_config("direct", 32, 32)
+    sv32 = gbk.Survey([m, other])
+    c32 = sv32.chi2(midx, rows).cpu().numpy()
+    single32, _ = m.chi2(rows[sel])
+    np.testing.assert_array_equal(c[sel], single32.cpu().numpy())
+    np.testing.assert_array_equal(c, c32)
+    np.testing.assert_allclose(c[sel], wide, rtol=1e-12)
+    for b in sel[:2]:
+        v, n = O.eval_chi2(d, rows[b], ob.vel, ob.sig, ob.evel, ob.esig, ob.mask, ob.W)
+        assert_chi2_close(c[b], v, n, f"row {b}", obs=ob)
