@@ -35,6 +35,11 @@
  *    pixels (channels) on every side, and each convolution pass is "valid",
  *    so every output voxel sees real model values (consistent with the
  *    N_DATA + N_PSF - 1 extent of eq. 10);
+ *  - a fine spaxel's line is kept only if it rises above 2^-40 of its peak
+ *    (|v - vlos| <= sigma sqrt(80 ln 2)) at some channel of the fine model
+ *    band (data channels plus the spectral halo); otherwise the spaxel has no
+ *    flux.  Where it is kept, the whole sampled Gaussian is used.  This
+ *    integer decision is taken in single precision (line_reaches_band);
  *  - m0 = dv * sum C; m1 = sum C v / sum C; m2 = sqrt(sum C (v - m1)^2 / sum C)
  *    (two-pass); a spectrum with sum C == 0 gets m0 = 0, m1 = Vsys, m2 = 0;
  *  - chi2 = sum over mask != 0 of (m1 - vo)^2/Ev^2 + W (m2 - so)^2/Es^2.
@@ -163,6 +168,22 @@ void go_sky_point(int rc, const double *p, double x, double y, double *vlos, dou
     *inten = p[P_I0] * exp(-rr);                              /* eq. 5 */
 }
 
+/* 1 if a line of centre vlos and width sig (km/s) rises above 2^-40 of its
+ * peak, i.e. |v - vlos| <= sig sqrt(80 ln 2), at some channel of the fine model
+ * band, whose channel zz (0 <= zz < nze) has velocity v_first + zz dvf.  The
+ * answer is an integer decision, taken in single precision: the nearest
+ * channels inside the window are ceil(c - s) and floor(c + s), with the line
+ * centre c and half-width s in channel units rounded to float. */
+int go_line_reaches_band(double vlos, double sig, double v_first, double dvf, int nze)
+{
+    float c = (float)((vlos - v_first) / dvf);
+    float s = (float)(sig / dvf * sqrt(80.0 * log(2.0)));
+    float lo = ceilf(c - s), hi = floorf(c + s);
+    if (lo < 0.0f) lo = 0.0f;
+    if (hi > (float)(nze - 1)) hi = (float)(nze - 1);
+    return lo <= hi;
+}
+
 /* Model cube on the fine grid plus halo: cube[z][y][x], size nze*nye*nxe
  * (go_cube_dims).  Returns 0, or -1 for parameters outside the domain. */
 int go_model_cube(const go_desc *d, const double *p, double *cube)
@@ -179,6 +200,8 @@ int go_model_cube(const go_desc *d, const double *p, double *cube)
             double x = ((xx - hp) + 0.5) / u - 0.5;
             double vlos, inten;
             go_sky_point(d->rc, p, x, y, &vlos, &inten);
+            double v_first = d->v0 + (((0 - hl) + 0.5) / u - 0.5 - d->crpix) * d->dv;
+            if (!go_line_reaches_band(vlos, sig, v_first, d->dv / u, nze)) inten = 0.0;
             for (int zz = 0; zz < nze; ++zz) {
                 double v = d->v0 + (((zz - hl) + 0.5) / u - 0.5 - d->crpix) * d->dv;
                 double t = (v - vlos) / sig;

@@ -299,6 +299,9 @@ __device__ __forceinline__ void line_sums_tile(const double *__restrict__ c,
         t1 *= amp;
         t2 *= amp;
     }
+    // a line below 2^-40 of its peak at every channel of the band has no flux
+    // (the wave's channel range may still have been run for the other lanes)
+    if (lo > hi) t0 = t1 = t2 = 0.0;
     if (in) {
         const size_t plane = (size_t)EX * EY;
         double *Tb = T + (size_t)gy * EX + gx;

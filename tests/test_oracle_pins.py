@@ -342,6 +342,39 @@ def test_moments_spikes(O):
     assert (m[0, 0, 3], m[1, 0, 3], m[2, 0, 3]) == (0.0, 42.0, 0.0)
 
 
+def test_lines_outside_the_band(O):
+    """Reading of Sec. 2.2.2 for lines outside the band: a fine spaxel keeps its
+    line only if the line rises above 2^-40 of its peak (|v - vlos| <= sigma
+    sqrt(80 ln 2) = 7.45 sigma) at some channel of the model band (data
+    channels plus the spectral halo); then the whole sampled Gaussian counts.
+    One spaxel on the kinematic centre (vlos = Vsys), channels -100..100 km/s
+    every 10 km/s, sigma 10 km/s, no PSF or LSF: a line 7 sigma above the
+    band gives the moments of its sampled wing over the band (written out
+    here from their definition); 8 and 30 sigma outside give no flux, i.e.
+    (0, Vsys, 0).  With an LSF the band grows by its halo (4 channels of
+    10 km/s here): a line 7 sigma beyond the halo still reaches it, 8 sigma
+    beyond does not."""
+    d = O.Desc(1, 1, 21, 1, 10.0, v0=0.0, crpix=10.0, psf_fwhm=0.0, lsf_sigma=0.0)
+    v = (np.arange(21) - 10) * 10.0
+    for vsys in (170.0, -170.0):
+        m = O.evaluate(d, par(xo=0.0, yo=0.0, vsys=vsys, sig=10.0, i0=1.3))
+        g = np.exp(-0.5 * ((v - vsys) / 10.0) ** 2)
+        m0 = 10.0 * 1.3 * g.sum() / (math.sqrt(2 * math.pi) * 10.0)
+        m1 = np.sum(v * g) / g.sum()
+        m2 = math.sqrt(np.sum(g * (v - m1) ** 2) / g.sum())
+        assert m[0, 0, 0] > 0.0
+        assert abs(m[0, 0, 0] - m0) <= 1e-12 * m0
+        assert abs(m[1, 0, 0] - m1) <= 1e-9 and abs(m[2, 0, 0] - m2) <= 1e-9
+    for vsys in (180.0, -180.0, 400.0, -400.0):
+        m = O.evaluate(d, par(xo=0.0, yo=0.0, vsys=vsys, sig=10.0))
+        assert (m[0, 0, 0], m[1, 0, 0], m[2, 0, 0]) == (0.0, vsys, 0.0)
+    dl = O.Desc(1, 1, 21, 1, 10.0, v0=0.0, crpix=10.0, psf_fwhm=0.0, lsf_sigma=10.0)
+    assert O.cube_dims(dl)[4] == 4
+    assert O.evaluate(dl, par(xo=0.0, yo=0.0, vsys=210.0, sig=10.0))[0, 0, 0] > 0.0
+    m = O.evaluate(dl, par(xo=0.0, yo=0.0, vsys=220.0, sig=10.0))
+    assert (m[0, 0, 0], m[1, 0, 0], m[2, 0, 0]) == (0.0, 220.0, 0.0)
+
+
 # ---------------------------------------------------------------------------
 # Goodness of fit (eq. 11): hand-computed fixture
 # ---------------------------------------------------------------------------
