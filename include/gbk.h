@@ -434,6 +434,23 @@ gk_status gk_surrogate_load(gk_model *instrument, const char *path, gk_surrogate
 gk_status gk_surrogate_gradients(gk_surrogate *s, const double *params, int32_t B, float *grads,
                                  double *loss);
 
+/* One Adam step on the caller's rows params [B][GK_NP] (host or device; B a
+ * multiple of 32, at most 65536) with step size lr > 0: targets and mask from
+ * the plain evaluation, the loss gradient as in gk_surrogate_gradients, then
+ * m = 0.9 m + 0.1 g, v = 0.999 v + 0.001 g^2 and
+ * w -= lr (m / (1 - 0.9^t)) / (sqrt(v / (1 - 0.999^t)) + 1e-8) on every master
+ * weight and bias (FP32), t counting the steps since the weights were set.
+ * gk_surrogate_train's step t of a call of n steps is this step on the rows
+ * drawn for it (row b, slot s: lo_s + u (hi_s - lo_s) rounded once (a fused
+ * multiply-add; lo_s where hi_s <= lo_s), u = (r_s + 1/2) 2^-32
+ * with r the 12 words of Philox4x32-10 blocks j = 0, 1, 2 at counter
+ * (b, t_total, t_total >> 32, j), key (seed, (seed >> 32) ^ 0x73757272), t_total
+ * = the steps since the weights were set) with step size
+ * lr_final + (lr - lr_final) (1 + cos(pi t / (n - 1))) / 2.  *loss (may be
+ * NULL) receives the loss before the update.  Blocks. */
+gk_status gk_surrogate_step(gk_surrogate *s, const double *params, int32_t B, double lr,
+                            double *loss);
+
 /* maps [B][2][ny][nx] (device, km/s: m1 then m2) predicted for params
  * [B][GK_NP] (host or device), enqueued on hip_stream. */
 gk_status gk_surrogate_predict(gk_surrogate *s, const double *params, int32_t B, float *maps,

@@ -69,23 +69,30 @@ def forward(x, Ws, bs):
     return y, cache
 
 
-def loss_and_grads(x, t, mask, Ws, bs):
+def loss_and_grads(x, t, mask, Ws, bs, with_terms=False):
     """Masked MSE and its gradients with respect to every weight and bias.
-    mask [B][n_out] (1/0)."""
+    mask [B][n_out] (1/0).  with_terms: also returns, per layer, the output
+    gradient d_l and the layer input h_{l-1} whose product gives the weight
+    gradient (for error bounds of lower-precision implementations)."""
     y, cache = forward(x, Ws, bs)
     cnt = max(float(mask.sum()), 1.0)
     r = (y - t) * mask
     loss = float(np.sum(r * r) / cnt)
     dy = 2.0 * r / cnt
     gW, gb = [None] * len(Ws), [None] * len(bs)
+    terms = [None] * len(Ws)
     _, h = cache[-1]
     gW[-1], gb[-1] = dy.T @ h, dy.sum(axis=0)
+    terms[-1] = (dy, h)
     dh = dy @ Ws[-1]
     for l in range(len(Ws) - 2, -1, -1):
         z, hin = cache[l]
         dz = dh * gelu_grad(z)
         gW[l], gb[l] = dz.T @ hin, dz.sum(axis=0)
+        terms[l] = (dz, hin)
         dh = dz @ Ws[l]
+    if with_terms:
+        return loss, gW, gb, terms
     return loss, gW, gb
 
 

@@ -292,8 +292,9 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g)
     }
 }
 
-// uniform draws of parameter rows in the box: slot s = lo_s + u (hi_s - lo_s),
-// u from Philox4x32-10 with counter (row, step, step >> 32, block) and the seed as key
+// uniform draws of parameter rows in the box: slot s = lo_s + u (hi_s - lo_s)
+// rounded once, u from Philox4x32-10 with counter (row, step, step >> 32, block)
+// and the seed as key
 __global__ void k_draw(uint64_t seed, uint64_t step, int B, const double *__restrict__ lo,
                        const double *__restrict__ hi, double *__restrict__ p)
 {
@@ -307,7 +308,8 @@ __global__ void k_draw(uint64_t seed, uint64_t step, int B, const double *__rest
     }
     for (int s = 0; s < NPAR; ++s) {
         const double u = ((double)r[s] + 0.5) * 0x1.0p-32;
-        p[(size_t)b * NPAR + s] = hi[s] > lo[s] ? lo[s] + u * (hi[s] - lo[s]) : lo[s];
+        // one rounding: fma(u, hi - lo, lo)
+        p[(size_t)b * NPAR + s] = hi[s] > lo[s] ? fma(u, hi[s] - lo[s], lo[s]) : lo[s];
     }
 }
 
@@ -1277,6 +1279,30 @@ gk_status gk_surrogate_gradients(gk_surrogate *s, const double *params, int32_t 
         HIP_TRY(hipMemcpy(grads + nw, s->gb[l], nb * sizeof(float), hipMemcpyDeviceToHost));
         grads += nw + nb;
     }
+    return GK_OK;
+}
+
+gk_status gk_surrogate_step(gk_surrogate *s, const double *params, int32_t B, double lr,
+                            double *loss)
+{
+    if (!s || !params) return fail(GK_EINVAL, "NULL argument");
+    if (B <= 0 || B > 65536) return fail(GK_EINVAL, "invalid batch size %d", B);
+    if (B % 32) return fail(GK_EINVAL, "training batches must be a multiple of 32 rows");
+    if (!(lr > 0.0) || !std::isfinite(lr)) return fail(GK_EINVAL, "step size must be finite and > 0");
+    DeviceGuard g(s->device);
+    HIP_TRY(g.err);
+    hipStream_t st = s->stream;
+    GK_TRY(stage_params(s, params, B, true, st));
+    if (!s->d_loss) {
+        HIP_TRY(hipMalloc((void **)&s->d_loss, 4096 * sizeof(float)));
+        s->loss_cap = 4096;
+    }
+    GK_TRY(loss_and_grads(s, B, s->d_loss, st));
+    GK_TRY(adam(s, lr, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    float lf;
+    HIP_TRY(hipMemcpy(&lf, s->d_loss, sizeof lf, hipMemcpyDeviceToHost));
+    if (loss) *loss = lf;
     return GK_OK;
 }
 

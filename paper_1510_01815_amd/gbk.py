@@ -35,7 +35,7 @@ SYMBOLS = (
     "gk_surrogate_gradients", "gk_surrogate_predict",
     "gk_surrogate_chi2", "gk_fit_nested_screened", "gk_gemm_bf16", "gk_model_conv_path",
     "gk_set_launch_mode", "gk_graph_launches", "gk_autotune", "gk_set_conv_config",
-    "gk_mc_errors", "gk_line_default_opts", "gk_fit_lines",
+    "gk_mc_errors", "gk_line_default_opts", "gk_fit_lines", "gk_surrogate_step",
 )
 MC = {"shuffle": 0, "perturb": 1}
 LM_REASONS = {1: "ftol", 2: "xtol", 3: "lambda", 4: "maxiter"}
@@ -245,6 +245,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.gk_surrogate_load.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(vp)]
     L.gk_surrogate_gradients.argtypes = [vp, vp, i32, vp, ctypes.POINTER(ctypes.c_double)]
     L.gk_surrogate_predict.argtypes = [vp, vp, i32, vp, vp]
+    L.gk_surrogate_step.argtypes = [vp, vp, i32, dp, ctypes.POINTER(ctypes.c_double)]
     L.gk_surrogate_chi2.argtypes = [vp, vp, vp, i32, vp, vp]
     L.gk_fit_nested_screened.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.POINTER(NSOpts), dp, dp,
                                          ctypes.POINTER(NSResult), vp, ctypes.c_int64, i64p]
@@ -681,6 +682,14 @@ class Surrogate:
         loss = ctypes.c_double(0.0)
         _check(load().gk_surrogate_gradients(self._h, p, B, g.ctypes.data, ctypes.byref(loss)))
         return loss.value, g
+
+    def step(self, params, lr: float) -> float:
+        """One Adam step on rows params [B][12] (gk_surrogate_step); returns the loss
+        before the update."""
+        p, B, keep = _params_arg(params)
+        loss = ctypes.c_double(0.0)
+        _check(load().gk_surrogate_step(self._h, p, B, float(lr), ctypes.byref(loss)))
+        return loss.value
 
     def predict(self, params, out=None, stream=None):
         """maps [B][2][ny][nx] float32 CUDA tensor (m1, m2 in km/s)."""
