@@ -209,3 +209,93 @@ def test_grid_five_dims_million_rows_per_level(O, gbk):
     print("grid5", one["chi2"], r["chi2"], r["best"][[2, 3, 5, 6, 7]], truth[[2, 3, 5, 6, 7]])
     assert r["levels"] == 3 and r["n_evals"] == 3 * 16 ** 5
     assert np.isfinite(r["chi2"]) and r["chi2"] <= one["chi2"] and r["chi2"] < 0.01 * one["chi2"] + 10
+
+
+@pytest.mark.parametrize("with_i0", [False, True])
+def test_nested_sampling_device_draws_closed_form(O, gbk, with_i0):
+    """The device-side candidate draws of gk_fit_nested against a posterior
+    and evidence known in closed form.  Only Vsys free and W = 0: the lines sit
+    far inside the band with sigma_line / dv = 1.7, so m1 shifts rigidly with
+    Vsys (up to exp(-2 pi^2 sigma_line^2 / dv^2) ~ 1e-24) and chi2(V) =
+    chi2_min + S (V - V_hat)^2 with S = sum 1/E_v^2 and V_hat the
+    E_v^-2-weighted mean of v_obs - m1(V = 0).  The posterior is then normal
+    with mean V_hat and sd S^-1/2, and log Z = -chi2_min / 2 +
+    ln(sqrt(2 pi / S) / width) (the box is > 100 sd wide).  With I0 free too
+    (it only scales the cube, so the likelihood is flat along it) its
+    marginal must be the uniform prior and log Z is unchanged.  Means within
+    0.1 sd, sd within 10%, log Z within 3 sqrt(H/N) + 0.05."""
+    grid = I.c1_grid()
+    d = oracle_desc(O, grid.as_dict())
+    truth = I.c1_truth()
+    truth[I.VSYS] = 7.3
+    rng = np.random.default_rng(14 + with_i0)
+    obs = I.make_observation(O.evaluate(d, truth), 5.0, rng, W=0.0)
+    obs.evel = (obs.evel * rng.uniform(0.7, 1.5, obs.evel.shape)).astype(np.float32)
+    base = truth.copy()
+    base[I.VSYS] = 0.0
+    m1_0 = O.evaluate(d, base)[1]
+    mk = obs.mask.astype(bool)
+    w = 1.0 / obs.evel.astype(np.float64)[mk] ** 2
+    r0 = obs.vel.astype(np.float64)[mk] - m1_0[mk]
+    S = float(np.sum(w))
+    v_hat = float(np.sum(w * r0) / S)
+    chi2_min = float(np.sum(w * (r0 - v_hat) ** 2))
+    sd = 1.0 / math.sqrt(S)
+    lo, hi = truth.copy(), truth.copy()
+    lo[I.VSYS], hi[I.VSYS] = -20.0, 40.0
+    free = [0] * 12
+    free[I.VSYS] = 1
+    if with_i0:
+        lo[I.I0], hi[I.I0] = 0.5, 2.0
+        free[I.I0] = 1
+    logz_true = -0.5 * chi2_min + math.log(math.sqrt(2 * math.pi / S) / (hi[I.VSYS] - lo[I.VSYS]))
+    m = gbk.Model.from_grid(grid)
+    m.set_obs(obs)
+    r = m.fit_nested(lo, hi, free, truth, n_live=400, seed=5)
+    print("logz", r["logz"], "+-", r["logz_err"], "closed form", logz_true, "evals", r["n_evals"])
+    print("Vsys mean", r["mean"][I.VSYS], "sd", r["sd"][I.VSYS], "closed form", v_hat, sd)
+    assert r["status"] == 0
+    assert abs(r["logz"] - logz_true) <= 3 * r["logz_err"] + 0.05
+    assert abs(r["mean"][I.VSYS] - v_hat) <= 0.1 * sd
+    assert abs(r["sd"][I.VSYS] - sd) <= 0.1 * sd
+    assert abs(r["median"][I.VSYS] - v_hat) <= 0.12 * sd
+    assert abs(r["q16"][I.VSYS] - (v_hat - sd)) <= 0.15 * sd
+    assert abs(r["q84"][I.VSYS] - (v_hat + sd)) <= 0.15 * sd
+    if with_i0:
+        width = hi[I.I0] - lo[I.I0]
+        print("I0 mean", r["mean"][I.I0], "sd", r["sd"][I.I0], "q16/50/84", r["q16"][I.I0],
+              r["median"][I.I0], r["q84"][I.I0])
+        assert abs(r["mean"][I.I0] - 1.25) <= 0.05 * width
+        assert abs(r["sd"][I.I0] - width / math.sqrt(12)) <= 0.05 * width
+        for q, key in ((0.16, "q16"), (0.5, "median"), (0.84, "q84")):
+            assert abs(r[key][I.I0] - (lo[I.I0] + q * width)) <= 0.06 * width
+
+
+def test_nested_sampling_fabry_perot_128x128x48(O, gbk):
+    """The 128 x 128 x 48 Fabry-Perot workload: nested sampling with 400 live
+    points over the 10 non-Epinat parameters (exponential-rise curve), every
+    round's candidates in one launch.  The truth lies inside the 68% interval
+    for most parameters and within 3 sd for all; I0, which only scales the
+    cube, keeps a flat marginal."""
+    grid = I.c2_grid()
+    d = oracle_desc(O, grid.as_dict())
+    truth = I.c2_draw(I.rng_for(2, 1, 40), 1)[0]
+    obs = I.make_observation(O.evaluate(d, truth), 3.0, I.rng_for(2, 1, 41))
+    lo, hi = I.c2_prior_box()
+    free = [1] * 10 + [0, 0]
+    m = gbk.Model.from_grid(grid)
+    m.set_obs(obs)
+    r = m.fit_nested(lo, hi, free, truth, n_live=400, seed=3)
+    print("NS 128x128x48:", r["n_evals"], "evaluations,", r["n_launches"], "launches,",
+          r["n_iter"], "retired, logz", r["logz"], "+-", r["logz_err"])
+    inside = 0
+    for k in range(10):
+        z = (truth[k] - r["median"][k]) / r["sd"][k]
+        ok68 = r["q16"][k] <= truth[k] <= r["q84"][k]
+        inside += ok68
+        print(f"  {I.PARAM_NAMES[k]:5s} truth {truth[k]:9.4f} median {r['median'][k]:9.4f} "
+              f"sd {r['sd'][k]:.4g} z {z:+.2f} in68 {ok68}")
+        assert abs(z) <= 3.0, k
+    assert r["status"] == 0
+    assert inside >= 6
+    assert abs(r["mean"][I.I0] - 1.25) < 0.1 and abs(r["sd"][I.I0] - 1.5 / math.sqrt(12)) < 0.06
