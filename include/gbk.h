@@ -269,7 +269,35 @@ typedef struct {
      * plain rows; default 0 and 0 (every round screened). */
     double screen_cost;
     int32_t screen_rows;
+    /* 1: mode separation (MultiNest's, simplified; Sec. 2.3.2).  When the
+     * ellipsoids of a mode's decomposition fall into groups that do not
+     * intersect, the mode splits into one mode per group (its live points and
+     * prior volume shared out in proportion to their points), and each mode
+     * then runs as a nested sampler of its own: a candidate drawn from a
+     * mode's ellipsoids (uniform over that mode's union, modes picked by
+     * volume) replaces that mode's lowest live point if its L is higher, and
+     * the mode's volume shrinks by exp(-1/n_m).  A mode stops receiving
+     * candidates once its remaining evidence L_max X_m is below
+     * (e^tol - 1) Z / (number of modes); the run ends when every mode has
+     * stopped.  Local evidence of a mode = its own retired and final live
+     * points plus its ancestors' evidence shared out by live points at each
+     * split.  At most GK_NS_MAX_MODES modes.  Meant for posteriors known to
+     * have separated modes: a connected but curved contour can also split,
+     * and its pieces may then count the same region twice.  0 (default): one
+     * mode. */
+    int32_t separate_modes;
 } gk_ns_opts;
+
+/* Per-mode results (gk_ns_result.modes). */
+#define GK_NS_MAX_MODES 8
+typedef struct {
+    double logz, logz_err;     /* local evidence and sqrt(H_m / n_m) */
+    double info_h;             /* information of the mode's own points (nats) */
+    int64_t n_live;            /* live points of the mode */
+    int64_t n_samples;         /* posterior points of the mode (its own, weight > 0) */
+    double mean[GK_NP], sd[GK_NP];                 /* over the mode's own points */
+    double median[GK_NP], q16[GK_NP], q84[GK_NP];
+} gk_ns_mode;
 
 typedef struct {
     double logz, logz_err;     /* log evidence and sqrt(H / N) */
@@ -288,6 +316,9 @@ typedef struct {
     int64_t n_audit_miss;      /* audited ones that the plain chi2 would have accepted */
     double t_wall_s;           /* wall time of the call (model fits; 0 for gk_nested_sample) */
     double t_wait_s;           /* of which blocked waiting for the device */
+    int32_t n_modes;           /* final modes (1 without mode separation) */
+    int32_t reserved_modes;
+    gk_ns_mode modes[GK_NS_MAX_MODES];  /* the first n_modes are filled */
 } gk_ns_result;
 
 gk_status gk_ns_default_opts(gk_ns_opts *opts);

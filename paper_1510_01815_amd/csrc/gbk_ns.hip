@@ -59,15 +59,19 @@ bool cholesky(std::vector<double> &M, int d)
 double ball_volume(int d) { return std::pow(M_PI, 0.5 * d) / std::tgamma(0.5 * d + 1.0); }
 
 // Sampling region of a round: the union of up to kMaxEll ellipsoids
-// x = mu_e + L_e z, |z| <= 1 (L_e lower triangular, row-major d x d), drawn
-// from in proportion to their volumes (cum = cumulative volume fractions),
-// or the whole unit cube when n_ell is 0.
-constexpr int kMaxEll = 8;
+// x = mu_e + L_e z, |z| <= 1 (L_e lower triangular, row-major d x d), each
+// belonging to one mode, drawn from in proportion to their volumes (cum =
+// cumulative volume fractions over the ellipsoids of unfinished modes), or
+// the whole unit cube when n_ell is 0.
+constexpr int kMaxEll = 16;
+constexpr int kMaxModes = GK_NS_MAX_MODES;
 constexpr int kMeansPoints = 256;  // points of the 2-means iterations of a split
 struct Bound {
     int n_ell;
     int d;
     double cum[kMaxEll];
+    double logvol[kMaxEll];
+    int mode[kMaxEll];
     double mu[kMaxEll][GK_NP];
     double L[kMaxEll][GK_NP * GK_NP];
     double inv_diag[kMaxEll][GK_NP];
@@ -123,30 +127,33 @@ bool fit_ellipsoid(const double *U, const int *idx, int n, int d, double enlarge
     return true;
 }
 
-// Region of the live points U [N][d] at prior volume exp(logX): one
-// enclosing ellipsoid, split recursively in two (2-means in unit-cube
-// coordinates) while the two children's volumes sum to less than half the
-// parent's and each child keeps at least 2 (d + 1) points, up to max_ell
-// ellipsoids (MultiNest's decomposition, simplified).  An ellipsoid is never
-// smaller than the prior volume its points stand for, n_e X / N.
-void build_bound(const double *U, int N, int d, double enlarge, double logX, int max_ell, Bound &bnd)
+// One ellipsoid of a decomposition and the live points it was fitted to.
+struct Ell {
+    std::vector<int> idx;
+    double mu[GK_NP], L[GK_NP * GK_NP], invd[GK_NP], logvol;
+};
+
+// Decomposition of the points `pts` of one mode (prior volume exp(logX),
+// n_ref live points): one enclosing ellipsoid, split recursively in two
+// (2-means in unit-cube coordinates) while the two children's volumes sum
+// to less than half the parent's and each child keeps at least 2 (d + 1)
+// points, up to max_ell ellipsoids (MultiNest's decomposition, simplified).
+// An ellipsoid is never smaller than the prior volume its points stand for,
+// n_e X / n_ref.  False if the first ellipsoid is degenerate.
+bool decompose(const double *U, const std::vector<int> &pts, int d, double enlarge, double logX,
+               int n_ref, int max_ell, std::vector<Ell> &done)
 {
-    bnd.d = d;
-    bnd.n_ell = 0;
-    struct Node {
-        std::vector<int> idx;
-        double mu[GK_NP], L[GK_NP * GK_NP], invd[GK_NP], logvol;
-    };
-    auto min_vol = [&](int n) { return logX + std::log((double)n / N); };
-    std::vector<Node> done, todo(1);
-    todo[0].idx.resize(N);
-    std::iota(todo[0].idx.begin(), todo[0].idx.end(), 0);
+    done.clear();
+    auto min_vol = [&](int n) { return logX + std::log((double)n / n_ref); };
+    std::vector<Ell> todo(1);
+    todo[0].idx = pts;
+    const int N = (int)pts.size();
     if (!fit_ellipsoid(U, todo[0].idx.data(), N, d, enlarge, min_vol(N), todo[0].mu, todo[0].L,
                        todo[0].invd, todo[0].logvol))
-        return;  // degenerate: the whole cube
+        return false;
     std::vector<double> w;
     while (!todo.empty()) {
-        Node nd = std::move(todo.back());
+        Ell nd = std::move(todo.back());
         todo.pop_back();
         const int n = (int)nd.idx.size();
         bool split = false;
@@ -195,7 +202,7 @@ void build_bound(const double *U, int N, int d, double enlarge, double logX, int
                 }
                 if (!changed && it > 0) break;
             }
-            Node ch[2];
+            Ell ch[2];
             for (int i = 0; i < n; ++i) {
                 const double *y = &w[(size_t)i * d];
                 ch[dist2(y, c1) < dist2(y, c0) ? 1 : 0].idx.push_back(nd.idx[i]);
@@ -214,30 +221,222 @@ void build_bound(const double *U, int N, int d, double enlarge, double logX, int
         }
         if (!split) done.push_back(std::move(nd));
     }
-    double logtot = -INFINITY;
-    for (auto &e : done) logtot = logaddexp(logtot, e.logvol);
-    if (logtot >= 0.0) return;  // the union is larger than the box: the whole cube
-    bnd.n_ell = (int)done.size();
-    double c = 0.0;
-    for (int e = 0; e < bnd.n_ell; ++e) {
-        c += std::exp(done[e].logvol - logtot);
-        bnd.cum[e] = c;
-        std::copy_n(done[e].mu, d, bnd.mu[e]);
-        std::copy_n(done[e].L, d * d, bnd.L[e]);
-        std::copy_n(done[e].invd, d, bnd.inv_diag[e]);
+    return true;
+}
+
+// delta^T (Sa / (1 - s) + Sb / s)^-1 delta for the covariances Sa, Sb (d x d)
+double overlap_q(const double *Sa, const double *Sb, const double *delta, int d, double s)
+{
+    std::vector<double> M((size_t)d * d);
+    for (int k = 0; k < d * d; ++k) M[k] = Sa[k] / (1.0 - s) + Sb[k] / s;
+    if (!cholesky(M, d)) return INFINITY;
+    double y[GK_NP], q = 0.0;
+    for (int a = 0; a < d; ++a) {
+        double t = delta[a];
+        for (int b = 0; b < a; ++b) t -= M[a * d + b] * y[b];
+        y[a] = t / M[a * d + a];
+        q += y[a] * y[a];
     }
-    bnd.cum[bnd.n_ell - 1] = 1.0;
+    return q;
+}
+
+// True if the ellipsoids x = mu_a + L_a z and x = mu_b + L_b z (|z| <= 1)
+// intersect.  With S = L L^T, they are disjoint exactly when
+// K(s) = 1 - delta^T (S_a / (1 - s) + S_b / s)^-1 delta is negative for some s
+// in (0, 1), delta = mu_b - mu_a (Gilitschenski & Hanebeck 2012); K is convex
+// in s, so a golden-section search finds its minimum.
+bool ellipsoids_overlap(const double *mua, const double *La, const double *mub, const double *Lb, int d)
+{
+    double Sa[GK_NP * GK_NP] = {}, Sb[GK_NP * GK_NP] = {}, delta[GK_NP];
+    for (int a = 0; a < d; ++a) {
+        delta[a] = mub[a] - mua[a];
+        for (int b = 0; b < d; ++b)
+            for (int k = 0; k <= std::min(a, b); ++k) {
+                Sa[a * d + b] += La[a * d + k] * La[b * d + k];
+                Sb[a * d + b] += Lb[a * d + k] * Lb[b * d + k];
+            }
+    }
+    const double g = 0.5 * (std::sqrt(5.0) - 1.0);
+    double lo = 1e-9, hi = 1.0 - 1e-9;
+    double x1 = hi - g * (hi - lo), x2 = lo + g * (hi - lo);
+    double f1 = 1.0 - overlap_q(Sa, Sb, delta, d, x1), f2 = 1.0 - overlap_q(Sa, Sb, delta, d, x2);
+    for (int it = 0; it < 80; ++it) {
+        if (f1 < 0.0 || f2 < 0.0) return false;
+        if (f1 < f2) {
+            hi = x2;
+            x2 = x1;
+            f2 = f1;
+            x1 = hi - g * (hi - lo);
+            f1 = 1.0 - overlap_q(Sa, Sb, delta, d, x1);
+        } else {
+            lo = x1;
+            x1 = x2;
+            f1 = f2;
+            x2 = lo + g * (hi - lo);
+            f2 = 1.0 - overlap_q(Sa, Sb, delta, d, x2);
+        }
+    }
+    return f1 >= 0.0 && f2 >= 0.0;
+}
+
+// Per-mode state of the sampler.  A mode's live points evolve as a nested
+// sampling run of their own: its prior volume starts at exp(logX0) and
+// shrinks by exp(-1/n) with each point it retires.
+struct Mode {
+    int n = 0;                  // live points
+    double logX0 = 0.0;         // log prior volume when the mode was created
+    int64_t j = 0;              // points retired since
+    double logz_own = -INFINITY;  // evidence of its own retired (and, at the end, live) points
+    double logz_inh = -INFINITY;  // share of its ancestors' evidence (by live points at each split)
+    double lmax = -DBL_MAX;     // highest live log-likelihood
+    bool split = false;         // replaced by child modes
+    bool finished = false;      // remaining evidence negligible: no more candidates
+    double logX() const { return logX0 - (double)j / n; }
+};
+
+// A split of mode `parent` into modes parent's children (live point indices).
+struct ModeSplit {
+    int parent;
+    std::vector<std::vector<int>> children;
+};
+
+// The region built from the live points at the start of a round: the bound
+// and the mode splits its decomposition found.
+struct Region {
+    Bound bnd;
+    std::vector<ModeSplit> splits;
+};
+
+// Builds the region of the live points U [N][d] (live_mode [N]) for the
+// modes' current volumes.  Every unsplit, unfinished mode is decomposed on
+// its own points; with `separate`, a mode whose ellipsoids fall into groups
+// that do not intersect is split into one mode per group (at most kMaxModes
+// modes in all; MultiNest's mode separation, simplified).  Ellipsoids per
+// mode: max_ell, fewer when several modes share the kMaxEll ellipsoids.  A
+// single mode whose ellipsoids outgrow the unit cube gets the whole cube.
+void build_region(const double *U, const int *live_mode, int N, int d, const std::vector<Mode> &modes,
+                  double enlarge, int max_ell, bool separate, Region &out)
+{
+    Bound &bnd = out.bnd;
+    bnd.d = d;
+    bnd.n_ell = 0;
+    out.splits.clear();
+    std::vector<int> act;
+    for (int m = 0; m < (int)modes.size(); ++m)
+        if (!modes[m].split && !modes[m].finished) act.push_back(m);
+    if (act.empty()) return;
+    const int per_mode = std::max(1, std::min(max_ell, kMaxEll / (int)act.size()));
+    int n_modes = (int)modes.size();
+    std::vector<std::vector<int>> pts(modes.size());
+    for (int i = 0; i < N; ++i) pts[live_mode[i]].push_back(i);
+    std::vector<Ell> ells;
+    std::vector<int> ell_mode;
+    for (int m : act) {
+        std::vector<Ell> e;
+        if (!decompose(U, pts[m], d, enlarge, modes[m].logX(), modes[m].n, per_mode, e)) {
+            if (act.size() == 1) return;  // degenerate single mode: the whole cube
+            // keep a ball of the mode's expected volume around its points
+            Ell b;
+            b.idx = pts[m];
+            double r2 = 0.0;
+            for (int a = 0; a < d; ++a) {
+                b.mu[a] = 0.0;
+                for (int i : pts[m]) b.mu[a] += U[(size_t)i * d + a];
+                b.mu[a] /= pts[m].size();
+            }
+            for (int i : pts[m]) {
+                double s = 0.0;
+                for (int a = 0; a < d; ++a) s += (U[(size_t)i * d + a] - b.mu[a]) * (U[(size_t)i * d + a] - b.mu[a]);
+                r2 = std::max(r2, s);
+            }
+            const double rad = std::max(std::sqrt(r2) * std::pow(enlarge, 1.0 / d),
+                                        std::exp((modes[m].logX() - std::log(ball_volume(d))) / d));
+            std::fill(b.L, b.L + d * d, 0.0);
+            for (int a = 0; a < d; ++a) {
+                b.L[a * d + a] = rad;
+                b.invd[a] = 1.0 / rad;
+            }
+            b.logvol = std::log(ball_volume(d)) + d * std::log(rad);
+            e.assign(1, std::move(b));
+        }
+        // groups of intersecting ellipsoids (connected components)
+        const int ne = (int)e.size();
+        std::vector<int> comp(ne);
+        std::iota(comp.begin(), comp.end(), 0);
+        std::function<int(int)> root = [&](int x) { return comp[x] == x ? x : comp[x] = root(comp[x]); };
+        if (separate && ne > 1)
+            for (int a = 0; a < ne; ++a)
+                for (int b = a + 1; b < ne; ++b)
+                    if (root(a) != root(b) && ellipsoids_overlap(e[a].mu, e[a].L, e[b].mu, e[b].L, d))
+                        comp[root(a)] = root(b);
+        std::vector<int> roots;
+        for (int a = 0; a < ne; ++a)
+            if (std::find(roots.begin(), roots.end(), root(a)) == roots.end()) roots.push_back(root(a));
+        const bool do_split = separate && roots.size() > 1 &&
+                              n_modes + (int)roots.size() <= kMaxModes;
+        ModeSplit sp{m, {}};
+        for (int a = 0; a < ne; ++a) {
+            int label = m;
+            if (do_split) {
+                const int g = (int)(std::find(roots.begin(), roots.end(), root(a)) - roots.begin());
+                label = n_modes + g;
+                if ((int)sp.children.size() <= g) sp.children.resize(g + 1);
+                sp.children[g].insert(sp.children[g].end(), e[a].idx.begin(), e[a].idx.end());
+            }
+            ells.push_back(std::move(e[a]));
+            ell_mode.push_back(label);
+        }
+        if (do_split) {
+            n_modes += (int)roots.size();
+            out.splits.push_back(std::move(sp));
+        }
+    }
+    double logtot = -INFINITY;
+    for (auto &e : ells) logtot = logaddexp(logtot, e.logvol);
+    if (act.size() == 1 && out.splits.empty() && logtot >= 0.0) return;  // the whole cube
+    if ((int)ells.size() > kMaxEll) return;  // cannot happen: per_mode * modes <= kMaxEll
+    bnd.n_ell = (int)ells.size();
+    for (int e = 0; e < bnd.n_ell; ++e) {
+        bnd.logvol[e] = ells[e].logvol;
+        bnd.mode[e] = ell_mode[e];
+        std::copy_n(ells[e].mu, d, bnd.mu[e]);
+        std::copy_n(ells[e].L, d * d, bnd.L[e]);
+        std::copy_n(ells[e].invd, d, bnd.inv_diag[e]);
+    }
+}
+
+// Cumulative draw weights of bnd's ellipsoids by volume, over the modes that
+// are not finished; false if none is left.
+bool set_draw_weights(Bound &bnd, const std::vector<Mode> &modes)
+{
+    double logtot = -INFINITY;
+    for (int e = 0; e < bnd.n_ell; ++e)
+        if (!modes[bnd.mode[e]].finished) logtot = logaddexp(logtot, bnd.logvol[e]);
+    if (logtot == -INFINITY) return false;
+    double c = 0.0;
+    int last = 0;
+    for (int e = 0; e < bnd.n_ell; ++e) {
+        if (!modes[bnd.mode[e]].finished) {
+            c += std::exp(bnd.logvol[e] - logtot);
+            last = e;
+        }
+        bnd.cum[e] = c;
+    }
+    for (int e = last; e < bnd.n_ell; ++e) bnd.cum[e] = 1.0;
+    return true;
 }
 
 // Draws n candidates from bnd (NULL: the first live points, uniform in the
-// cube), evaluates them and returns their unit-cube coordinates u [n][d] and
-// log-likelihoods; floor is the lowest live log-likelihood when the round
-// starts (candidates at or below it cannot be accepted in this round).
+// cube), evaluates them and returns their unit-cube coordinates u [n][d],
+// log-likelihoods, and the mode of the ellipsoid each was drawn from (-1 for
+// a draw from the whole cube); floor is the lowest live log-likelihood when
+// the round starts (candidates at or below it cannot be accepted in this
+// round).
 using DrawEval = std::function<gk_status(const Bound *bnd, int n, int64_t round, double floor,
-                                         double *u, double *logl)>;
+                                         double *u, double *logl, int *mode)>;
 
-// True if x lies in ellipsoid e of bnd.
-__host__ __device__ inline bool in_ellipsoid(const Bound &bnd, int e, const double *x)
+// Mahalanobis radius^2 of x in ellipsoid e of bnd (<= 1 inside).
+__host__ __device__ inline double ellipsoid_m2(const Bound &bnd, int e, const double *x)
 {
     const int d = bnd.d;
     double y[GK_NP], m2 = 0.0;
@@ -247,19 +446,26 @@ __host__ __device__ inline bool in_ellipsoid(const Bound &bnd, int e, const doub
         y[a] = t * bnd.inv_diag[e][a];
         m2 += y[a] * y[a];
     }
-    return m2 <= 1.0;
+    return m2;
+}
+
+// True if x lies in ellipsoid e of bnd.
+__host__ __device__ inline bool in_ellipsoid(const Bound &bnd, int e, const double *x)
+{
+    return ellipsoid_m2(bnd, e, x) <= 1.0;
 }
 
 // Candidates from bnd with a sequential Philox stream (host side): pick an
 // ellipsoid by volume, a direction from d normals and a radius U^(1/d);
-// reject outside the cube, and keep a point lying in q ellipsoids with
-// probability 1/q (uniform over the union).  After 10^5 rejections, uniform
-// in the cube.
-void draw_host(const Bound *bnd, int n, int d, Rng &rng, double *ub)
+// reject outside the cube, and keep a point lying in q ellipsoids of the
+// picked one's mode with probability 1/q (uniform over that mode's union).
+// After 10^5 rejections, uniform in the cube.
+void draw_host(const Bound *bnd, int n, int d, Rng &rng, double *ub, int *mode)
 {
     double z[GK_NP];
     for (int c = 0; c < n; ++c) {
         double *u = ub + (size_t)c * d;
+        mode[c] = -1;
         for (int tries = 0;; ++tries) {
             if (!bnd || bnd->n_ell == 0 || tries > 100000) {
                 for (int a = 0; a < d; ++a) u[a] = rng.uniform();
@@ -286,9 +492,11 @@ void draw_host(const Bound *bnd, int n, int d, Rng &rng, double *ub)
             if (!inside) continue;
             if (bnd->n_ell > 1) {
                 int q = 1;
-                for (int f = 0; f < bnd->n_ell; ++f) q += f != e && in_ellipsoid(*bnd, f, u);
+                for (int f = 0; f < bnd->n_ell; ++f)
+                    q += f != e && bnd->mode[f] == bnd->mode[e] && in_ellipsoid(*bnd, f, u);
                 if (q > 1 && !(rng.uniform() * q < 1.0)) continue;
             }
+            mode[c] = bnd->mode[e];
             break;
         }
     }
@@ -347,20 +555,26 @@ class Worker {
 };
 
 // Runs the sampler in the unit cube [0,1]^d.  Fills the evidence fields of
-// res, best[] in unit-cube coordinates, and the posterior samples post_u
-// [M][d] with normalised weights post_w [M].
+// res, best[] in unit-cube coordinates, the posterior samples post_u [M][d]
+// with normalised weights post_w [M] and their modes post_mode [M], and the
+// final modes (split ones included, with n = 0 live points after the split).
 gk_status ns_run(int d, const DrawEval &draw_eval, const gk_ns_opts &o, gk_ns_result *res,
-                 std::vector<double> &post_u, std::vector<double> &post_w, bool &capped)
+                 std::vector<double> &post_u, std::vector<double> &post_w,
+                 std::vector<int> &post_mode, std::vector<Mode> &modes, bool &capped)
 {
     const int N = o.n_live, Bmax = std::max(o.batch, o.batch_max);
+    const bool separate = o.separate_modes != 0;
     std::vector<double> live_u((size_t)N * d), live_l(N);
+    std::vector<int> live_mode(N, 0);
     std::vector<double> ub((size_t)std::max(N, Bmax) * d), lb(std::max(N, Bmax));
+    std::vector<int> mb(std::max(N, Bmax));
     int B = o.batch;
     double acc_prev = -1.0, cand_prev = 0.0;  // acceptances and candidates of the last round
-    GK_TRY(draw_eval(nullptr, N, 0, -DBL_MAX, live_u.data(), lb.data()));
+    GK_TRY(draw_eval(nullptr, N, 0, -DBL_MAX, live_u.data(), lb.data(), mb.data()));
     int64_t n_evals = N, n_launch = 1;
     for (int i = 0; i < N; ++i) live_l[i] = std::isfinite(lb[i]) ? lb[i] : -DBL_MAX;
     std::vector<double> dead_u, dead_l, dead_logwt;
+    std::vector<int> dead_mode;
     double logz = -INFINITY, max_logl = -INFINITY;
     std::vector<double> best(d, 0.0);
     for (int i = 0; i < N; ++i)
@@ -368,70 +582,170 @@ gk_status ns_run(int d, const DrawEval &draw_eval, const gk_ns_opts &o, gk_ns_re
             max_logl = live_l[i];
             std::copy_n(&live_u[(size_t)i * d], d, best.begin());
         }
-    // min-heap of (logl, index): the lowest live point, ties to the lowest index
-    std::vector<std::pair<double, int>> heap(N);
-    for (int i = 0; i < N; ++i) heap[i] = {live_l[i], i};
-    std::make_heap(heap.begin(), heap.end(), std::greater<>());
-    const double log_shrink = std::log1p(-std::exp(-1.0 / N));  // log(1 - e^{-1/N})
+    modes.assign(1, Mode{});
+    modes[0].n = N;
+    modes[0].lmax = max_logl;
+    // per mode, a min-heap of (logl, index): its lowest live point, ties to the lowest index
+    std::vector<std::vector<std::pair<double, int>>> heaps(1);
+    auto make_heaps = [&] {
+        heaps.assign(modes.size(), {});
+        for (int i = 0; i < N; ++i) heaps[live_mode[i]].push_back({live_l[i], i});
+        for (auto &h : heaps) std::make_heap(h.begin(), h.end(), std::greater<>());
+    };
+    make_heaps();
+    std::vector<double> log_shrink(1, std::log1p(-std::exp(-1.0 / N)));  // log(1 - e^{-1/n})
     int64_t k = 0;
     bool done = false;
     capped = false;
-    // The bound is rebuilt after every N/20 retired points.  The first one is
+    auto lowest_live = [&] {
+        double f = DBL_MAX;
+        for (size_t m = 0; m < modes.size(); ++m)
+            if (!heaps[m].empty()) f = std::min(f, heaps[m].front().first);
+        return f;
+    };
+    // A mode is finished when its remaining evidence, at most L_max X, is
+    // below (e^tol - 1) Z / (number of modes), so that the sum over modes
+    // meets the stopping rule log(Z + sum L_max X) - log Z < tol.
+    auto check_finished = [&] {
+        int leaves = 0;
+        for (auto &md : modes) leaves += !md.split;
+        bool all = true;
+        for (auto &md : modes) {
+            if (md.split || md.finished) continue;
+            if (logaddexp(logz, std::log((double)leaves) + md.lmax + md.logX()) - logz < o.tol)
+                md.finished = true;
+            else
+                all = false;
+        }
+        return all;
+    };
+    // The region is rebuilt after every N/20 retired points.  The first one is
     // built before the first round; later ones are built on a worker thread
     // from the live points at the start of a round, while that round is drawn
-    // and evaluated, and are used from the next round on.  A bound one round
+    // and evaluated, and are used from the next round on.  A region one round
     // old still contains the current, smaller constrained region, so it stays
-    // valid, only less tight.
+    // valid, only less tight.  Mode splits it finds take effect when it is
+    // installed: the split mode's live points and this round's candidates
+    // drawn from it pass to the child modes.
     const int64_t rebuild = std::max(1, N / 20);
-    Bound bnd{}, next{};
-    build_bound(live_u.data(), N, d, o.enlarge, 0.0, o.max_ell, bnd);
+    Region cur{}, next{};
+    auto install = [&](Region &r, int ncand) {
+        for (const ModeSplit &sp : r.splits) {
+            // (modes grows below: copy what the children need from the parent)
+            const Mode par = modes[sp.parent];
+            const double logz_par = logaddexp(par.logz_inh, par.logz_own);
+            const int first = (int)modes.size();
+            for (const auto &ch : sp.children) {
+                Mode c;
+                c.n = (int)ch.size();
+                c.logX0 = par.logX() + std::log((double)c.n / par.n);
+                c.logz_inh = logz_par + std::log((double)c.n / par.n);
+                for (int i : ch) {
+                    live_mode[i] = (int)modes.size();
+                    c.lmax = std::max(c.lmax, live_l[i]);
+                }
+                modes.push_back(c);
+                log_shrink.push_back(std::log1p(-std::exp(-1.0 / c.n)));
+            }
+            modes[sp.parent].split = true;
+            // this round's candidates from the split mode: the child whose
+            // ellipsoid holds them, else the one whose ellipsoid is nearest
+            for (int c = 0; c < ncand; ++c) {
+                if (mb[c] != sp.parent) continue;
+                double best_m2 = INFINITY;
+                int to = first;
+                for (int e = 0; e < r.bnd.n_ell; ++e) {
+                    if (r.bnd.mode[e] < first || r.bnd.mode[e] >= (int)modes.size()) continue;
+                    const double m2 = ellipsoid_m2(r.bnd, e, &ub[(size_t)c * d]);
+                    if (m2 < best_m2) {
+                        best_m2 = m2;
+                        to = r.bnd.mode[e];
+                    }
+                }
+                mb[c] = to;
+            }
+        }
+        if (!r.splits.empty()) make_heaps();
+        cur = r;
+    };
+    build_region(live_u.data(), live_mode.data(), N, d, modes, o.enlarge, o.max_ell, separate, next);
+    install(next, 0);
     int64_t k_built = 0;
     Worker worker;
+    Bound draw{};
     while (!done) {
         const bool building = k - k_built >= rebuild;
         bool build_failed = false;
         if (building) {
-            const double logX = -(double)k / N;
-            worker.submit([&, logX] {
+            worker.submit([&] {
                 try {
-                    build_bound(live_u.data(), N, d, o.enlarge, logX, o.max_ell, next);
+                    build_region(live_u.data(), live_mode.data(), N, d, modes, o.enlarge, o.max_ell,
+                                 separate, next);
                 } catch (const std::bad_alloc &) {
                     build_failed = true;
                 }
             });
         }
-        const gk_status st = draw_eval(&bnd, B, n_launch, heap.front().first, ub.data(), lb.data());
+        draw = cur.bnd;
+        const bool any = draw.n_ell == 0 || set_draw_weights(draw, modes);
+        gk_status st = GK_OK;
+        if (any) st = draw_eval(&draw, B, n_launch, lowest_live(), ub.data(), lb.data(), mb.data());
         if (building) {  // the live points change below: the build must be over
             worker.wait();
-            bnd = next;
+            if (!build_failed) install(next, any ? B : 0);
             k_built = k;
         }
         GK_TRY(st);
         if (build_failed) return fail(GK_ENOMEM, "out of host memory building the bound");
+        if (!any) break;  // every mode finished
         n_evals += B;
         ++n_launch;
         const int64_t k_round = k;
         for (int c = 0; c < B && !done; ++c) {
             const double lc = std::isfinite(lb[c]) ? lb[c] : -DBL_MAX;
-            const int imin = heap.front().second;
+            int m = mb[c];
+            if (modes.size() == 1) {
+                m = 0;
+            } else if (m < 0 || m >= (int)modes.size() || modes[m].split) {
+                // a draw from the whole cube: the mode whose live point is nearest
+                double bd = INFINITY;
+                m = 0;
+                for (int i = 0; i < N; ++i) {
+                    double s = 0.0;
+                    for (int a = 0; a < d; ++a) {
+                        const double t = ub[(size_t)c * d + a] - live_u[(size_t)i * d + a];
+                        s += t * t;
+                    }
+                    if (s < bd) {
+                        bd = s;
+                        m = live_mode[i];
+                    }
+                }
+            }
+            auto &hp = heaps[m];
+            const int imin = hp.front().second;
             if (!(lc > live_l[imin])) continue;
-            std::pop_heap(heap.begin(), heap.end(), std::greater<>());
-            heap.back() = {lc, imin};
-            std::push_heap(heap.begin(), heap.end(), std::greater<>());
+            std::pop_heap(hp.begin(), hp.end(), std::greater<>());
+            hp.back() = {lc, imin};
+            std::push_heap(hp.begin(), hp.end(), std::greater<>());
             ++k;
-            const double logwt = live_l[imin] + (-(double)(k - 1) / N + log_shrink);
+            Mode &md = modes[m];
+            const double logwt = live_l[imin] + md.logX() + log_shrink[m];
+            md.j += 1;
+            md.logz_own = logaddexp(md.logz_own, logwt);
             logz = logaddexp(logz, logwt);
             dead_u.insert(dead_u.end(), &live_u[(size_t)imin * d], &live_u[(size_t)imin * d] + d);
             dead_l.push_back(live_l[imin]);
             dead_logwt.push_back(logwt);
+            dead_mode.push_back(m);
             std::copy_n(&ub[(size_t)c * d], d, &live_u[(size_t)imin * d]);
             live_l[imin] = lc;
+            md.lmax = std::max(md.lmax, lc);
             if (lc > max_logl) {
                 max_logl = lc;
                 std::copy_n(&ub[(size_t)c * d], d, best.begin());
             }
-            // the retired point is the lowest, so the live maximum is the running one
-            if (logaddexp(logz, max_logl - (double)k / N) - logz < o.tol) done = true;
+            if (check_finished()) done = true;
             if (k >= o.max_iter) {
                 done = true;
                 capped = true;
@@ -447,21 +761,32 @@ gk_status ns_run(int d, const DrawEval &draw_eval, const gk_ns_opts &o, gk_ns_re
             B = (int)std::min<double>(Bmax, std::max<double>(o.batch, want));
         }
     }
-    // final live points with weight X_k / N
+    // final live points of each mode with weight X_m / n_m
     for (int i = 0; i < N; ++i) {
-        const double logwt = live_l[i] - (double)k / N - std::log((double)N);
+        Mode &md = modes[live_mode[i]];
+        const double logwt = live_l[i] + md.logX() - std::log((double)md.n);
+        md.logz_own = logaddexp(md.logz_own, logwt);
         logz = logaddexp(logz, logwt);
         dead_u.insert(dead_u.end(), &live_u[(size_t)i * d], &live_u[(size_t)i * d] + d);
         dead_l.push_back(live_l[i]);
         dead_logwt.push_back(logwt);
+        dead_mode.push_back(live_mode[i]);
     }
     double H = 0.0;
     post_u.swap(dead_u);
+    post_mode.swap(dead_mode);
     post_w.resize(dead_l.size());
     for (size_t i = 0; i < dead_l.size(); ++i) {
         const double pw = std::exp(dead_logwt[i] - logz);
         if (pw > 0.0 && dead_l[i] > -DBL_MAX) H += pw * (dead_l[i] - logz);
         post_w[i] = pw;
+    }
+    // per-mode information over the mode's own points, normalised by their evidence
+    std::vector<double> Hm(modes.size(), 0.0);
+    for (size_t i = 0; i < dead_l.size(); ++i) {
+        const Mode &md = modes[post_mode[i]];
+        const double pw = std::exp(dead_logwt[i] - md.logz_own);
+        if (pw > 0.0 && dead_l[i] > -DBL_MAX) Hm[post_mode[i]] += pw * (dead_l[i] - md.logz_own);
     }
     res->logz = logz;
     res->info_h = H;
@@ -471,27 +796,50 @@ gk_status ns_run(int d, const DrawEval &draw_eval, const gk_ns_opts &o, gk_ns_re
     res->n_evals = n_evals;
     res->n_launches = n_launch;
     for (int a = 0; a < d; ++a) res->best[a] = best[a];
+    int nm = 0;
+    for (size_t m = 0; m < modes.size() && nm < kMaxModes; ++m) {
+        if (modes[m].split) continue;
+        gk_ns_mode &r = res->modes[nm++];
+        r.logz = logaddexp(modes[m].logz_inh, modes[m].logz_own);
+        r.info_h = Hm[m];
+        r.logz_err = std::sqrt(std::max(Hm[m], 0.0) / modes[m].n);
+        r.n_live = modes[m].n;
+    }
+    res->n_modes = nm;
     return GK_OK;
 }
 
-// Weighted mean, sd and quantiles of coordinate a of the posterior.
-void posterior_stats(const std::vector<double> &pu, const std::vector<double> &pw, int d, int a,
-                     double scale, double offset, gk_ns_result *res, int slot)
+// Posterior summaries of one parameter: mean, sd and the 16/50/84% quantiles.
+struct StatOut {
+    double *mean, *sd, *q16, *median, *q84;
+};
+
+// Weighted mean, sd and quantiles of coordinate a of the posterior points
+// whose mode is `mode` (every point for mode < 0), x = offset + scale u;
+// writes element `slot` of each output.
+void posterior_stats(const std::vector<double> &pu, const std::vector<double> &pw,
+                     const std::vector<int> &pmode, int mode, int d, int a, double scale,
+                     double offset, const StatOut &out, int slot)
 {
     std::vector<std::pair<double, double>> v;
     v.reserve(pw.size());
     double m = 0.0, w = 0.0;
     for (size_t i = 0; i < pw.size(); ++i) {
+        if (mode >= 0 && pmode[i] != mode) continue;
         const double x = offset + scale * pu[i * d + a];
         v.emplace_back(x, pw[i]);
         m += pw[i] * x;
         w += pw[i];
     }
+    if (v.empty() || !(w > 0.0)) {
+        out.mean[slot] = out.sd[slot] = out.q16[slot] = out.median[slot] = out.q84[slot] = NAN;
+        return;
+    }
     m /= w;
     double var = 0.0;
     for (auto &x : v) var += x.second * (x.first - m) * (x.first - m);
-    res->mean[slot] = m;
-    res->sd[slot] = std::sqrt(var / w);
+    out.mean[slot] = m;
+    out.sd[slot] = std::sqrt(var / w);
     std::sort(v.begin(), v.end());
     auto quant = [&](double q) {
         double c = 0.0;
@@ -506,16 +854,47 @@ void posterior_stats(const std::vector<double> &pu, const std::vector<double> &p
         }
         return v.back().first;
     };
-    res->q16[slot] = quant(0.16);
-    res->median[slot] = quant(0.5);
-    res->q84[slot] = quant(0.84);
+    out.q16[slot] = quant(0.16);
+    out.median[slot] = quant(0.5);
+    out.q84[slot] = quant(0.84);
+}
+
+// The whole posterior's summaries of coordinate a into res, and each final
+// mode's (in the order of res->modes) into res->modes[].
+void all_stats(const std::vector<double> &pu, const std::vector<double> &pw,
+               const std::vector<int> &pmode, const std::vector<Mode> &modes, int d, int a,
+               double scale, double offset, gk_ns_result *res, int slot)
+{
+    posterior_stats(pu, pw, pmode, -1, d, a, scale, offset,
+                    StatOut{res->mean, res->sd, res->q16, res->median, res->q84}, slot);
+    int k = 0;
+    for (int m = 0; m < (int)modes.size() && k < res->n_modes; ++m) {
+        if (modes[m].split) continue;
+        gk_ns_mode &r = res->modes[k++];
+        posterior_stats(pu, pw, pmode, m, d, a, scale, offset,
+                        StatOut{r.mean, r.sd, r.q16, r.median, r.q84}, slot);
+    }
+}
+
+// Posterior points of each final mode (weights above zero).
+void mode_counts(const std::vector<double> &pw, const std::vector<int> &pmode,
+                 const std::vector<Mode> &modes, gk_ns_result *res)
+{
+    int k = 0;
+    for (int m = 0; m < (int)modes.size() && k < res->n_modes; ++m) {
+        if (modes[m].split) continue;
+        int64_t c = 0;
+        for (size_t i = 0; i < pw.size(); ++i) c += pmode[i] == m && pw[i] > 0.0;
+        res->modes[k++].n_samples = c;
+    }
 }
 
 gk_status check_opts(const gk_ns_opts &o)
 {
     if (o.n_live < 2 || o.batch < 1 || o.max_iter < 1 || !(o.enlarge >= 1.0) || !(o.tol > 0.0) ||
         o.max_ell < 1 || o.max_ell > kMaxEll || (o.batch_max != 0 && o.batch_max < o.batch) ||
-        o.accept_target < 0 || !(o.screen_cost >= 0.0) || o.screen_rows < 0)
+        o.accept_target < 0 || !(o.screen_cost >= 0.0) || o.screen_rows < 0 ||
+        (o.separate_modes != 0 && o.separate_modes != 1))
         return fail(GK_EINVAL, "invalid nested-sampling options");
     return GK_OK;
 }
@@ -543,6 +922,7 @@ extern "C" gk_status gk_ns_default_opts(gk_ns_opts *o)
     o->accept_target = 0;
     o->screen_cost = 0.0;
     o->screen_rows = 0;
+    o->separate_modes = 0;
     return GK_OK;
 }
 
@@ -561,9 +941,9 @@ extern "C" gk_status gk_nested_sample(int32_t dim, const double *lo, const doubl
         if (!(hi[a] > lo[a])) return fail(GK_EINVAL, "empty prior range in dimension %d", a);
     std::vector<double> theta;
     Rng rng(o.seed, 0x6e73u);
-    DrawEval eval = [&](const Bound *bnd, int n, int64_t, double, double *u,
-                        double *logl) -> gk_status {
-        draw_host(bnd, n, dim, rng, u);
+    DrawEval eval = [&](const Bound *bnd, int n, int64_t, double, double *u, double *logl,
+                        int *mode) -> gk_status {
+        draw_host(bnd, n, dim, rng, u, mode);
         theta.resize((size_t)n * dim);
         for (int i = 0; i < n; ++i)
             for (int a = 0; a < dim; ++a)
@@ -574,12 +954,15 @@ extern "C" gk_status gk_nested_sample(int32_t dim, const double *lo, const doubl
     };
     std::memset(res, 0, sizeof *res);
     std::vector<double> pu, pw;
+    std::vector<int> pm;
+    std::vector<Mode> modes;
     bool capped = false;
-    GK_TRY(ns_run(dim, eval, o, res, pu, pw, capped));
+    GK_TRY(ns_run(dim, eval, o, res, pu, pw, pm, modes, capped));
     for (int a = 0; a < dim; ++a) {
         res->best[a] = lo[a] + res->best[a] * (hi[a] - lo[a]);
-        posterior_stats(pu, pw, dim, a, hi[a] - lo[a], lo[a], res, a);
+        all_stats(pu, pw, pm, modes, dim, a, hi[a] - lo[a], lo[a], res, a);
     }
+    mode_counts(pw, pm, modes, res);
     if (samples && n_samples) {
         const int64_t n = std::min<int64_t>(cap, (int64_t)pw.size());
         for (int64_t i = 0; i < n; ++i) {
@@ -605,7 +988,7 @@ namespace {
 // the seed (high word xor a tag), one per (candidate, round, trial); normals
 // by Box-Muller (both outputs).  Same rule as draw_host: ellipsoid by volume,
 // direction from d normals, radius U^(1/d), rejected outside the cube and
-// kept with probability 1/q where q ellipsoids overlap.
+// kept with probability 1/q where q ellipsoids of its mode overlap.
 // ---------------------------------------------------------------------------
 struct DrawArgs {
     const Bound *bnd;  // device copy of the round's region
@@ -616,6 +999,7 @@ struct DrawArgs {
     double lo[GK_NP], span[GK_NP], fixed[GK_NP];
     double *u;     // [n][d]
     double *rows;  // [n][GK_NP]
+    int *mode;     // [n]: mode of the ellipsoid drawn from, -1 for the whole cube
 };
 
 struct DevStream {
@@ -644,8 +1028,9 @@ struct DevStream {
 // One wave per candidate: the 64 lanes make independent trials (lane l of
 // attempt t uses counter (c, r, l + 256 t, block)) and the lowest lane whose
 // trial is accepted supplies the candidate -- the first success of trials
-// taken in lane order, so the candidate is uniform over the region.  After
-// 156 attempts (~10^4 trials) lane 0 draws uniformly in the cube.
+// taken in lane order, so the candidate is uniform over its mode's part of
+// the region, and the mode is picked in proportion to that part's volume.
+// After 156 attempts (~10^4 trials) lane 0 draws uniformly in the cube.
 __global__ __launch_bounds__(256) void k_ns_draw(DrawArgs g)
 {
     const int c = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
@@ -653,7 +1038,7 @@ __global__ __launch_bounds__(256) void k_ns_draw(DrawArgs g)
     const int d = g.d;
     double x[GK_NP], z[GK_NP];
     bool drawn = false;
-    int attempt = 0;
+    int attempt = 0, mode = -1;
     auto stream = [&](int t) {
         DevStream rs;
         rs.ctr[0] = (uint32_t)c;
@@ -695,13 +1080,15 @@ __global__ __launch_bounds__(256) void k_ns_draw(DrawArgs g)
             }
             if (ok && bnd.n_ell > 1) {
                 int q = 1;
-                for (int f = 0; f < bnd.n_ell; ++f) q += f != e && in_ellipsoid(bnd, f, x);
+                for (int f = 0; f < bnd.n_ell; ++f)
+                    q += f != e && bnd.mode[f] == bnd.mode[e] && in_ellipsoid(bnd, f, x);
                 ok = q == 1 || rs.uniform() * q < 1.0;
             }
             const unsigned long long hits = __ballot(ok);
             if (hits) {  // uniform over the wave
                 drawn = lane == __ffsll((long long)hits) - 1;
                 if (!drawn) return;
+                mode = bnd.mode[e];
                 break;
             }
         }
@@ -711,6 +1098,7 @@ __global__ __launch_bounds__(256) void k_ns_draw(DrawArgs g)
         DevStream rs = stream(attempt);
         for (int a = 0; a < d; ++a) x[a] = rs.uniform();
     }
+    g.mode[c] = mode;
     double *row = g.rows + (size_t)c * GK_NP;
     for (int k = 0; k < GK_NP; ++k) row[k] = g.fixed[k];
     for (int a = 0; a < d; ++a) {
@@ -732,7 +1120,7 @@ __global__ void k_gather_rows(const double *__restrict__ src, const int *__restr
 // Device buffers of one fit, freed on scope exit.
 struct NsBuffers {
     double *d_u = nullptr, *d_rows2 = nullptr, *h_u = nullptr;
-    int *d_idx = nullptr, *h_idx = nullptr;
+    int *d_idx = nullptr, *h_idx = nullptr, *d_mode = nullptr, *h_mode = nullptr;
     Bound *d_bnd = nullptr, *h_bnd = nullptr;
     ~NsBuffers()
     {
@@ -741,8 +1129,10 @@ struct NsBuffers {
         (void)hipFree(d_u);
         (void)hipFree(d_rows2);
         (void)hipFree(d_idx);
+        (void)hipFree(d_mode);
         if (h_u) (void)hipHostFree(h_u);
         if (h_idx) (void)hipHostFree(h_idx);
+        if (h_mode) (void)hipHostFree(h_mode);
     }
 };
 
@@ -799,6 +1189,8 @@ gk_status fit_nested(gk_model *m, gk_surrogate *sur, const double *lo, const dou
     HIP_TRY(hipMalloc((void **)&nb.d_bnd, sizeof(Bound)));
     HIP_TRY(hipHostMalloc((void **)&nb.h_bnd, sizeof(Bound), 0));
     HIP_TRY(hipHostMalloc((void **)&nb.h_u, sizeof(double) * rows * d, 0));
+    HIP_TRY(hipMalloc((void **)&nb.d_mode, sizeof(int) * rows));
+    HIP_TRY(hipHostMalloc((void **)&nb.h_mode, sizeof(int) * rows, 0));
     if (sur) {
         HIP_TRY(hipMalloc((void **)&nb.d_rows2, sizeof(double) * rows * NPAR));
         HIP_TRY(hipMalloc((void **)&nb.d_idx, sizeof(int) * rows));
@@ -815,7 +1207,7 @@ gk_status fit_nested(gk_model *m, gk_surrogate *sur, const double *lo, const dou
     double pass_frac = 0.0;  // of the last screened round
     int since_screen = 8;    // rounds since the last screened one (the first is screened)
     DrawEval eval = [&](const Bound *bnd, int n, int64_t round, double floor, double *u,
-                        double *logl) -> gk_status {
+                        double *logl, int *mode) -> gk_status {
         g.n = n;
         g.d = d;
         g.round = (uint64_t)round;
@@ -828,9 +1220,11 @@ gk_status fit_nested(gk_model *m, gk_surrogate *sur, const double *lo, const dou
         g.bnd = nb.d_bnd;
         g.u = nb.d_u;
         g.rows = d_params;
+        g.mode = nb.d_mode;
         hipLaunchKernelGGL(k_ns_draw, dim3((n + 3) / 4), dim3(256), 0, stream, g);
         HIP_TRY(hipGetLastError());
         HIP_TRY(hipMemcpyAsync(nb.h_u, nb.d_u, sizeof(double) * n * d, hipMemcpyDeviceToHost, stream));
+        HIP_TRY(hipMemcpyAsync(nb.h_mode, nb.d_mode, sizeof(int) * n, hipMemcpyDeviceToHost, stream));
         for (int i = 0; i < n; ++i) logl[i] = -INFINITY;
         // screen this round only where the plain evaluations it saves (at the
         // last screened round's pass fraction) outweigh its own cost
@@ -843,6 +1237,7 @@ gk_status fit_nested(gk_model *m, gk_surrogate *sur, const double *lo, const dou
             HIP_TRY(hipMemcpyAsync(h_chi2, d_chi2, sizeof(double) * n, hipMemcpyDeviceToHost, stream));
             HIP_TRY(wait(stream));
             std::memcpy(u, nb.h_u, sizeof(double) * n * d);
+            std::memcpy(mode, nb.h_mode, sizeof(int) * n);
             n_plain += n;
             for (int i = 0; i < n; ++i) logl[i] = -0.5 * h_chi2[i];
             return GK_OK;
@@ -852,6 +1247,7 @@ gk_status fit_nested(gk_model *m, gk_surrogate *sur, const double *lo, const dou
         HIP_TRY(hipMemcpyAsync(h_chi2s, d_chi2s, sizeof(double) * n, hipMemcpyDeviceToHost, stream));
         HIP_TRY(wait(stream));
         std::memcpy(u, nb.h_u, sizeof(double) * n * d);
+        std::memcpy(mode, nb.h_mode, sizeof(int) * n);
         const double chi2_floor = floor > -DBL_MAX ? -2.0 * floor : INFINITY;
         const double cut = chi2_floor + shift + margin;
         keep.clear();
@@ -917,8 +1313,10 @@ gk_status fit_nested(gk_model *m, gk_surrogate *sur, const double *lo, const dou
         return GK_OK;
     };
     std::vector<double> pu, pw;
+    std::vector<int> pm;
+    std::vector<Mode> modes;
     bool capped = false;
-    GK_TRY(ns_run(d, eval, o, res, pu, pw, capped));
+    GK_TRY(ns_run(d, eval, o, res, pu, pw, pm, modes, capped));
     res->n_evals = n_plain;  // plain evaluations only
     res->t_wall_s = std::chrono::duration<double>(clock::now() - t_start).count();
     res->t_wait_s = t_wait;
@@ -927,12 +1325,18 @@ gk_status fit_nested(gk_model *m, gk_surrogate *sur, const double *lo, const dou
     for (int k = 0; k < NPAR; ++k) {
         res->best[k] = res->mean[k] = res->median[k] = res->q16[k] = res->q84[k] = fixed[k];
         res->sd[k] = 0.0;
+        for (int j = 0; j < res->n_modes; ++j) {
+            gk_ns_mode &r = res->modes[j];
+            r.mean[k] = r.median[k] = r.q16[k] = r.q84[k] = fixed[k];
+            r.sd[k] = 0.0;
+        }
     }
     for (int a = 0; a < d; ++a) {
         const int k = g.fr[a];
         res->best[k] = lo[k] + best_u[a] * (hi[k] - lo[k]);
-        posterior_stats(pu, pw, d, a, hi[k] - lo[k], lo[k], res, k);
+        all_stats(pu, pw, pm, modes, d, a, hi[k] - lo[k], lo[k], res, k);
     }
+    mode_counts(pw, pm, modes, res);
     if (samples && n_samples) {
         const int64_t n = std::min<int64_t>(cap, (int64_t)pw.size());
         for (int64_t i = 0; i < n; ++i) {

@@ -84,7 +84,17 @@ class NSOpts(ctypes.Structure):
                 ("enlarge", ctypes.c_double), ("tol", ctypes.c_double), ("seed", ctypes.c_uint64),
                 ("max_ell", ctypes.c_int32), ("batch_max", ctypes.c_int32),
                 ("accept_target", ctypes.c_int32), ("screen_cost", ctypes.c_double),
-                ("screen_rows", ctypes.c_int32)]
+                ("screen_rows", ctypes.c_int32), ("separate_modes", ctypes.c_int32)]
+
+
+NS_MAX_MODES = 8  # GK_NS_MAX_MODES
+
+
+class NSMode(ctypes.Structure):
+    _fields_ = [("logz", ctypes.c_double), ("logz_err", ctypes.c_double),
+                ("info_h", ctypes.c_double), ("n_live", ctypes.c_int64),
+                ("n_samples", ctypes.c_int64)] + [
+                (n, ctypes.c_double * NPAR) for n in ("mean", "sd", "median", "q16", "q84")]
 
 
 class NSResult(ctypes.Structure):
@@ -94,7 +104,9 @@ class NSResult(ctypes.Structure):
                 ("n_launches", ctypes.c_int64)] + [
                 (n, ctypes.c_double * NPAR) for n in ("best", "mean", "sd", "median", "q16", "q84")] + [
                 (n, ctypes.c_int64) for n in ("n_screened", "n_rejected", "n_audited", "n_audit_miss")] + [
-                ("t_wall_s", ctypes.c_double), ("t_wait_s", ctypes.c_double)]
+                ("t_wall_s", ctypes.c_double), ("t_wait_s", ctypes.c_double),
+                ("n_modes", ctypes.c_int32), ("reserved_modes", ctypes.c_int32),
+                ("modes", NSMode * NS_MAX_MODES)]
 
 
 class TuneResult(ctypes.Structure):
@@ -142,6 +154,14 @@ def _ns_dict(r: "NSResult", st: int, dim: int, samples=None) -> dict:
            "n_audit_miss": r.n_audit_miss, "t_wall_s": r.t_wall_s, "t_wait_s": r.t_wait_s}
     for n in ("best", "mean", "sd", "median", "q16", "q84"):
         out[n] = np.array(getattr(r, n)[:dim])
+    out["modes"] = []
+    for k in range(r.n_modes):
+        md = r.modes[k]
+        e = {"logz": md.logz, "logz_err": md.logz_err, "info_h": md.info_h,
+             "n_live": md.n_live, "n_samples": md.n_samples}
+        for n in ("mean", "sd", "median", "q16", "q84"):
+            e[n] = np.array(getattr(md, n)[:dim])
+        out["modes"].append(e)
     if samples is not None:
         out["samples"] = samples
     return out

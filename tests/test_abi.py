@@ -33,7 +33,7 @@ STRUCTS = [("ModelDesc", "gk_model_desc"), ("ProfileStats", "gk_profile_stats"),
            ("LMOpts", "gk_lm_opts"), ("LMResult", "gk_lm_result"), ("NSOpts", "gk_ns_opts"),
            ("NSResult", "gk_ns_result"), ("GridResult", "gk_grid_result"),
            ("SurrogateOpts", "gk_surrogate_opts"), ("LineOpts", "gk_line_opts"),
-           ("TuneResult", "gk_tune_result")]
+           ("TuneResult", "gk_tune_result"), ("NSMode", "gk_ns_mode")]
 
 
 def test_binding_structs_match_the_header(tmp_path):

@@ -299,3 +299,52 @@ def test_nested_sampling_fabry_perot_128x128x48(O, gbk):
     assert r["status"] == 0
     assert inside >= 6
     assert abs(r["mean"][I.I0] - 1.25) < 0.1 and abs(r["sd"][I.I0] - 1.5 / math.sqrt(12)) < 0.06
+
+
+def test_nested_sampling_mode_separation_device_draws(O, gbk):
+    """Clustered nested sampling through the device draws (Sec. 2.3.2) on an
+    exactly bimodal posterior: in a velocity field (Sec. 2.2.1) turning the
+    position angle by 180 degrees and flipping the sign of Vt gives the same
+    map, so with PA free over a full turn and Vt over [-300, 300] the
+    posterior has two mirror modes of equal evidence.  With mode separation
+    the sampler finds both: local evidences equal to each other and to half
+    the total, means at (PA, Vt) and (PA + 180, -Vt) with the same i and
+    Vsys, and the total equal to the evidence of the half box Vt > 0 (twice
+    the prior density over half the volume)."""
+    side = 64
+    grid = I.ghasp_grid(side)
+    truth = I.ghasp_draw(I.rng_for(6, 9, 0), 1, side)[0]
+    truth[I.PA], truth[I.VT], truth[I.VSYS] = 100.0, 180.0, 1500.0
+    from test_gpu_vfield import vf_obs
+    obs = vf_obs(O, grid, truth, 9, noise=5.0, random_mask=I.GHASP_HOLES)
+    m = gbk.Model.from_grid(grid)
+    m.set_obs(obs)
+    free = [0, 0, 1, 1, 1, 1, 0, 0, 0, 0, 0, 0]
+    lo, hi = truth.copy(), truth.copy()
+    lo[I.PA], hi[I.PA] = 0.0, 360.0
+    lo[I.INC], hi[I.INC] = 20.0, 80.0
+    lo[I.VSYS], hi[I.VSYS] = 1470.0, 1530.0
+    lo[I.VT], hi[I.VT] = -300.0, 300.0
+    r = m.fit_nested(lo, hi, free, truth, n_live=400, seed=21, separate_modes=1)
+    half_lo = lo.copy()
+    half_lo[I.VT] = 0.0
+    half = m.fit_nested(half_lo, hi, free, truth, n_live=400, seed=22)
+    print("logz", r["logz"], "+-", r["logz_err"], "half box", half["logz"], "+-", half["logz_err"],
+          "evals", r["n_evals"], half["n_evals"])
+    assert r["status"] == 0 and len(r["modes"]) == 2
+    a, b = sorted(r["modes"], key=lambda md: md["mean"][I.VT])
+    for md in (a, b):
+        print("  mode logz", md["logz"], "+-", md["logz_err"], "live", md["n_live"],
+              "mean", md["mean"][2:6], "sd", md["sd"][2:6])
+    assert abs(a["logz"] - b["logz"]) <= 3 * math.hypot(a["logz_err"], b["logz_err"])
+    for md in (a, b):
+        assert abs(md["logz"] - (r["logz"] - math.log(2.0))) <= 3 * md["logz_err"] + 0.05
+    assert abs(r["logz"] - half["logz"]) <= 3 * math.hypot(r["logz_err"], half["logz_err"])
+    assert b["mean"][I.VT] > 0 > a["mean"][I.VT]
+    sd = lambda k: math.hypot(a["sd"][k], b["sd"][k])
+    assert abs(abs(a["mean"][I.PA] - b["mean"][I.PA]) - 180.0) <= 3 * sd(I.PA)
+    assert abs(a["mean"][I.VT] + b["mean"][I.VT]) <= 3 * sd(I.VT)
+    for k in (I.INC, I.VSYS):
+        assert abs(a["mean"][k] - b["mean"][k]) <= 3 * sd(k)
+    for k in (I.PA, I.INC, I.VSYS, I.VT):
+        assert abs(b["median"][k] - half["median"][k]) <= 0.4 * half["sd"][k] + 1e-6, k
