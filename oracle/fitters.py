@@ -322,25 +322,31 @@ class GridResult:
 
 
 def nested_grid(chi2_fn, lo0, hi0, free, fixed, n=16, max_levels=3, accuracy=None) -> GridResult:
-    """Nested grids (Sec. 2.3.3): a regular grid of n nodes per free slot (end
-    points included) over the current box; the least-chi2 node (lowest linear
-    index on ties, first free slot varying slowest) centres the next box,
-    node +- one spacing clipped to the initial box.  Stops after max_levels or
-    when every spacing is below accuracy."""
+    """Nested grids (Sec. 2.3.3): a regular grid of n_k nodes along each free
+    slot k (end points included; n an int for every slot, or one count per
+    slot as the paper's per-parameter grids of Sec. 4) over the current box;
+    the least-chi2 node (lowest linear index on ties; the index is mixed
+    radix, first free slot varying slowest) centres the next box, node +- one
+    spacing clipped to the initial box.  Stops after max_levels or when every
+    spacing is below accuracy."""
     slots = [k for k in range(len(fixed)) if free[k]]
+    nk = {k: (n if np.isscalar(n) else int(n[k])) for k in slots}
     lo = np.array(lo0, dtype=np.float64).copy()
     hi = np.array(hi0, dtype=np.float64).copy()
     best_p, best_v, best_i, n_evals, level = None, math.inf, -1, 0, 0
     spacing = np.zeros(len(fixed))
+    total = 1
+    for k in slots:
+        total *= nk[k]
     for level in range(1, max_levels + 1):
-        step = {k: (hi[k] - lo[k]) / (n - 1) for k in slots}
+        step = {k: (hi[k] - lo[k]) / (nk[k] - 1) for k in slots}
         best_v, best_i = math.inf, -1
-        for L in range(n ** len(slots)):
+        for L in range(total):
             p = np.array(fixed, dtype=np.float64).copy()
             rem = L
             for k in reversed(slots):
-                p[k] = lo[k] + (rem % n) * step[k]
-                rem //= n
+                p[k] = lo[k] + (rem % nk[k]) * step[k]
+                rem //= nk[k]
             v = chi2_fn(p)
             n_evals += 1
             if v < best_v:

@@ -85,3 +85,32 @@ def test_nested_grid_accuracy_stop():
     r = F.nested_grid(lambda p: (p[0] - 0.25) ** 2, [0.0], [1.0], [1], [0.0], n=11,
                       max_levels=10, accuracy=[0.01])
     assert r.levels == 3 and r.spacing[0] < 0.01 and abs(r.best[0] - 0.25) <= r.spacing[0]
+
+
+def test_nested_grid_per_slot_node_counts():
+    """Per-slot node counts (the paper's grids of 7, 11, 11, 5, 5, 5 nodes,
+    Sec. 4): the first level's nodes are exactly the mixed-radix product of
+    the per-slot grids, enumerated by brute force here; on a quadratic bowl
+    the search stops at the requested accuracy per slot with the bowl's
+    minimum inside the last box."""
+    import itertools
+    lo, hi = [0.0, -1.0, 2.0], [6.0, 1.0, 4.0]
+    n = [4, 3, 5]
+    seen = []
+    F.nested_grid(lambda p: seen.append(p.copy()) or 0.0, lo, hi, [1, 1, 1], [0.0, 0.0, 0.0],
+                  n=n, max_levels=1)
+    expect = [np.array(t) for t in itertools.product(np.linspace(0, 6, 4), np.linspace(-1, 1, 3),
+                                                     np.linspace(2, 4, 5))]
+    assert len(seen) == 60
+    for a, b in zip(seen, expect):
+        np.testing.assert_allclose(a, b, atol=1e-15)
+    mu = np.array([2.3, 0.37, 3.11])
+    f = lambda p: float(np.sum((p - mu) ** 2 * [1.0, 4.0, 9.0]))
+    acc = [0.01, 0.1, 0.1]
+    r = F.nested_grid(f, lo, hi, [1, 1, 1], [0.0, 0.0, 0.0], n=[7, 11, 5], max_levels=50,
+                      accuracy=acc)
+    assert all(r.spacing[k] < acc[k] for k in range(3))
+    assert np.all(np.abs(r.best - mu) <= r.spacing)
+    # an index on a tie goes to the lowest linear index (first slot slowest)
+    r = F.nested_grid(lambda p: 0.0, lo, hi, [1, 1, 1], [0.0, 0.0, 0.0], n=n, max_levels=1)
+    assert r.best_index == 0
