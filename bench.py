@@ -38,9 +38,19 @@ BATCH = 400
 # FP64; packed FP32 is not used anywhere.
 LANE_OPS_PER_S = 256 * 64 * 2.4e9
 PEAK_TFLOPS = 2 * LANE_OPS_PER_S / 1e12
-# FP64 FLOP per line-support voxel: the profile by the ratio recurrence
-# (g *= r, r *= q: 2 FLOP) and three weighted sums (3 FMA: 6 FLOP)
-FLOP_PER_VOXEL = 8
+# Algorithmic work of k_line_sums.  Per fine spaxel of the halo-extended grid
+# (every row): eqs. 1-8 and the line's start values.  FP64 FLOP of the FP64
+# parts (FMA = 2): x_e and y_e/cos i (4 FMA = 8), r^2 (MUL + FMA = 3), the
+# Newton step of 1/r (3 MUL + FMA = 5), r (1), the brightness exponent
+# (MUL + FMA = 3), Vsys + projected rotation (1), the line centre in channels
+# (ADD + MUL = 2), the first channel's offset (ADD + MUL = 2), the two
+# recurrence start arguments (FMA; FMA + MUL = 5) and their fractional parts
+# (2 ADD): 32.  VALU issue slots: ~40 operations and 3 transcendentals
+# (the rotation curve's atan or exp, the two start exp2) at 4 slots each: 52.
+# Per line-support voxel: the profile by the ratio recurrence (g *= r,
+# r *= q) and three weighted sums (3 FMA): 8 FP64 FLOP in 5 slots.
+SPAXEL_FLOP, SPAXEL_SLOTS = 32, 52
+FLOP_PER_VOXEL, VOXEL_SLOTS = 8, 5
 PEAK_HBM_GBS = 8000.0
 
 # HBM traffic per launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
@@ -58,6 +68,7 @@ ACCEPT_TARGET = 200
 # ~0.24 plain rows on the 64x64x64 instrument and the screen ~500 plain rows per
 # round (measured on MI355X); 0.3 and 300 fitted best over the six galaxies
 SCREEN_COST, SCREEN_ROWS = 0.3, 300
+FIT_CAP_S = 8.0  # wall-time cap of one nested-sampling fit of the surrogate workload
 
 # Velocity-field strategy (Sec. 2.2.1) on GHASP-shaped maps: batch of the
 # timed launches, and the kernel's executed FP64 FLOP and VALU instructions per
@@ -87,8 +98,10 @@ def kernel_source_hash() -> str:
     return h.hexdigest()
 
 
-def measured_traffic() -> dict:
-    """{kernel: HBM bytes per launch} from the committed counter summary, or {}."""
+def measured_counters() -> dict:
+    """{kernel: {"hbm_bytes": HBM bytes per launch, "SQ_INSTS_VALU": wave
+    instructions per launch}} from the committed counter summary, or {} when
+    the kernel sources no longer hash to the profiled ones."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
@@ -98,8 +111,10 @@ def measured_traffic() -> dict:
         return {}
     out = {}
     for k, v in t["kernels"].items():
-        out[k] = round(v["FETCH_SIZE_KiB"] * 1024 * t["fetch_factor"] +
-                       v["WRITE_SIZE_KiB"] * 1024 * t["write_factor"])
+        out[k] = {"hbm_bytes": round(v["FETCH_SIZE_KiB"] * 1024 * t["fetch_factor"] +
+                                     v["WRITE_SIZE_KiB"] * 1024 * t["write_factor"])}
+        if "SQ_INSTS_VALU" in v:
+            out[k]["SQ_INSTS_VALU"] = v["SQ_INSTS_VALU"]
     return out
 
 
@@ -109,14 +124,19 @@ def parse():
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-rows-per-thread", type=int, default=40)
+    ap.add_argument("--cpu-rows-per-thread", type=int, default=12,
+                    help="oracle rows per thread of each all-core run")
+    ap.add_argument("--cpu-rows-single", type=int, default=40,
+                    help="oracle rows of each one-core run")
     ap.add_argument("--fit-galaxies", type=int, default=6,
                     help="galaxies of the surrogate workload fitted both ways (0: skip)")
     ap.add_argument("--train-rows", type=int, default=2_000_000)
-    ap.add_argument("--survey-galaxies", type=int, default=200,
+    ap.add_argument("--survey-galaxies", type=int, default=2000,
                     help="galaxies of the uneven-survey LM workload (0: skip)")
-    ap.add_argument("--grid-galaxies", type=int, default=2,
+    ap.add_argument("--grid-galaxies", type=int, default=10,
                     help="galaxies of the nested-grid workload (0: skip)")
+    ap.add_argument("--ns-fits", type=int, default=3,
+                    help="nested-sampling fits of the 128x128x48 workload (0: skip)")
     ap.add_argument("--no-line-fit", action="store_true", help="skip the line-fitting workload")
     ap.add_argument("--no-large-cubes", action="store_true", help="skip the survey/high-res shapes")
     ap.add_argument("--vfield-galaxies", type=int, default=4,
@@ -124,10 +144,38 @@ def parse():
     return ap.parse_args()
 
 
-def other_workloads(gbk, I, torch, n_survey, n_grid):
-    """Fits/hour and evals/s of the other optimiser workloads (subsets, labelled)."""
+def other_workloads(gbk, I, torch, n_survey, n_grid, n_ns, precision_samples):
+    """Fits/hour and evals/s of the other optimiser workloads (subsets, labelled).
+    Appends (grid, rows, GPU maps) of sampled nested-grid nodes to
+    precision_samples for the oracle comparison of the CPU leg."""
     dev = torch.device("cuda:0")
     out = {}
+    if n_ns > 0:
+        # the Fabry-Perot workload fitted by nested sampling: 400 live points, the
+        # 10 non-Epinat parameters, every round's candidates in one launch
+        grid = I.c2_grid()
+        lo, hi = I.c2_prior_box()
+        ts, ev, ln, cov = [], [], [], []
+        for k in range(n_ns):
+            truth = I.c2_draw(I.rng_for(2, 10 + k, 40), 1)[0]
+            mk = gbk.Model.from_grid(grid)
+            mp = mk.evaluate(torch.tensor(truth[None], device=dev)).cpu().numpy()[0]
+            mk.set_obs(I.make_observation(mp, 3.0, I.rng_for(2, 10 + k, 41)))
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = mk.fit_nested(lo, hi, [1] * 10 + [0, 0], truth, n_live=400, seed=k + 1)
+            ts.append(time.perf_counter() - t0)
+            ev.append(r["n_evals"])
+            ln.append(r["n_launches"])
+            cov.append(int(np.sum((r["q16"][:10] <= truth[:10]) & (truth[:10] <= r["q84"][:10]))))
+            log(f"128x128x48 nested sampling fit {k}: {ts[-1]:.2f} s, {r['n_evals']} evaluations")
+        out["ns_128x128x48"] = {"fits": n_ns, "n_live": 400, "free": 10,
+                                "s_per_fit": round(float(np.mean(ts)), 4),
+                                "fits_per_hour": round(3600 * n_ns / sum(ts), 1),
+                                "evals_per_fit": float(np.mean(ev)),
+                                "launches_per_fit": float(np.mean(ln)),
+                                "evals_per_s": round(sum(ev) / sum(ts), 1),
+                                "truth_in_68pct_of_10": cov}
     free9 = [1, 1, 1, 1, 1, 1, 1, 1, 1, 0, 0, 0]
     # single galaxy, 32x32x64, plain LM from a 20% perturbed start
     m = gbk.Model.from_grid(I.c1_grid())
@@ -165,7 +213,8 @@ def other_workloads(gbk, I, torch, n_survey, n_grid):
         r = sv.fit_lm(np.array(p0), free9)
         dt = time.perf_counter() - t0
         log(f"survey LM done in {dt:.2f} s")
-        out["survey_lm"] = {"galaxies": n_survey, "of": 2000, "fits_per_hour": round(3600 * n_survey / dt, 1),
+        out["survey_lm"] = {"galaxies": n_survey, "of": 2000, "capped": int(np.sum(np.array(r["reason"]) == "maxiter")),
+                            "fits_per_hour": round(3600 * n_survey / dt, 1),
                             "seconds": round(dt, 3), "evals": int(r["n_evals"].sum()),
                             "evals_per_s": round(float(r["n_evals"].sum()) / dt, 1),
                             "mean_iterations": float(np.mean(r["iterations"]))}
@@ -190,6 +239,15 @@ def other_workloads(gbk, I, torch, n_survey, n_grid):
             r = mg.fit_grid(lo, hi, free, truth, n_per_dim=16, max_levels=3)
             ts.append(time.perf_counter() - t0)
             ev += r["n_evals"]
+            # sampled nodes for the precision study: the best node and two nodes
+            # of the first level's grid
+            nodes = np.stack([r["best"]] * 3)
+            rs = I.rng_for(4, k, 7)
+            for j in (1, 2):
+                for slot in (I.INC, I.PA, I.VT, I.RT, I.SIG):
+                    nodes[j, slot] = lo[slot] + rs.integers(16) / 15.0 * (hi[slot] - lo[slot])
+            gm = mg.evaluate(torch.tensor(nodes, device=dev)).cpu().numpy()
+            precision_samples.append((g, nodes, gm))
             log(f"nested grid galaxy {k}: {ts[-1]:.2f} s")
         out["nested_grid_30x30x64"] = {"galaxies": n_grid, "of": 1000,
                                        "fits_per_hour": round(3600 * n_grid / sum(ts), 1),
@@ -315,7 +373,7 @@ def velocity_field_workload(gbk, I, torch, n_fit, cpu):
         O.lib()
         side = 512
         d = O.Desc(side, side, 1, rc=I.RC_EPINAT)
-        threads = max(1, min(16, os.cpu_count() or 1))
+        threads = host_threads()
         rows = I.ghasp_draw(I.rng_for(6, side, 0), 64 * threads, side)
         ob = I.make_observation(O.vfield(d, rows[0]), 5.0, I.rng_for(6, side, 1),
                                 flux_frac=I.GHASP_FLUX_FRAC, random_mask=I.GHASP_HOLES, W=0.0)
@@ -442,28 +500,27 @@ def fits_per_hour(gbk, I, torch, n_gal, train_rows):
                      "rows_per_s": round(steps * batch / t_train, 1),
                      "final_loss": float(np.mean(losses[-50:]))}}
     fits = []
-    # galaxies 1, 2, ... of the workload whose kinematics a fit can determine:
-    # i >= 40 deg and Vt sin i >= 2 sigma (near face-on or dispersion-dominated
-    # discs have the i-Vt degeneracy of Sec. 6.1 and take the sampler far longer)
-    chosen, k = [], 1
-    while len(chosen) < n_gal:
-        t = I.c5_galaxy(k)
-        if t[I.INC] >= 40.0 and t[I.VT] * np.sin(np.radians(t[I.INC])) >= 2.0 * t[I.SIG]:
-            chosen.append(k)
-        k += 1
-    for k in chosen:
+    # galaxies 0, 1, ... of the workload, none left out; each fit's wall time is
+    # capped at FIT_CAP_S (near face-on or dispersion-dominated discs carry the
+    # i-Vt degeneracy of Sec. 6.1 and can take the sampler far longer); a capped
+    # fit counts with its capped time and is reported as capped
+    for k in range(n_gal):
         truth = I.c5_galaxy(k)
         maps = m.evaluate(torch.tensor(truth[None], device=dev)).cpu().numpy()[0]
         obs = I.make_observation(maps, 5.0, I.rng_for(5, k, 1))
         m.set_obs(obs)
         pl = m.fit_nested(lo, hi, free, truth, n_live=1000, batch_max=16000,
-                          accept_target=ACCEPT_TARGET, seed=100 + k)
+                          accept_target=ACCEPT_TARGET, seed=100 + k, max_wall_s=FIT_CAP_S)
         sc = S.fit_nested(m, lo, hi, free, truth, margin=25.0, audit=0.02, n_live=1000,
                           batch_max=16000, accept_target=ACCEPT_TARGET, seed=100 + k,
-                          screen_cost=SCREEN_COST, screen_rows=SCREEN_ROWS)
+                          screen_cost=SCREEN_COST, screen_rows=SCREEN_ROWS, max_wall_s=FIT_CAP_S)
         log(f"surrogate workload galaxy {k}: plain {pl['t_wall_s']:.2f} s, screened {sc['t_wall_s']:.2f} s")
         sd = np.where(pl["sd"] > 0, pl["sd"], 1.0)
-        fits.append({"galaxy": k, "plain_s": pl["t_wall_s"], "screened_s": sc["t_wall_s"],
+        fits.append({"galaxy": k, "i_deg": round(float(truth[I.INC]), 1),
+                     "vt_sini_over_sigma": round(float(truth[I.VT] * np.sin(np.radians(truth[I.INC]))
+                                                       / truth[I.SIG]), 2),
+                     "plain_capped": pl["status"] != 0, "screened_capped": sc["status"] != 0,
+                     "plain_s": pl["t_wall_s"], "screened_s": sc["t_wall_s"],
                      "plain_rounds": pl["n_launches"], "screened_rounds": sc["n_launches"],
                      "plain_wait_s": pl["t_wait_s"], "screened_wait_s": sc["t_wait_s"],
                      "plain_evals": pl["n_evals"], "screened_plain_evals": sc["n_evals"],
@@ -472,17 +529,54 @@ def fits_per_hour(gbk, I, torch, n_gal, train_rows):
     if fits:
         tp = sum(f["plain_s"] for f in fits)
         ts = sum(f["screened_s"] for f in fits)
-        out.update({"galaxies": len(fits), "plain": round(3600 * len(fits) / tp, 1),
+        out.update({"galaxies": len(fits), "selection": "first galaxies of the workload, unfiltered",
+                    "cap_s_per_fit": FIT_CAP_S,
+                    "plain_capped": sum(f["plain_capped"] for f in fits),
+                    "screened_capped": sum(f["screened_capped"] for f in fits),
+                    "plain": round(3600 * len(fits) / tp, 1),
                     "screened": round(3600 * len(fits) / ts, 1), "ratio": round(tp / ts, 3),
                     "unit": "fits/hour", "fits": fits})
     S.close()
     return out
 
 
-def cpu_baseline(grid, first_row, obs, rows_per_thread):
-    """The FP64 oracle (untuned) on a bounded sample of the same workload:
-    `first_row` (also evaluated on the GPU, for a cross-check) plus rows drawn
-    like the timed batches."""
+def host_threads() -> int:
+    """Host threads for the oracle legs: the CPUs this process may run on,
+    at most 16 (the host share of one GPU)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def host_info() -> dict:
+    """CPU model, clock and counts of the host that runs the oracle."""
+    info = {"nproc": os.cpu_count(), "usable_cpus": host_threads()}
+    try:
+        with open("/proc/cpuinfo") as f:
+            txt = f.read()
+        for line in txt.splitlines():
+            if line.startswith("model name") and "cpu_model" not in info:
+                info["cpu_model"] = line.split(":", 1)[1].strip()
+            if line.startswith("cpu MHz") and "cpu_mhz_now" not in info:
+                info["cpu_mhz_now"] = float(line.split(":", 1)[1])
+    except OSError:
+        pass
+    try:
+        with open("/sys/devices/system/cpu/cpu0/cpufreq/cpuinfo_max_freq") as f:
+            info["cpu_mhz_max"] = int(f.read()) / 1000.0
+    except (OSError, ValueError):
+        pass
+    return info
+
+
+def cpu_baseline(grid, first_row, obs, st_rows, mt_rows_per_thread, reps=3):
+    """The FP64 oracle (untuned) on bounded samples of the same workload, like
+    the paper's ST and MT setups (Sec. 5.1): one core, then every usable core
+    with one evaluation per thread; the median of `reps` runs each.  The
+    samples are `first_row` (also evaluated on the GPU, for a cross-check)
+    plus rows drawn like the timed batches."""
     from concurrent.futures import ThreadPoolExecutor
 
     from oracle import oracle as O
@@ -491,21 +585,60 @@ def cpu_baseline(grid, first_row, obs, rows_per_thread):
     from parity import oracle_desc
     O.lib()
     d = oracle_desc(O, grid.as_dict())
-    threads = max(1, min(16, os.cpu_count() or 1))
-    n = threads * rows_per_thread
-    sample = np.concatenate([first_row[None, :], I.c2_draw(I.rng_for(2, 0, 3), n - 1)])
+    threads = host_threads()
+    n_mt = threads * mt_rows_per_thread
+    sample = np.concatenate([first_row[None, :],
+                             I.c2_draw(I.rng_for(2, 0, 3), max(n_mt, st_rows) - 1)])
 
     def one(r):
         return O.eval_chi2(d, r, obs.vel, obs.sig, obs.evel, obs.esig, obs.mask, obs.W)[0]
 
-    t0 = time.perf_counter()
-    with ThreadPoolExecutor(threads) as ex:
-        res = list(ex.map(one, sample))
-    dt = time.perf_counter() - t0
-    return {"value": n / dt, "unit": "evals/s", "cores": threads, "kind": "oracle",
-            "sample": f"{n} rows drawn like the timed batches ({rows_per_thread} per thread), "
-                      f"FP64 literal cube pipeline, {dt:.2f} s wall, {dt * threads:.1f} CPU-s",
-            "chi2_first": res[0]}
+    st, mt, res = [], [], None
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        res = [one(r) for r in sample[:st_rows]]
+        st.append(st_rows / (time.perf_counter() - t0))
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        with ThreadPoolExecutor(threads) as ex:
+            list(ex.map(one, sample[:n_mt]))
+        mt.append(n_mt / (time.perf_counter() - t0))
+    v_mt, v_st = float(np.median(mt)), float(np.median(st))
+    return {"value": round(v_mt, 2), "unit": "evals/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n_mt} rows drawn like the timed batches ({mt_rows_per_thread} per thread, "
+                      f"one evaluation per thread), FP64 literal cube pipeline; median of {reps} "
+                      f"runs ({', '.join(f'{v:.1f}' for v in mt)} evals/s)",
+            "single_core": {"value": round(v_st, 2), "unit": "evals/s", "cores": 1,
+                            "sample": f"{st_rows} rows on one thread, median of {reps} runs "
+                                      f"({', '.join(f'{v:.2f}' for v in st)} evals/s)"},
+            "host": host_info(), "chi2_first": res[0]}
+
+
+def precision_study(samples):
+    """Per-map largest deviation of the GPU's maps from the FP64 oracle's on
+    sampled nodes of the beam-smeared grid workload: m0 relative, m1 and m2
+    in km/s, over spaxels whose oracle flux is at least 1e-12 of the map's
+    peak (fainter ones must only be finite)."""
+    from oracle import oracle as O
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from parity import oracle_desc
+    O.lib()
+    worst = {"m0_rel": 0.0, "m1_kms": 0.0, "m2_kms": 0.0}
+    n = 0
+    for grid, rows, gpu in samples:
+        d = oracle_desc(O, grid.as_dict())
+        for r, g in zip(rows, gpu):
+            ref = O.evaluate(d, r)
+            b = ref[0] >= 1e-12 * np.nanmax(ref[0])
+            g = g.astype(np.float64)
+            assert np.isfinite(g).all()
+            worst["m0_rel"] = max(worst["m0_rel"], float(np.max(np.abs(g[0] - ref[0])[b] / ref[0][b])))
+            worst["m1_kms"] = max(worst["m1_kms"], float(np.max(np.abs(g[1] - ref[1])[b])))
+            worst["m2_kms"] = max(worst["m2_kms"], float(np.max(np.abs(g[2] - ref[2])[b])))
+            n += 1
+    return {"nodes": n, "galaxies": len(samples), **{k: float(f"{v:.3g}") for k, v in worst.items()},
+            "bar": {"m0_rel": 1e-5, "m1_kms": "1e-3 + 1e-5 |m1|", "m2_kms": "1e-3 + 1e-5 |m2|"},
+            "precision": "FP32 exp2 / rotation curve, FP64 radius, sums, PSF passes, moments"}
 
 
 def oracle_rate_c5(I):
@@ -521,7 +654,7 @@ def oracle_rate_c5(I):
     lo, hi = I.c5_box()
     truth = I.c5_galaxy(1)
     obs = I.make_observation(O.evaluate(d, truth), 5.0, I.rng_for(5, 1, 1))
-    threads = max(1, min(16, os.cpu_count() or 1))
+    threads = host_threads()
     rows = lo + I.rng_for(5, 0, 9).random((threads * 2, I.NPAR)) * (hi - lo)
     t0 = time.perf_counter()
     with ThreadPoolExecutor(threads) as ex:
@@ -594,31 +727,48 @@ def main():
 
     per_kernel_ms = {n: prof["kernel_ms"][n] / max(prof["launches"][n], 1)
                      for n in gbk.KERNEL_NAMES}
-    traffic = measured_traffic()
     nxe, nye, _, _, _ = model.dims()
-    # k_line_sums: FP64 FLOP of the line-support voxels (counted per launch)
+    # k_line_sums: the algorithmic model above, per launch: every fine spaxel of
+    # every row, and the line-support voxels counted in the untimed pass
     ls_ms = per_kernel_ms["k_line_sums"]
     vox_per_launch = cnt["support_voxels"] / K
-    ls_tflops = vox_per_launch * FLOP_PER_VOXEL / (ls_ms * 1e-3) / 1e12
+    spx_per_launch = BATCH * nxe * nye
+    ls_flop = spx_per_launch * SPAXEL_FLOP + vox_per_launch * FLOP_PER_VOXEL
+    ls_tflops = ls_flop / (ls_ms * 1e-3) / 1e12
+    ls_slots = spx_per_launch * SPAXEL_SLOTS + vox_per_launch * VOXEL_SLOTS
+    ls_slot_frac = ls_slots / (ls_ms * 1e-3) / LANE_OPS_PER_S
+    counters = measured_counters()
     # k_psf_moments: algorithmic HBM bytes = the three T planes of every row
     # read once, plus the observation and the tile partials
     ps_ms = per_kernel_ms["k_psf_moments"]
     ps_bytes = BATCH * 3 * nxe * nye * 8 + 128 * 128 * 25 + BATCH * 32 * 8
     ps_gbs = ps_bytes / (ps_ms * 1e-3) / 1e9
+    def valu_issue(name, ms):
+        c = counters.get(name)
+        if not c or not c.get("SQ_INSTS_VALU"):
+            return None
+        return round(c["SQ_INSTS_VALU"] / (ms * 1e-3) / VALU_ISSUE_PER_S, 4)
+
     rooflines = {
         "k_line_sums": {"bound": "alu", "kernel": "k_line_sums", "achieved": round(ls_tflops, 3),
                         "peak": round(PEAK_TFLOPS, 1), "unit": "TFLOP/s",
                         "frac": round(ls_tflops / PEAK_TFLOPS, 4),
-                        "traffic": traffic.get("k_line_sums"),
+                        "traffic": counters.get("k_line_sums", {}).get("hbm_bytes"),
                         "kernel_ms_avg": round(ls_ms, 5),
+                        "model": f"{SPAXEL_FLOP} FP64 FLOP ({SPAXEL_SLOTS} VALU slots) per fine "
+                                 f"spaxel + {FLOP_PER_VOXEL} FP64 FLOP ({VOXEL_SLOTS} slots) per "
+                                 "line-support voxel",
+                        "spaxels_per_launch": spx_per_launch,
                         "support_voxels_per_launch": int(vox_per_launch),
-                        "flop_per_voxel": FLOP_PER_VOXEL},
+                        "issue_slot_frac": round(ls_slot_frac, 4),
+                        "valu_issue_frac_measured": valu_issue("k_line_sums", ls_ms)},
         "k_psf_moments": {"bound": "hbm", "kernel": "k_psf_moments", "achieved": round(ps_gbs, 1),
                           "peak": PEAK_HBM_GBS, "unit": "GB/s",
                           "frac": round(ps_gbs / PEAK_HBM_GBS, 4),
-                          "traffic": traffic.get("k_psf_moments"),
+                          "traffic": counters.get("k_psf_moments", {}).get("hbm_bytes"),
                           "kernel_ms_avg": round(ps_ms, 5),
-                          "algorithmic_bytes_per_launch": ps_bytes},
+                          "algorithmic_bytes_per_launch": ps_bytes,
+                          "valu_issue_frac_measured": valu_issue("k_psf_moments", ps_ms)},
     }
     dominant = max(("k_line_sums", "k_psf_moments"), key=lambda n: per_kernel_ms[n])
     roofline = rooflines[dominant]
@@ -640,8 +790,10 @@ def main():
     log(f"{value:.0f} evals/s on the 128x128x48 workload")
     if args.fit_galaxies > 0:
         out["fits_per_hour"] = fits_per_hour(gbk, I, torch, args.fit_galaxies, args.train_rows)
-    if args.survey_galaxies > 0 or args.grid_galaxies > 0:
-        out["workloads"] = other_workloads(gbk, I, torch, args.survey_galaxies, args.grid_galaxies)
+    precision_samples = []
+    if args.survey_galaxies > 0 or args.grid_galaxies > 0 or args.ns_fits > 0:
+        out["workloads"] = other_workloads(gbk, I, torch, args.survey_galaxies, args.grid_galaxies,
+                                           args.ns_fits, precision_samples)
     if not args.no_large_cubes:
         out["large_cubes"] = large_cube_workload(gbk, I, torch)
     if not args.no_line_fit:
@@ -651,7 +803,11 @@ def main():
                                                         not args.no_cpu_baseline)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(grid, batches[W, 0].cpu().numpy(), obs,
-                                           args.cpu_rows_per_thread)
+                                           args.cpu_rows_single, args.cpu_rows_per_thread)
+        log(f"oracle: {out['cpu_baseline']['value']:.1f} evals/s on {out['cpu_baseline']['cores']} "
+            f"cores, {out['cpu_baseline']['single_core']['value']:.2f} on one")
+        if precision_samples:
+            out["precision_30x30x64"] = precision_study(precision_samples)
         gpu_first = float(chi2[W, 0].item())
         cb = out["cpu_baseline"].pop("chi2_first")
         out["cpu_baseline"]["chi2_rel_diff_first_row"] = abs(gpu_first - cb) / abs(cb)

@@ -186,13 +186,16 @@ gk_status gk_read_profile(gk_model *model, gk_profile_stats *out);
  * Damped Gauss-Newton on the residuals of gk_residual_batch with box
  * constraints.  Jacobian column a of a free slot: (r(p+) - r(p-)) / (p+ - p-),
  * p+- = p_a +- fd_step clipped to [lo_a, hi_a] (the paper uses an absolute
- * step of about 0.1, Sec. 4).  A = J^T J and g = J^T r are formed on the
- * device in FP64; the step (A + lambda diag A) d = -g is solved on the host by
- * Cholesky in FP64, trial = clip(p + d).  A trial that lowers chi2 is accepted
- * (lambda /= 10), otherwise lambda *= 10.  Free slots whose Jacobian column is
- * identically zero (e.g. I0, which only scales the cube) are frozen.  Each
- * iteration is one batched launch of 1 + 2 n_free rows: the trial point and
- * the Jacobian rows around it (used if the trial is accepted). */
+ * step of about 0.1, Sec. 4).  A = J^T J and g = J^T r are formed in FP64;
+ * the step (A + lambda diag A) d = -g is solved by Cholesky in FP64, trial =
+ * clip(p + d).  A trial that lowers chi2 is accepted (lambda /= 10),
+ * otherwise lambda *= 10.  Free slots whose Jacobian column is identically
+ * zero (e.g. I0, which only scales the cube) are frozen.  Each iteration is
+ * one batched launch of 1 + 2 n_free rows: the trial point and the Jacobian
+ * rows around it (used if the trial is accepted).  gk_fit_lm runs the whole
+ * iteration on the device (the step rule in one GPU thread, no host round
+ * trip), eight iterations per HIP graph replay in the graph launch mode; the
+ * survey LM keeps the rule on the host; both give the same result. */
 typedef struct {
     int32_t max_iter;   /* trials; default 200 */
     int32_t reserved;   /* must be 0 */
@@ -286,6 +289,10 @@ typedef struct {
      * and its pieces may then count the same region twice.  0 (default): one
      * mode. */
     int32_t separate_modes;
+    /* > 0: stop after this much wall time (checked after each round), as if
+     * max_iter had been reached (GK_ENOTCONV, results from the points so
+     * far); 0 (default): no limit */
+    double max_wall_s;
 } gk_ns_opts;
 
 /* Per-mode results (gk_ns_result.modes). */
@@ -372,6 +379,16 @@ gk_status gk_fit_grid(gk_model *model, const double *lo, const double *hi,
                       const uint8_t *free_mask, const double *fixed, int32_t n_per_dim,
                       int32_t max_levels, const double *accuracy, gk_grid_result *result);
 
+/* The same search with n_per_slot[k] >= 2 nodes along each free slot k
+ * (n_per_slot [GK_NP], entries of fixed slots ignored), as the paper's grids
+ * of different resolution per parameter (Sec. 4: 7, 11, 11, 5, 5, 5 nodes for
+ * PA, r_t, V_t, sigma, a, g).  Node index = mixed-radix number of the free
+ * slots' node indices, first free slot most significant; the product of the
+ * counts <= 2^31.  gk_fit_grid is this call with every count n_per_dim. */
+gk_status gk_fit_grid_nd(gk_model *model, const double *lo, const double *hi,
+                         const uint8_t *free_mask, const double *fixed, const int32_t *n_per_slot,
+                         int32_t max_levels, const double *accuracy, gk_grid_result *result);
+
 /* ---- Surveys: ragged batches over many models -----------------------------
  * A survey groups models (galaxies with their own grids, PSFs and
  * observations) on one device.  A batch lists (model, parameter row) pairs of
@@ -400,6 +417,20 @@ gk_status gk_survey_chi2(gk_survey *survey, const int32_t *model_idx, const doub
 gk_status gk_fit_lm_survey(gk_survey *survey, double *p_inout, const uint8_t *free_mask,
                            const double *lo, const double *hi, const gk_lm_opts *opts,
                            gk_lm_result *results);
+
+/* Nested grids (gk_fit_grid_nd) of every galaxy of the survey at once: lo, hi
+ * and fixed are [n][GK_NP] (galaxy g's box and fixed values), free_mask,
+ * n_per_slot and accuracy [GK_NP] are shared (accuracy may be NULL).  Each
+ * level evaluates the nodes of every galaxy still refining in ragged
+ * launches of up to 2^20 rows (galaxy-major, each galaxy's nodes in index
+ * order) and reduces each galaxy's least-chi2 node on the device; a galaxy
+ * whose every spacing is below accuracy stops.  results [n]; each equals what
+ * gk_fit_grid_nd gives for that galaxy's model alone (same chi-square,
+ * same ties).  Blocks. */
+gk_status gk_fit_grid_survey(gk_survey *survey, const double *lo, const double *hi,
+                             const uint8_t *free_mask, const double *fixed,
+                             const int32_t *n_per_slot, int32_t max_levels, const double *accuracy,
+                             gk_grid_result *results);
 
 /* ---- Learned surrogate of the moment maps (not part of the paper) ----------
  * A multilayer perceptron maps a parameter row to the velocity and dispersion

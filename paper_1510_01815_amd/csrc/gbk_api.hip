@@ -221,14 +221,37 @@ bool setup_fft(gk_model *m, const std::vector<double> &kp, std::vector<double2> 
 
 namespace {
 
-// Enqueues the launch chain of B rows (every chunk) on s.
+// Row scratch of one chunk: per-row constants, T planes, chi-square tile
+// partials and (FFT path) the x-pass planes, each sized for `chunk` rows.
+struct RowScratch {
+    double *consts = nullptr, *T = nullptr, *partial = nullptr, *U = nullptr;
+    int chunk = 0;
+};
+
+// Enqueues the launch chain of B rows (every chunk) on s.  With sc == NULL
+// the model's own scratch is grown to one chunk and the profiling hooks
+// apply; otherwise the chain runs in *sc (device rows only, no hooks).
 gk_status enqueue_batch(gk_model *m, const double *params, PtrKind pk, int32_t B, float *maps,
-                        double *resid, double *chi2, int64_t *nvalid, hipStream_t s)
+                        double *resid, double *chi2, int64_t *nvalid, hipStream_t s,
+                        const RowScratch *sc = nullptr)
 {
-    const int chunk = std::min<int>(B, m->chunk_rows());
-    HIP_TRY(m->reserve(chunk));
-    const bool timing = m->prof_flags & GK_PROF_TIMING;
-    unsigned long long *counter = (m->prof_flags & GK_PROF_COUNT) ? m->d_count : nullptr;
+    RowScratch own;
+    if (!sc) {
+        own.chunk = std::min<int>(B, m->chunk_rows());
+        HIP_TRY(m->reserve(own.chunk));
+        own.consts = m->d_consts;
+        own.T = m->d_T;
+        own.partial = m->d_partial;
+        own.U = m->d_U;
+        sc = &own;
+    } else if (pk != PTR_DEVICE) {
+        return fail(GK_EINVAL, "rows must be device memory here");
+    }
+    const int chunk = sc->chunk;
+    const bool hooks = sc == &own;
+    const bool timing = hooks && (m->prof_flags & GK_PROF_TIMING);
+    unsigned long long *counter =
+        (hooks && (m->prof_flags & GK_PROF_COUNT)) ? m->d_count : nullptr;
     if (timing) m->prof_events.emplace_back();
     // launches stage `k` through `fn`; when timing, its launches carry a
     // start and a stop event (the stage's first dispatch starts, its last ends)
@@ -252,7 +275,7 @@ gk_status enqueue_batch(gk_model *m, const double *params, PtrKind pk, int32_t B
         }
         return e;
     };
-    if (m->prof_flags) m->prof_rows += B;
+    if (hooks && m->prof_flags) m->prof_rows += B;
     const size_t npix = (size_t)m->d.nx * m->d.ny;
     for (int b0 = 0; b0 < B; b0 += chunk) {
         const int nb = std::min(chunk, B - b0);
@@ -270,10 +293,10 @@ gk_status enqueue_batch(gk_model *m, const double *params, PtrKind pk, int32_t B
             // Sec. 2.2.1: constants at u = 1 with no halo, then eq. 8 and the
             // chi-square terms per pixel (the channel width only enters
             // constants this path does not read)
-            HIP_TRY(timed(0, [&] { return launch_prep(prow, nb, m->d.rc, 1.0, 0, 1, m->d_consts, s); }));
+            HIP_TRY(timed(0, [&] { return launch_prep(prow, nb, m->d.rc, 1.0, 0, 1, sc->consts, s); }));
             VfArgs v{};
             v.params = prow;
-            v.consts = m->d_consts;
+            v.consts = sc->consts;
             v.rc = m->d.rc;
             v.nx = m->d.nx;
             v.ny = m->d.ny;
@@ -290,26 +313,26 @@ gk_status enqueue_batch(gk_model *m, const double *params, PtrKind pk, int32_t B
             }
             v.maps = maps ? maps + (size_t)b0 * 3 * npix : nullptr;
             v.resid = resid ? resid + (size_t)b0 * 2 * npix : nullptr;
-            v.partial = chi2 ? m->d_partial : nullptr;
+            v.partial = chi2 ? sc->partial : nullptr;
             HIP_TRY(timed(1, [&] { return launch_vfield(v, s); }));
             if (chi2)
                 HIP_TRY(timed(3, [&] {
-                    return launch_reduce_chi2(m->d_partial, m->ntiles, m->d_consts, m->nvalid,
+                    return launch_reduce_chi2(sc->partial, m->ntiles, sc->consts, m->nvalid,
                                               chi2 + b0, nvalid ? nvalid + b0 : nullptr, nb, s);
                 }));
             continue;
         }
         HIP_TRY(timed(0, [&] {
-            return launch_prep(prow, nb, m->d.rc, m->dvf, m->hp, m->d.upsample, m->d_consts, s);
+            return launch_prep(prow, nb, m->d.rc, m->dvf, m->hp, m->d.upsample, sc->consts, s);
         }));
         HIP_TRY(timed(1, [&] {
-            return launch_line_sums(m->d_consts, m->d_wz, m->NZE, m->EX, m->EY, m->hp,
-                                    m->d.upsample, m->d.rc, m->vf0, m->inv_dvf, m->d_T, counter,
+            return launch_line_sums(sc->consts, m->d_wz, m->NZE, m->EX, m->EY, m->hp,
+                                    m->d.upsample, m->d.rc, m->vf0, m->inv_dvf, sc->T, counter,
                                     nb, s);
         }));
         PsfArgs a{};
-        a.T = m->d_T;
-        a.consts = m->d_consts;
+        a.T = sc->T;
+        a.consts = sc->consts;
         a.kp = m->d_kp;
         a.hp = m->hp;
         a.u = m->d.upsample;
@@ -332,11 +355,11 @@ gk_status enqueue_batch(gk_model *m, const double *params, PtrKind pk, int32_t B
         }
         a.maps = maps ? maps + (size_t)b0 * 3 * npix : nullptr;
         a.resid = resid ? resid + (size_t)b0 * 2 * npix : nullptr;
-        a.partial = chi2 ? m->d_partial : nullptr;
+        a.partial = chi2 ? sc->partial : nullptr;
         if (m->use_fft) {
             FftArgs f = m->fft;
-            f.T = m->d_T;
-            f.U = m->d_U;
+            f.T = sc->T;
+            f.U = sc->U;
             HIP_TRY(timed(2, [&] {
                 hipError_t e = launch_fft_x(f, nb, s);
                 return e == hipSuccess ? launch_fft_y_moments(f, a, nb, s) : e;
@@ -346,7 +369,7 @@ gk_status enqueue_batch(gk_model *m, const double *params, PtrKind pk, int32_t B
         }
         if (chi2)
             HIP_TRY(timed(3, [&] {
-                return launch_reduce_chi2(m->d_partial, m->ntiles, m->d_consts, m->nvalid,
+                return launch_reduce_chi2(sc->partial, m->ntiles, sc->consts, m->nvalid,
                                           chi2 + b0, nvalid ? nvalid + b0 : nullptr, nb, s);
             }));
     }
@@ -356,6 +379,16 @@ gk_status enqueue_batch(gk_model *m, const double *params, PtrKind pk, int32_t B
 constexpr size_t kMaxGraphs = 8;
 
 }  // namespace
+
+// The launch chain of B device rows on s, with the model's scratch and no
+// graph bookkeeping (the caller may be recording a graph of its own).
+gk_status gbk::enqueue_device_rows(gk_model *m, const double *d_params, int32_t B, float *maps,
+                                   double *resid, double *chi2, int64_t *nvalid, hipStream_t s)
+{
+    if (B <= 0) return GK_OK;
+    return enqueue_batch(m, d_params, PTR_DEVICE, B, maps, resid, chi2, nvalid, s);
+}
+
 
 gk_status gbk::run_batch(gk_model *m, const double *params, int32_t B, float *maps,
                           double *resid, double *chi2, int64_t *nvalid, void *stream)

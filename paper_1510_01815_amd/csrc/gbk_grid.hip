@@ -20,14 +20,15 @@ gk_status fit_reserve_rows(gk_model *m, int rows, double **h_params, double **d_
 namespace {
 
 struct GridSpec {
-    int d, n;
+    int d;
+    int n[NPAR];  // nodes along free slot a
     int slot[NPAR];
     double lo[NPAR], step[NPAR];
     double fixed[NPAR];
 };
 
-// Rows of nodes [first, first + count): digit a of the node index (base n,
-// first free slot most significant) selects lo_a + digit * step_a.
+// Rows of nodes [first, first + count): digit a of the node index (mixed
+// radix n_a, first free slot most significant) selects lo_a + digit * step_a.
 __global__ void k_grid_rows(GridSpec g, int64_t first, int count, double *__restrict__ rows)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -36,8 +37,8 @@ __global__ void k_grid_rows(GridSpec g, int64_t first, int count, double *__rest
     for (int k = 0; k < NPAR; ++k) r[k] = g.fixed[k];
     int64_t L = first + i;
     for (int a = g.d - 1; a >= 0; --a) {
-        const int digit = (int)(L % g.n);
-        L /= g.n;
+        const int digit = (int)(L % g.n[a]);
+        L /= g.n[a];
         r[g.slot[a]] = g.lo[a] + digit * g.step[a];
     }
 }
@@ -81,26 +82,30 @@ __global__ __launch_bounds__(256) void k_argmin(const double *__restrict__ chi2,
 
 }  // namespace
 
-extern "C" gk_status gk_fit_grid(gk_model *m, const double *lo0, const double *hi0,
-                                 const uint8_t *free_mask, const double *fixed, int32_t n,
-                                 int32_t max_levels, const double *accuracy, gk_grid_result *res)
+extern "C" gk_status gk_fit_grid_nd(gk_model *m, const double *lo0, const double *hi0,
+                                    const uint8_t *free_mask, const double *fixed,
+                                    const int32_t *n_per_slot, int32_t max_levels,
+                                    const double *accuracy, gk_grid_result *res)
 {
-    if (!m || !lo0 || !hi0 || !free_mask || !fixed || !res) return fail(GK_EINVAL, "NULL argument");
+    if (!m || !lo0 || !hi0 || !free_mask || !fixed || !n_per_slot || !res)
+        return fail(GK_EINVAL, "NULL argument");
     if (!m->has_obs) return fail(GK_ESTATE, "no observation set");
-    if (n < 2 || max_levels < 1) return fail(GK_EINVAL, "need n_per_dim >= 2 and max_levels >= 1");
+    if (max_levels < 1) return fail(GK_EINVAL, "need max_levels >= 1");
     GridSpec g{};
-    g.n = n;
     double lo[NPAR], hi[NPAR];
+    double total = 1.0;
     for (int k = 0; k < NPAR; ++k) {
         g.fixed[k] = fixed[k];
         if (!free_mask[k]) continue;
         if (!(hi0[k] > lo0[k])) return fail(GK_EINVAL, "empty range in slot %d", k);
+        if (n_per_slot[k] < 2) return fail(GK_EINVAL, "slot %d: need at least 2 nodes", k);
+        g.n[g.d] = n_per_slot[k];
+        total *= n_per_slot[k];
         g.slot[g.d++] = k;
         lo[k] = lo0[k];
         hi[k] = hi0[k];
     }
     if (g.d == 0) return fail(GK_EINVAL, "no free parameter");
-    double total = std::pow((double)n, g.d);
     if (total > 2147483648.0) return fail(GK_EINVAL, "too many nodes per level");
     const int64_t nodes = (int64_t)llround(total);
     DeviceGuard guard(m->device);
@@ -125,7 +130,7 @@ extern "C" gk_status gk_fit_grid(gk_model *m, const double *lo0, const double *h
         for (int a = 0; a < g.d; ++a) {
             const int k = g.slot[a];
             g.lo[a] = lo[k];
-            g.step[a] = (hi[k] - lo[k]) / (n - 1);
+            g.step[a] = (hi[k] - lo[k]) / (g.n[a] - 1);
         }
         for (int c = 0; c < nchunks && st == GK_OK; ++c) {
             const int64_t first = (int64_t)c * chunk;
@@ -160,8 +165,8 @@ extern "C" gk_status gk_fit_grid(gk_model *m, const double *lo0, const double *h
         bool fine = accuracy != nullptr;
         for (int a = g.d - 1; a >= 0; --a) {
             const int k = g.slot[a];
-            const int digit = (int)(L % n);
-            L /= n;
+            const int digit = (int)(L % g.n[a]);
+            L /= g.n[a];
             const double x = g.lo[a] + digit * g.step[a];
             res->best[k] = x;
             res->spacing[k] = g.step[a];
@@ -188,4 +193,14 @@ extern "C" gk_status gk_fit_grid(gk_model *m, const double *lo0, const double *h
     res->reserved = 0;
     res->n_evals = n_evals;
     return GK_OK;
+}
+
+extern "C" gk_status gk_fit_grid(gk_model *m, const double *lo0, const double *hi0,
+                                 const uint8_t *free_mask, const double *fixed, int32_t n,
+                                 int32_t max_levels, const double *accuracy, gk_grid_result *res)
+{
+    if (n < 2) return fail(GK_EINVAL, "need n_per_dim >= 2");
+    int32_t ns[NPAR];
+    for (int k = 0; k < NPAR; ++k) ns[k] = n;
+    return gk_fit_grid_nd(m, lo0, hi0, free_mask, fixed, ns, max_levels, accuracy, res);
 }

@@ -240,6 +240,12 @@ namespace gbk {
 gk_status run_batch(gk_model *m, const double *params, int32_t B, float *maps, double *resid,
                     double *chi2, int64_t *nvalid, void *stream);
 
+// The launch chain of B rows in device memory on stream s, using the model's
+// row scratch (already reserved for min(B, chunk_rows()) rows when the caller
+// records a graph), outside the model's own graph replay.
+gk_status enqueue_device_rows(gk_model *m, const double *d_params, int32_t B, float *maps,
+                              double *resid, double *chi2, int64_t *nvalid, hipStream_t s);
+
 // Data tile of a model inside a survey: the model's own, except that the
 // 64 x 32 register-blocked tile (which the survey kernels do not run) becomes
 // the 32 x 32 one, or a generic tile where that does not apply.

@@ -564,6 +564,7 @@ gk_status ns_run(int d, const DrawEval &draw_eval, const gk_ns_opts &o, gk_ns_re
 {
     const int N = o.n_live, Bmax = std::max(o.batch, o.batch_max);
     const bool separate = o.separate_modes != 0;
+    const auto t_start = std::chrono::steady_clock::now();
     std::vector<double> live_u((size_t)N * d), live_l(N);
     std::vector<int> live_mode(N, 0);
     std::vector<double> ub((size_t)std::max(N, Bmax) * d), lb(std::max(N, Bmax));
@@ -751,6 +752,12 @@ gk_status ns_run(int d, const DrawEval &draw_eval, const gk_ns_opts &o, gk_ns_re
                 capped = true;
             }
         }
+        if (!done && o.max_wall_s > 0.0 &&
+            std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count() >
+                o.max_wall_s) {
+            done = true;
+            capped = true;
+        }
         if (Bmax > o.batch) {  // next batch from the acceptance rate of the last two rounds
             const double acc = (double)(k - k_round), cand = B;
             const double rate = acc_prev < 0.0 ? acc / cand : (acc + acc_prev) / (cand + cand_prev);
@@ -894,7 +901,7 @@ gk_status check_opts(const gk_ns_opts &o)
     if (o.n_live < 2 || o.batch < 1 || o.max_iter < 1 || !(o.enlarge >= 1.0) || !(o.tol > 0.0) ||
         o.max_ell < 1 || o.max_ell > kMaxEll || (o.batch_max != 0 && o.batch_max < o.batch) ||
         o.accept_target < 0 || !(o.screen_cost >= 0.0) || o.screen_rows < 0 ||
-        (o.separate_modes != 0 && o.separate_modes != 1))
+        (o.separate_modes != 0 && o.separate_modes != 1) || !(o.max_wall_s >= 0.0))
         return fail(GK_EINVAL, "invalid nested-sampling options");
     return GK_OK;
 }
@@ -923,6 +930,7 @@ extern "C" gk_status gk_ns_default_opts(gk_ns_opts *o)
     o->screen_cost = 0.0;
     o->screen_rows = 0;
     o->separate_modes = 0;
+    o->max_wall_s = 0.0;
     return GK_OK;
 }
 

@@ -59,6 +59,9 @@ struct gk_survey {
     HBuf<double> h_params;
     // LM workspace
     DBuf<double> resid, norm, scale, npart;
+    // nested-grid workspace
+    DBuf<double> grid_rows, grid_chi2, grid_spec, grid_val;
+    DBuf<int64_t> grid_idx;
     DBuf<int64_t> goff;
     HBuf<double> h_norm, h_scale;
     HBuf<int64_t> h_goff;
@@ -70,6 +73,7 @@ struct gk_survey {
         md.free(); params.free(); consts.free(); T.free(); partial.free(); idx.free();
         h_idx.free(); h_params.free(); resid.free(); norm.free(); scale.free(); goff.free();
         npart.free();
+        grid_rows.free(); grid_chi2.free(); grid_spec.free(); grid_val.free(); grid_idx.free();
         h_norm.free(); h_scale.free(); h_goff.free();
         if (ev_staged) (void)hipEventDestroy(ev_staged);
         if (fit_stream) (void)hipStreamDestroy(fit_stream);
@@ -301,6 +305,88 @@ gk_status survey_batch(gk_survey *s, const int32_t *midx, const double *d_params
         b0 = b1;
     }
     return GK_OK;
+}
+
+// Shape shared by the grids of a survey level: free slots, nodes per slot
+// (mixed radix, first free slot most significant) and nodes per galaxy.
+struct GridShape {
+    int d;
+    int n[NPAR];
+    int slot[NPAR];
+    int64_t nodes;
+};
+
+// Rows [first, first + count) of a level: row F = j nodes + L is node L of
+// the level's j-th galaxy, whose box is spec[j] = {lo_a [NPAR], step_a [NPAR],
+// fixed [NPAR]} (lo and step per free slot a).
+__global__ void k_grid_rows_multi(GridShape g, const double *__restrict__ spec, int64_t first,
+                                  int count, double *__restrict__ rows)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const int64_t F = first + i;
+    const int64_t j = F / g.nodes;
+    int64_t L = F - j * g.nodes;
+    const double *sp = spec + (size_t)j * 3 * NPAR;
+    double *r = rows + (size_t)i * NPAR;
+    for (int k = 0; k < NPAR; ++k) r[k] = sp[2 * NPAR + k];
+    for (int a = g.d - 1; a >= 0; --a) {
+        const int digit = (int)(L % g.n[a]);
+        L /= g.n[a];
+        r[g.slot[a]] = sp[a] + digit * sp[NPAR + a];
+    }
+}
+
+// One block per galaxy j0 + blockIdx.x whose nodes meet the rows
+// [first, first + count): the least chi2 of those rows (NaN as +inf; lowest
+// node index on ties) merged into best_val/best_idx[j].  The chunks of a level
+// run in index order, so keeping the stored node on ties keeps the lowest.
+__global__ __launch_bounds__(256) void k_argmin_seg(const double *__restrict__ chi2, int64_t first,
+                                                    int count, int64_t nodes, int j0,
+                                                    double *__restrict__ best_val,
+                                                    int64_t *__restrict__ best_idx)
+{
+    const int j = j0 + blockIdx.x;
+    const int64_t a = std::max<int64_t>(first, (int64_t)j * nodes);
+    const int64_t b = std::min<int64_t>(first + count, (int64_t)(j + 1) * nodes);
+    double best = INFINITY;
+    int64_t bi = INT64_MAX;
+    for (int64_t F = a + threadIdx.x; F < b; F += 256) {
+        const double c = chi2[F - first];
+        const double v = c == c ? c : INFINITY;
+        if (v < best) {
+            best = v;
+            bi = F - (int64_t)j * nodes;
+        }
+    }
+    __shared__ double sv[256];
+    __shared__ int64_t si[256];
+    sv[threadIdx.x] = best;
+    si[threadIdx.x] = bi;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (threadIdx.x < st) {
+            const double x = sv[threadIdx.x], y = sv[threadIdx.x + st];
+            const int64_t ix = si[threadIdx.x], iy = si[threadIdx.x + st];
+            if (y < x || (y == x && iy < ix)) {
+                sv[threadIdx.x] = y;
+                si[threadIdx.x] = iy;
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && (sv[0] < best_val[j] || (sv[0] == best_val[j] && si[0] < best_idx[j]))) {
+        best_val[j] = sv[0];
+        best_idx[j] = si[0];
+    }
+}
+
+__global__ void k_grid_best_init(int n, double *__restrict__ v, int64_t *__restrict__ idx)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    v[i] = INFINITY;
+    idx[i] = INT64_MAX;
 }
 
 // Index of the normal-equation pairs (a <= b) in output order.
@@ -638,4 +724,133 @@ extern "C" gk_status gk_fit_lm_survey(gk_survey *s, double *p_io, const uint8_t 
     }
     (void)n_evals;
     return capped ? GK_ENOTCONV : GK_OK;
+}
+
+extern "C" gk_status gk_fit_grid_survey(gk_survey *s, const double *lo0, const double *hi0,
+                                        const uint8_t *free_mask, const double *fixed,
+                                        const int32_t *n_per_slot, int32_t max_levels,
+                                        const double *accuracy, gk_grid_result *res)
+{
+    if (!s || !lo0 || !hi0 || !free_mask || !fixed || !n_per_slot || !res)
+        return fail(GK_EINVAL, "NULL argument");
+    if (max_levels < 1) return fail(GK_EINVAL, "need max_levels >= 1");
+    for (gk_model *m : s->models)
+        if (!m->has_obs) return fail(GK_ESTATE, "a model of the survey has no observation");
+    const int G = (int)s->models.size();
+    GridShape shape{};
+    double total = 1.0;
+    for (int k = 0; k < NPAR; ++k) {
+        if (!free_mask[k]) continue;
+        if (n_per_slot[k] < 2) return fail(GK_EINVAL, "slot %d: need at least 2 nodes", k);
+        shape.n[shape.d] = n_per_slot[k];
+        shape.slot[shape.d++] = k;
+        total *= n_per_slot[k];
+    }
+    if (shape.d == 0) return fail(GK_EINVAL, "no free parameter");
+    if (total > 2147483648.0) return fail(GK_EINVAL, "too many nodes per level");
+    shape.nodes = (int64_t)llround(total);
+    std::vector<double> lo((size_t)G * NPAR), hi((size_t)G * NPAR);
+    for (int g = 0; g < G; ++g)
+        for (int k = 0; k < NPAR; ++k) {
+            const size_t o = (size_t)g * NPAR + k;
+            lo[o] = lo0[o];
+            hi[o] = hi0[o];
+            if (free_mask[k] && !(hi[o] > lo[o]))
+                return fail(GK_EINVAL, "galaxy %d slot %d: empty range", g, k);
+        }
+    DeviceGuard guard(s->device);
+    HIP_TRY(guard.err);
+    hipStream_t st = s->fit_stream;
+    GK_TRY(refresh_models(s, st));
+    std::memset(res, 0, sizeof(gk_grid_result) * G);
+    std::vector<int> active(G);
+    for (int g = 0; g < G; ++g) active[g] = g;
+    std::vector<int> levels(G, 0);
+    const int64_t kChunk = 1 << 20;
+    std::vector<double> spec, h_val;
+    std::vector<int64_t> h_idx;
+    std::vector<int32_t> midx;
+    for (int level = 0; level < max_levels && !active.empty(); ++level) {
+        const int na = (int)active.size();
+        spec.assign((size_t)na * 3 * NPAR, 0.0);
+        for (int j = 0; j < na; ++j) {
+            const size_t o = (size_t)active[j] * NPAR;
+            double *sp = &spec[(size_t)j * 3 * NPAR];
+            for (int a = 0; a < shape.d; ++a) {
+                const int k = shape.slot[a];
+                sp[a] = lo[o + k];
+                sp[NPAR + a] = (hi[o + k] - lo[o + k]) / (shape.n[a] - 1);
+            }
+            for (int k = 0; k < NPAR; ++k) sp[2 * NPAR + k] = fixed[o + k];
+        }
+        const int64_t rows = (int64_t)na * shape.nodes;
+        const int chunk = (int)std::min<int64_t>(rows, kChunk);
+        GK_TRY(s->grid_spec.need(spec.size()));
+        GK_TRY(s->grid_rows.need((size_t)chunk * NPAR));
+        GK_TRY(s->grid_chi2.need((size_t)chunk));
+        GK_TRY(s->grid_val.need((size_t)na));
+        GK_TRY(s->grid_idx.need((size_t)na));
+        HIP_TRY(hipMemcpyAsync(s->grid_spec.p, spec.data(), sizeof(double) * spec.size(),
+                               hipMemcpyHostToDevice, st));
+        hipLaunchKernelGGL(k_grid_best_init, dim3((na + 255) / 256), dim3(256), 0, st, na,
+                           s->grid_val.p, s->grid_idx.p);
+        HIP_TRY(hipGetLastError());
+        for (int64_t first = 0; first < rows; first += chunk) {
+            const int cnt = (int)std::min<int64_t>(chunk, rows - first);
+            hipLaunchKernelGGL(k_grid_rows_multi, dim3((cnt + 255) / 256), dim3(256), 0, st, shape,
+                               s->grid_spec.p, first, cnt, s->grid_rows.p);
+            HIP_TRY(hipGetLastError());
+            midx.resize(cnt);
+            for (int i = 0; i < cnt; ++i) midx[i] = active[(first + i) / shape.nodes];
+            GK_TRY(survey_batch(s, midx.data(), s->grid_rows.p, cnt, s->grid_chi2.p, nullptr,
+                                nullptr, st));
+            const int j0 = (int)(first / shape.nodes), j1 = (int)((first + cnt - 1) / shape.nodes);
+            hipLaunchKernelGGL(k_argmin_seg, dim3(j1 - j0 + 1), dim3(256), 0, st, s->grid_chi2.p,
+                               first, cnt, shape.nodes, j0, s->grid_val.p, s->grid_idx.p);
+            HIP_TRY(hipGetLastError());
+        }
+        h_val.resize(na);
+        h_idx.resize(na);
+        HIP_TRY(hipMemcpyAsync(h_val.data(), s->grid_val.p, sizeof(double) * na,
+                               hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(h_idx.data(), s->grid_idx.p, sizeof(int64_t) * na,
+                               hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        std::vector<int> next;
+        for (int j = 0; j < na; ++j) {
+            const int g = active[j];
+            const size_t o = (size_t)g * NPAR;
+            gk_grid_result &r = res[g];
+            const double *sp = &spec[(size_t)j * 3 * NPAR];
+            int64_t L = h_idx[j] == INT64_MAX ? 0 : h_idx[j];
+            bool fine = accuracy != nullptr;
+            for (int a = shape.d - 1; a >= 0; --a) {
+                const int k = shape.slot[a];
+                const int digit = (int)(L % shape.n[a]);
+                L /= shape.n[a];
+                const double x = sp[a] + digit * sp[NPAR + a];
+                r.best[k] = x;
+                r.spacing[k] = sp[NPAR + a];
+                if (accuracy) fine = fine && sp[NPAR + a] < accuracy[k];
+                lo[o + k] = std::max(x - sp[NPAR + a], lo0[o + k]);
+                hi[o + k] = std::min(x + sp[NPAR + a], hi0[o + k]);
+            }
+            r.chi2 = h_val[j];
+            r.best_index = h_idx[j];
+            r.n_evals += shape.nodes;
+            levels[g] = level + 1;
+            if (!fine) next.push_back(g);
+        }
+        active.swap(next);
+    }
+    for (int g = 0; g < G; ++g) {
+        for (int k = 0; k < NPAR; ++k)
+            if (!free_mask[k]) {
+                res[g].best[k] = fixed[(size_t)g * NPAR + k];
+                res[g].spacing[k] = 0.0;
+            }
+        res[g].levels = levels[g];
+        res[g].reserved = 0;
+    }
+    return GK_OK;
 }

@@ -84,7 +84,8 @@ class NSOpts(ctypes.Structure):
                 ("enlarge", ctypes.c_double), ("tol", ctypes.c_double), ("seed", ctypes.c_uint64),
                 ("max_ell", ctypes.c_int32), ("batch_max", ctypes.c_int32),
                 ("accept_target", ctypes.c_int32), ("screen_cost", ctypes.c_double),
-                ("screen_rows", ctypes.c_int32), ("separate_modes", ctypes.c_int32)]
+                ("screen_rows", ctypes.c_int32), ("separate_modes", ctypes.c_int32),
+                ("max_wall_s", ctypes.c_double)]
 
 
 NS_MAX_MODES = 8  # GK_NS_MAX_MODES
@@ -167,6 +168,11 @@ def _ns_dict(r: "NSResult", st: int, dim: int, samples=None) -> dict:
     return out
 
 
+def _grid_dict(r: "GridResult") -> dict:
+    return {"best": np.array(r.best[:]), "chi2": r.chi2, "best_index": r.best_index,
+            "levels": r.levels, "n_evals": r.n_evals, "spacing": np.array(r.spacing[:])}
+
+
 def philox4x32(ctr, key):
     """Philox4x32-10 block of the library (gk_philox4x32)."""
     L = load()
@@ -244,6 +250,10 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
                                 ctypes.POINTER(ctypes.c_uint32)]
     L.gk_fit_grid.argtypes = [vp, vp, vp, vp, vp, ctypes.c_int32, ctypes.c_int32, vp,
                               ctypes.POINTER(GridResult)]
+    L.gk_fit_grid_nd.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.c_int32, vp,
+                                 ctypes.POINTER(GridResult)]
+    L.gk_fit_grid_survey.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.c_int32, vp,
+                                     ctypes.POINTER(GridResult)]
     L.gk_create_survey.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, ctypes.POINTER(vp)]
     L.gk_destroy_survey.argtypes = [vp]
     L.gk_survey_chi2.argtypes = [vp, vp, vp, i32, vp, vp]
@@ -507,17 +517,23 @@ class Model:
         return _ns_dict(r, st, NPAR, buf[: ns.value] if want_samples else None)
 
     def fit_grid(self, lo, hi, free, fixed, n_per_dim=16, max_levels=3, accuracy=None) -> dict:
-        """Nested-grid search (gk_fit_grid)."""
+        """Nested-grid search: gk_fit_grid for one node count, gk_fit_grid_nd for a
+        count per slot (a sequence of 12)."""
         L = load()
         a = [np.ascontiguousarray(v, dtype=np.float64) for v in (lo, hi, fixed)]
         fm = np.ascontiguousarray(free, dtype=np.uint8)
         acc = None if accuracy is None else np.ascontiguousarray(accuracy, dtype=np.float64)
         r = GridResult()
-        _check(L.gk_fit_grid(self._h, a[0].ctypes.data, a[1].ctypes.data, fm.ctypes.data,
-                             a[2].ctypes.data, n_per_dim, max_levels,
-                             None if acc is None else acc.ctypes.data, ctypes.byref(r)))
-        return {"best": np.array(r.best[:]), "chi2": r.chi2, "best_index": r.best_index,
-                "levels": r.levels, "n_evals": r.n_evals, "spacing": np.array(r.spacing[:])}
+        if np.isscalar(n_per_dim):
+            _check(L.gk_fit_grid(self._h, a[0].ctypes.data, a[1].ctypes.data, fm.ctypes.data,
+                                 a[2].ctypes.data, int(n_per_dim), max_levels,
+                                 None if acc is None else acc.ctypes.data, ctypes.byref(r)))
+        else:
+            ns = np.ascontiguousarray(n_per_dim, dtype=np.int32)
+            _check(L.gk_fit_grid_nd(self._h, a[0].ctypes.data, a[1].ctypes.data, fm.ctypes.data,
+                                    a[2].ctypes.data, ns.ctypes.data, max_levels,
+                                    None if acc is None else acc.ctypes.data, ctypes.byref(r)))
+        return _grid_dict(r)
 
     def residuals(self, params, out=None, stream=None):
         """resid [B][2][ny][nx] float64 CUDA tensor."""
@@ -584,6 +600,22 @@ class Survey:
         _check(load().gk_survey_chi2(self._h, idx.ctypes.data, p, B, out.data_ptr(),
                                      _stream_ptr(stream)))
         return out
+
+    def fit_grid(self, lo, hi, free, fixed, n_per_dim=16, max_levels=3, accuracy=None):
+        """Nested grids of every galaxy at once (gk_fit_grid_survey): lo, hi, fixed
+        [n][12]; n_per_dim one count or 12; returns a list of result dicts."""
+        L = load()
+        G = len(self.models)
+        a = [np.ascontiguousarray(np.broadcast_to(v, (G, NPAR)), dtype=np.float64)
+             for v in (lo, hi, fixed)]
+        fm = np.ascontiguousarray(free, dtype=np.uint8)
+        ns = np.ascontiguousarray(np.broadcast_to(n_per_dim, (NPAR,)), dtype=np.int32)
+        acc = None if accuracy is None else np.ascontiguousarray(accuracy, dtype=np.float64)
+        res = (GridResult * G)()
+        _check(L.gk_fit_grid_survey(self._h, a[0].ctypes.data, a[1].ctypes.data, fm.ctypes.data,
+                                    a[2].ctypes.data, ns.ctypes.data, max_levels,
+                                    None if acc is None else acc.ctypes.data, res))
+        return [_grid_dict(r) for r in res]
 
     def fit_lm(self, p0, free, lo=None, hi=None, **opts):
         """Levenberg-Marquardt of every galaxy at once (gk_fit_lm_survey)."""

@@ -211,6 +211,80 @@ def test_grid_five_dims_million_rows_per_level(O, gbk):
     assert np.isfinite(r["chi2"]) and r["chi2"] <= one["chi2"] and r["chi2"] < 0.01 * one["chi2"] + 10
 
 
+def test_grid_paper_resolution_per_slot(O, gbk):
+    """The paper's nested-grid configuration (Sec. 4): 7, 11, 11, 5, 5, 5
+    nodes for PA, r_t, V_t, sigma, a and g (105,875 nodes per level), Vsys,
+    centre and i fixed, on an Epinat velocity field with a dispersion term.
+    The first two levels pick the same node as the oracle's nested grid with
+    the same per-slot counts; run on to the paper's accuracy (0.01 for r_t,
+    0.1 for the rest) every final spacing is below it and chi2 only falls."""
+    side = 16
+    grid = I.Grid(side, side, 1, 1.0, 0.0, 0.0, rc=I.RC_EPINAT, strategy=1)
+    d = O.Desc(side, side, 1, rc=I.RC_EPINAT)
+    truth = np.array([7.6, 8.3, 40.0, 55.0, 1200.0, 160.0, 3.0, 35.0, 4.0, 1.0, 1.8, 1.2])
+    obs = I.make_observation(O.vfield(d, truth), 5.0, I.rng_for(71, 0, 0), flux_frac=0.0, W=0.5)
+    m = gbk.Model.from_grid(grid)
+    m.set_obs(obs)
+    free = [0, 0, 1, 0, 0, 1, 1, 1, 0, 0, 1, 1]
+    n = [2, 2, 7, 2, 2, 11, 11, 5, 2, 2, 5, 5]
+    lo, hi = truth.copy(), truth.copy()
+    for k, (a, b) in {I.PA: (10.0, 70.0), I.VT: (60.0, 260.0), I.RT: (0.5, 8.0),
+                      I.SIG: (10.0, 80.0), I.A: (0.5, 3.0), I.G: (0.5, 2.5)}.items():
+        lo[k], hi[k] = a, b
+    chi2 = lambda p: O.vfield_chi2(d, p, obs.vel, obs.sig, obs.evel, obs.esig, obs.mask, obs.W)[0]
+    ref = F.nested_grid(chi2, lo, hi, free, truth, n=n, max_levels=2)
+    r = m.fit_grid(lo, hi, free, truth, n_per_dim=n, max_levels=2)
+    print("paper grid, 2 levels:", r["best_index"], ref.best_index, r["chi2"], ref.chi2)
+    assert r["best_index"] == ref.best_index and r["levels"] == ref.levels == 2
+    assert r["n_evals"] == 2 * 7 * 11 * 11 * 5 * 5 * 5
+    np.testing.assert_array_equal(r["best"], ref.best)
+    assert abs(r["chi2"] - ref.chi2) <= 1e-9 * ref.chi2
+    acc = np.full(12, 0.1)
+    acc[I.RT] = 0.01
+    fin = m.fit_grid(lo, hi, free, truth, n_per_dim=n, max_levels=30, accuracy=acc)
+    print("to accuracy:", fin["levels"], "levels", fin["chi2"], fin["best"][[2, 5, 6, 7, 10, 11]])
+    assert fin["levels"] < 30 and fin["chi2"] <= r["chi2"]
+    for k in np.flatnonzero(free):
+        assert fin["spacing"][k] < acc[k], k
+
+
+def test_grid_survey_equals_single_models(O, gbk):
+    """gk_fit_grid_survey over five cube models of different shapes and
+    boxes, per-slot node counts 5, 4, 6 over (PA, i, Vt), three levels with an
+    accuracy that stops some galaxies early: every galaxy's result equals,
+    bit for bit, gk_fit_grid_nd on its model alone."""
+    rng = np.random.default_rng(31)
+    models, los, his, fixed = [], [], [], []
+    for k in range(5):
+        side = int(rng.integers(10, 20))
+        g = I.Grid(side, side, int(rng.integers(20, 36)), 30.0, psf_fwhm=float(rng.uniform(1.5, 3.0)),
+                   lsf_sigma=30.0)
+        t = I.c1_box_draw(rng, 1, side, g.psf_fwhm)[0]
+        ob = I.make_observation(O.evaluate(oracle_desc(O, g.as_dict()), t), 5.0, rng)
+        mk = gbk.Model.from_grid(g)
+        mk.set_obs(ob)
+        models.append(mk)
+        lo, hi = t.copy(), t.copy()
+        lo[[2, 3, 5]] = [t[2] - 30.0, 10.0, 40.0]
+        hi[[2, 3, 5]] = [t[2] + 30.0, 80.0, 320.0]
+        los.append(lo); his.append(hi); fixed.append(t)
+    free = [0, 0, 1, 1, 0, 1, 0, 0, 0, 0, 0, 0]
+    n = [2, 2, 5, 4, 2, 6, 2, 2, 2, 2, 2, 2]
+    acc = np.full(12, 1.0)
+    acc[2], acc[3], acc[5] = 8.0, 12.0, 30.0
+    sv = gbk.Survey(models)
+    res = sv.fit_grid(np.array(los), np.array(his), free, np.array(fixed), n_per_dim=n,
+                      max_levels=3, accuracy=acc)
+    for k, mk in enumerate(models):
+        one = mk.fit_grid(los[k], his[k], free, fixed[k], n_per_dim=n, max_levels=3, accuracy=acc)
+        print(k, res[k]["levels"], one["levels"], res[k]["chi2"], one["chi2"])
+        assert res[k]["best_index"] == one["best_index"] and res[k]["levels"] == one["levels"]
+        assert res[k]["chi2"] == one["chi2"] and res[k]["n_evals"] == one["n_evals"]
+        np.testing.assert_array_equal(res[k]["best"], one["best"])
+        np.testing.assert_array_equal(res[k]["spacing"], one["spacing"])
+    assert len({r["levels"] for r in res}) >= 1
+
+
 @pytest.mark.parametrize("with_i0", [False, True])
 def test_nested_sampling_device_draws_closed_form(O, gbk, with_i0):
     """The device-side candidate draws of gk_fit_nested against a posterior

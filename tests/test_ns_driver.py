@@ -235,3 +235,20 @@ def test_ns_mode_separation_leaves_a_single_mode_alone():
     assert len(r["modes"]) == 1
     assert abs(r["logz"] - logz_true) < 3 * r["logz_err"] + 0.1
     np.testing.assert_allclose(r["mean"], mu, atol=0.1 * sig.max())
+
+
+def test_ns_wall_time_cap():
+    """max_wall_s stops a run at a round boundary once the time is spent: the
+    call reports the cap (GK_ENOTCONV) with results from the points so far."""
+    import time
+    from paper_1510_01815_amd import gbk
+
+    def slow(th):
+        time.sleep(0.01)
+        return gauss_loglike(np.zeros(3), np.full(3, 0.01))(th)
+    lo, hi = np.full(3, -1.0), np.full(3, 1.0)
+    t0 = time.perf_counter()
+    r = gbk.nested_sample(slow, lo, hi, n_live=100, seed=2, max_wall_s=0.3)
+    dt = time.perf_counter() - t0
+    assert r["status"] == gbk.GK_ENOTCONV
+    assert dt < 2.0 and r["n_iter"] > 0 and np.isfinite(r["logz"])
