@@ -46,6 +46,7 @@
 #ifndef GBK_H
 #define GBK_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -160,6 +161,27 @@ gk_status gk_chi2_batch(gk_model *model, const double *params, int32_t B, double
  * observation. */
 gk_status gk_residual_batch(gk_model *model, const double *params, int32_t B, double *resid,
                             void *hip_stream);
+
+/* Allocation-free chi-square, for callers that cannot allocate device memory:
+ * code under HIP graph capture, tight serving loops and harnesses that forbid
+ * hipMalloc.  Same arguments, kernels and results (bit for bit) as
+ * gk_chi2_batch, but the per-row scratch (row constants, T_j planes,
+ * chi-square tile partials, FFT x-pass planes) lives in one fixed device
+ * array of GK_NOALLOC_SCRATCH_BYTES per GPU, part of the library's device
+ * code and held by every GPU the call has run on until the process ends;
+ * batches larger than it holds run in chunks on the caller's stream.  The call
+ * makes no hipMalloc, hipFree, pinned staging or graph (its first call on a
+ * GPU looks the array's address up once).  params, chi2 and n_valid
+ * (nullable) must be device memory.  All calls on one GPU share its array, so
+ * calls that overlap on one GPU (other streams or threads without ordering
+ * between them) race and give undefined results; the array keeps the last
+ * call's contents, none of which the next call reads.  Errors: GK_EINVAL for
+ * host rows or outputs, or a model one of whose rows needs more scratch than
+ * the array holds (about 5.5 M halo-extended fine spaxels); GK_ESTATE without
+ * an observation. */
+#define GK_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+gk_status gk_chi2_batch_noalloc(gk_model *model, const double *params, int32_t B,
+                                double *chi2, int64_t *n_valid, void *hip_stream);
 
 /* Measurement hooks for the benchmark (not needed for correct results).
  * flags: GK_PROF_TIMING brackets every kernel launch of the following calls

@@ -12,6 +12,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -21,6 +22,9 @@
 using namespace gbk;
 
 thread_local std::string g_err;
+
+// The allocation-free entry point's row scratch (see noalloc_scratch).
+static __device__ __align__(256) unsigned char scratch[GK_NOALLOC_SCRATCH_BYTES];
 
 namespace gbk {
 
@@ -377,6 +381,64 @@ gk_status enqueue_batch(gk_model *m, const double *params, PtrKind pk, int32_t B
 }
 
 constexpr size_t kMaxGraphs = 8;
+
+// Row scratch of gk_chi2_batch_noalloc: one fixed array per GPU, loaded with
+// the library's code object and held until the process ends.  Host code never
+// passes the array's name to a kernel (on the host it is only a stand-in
+// symbol): its device address, looked up once per device with that device
+// current, is kept in scratch_addr.
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+unsigned char *scratch_addr[kMaxDevices] = {};
+
+// Per-row scratch carved from the fixed array: for `rows` rows, the row
+// constants, the T_j planes, the chi-square tile partials and (FFT path) the
+// x-pass planes, each region 256-byte aligned.
+struct NoAllocLayout {
+    int rows = 0;
+    size_t row_bytes = 0;
+    size_t off_consts = 0, off_T = 0, off_partial = 0, off_U = 0;
+    bool T = false, U = false;
+};
+
+size_t align256(size_t n) { return (n + 255) & ~size_t(255); }
+
+NoAllocLayout noalloc_layout(const gk_model *m)
+{
+    NoAllocLayout L;
+    L.T = !m->vfield;
+    L.U = !m->vfield && m->use_fft;
+    const size_t c = gbk::NCONST * sizeof(double);
+    const size_t t = L.T ? (size_t)3 * m->EX * m->EY * sizeof(double) : 0;
+    const size_t p = (size_t)m->ntiles * sizeof(double);
+    const size_t u = L.U ? (size_t)3 * m->EY * m->NX * sizeof(double) : 0;
+    L.row_bytes = c + t + p + u;
+    const size_t cap = (size_t)GK_NOALLOC_SCRATCH_BYTES;
+    // four regions lose at most 255 bytes each to alignment
+    size_t rows = cap > 4 * 256 ? (cap - 4 * 256) / L.row_bytes : 0;
+    rows = std::min<size_t>(rows, 65535);
+    L.rows = (int)rows;
+    L.off_consts = 0;
+    L.off_T = align256(L.off_consts + rows * c);
+    L.off_partial = align256(L.off_T + rows * t);
+    L.off_U = align256(L.off_partial + rows * p);
+    return L;
+}
+
+// Device address of `scratch` on `dev` (the current device).
+hipError_t noalloc_scratch(int dev, unsigned char **out)
+{
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_addr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        scratch_addr[dev] = static_cast<unsigned char *>(p);
+    }
+    *out = scratch_addr[dev];
+    return hipSuccess;
+}
 
 }  // namespace
 
@@ -807,6 +869,37 @@ gk_status gk_residual_batch(gk_model *m, const double *params, int32_t B, double
 {
     if (!resid && B > 0) return fail(GK_EINVAL, "resid is NULL");
     return run_batch(m, params, B, nullptr, resid, nullptr, nullptr, stream);
+}
+
+gk_status gk_chi2_batch_noalloc(gk_model *m, const double *params, int32_t B, double *chi2,
+                                int64_t *n_valid, void *stream)
+{
+    if (!m) return fail(GK_EINVAL, "model is NULL");
+    if (B < 0) return fail(GK_EINVAL, "negative batch size %d", B);
+    if (B == 0) return GK_OK;
+    if (!params || !chi2) return fail(GK_EINVAL, "params or chi2 is NULL");
+    DeviceGuard g(m->device);
+    HIP_TRY(g.err);
+    if (pointer_kind(params) != PTR_DEVICE) return fail(GK_EINVAL, "rows must be device memory");
+    if (pointer_kind(chi2) != PTR_DEVICE || (n_valid && pointer_kind(n_valid) != PTR_DEVICE))
+        return fail(GK_EINVAL, "output arrays must be device memory");
+    const NoAllocLayout lay = noalloc_layout(m);
+    if (lay.rows < 1)
+        return fail(GK_EINVAL,
+                    "one row of this model needs %zu bytes of scratch; the allocation-free "
+                    "array holds %zu",
+                    lay.row_bytes, (size_t)GK_NOALLOC_SCRATCH_BYTES);
+    if (!m->has_obs) return fail(GK_ESTATE, "no observation set");
+    unsigned char *base = nullptr;
+    HIP_TRY(noalloc_scratch(m->device, &base));
+    RowScratch sc;
+    sc.chunk = std::min(lay.rows, (int)B);
+    sc.consts = reinterpret_cast<double *>(base + lay.off_consts);
+    sc.T = lay.T ? reinterpret_cast<double *>(base + lay.off_T) : nullptr;
+    sc.partial = reinterpret_cast<double *>(base + lay.off_partial);
+    sc.U = lay.U ? reinterpret_cast<double *>(base + lay.off_U) : nullptr;
+    return enqueue_batch(m, params, PTR_DEVICE, B, nullptr, nullptr, chi2, n_valid,
+                         (hipStream_t)stream, &sc);
 }
 
 }  // extern "C"

@@ -36,6 +36,7 @@ SYMBOLS = (
     "gk_surrogate_chi2", "gk_fit_nested_screened", "gk_gemm_bf16", "gk_model_conv_path",
     "gk_set_launch_mode", "gk_graph_launches", "gk_autotune", "gk_set_conv_config",
     "gk_mc_errors", "gk_line_default_opts", "gk_fit_lines", "gk_surrogate_step",
+    "gk_chi2_batch_noalloc",
 )
 MC = {"shuffle": 0, "perturb": 1}
 LM_REASONS = {1: "ftol", 2: "xtol", 3: "lambda", 4: "maxiter"}
@@ -233,6 +234,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.gk_observation_count.argtypes = [vp, i64p]
     L.gk_evaluate_batch.argtypes = [vp, vp, i32, vp, vp]
     L.gk_chi2_batch.argtypes = [vp, vp, i32, vp, vp, vp]
+    L.gk_chi2_batch_noalloc.argtypes = [vp, vp, i32, vp, vp, vp]
     L.gk_residual_batch.argtypes = [vp, vp, i32, vp, vp]
     L.gk_model_dims.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
     L.gk_set_profiling.argtypes = [vp, ctypes.c_int]
@@ -438,6 +440,16 @@ class Model:
             n_valid = torch.empty(B, dtype=torch.int64, device=dev)
         self.last_status = _check(load().gk_chi2_batch(self._h, p, B, out.data_ptr(),
                                                        n_valid.data_ptr(), _stream_ptr(stream)))
+        return out, n_valid
+
+    def chi2_noalloc(self, params, out, n_valid=None, stream=None):
+        """gk_chi2_batch_noalloc: chi2 of device rows into the caller's device
+        tensors out [B] float64 and n_valid [B] int64 (optional), with the
+        library's fixed scratch array (nothing is allocated)."""
+        p, B, keep = _params_arg(params)
+        self.last_status = _check(load().gk_chi2_batch_noalloc(
+            self._h, p, B, out.data_ptr(),
+            None if n_valid is None else n_valid.data_ptr(), _stream_ptr(stream)))
         return out, n_valid
 
     def set_profiling(self, flags: int):
