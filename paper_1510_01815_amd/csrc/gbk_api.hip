@@ -297,7 +297,9 @@ gk_status enqueue_batch(gk_model *m, const double *params, PtrKind pk, int32_t B
             // Sec. 2.2.1: constants at u = 1 with no halo, then eq. 8 and the
             // chi-square terms per pixel (the channel width only enters
             // constants this path does not read)
-            HIP_TRY(timed(0, [&] { return launch_prep(prow, nb, m->d.rc, 1.0, 0, 1, sc->consts, s); }));
+            HIP_TRY(timed(0, [&] {
+                return launch_prep(prow, nb, m->d.rc, 1.0, 0, 1, sc->consts, s);
+            }));
             VfArgs v{};
             v.params = prow;
             v.consts = sc->consts;
@@ -331,8 +333,8 @@ gk_status enqueue_batch(gk_model *m, const double *params, PtrKind pk, int32_t B
         }));
         HIP_TRY(timed(1, [&] {
             return launch_line_sums(sc->consts, m->d_wz, m->NZE, m->EX, m->EY, m->hp,
-                                    m->d.upsample, m->d.rc, m->vf0, m->inv_dvf, sc->T, counter,
-                                    nb, s);
+                                    m->d.upsample, m->d.rc, m->vf0, m->inv_dvf, m->zedge_lo,
+                                    m->zedge_hi, sc->T, counter, nb, s);
         }));
         PsfArgs a{};
         a.T = sc->T;
@@ -659,6 +661,18 @@ gk_status gk_create_model(const gk_model_desc *desc, int device, gk_model **out)
         wz[4 * (size_t)zp + 0] = w0 / u;
         wz[4 * (size_t)zp + 1] = w1 / u;
         wz[4 * (size_t)zp + 2] = w2 / u;
+    }
+    {
+        double wmax = 0.0;
+        for (int zp = 0; zp < m->NZE; ++zp) wmax = std::max(wmax, wz[4 * (size_t)zp]);
+        int lo = m->NZE - 1, hi = 0;
+        for (int zp = 0; zp < m->NZE; ++zp)
+            if (wz[4 * (size_t)zp] >= std::ldexp(wmax, -5)) {
+                lo = std::min(lo, zp);
+                hi = std::max(hi, zp);
+            }
+        m->zedge_lo = (float)lo;
+        m->zedge_hi = (float)hi;
     }
     choose_tile(m);
     const bool direct_ok = m->lds_bytes <= kMaxLds;

@@ -91,6 +91,7 @@ struct ModelDev {
     const double *wz;       // channel weight table [NZE][4]
     int NZE, EX, EY, hp, u, rc;
     double dvf, inv_dvf, vf0;
+    float zedge_lo, zedge_hi;  // see gk_model::zedge_lo
     int64_t nvalid;         // unmasked pixels of the observation
     int fast_hp;            // >= 0: register-blocked u = 1 kernel with this half-width; -1: generic
     int lds_bytes;          // dynamic LDS of its PSF/moment kernel
@@ -128,8 +129,9 @@ hipError_t launch_reduce_multi(const double *partial, const ModelDev *md, const 
 hipError_t launch_prep(const double *params, int B, int rc, double dvf, int hp, int u,
                        double *consts, hipStream_t s);
 hipError_t launch_line_sums(const double *consts, const double *wz, int NZE, int EX, int EY,
-                            int hp, int u, int rc, double vf0, double inv_dvf, double *T,
-                            unsigned long long *support_count, int B, hipStream_t s);
+                            int hp, int u, int rc, double vf0, double inv_dvf, float zedge_lo,
+                            float zedge_hi, double *T, unsigned long long *support_count, int B,
+                            hipStream_t s);
 hipError_t launch_psf_moments(const PsfArgs &a, int B, size_t lds_bytes, hipStream_t s);
 
 // FFT path of the spatial convolution (gbk_fft.hip): k_fft_x convolves every

@@ -170,6 +170,28 @@ __device__ inline double exp2_wide(double x)
     return ldexp((double)__builtin_amdgcn_exp2f((float)(x - n)), (int)n);
 }
 
+// 2^x in FP64 to ~1e-11 relative for x in roughly [-1070, 1000]: x = n + f
+// with n the nearest integer and |f| <= 1/2, 2^f by its Taylor series
+// sum_k (f ln 2)^k / k! to degree 9 (remainder below 1.1e-11 for |f ln 2| <=
+// 0.347), then scaled by 2^n.  Used for the ratio of the channel recurrences,
+// whose rounding would otherwise grow linearly along a long channel range.
+__device__ inline double exp2_precise(double x)
+{
+    const double n = rint(x), f = x - n;
+    // (ln 2)^k / k!, k = 9 .. 1
+    double p = 1.0178086009239696e-07;
+    p = fma(p, f, 1.3215486790144305e-06);
+    p = fma(p, f, 1.5252733804059838e-05);
+    p = fma(p, f, 0.00015403530393381606);
+    p = fma(p, f, 0.0013333558146428441);
+    p = fma(p, f, 0.009618129107628477);
+    p = fma(p, f, 0.055504108664821576);
+    p = fma(p, f, 0.2402265069591007);
+    p = fma(p, f, 0.6931471805599453);
+    p = fma(p, f, 1.0);
+    return ldexp(p, (int)n);
+}
+
 // ---------------------------------------------------------------------------
 // k_line_sums: T_j for every fine spaxel of the halo-extended grid.
 // grid = (ceil(EX/16), ceil(EY/16), B); a block covers 16 x 16 spaxels and
@@ -192,8 +214,9 @@ __device__ inline double exp2_wide(double x)
 __device__ __forceinline__ void line_sums_tile(const double *__restrict__ c,
                                                const double *__restrict__ wz, int NZE, int EX,
                                                int EY, int hp, int u, int rc, double vf0,
-                                               double inv_dvf, double *__restrict__ T, int tile_x,
-                                               int tile_y, unsigned long long *__restrict__ count)
+                                               double inv_dvf, float zedge_lo, float zedge_hi,
+                                               double *__restrict__ T, int tile_x, int tile_y,
+                                               unsigned long long *__restrict__ count)
 {
     if (c[C_VALID] == 0.0) return;  // uniform over the block
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -244,13 +267,18 @@ __device__ __forceinline__ void line_sums_tile(const double *__restrict__ c,
     const float zcf = (float)zc, span = (float)c[C_ZSPAN];
     // clamp in floating point first so that the integer conversion cannot overflow;
     // an empty range is lo = NZE, hi = -1 (packed below as NZE - hi = NZE + 1)
-    const int lo = in ? (int)fminf(fmaxf(ceilf(zcf - span), 0.0f), (float)NZE) : NZE;
-    const int hi = in ? (int)fmaxf(fminf(floorf(zcf + span), (float)(NZE - 1)), -1.0f) : -1;
+    const int lo0 = in ? (int)fminf(fmaxf(ceilf(zcf - span), 0.0f), (float)NZE) : NZE;
+    const int hi0 = in ? (int)fmaxf(fminf(floorf(zcf + span), (float)(NZE - 1)), -1.0f) : -1;
+    // a line centred where the spectral weight tapers off (or beyond the band)
+    // sums over the whole band: the channels it would drop can carry more
+    // weighted flux than the ones it keeps
+    const bool edge = lo0 <= hi0 && (zcf < zedge_lo || zcf > zedge_hi);
+    const int lo = edge ? 0 : lo0, hi = edge ? NZE - 1 : hi0;
     int zlo, nhi;
     wave_min2(lo, NZE - hi, zlo, nhi);
     const int zhi = NZE - nhi;
     if (count) {  // measurement only: voxels inside each lane's own support
-        int n = max(hi - lo + 1, 0);
+        int n = max(hi0 - lo0 + 1, 0);
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) n += __shfl_xor(n, o, 64);
         // one slot per (block, wave): launches on a stream are ordered, so += is race-free
@@ -266,7 +294,10 @@ __device__ __forceinline__ void line_sums_tile(const double *__restrict__ c,
     double t0 = 0.0, t1 = 0.0, t2 = 0.0;
     if (!__any(in && e0 * e0 - lamp > 1020.0)) {
         double g = exp2_wide(lamp - e0 * e0);
-        double rt = exp2_wide(-(2.0 * e0 + sqk) * sqk);
+        // the ratio's rounding grows linearly along the range: beyond 48
+        // channels it is formed to ~1e-11 instead of FP32's ~6e-8
+        const double ra = -(2.0 * e0 + sqk) * sqk;
+        double rt = zhi - zlo >= 48 ? exp2_precise(ra) : exp2_wide(ra);
         const double qq = c[C_Q];
         // the next channel's weights are requested one step ahead, which
         // lets the scalar loads of two channels merge into one
@@ -314,15 +345,16 @@ __device__ __forceinline__ void line_sums_tile(const double *__restrict__ c,
 __global__ __launch_bounds__(256) void k_line_sums(const double *__restrict__ consts,
                                                    const double *__restrict__ wz, int NZE, int EX,
                                                    int EY, int hp, int u, int rc, double vf0,
-                                                   double inv_dvf, double *__restrict__ T,
+                                                   double inv_dvf, float zedge_lo, float zedge_hi,
+                                                   double *__restrict__ T,
                                                    unsigned long long *__restrict__ support_count)
 {
     const int b = blockIdx.z;
     unsigned long long *cnt = nullptr;
     if (support_count)
         cnt = support_count + (((size_t)b * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x) * 4;
-    line_sums_tile(consts + (size_t)b * NCONST, wz, NZE, EX, EY, hp, u, rc, vf0, inv_dvf,
-                   T + (size_t)b * 3 * EX * EY, blockIdx.x, blockIdx.y, cnt);
+    line_sums_tile(consts + (size_t)b * NCONST, wz, NZE, EX, EY, hp, u, rc, vf0, inv_dvf, zedge_lo,
+                   zedge_hi, T + (size_t)b * 3 * EX * EY, blockIdx.x, blockIdx.y, cnt);
 }
 
 // Ragged rows of several models: block -> (row, tile) through the tile prefix
@@ -334,8 +366,9 @@ __global__ __launch_bounds__(256) void k_line_sums_multi(const double *__restric
     const int b = find_row(rm.ls_base, rm.B, blockIdx.x);
     const ModelDev &m = md[rm.row_model[b]];
     const int t = blockIdx.x - rm.ls_base[b], tiles_x = (m.EX + 15) >> 4;
-    line_sums_tile(consts + (size_t)b * NCONST, m.wz, m.NZE, m.EX, m.EY, m.hp, m.u, m.rc, m.vf0,
-                   m.inv_dvf, T + rm.T_off[b], t % tiles_x, t / tiles_x, nullptr);
+    line_sums_tile(consts + (size_t)b * NCONST, m.wz, m.NZE, m.EX, m.EY, m.hp, m.u, m.rc,
+                   m.vf0, m.inv_dvf, m.zedge_lo, m.zedge_hi, T + rm.T_off[b], t % tiles_x,
+                   t / tiles_x, nullptr);
 }
 
 // ---------------------------------------------------------------------------
@@ -998,18 +1031,18 @@ hipError_t launch_reduce_multi(const double *partial, const ModelDev *md, const 
 hipError_t launch_prep(const double *params, int B, int rc, double dvf, int hp, int u,
                        double *consts, hipStream_t s)
 {
-    launch(k_prep, dim3((B + 63) / 64), dim3(64), 0, s, params, B, rc, dvf, hp, u,
-                       consts);
+    launch(k_prep, dim3((B + 63) / 64), dim3(64), 0, s, params, B, rc, dvf, hp, u, consts);
     return hipGetLastError();
 }
 
 hipError_t launch_line_sums(const double *consts, const double *wz, int NZE, int EX, int EY,
-                            int hp, int u, int rc, double vf0, double inv_dvf, double *T,
-                            unsigned long long *support_count, int B, hipStream_t s)
+                            int hp, int u, int rc, double vf0, double inv_dvf, float zedge_lo,
+                            float zedge_hi, double *T, unsigned long long *support_count, int B,
+                            hipStream_t s)
 {
     dim3 grid((EX + 15) / 16, (EY + 15) / 16, B);
-    launch(k_line_sums, grid, dim3(256), 0, s, consts, wz, NZE, EX, EY, hp, u, rc, vf0,
-                       inv_dvf, T, support_count);
+    launch(k_line_sums, grid, dim3(256), 0, s, consts, wz, NZE, EX, EY, hp, u, rc, vf0, inv_dvf,
+           zedge_lo, zedge_hi, T, support_count);
     return hipGetLastError();
 }
 

@@ -73,6 +73,12 @@ struct gk_model {
     int device = 0;
     int hp = 0, hl = 0, NX = 0, NY = 0, NZ = 0, EX = 0, EY = 0, NZE = 0;
     double vf0 = 0, dvf = 0, inv_dvf = 0, vref = 0;
+    // Fine channel positions between which the spectral weight W0 is at least
+    // 2^-5 of its largest value.  A line centred outside them (in the LSF
+    // taper at a band edge, or beyond the band) can have most of its weighted
+    // flux in channels below the 2^-40 support cut, so its sums run over the
+    // whole band.
+    float zedge_lo = 0.0f, zedge_hi = 0.0f;
     int TXd = 0, TYd = 0, ntx = 0, nty = 0, ntiles = 0;
     // velocity-field strategy (Sec. 2.2.1): no cube, ntiles = pixel tiles of k_vfield
     bool vfield = false;

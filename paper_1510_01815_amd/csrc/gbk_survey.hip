@@ -124,6 +124,8 @@ gk_status refresh_models(gk_survey *s, hipStream_t st)
         d.dvf = m->dvf;
         d.inv_dvf = m->inv_dvf;
         d.vf0 = m->vf0;
+        d.zedge_lo = m->zedge_lo;
+        d.zedge_hi = m->zedge_hi;
         d.nvalid = m->nvalid;
         d.fast_hp = (m->d.upsample == 1 && tile.TXd == 32 && tile.TYd == 32 &&
                      m->hp <= kMaxFastHalo) ? m->hp : -1;

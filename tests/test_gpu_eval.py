@@ -293,15 +293,11 @@ def test_lines_outside_the_band(O, gbk):
     the model band (data channels plus the LSF halo), above or below it: no
     line reaches 2^-40 of its peak at any channel, so every spaxel has no flux
     and the maps are (0, Vsys, 0) on both sides, exactly.  Lines straddling
-    the band edge: the usual tolerances.  Lines 2.6 to 7.4 sigma beyond the
-    band: only wings reach it; the kernels run a wave's channels over the
-    union of its lanes' supports and drop what lies beyond, < 2^-40 of a
-    line's peak per channel, which the oracle keeps, so where a pixel's whole
-    flux sits within a few e-folds of that cut its moments differ by up to
-    ~1e-3 relative; compared where the flux is >= 1e-4 of the row's peak (no
-    such pixel there), and its chi-square, which sums over every unmasked
-    pixel, is not compared.  Chi-square of the other rows against the
-    oracle."""
+    the band edge, and lines 2.6 to 7.4 sigma beyond the band whose wings
+    alone reach it (a spaxel centred in the LSF taper or beyond the band sums
+    over the whole band, since the channels below the 2^-40 support cut can
+    carry more weighted flux than the ones above it): the usual tolerances on
+    every pixel and on chi-square."""
     import torch
     grid = I.Grid(20, 18, 40, 25.0, psf_fwhm=2.0, lsf_sigma=20.0)
     base = np.array([9.7, 8.6, 40.0, 45.0, 0.0, 100.0, 3.0, 30.0, 4.0, 1.0, 1.0, 1.0])
@@ -316,8 +312,8 @@ def test_lines_outside_the_band(O, gbk):
         for k, want in ((0, 0.0), (1, np.float32(rows[b, I.VSYS])), (2, 0.0)):
             assert np.all(ref[b][k] == rows[b, I.VSYS] if k == 1 else ref[b][k] == 0.0)
             assert np.all(maps[b][k] == want), (b, k)
-    assert ref[2][0].max() > 0.0 and np.all(np.isfinite(maps[2]))
-    assert_maps_close(maps[2], ref[2], "wings-only row 2", bright_frac=1e-4)
+    assert ref[2][0].max() > 0.0
+    assert_maps_close(maps[2], ref[2], "wings-only row 2")
     for b in (3, 4):
         assert ref[b][0].max() > 0.0
         assert_maps_close(maps[b], ref[b], f"band-edge row {b}")
@@ -325,6 +321,5 @@ def test_lines_outside_the_band(O, gbk):
     c, n = c.cpu().numpy(), n.cpu().numpy()
     rc, rn = oracle_chi2(O, grid, rows, obs)
     np.testing.assert_array_equal(n, rn)
-    for b in (0, 1, 3, 4):
+    for b in range(5):
         assert_chi2_close(c[b], rc[b], rn[b], f"outside-band row {b}", obs=obs)
-    assert np.isfinite(c[2])
