@@ -298,7 +298,7 @@ gk_status enqueue_batch(gk_model *m, const double *params, PtrKind pk, int32_t B
             // chi-square terms per pixel (the channel width only enters
             // constants this path does not read)
             HIP_TRY(timed(0, [&] {
-                return launch_prep(prow, nb, m->d.rc, 1.0, 0, 1, sc->consts, s);
+                return launch_prep(prow, nb, m->d.rc, 1.0, 0, 1, 0.0, 1.0, sc->consts, s);
             }));
             VfArgs v{};
             v.params = prow;
@@ -329,7 +329,8 @@ gk_status enqueue_batch(gk_model *m, const double *params, PtrKind pk, int32_t B
             continue;
         }
         HIP_TRY(timed(0, [&] {
-            return launch_prep(prow, nb, m->d.rc, m->dvf, m->hp, m->d.upsample, sc->consts, s);
+            return launch_prep(prow, nb, m->d.rc, m->dvf, m->hp, m->d.upsample, m->vf0, m->inv_dvf,
+                               sc->consts, s);
         }));
         HIP_TRY(timed(1, [&] {
             return launch_line_sums(sc->consts, m->d_wz, m->NZE, m->EX, m->EY, m->hp,

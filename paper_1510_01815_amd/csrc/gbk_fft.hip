@@ -157,17 +157,8 @@ __global__ __launch_bounds__(256) void k_fft_y_moments(FftArgs f, PsfArgs a)
         if (!valid) {
             m0 = m1 = m2 = __builtin_nan("");
         } else {
-            const double s0 = S[0] * inv_uu, s1 = S[1] * inv_uu, s2 = S[2] * inv_uu;
-            if (s0 > 0.0) {
-                const double mr = s1 / s0;
-                m0 = a.dv * s0;
-                m1 = a.vref + mr;
-                m2 = sqrt(fmax(s2 / s0 - mr * mr, 0.0));
-            } else {
-                m0 = 0.0;
-                m1 = cbp[C_VSYS];
-                m2 = 0.0;
-            }
+            moment_maps(S[0] * inv_uu, S[1] * inv_uu, S[2] * inv_uu, a.dv, a.vref, cbp[C_VSYS], m0,
+                        m1, m2);
         }
         if (a.maps) {
             float *mb = a.maps + (size_t)b * 3 * npix;

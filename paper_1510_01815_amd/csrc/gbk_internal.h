@@ -41,6 +41,13 @@ enum { RC_ARCTAN = 0, RC_EPINAT = 1, RC_BOISSIER = 2 };
 enum {
     C_XO = 0, C_YO, C_SPA, C_CPA, C_SECI, C_SINI, C_VSYS, C_VT, C_IRT, C_IR0, C_LOG2AMP, C_KAPPA,
     C_A, C_G, C_VALID, C_ZSPAN, C_SQK, C_Q, C_VTSINI, C_XEX, C_XEY, C_XE0, C_YEX, C_YEY, C_YE0,
+    // for the line-sum kernel: two FP32 values packed in one slot each (read
+    // straight from scalar registers), the line centre at zero projected
+    // rotation in fine halo channels, and the brightness exponent's factor
+    C_F32A,  // {1 / r_t, V_t sin i / fine channel width}
+    C_F32B,  // {channel span of the 2^-40 support, 0}
+    C_ZC0,   // (Vsys - v(first fine halo channel)) / fine channel width
+    C_IR0L,  // log2(e) / r0
     NCONST
 };
 
@@ -57,6 +64,33 @@ constexpr int kMaxFastHalo = 16;
 // Fine channels with the LSF halo (NZE) a model may have: the line-sum kernel
 // packs a wave's channel range into two 16-bit fields of values up to NZE + 1.
 constexpr int kMaxFineChannels = 65534;
+
+// Moment maps of one pixel (Sec. 2.2.5) from its sums s0 = sum C, s1 =
+// sum C vrel, s2 = sum C vrel^2 (vrel: channel velocity minus vref):
+// m0 = dv s0, m1 = vref + s1/s0, m2 = sqrt(max(s2/s0 - (s1/s0)^2, 0)); a pixel
+// without flux gives (0, vsys, 0).  1/s0 and the square root come from the
+// hardware reciprocal and reciprocal square root, each refined by one Newton
+// step (relative error ~1e-16); a variance below 2^-1000 gives m2 = 0.
+__device__ inline void moment_maps(double s0, double s1, double s2, double dv, double vref,
+                                   double vsys, double &m0, double &m1, double &m2)
+{
+    if (s0 > 0.0) {
+        double inv = __builtin_amdgcn_rcp(s0);
+        inv = fma(inv, fma(-s0, inv, 1.0), inv);
+        const double mr = s1 * inv;
+        m0 = dv * s0;
+        m1 = vref + mr;
+        const double var = s2 * inv - mr * mr;
+        const double r = __builtin_amdgcn_rsq(var);
+        double sd = var * r;
+        sd = fma(fma(-sd, sd, var), 0.5 * r, sd);
+        m2 = var > 0x1p-1000 ? sd : 0.0;
+    } else {
+        m0 = 0.0;
+        m1 = vsys;
+        m2 = 0.0;
+    }
+}
 
 struct PsfArgs {
     const double *T;       // [B][3][EY][EX]
@@ -127,7 +161,7 @@ hipError_t launch_reduce_multi(const double *partial, const ModelDev *md, const 
                                const double *consts, double *chi2, int B, hipStream_t s);
 
 hipError_t launch_prep(const double *params, int B, int rc, double dvf, int hp, int u,
-                       double *consts, hipStream_t s);
+                       double vf0, double inv_dvf, double *consts, hipStream_t s);
 hipError_t launch_line_sums(const double *consts, const double *wz, int NZE, int EX, int EY,
                             int hp, int u, int rc, double vf0, double inv_dvf, float zedge_lo,
                             float zedge_hi, double *T, unsigned long long *support_count, int B,

@@ -50,8 +50,13 @@ constexpr double kPi = 3.14159265358979323846;
 // ---------------------------------------------------------------------------
 // k_prep: per-row constants (FP64) -- slot layout in gbk_internal.h
 // ---------------------------------------------------------------------------
+__device__ inline double pack_f32x2(float lo, float hi)
+{
+    return __builtin_bit_cast(double, make_float2(lo, hi));
+}
+
 __device__ void prep_row(const double *__restrict__ p, double *__restrict__ c, int rc, double dvf,
-                         int hp, int u)
+                         int hp, int u, double vf0, double inv_dvf)
 {
     bool ok = true;
     for (int k = 0; k < NPAR; ++k) ok = ok && isfinite(p[k]);
@@ -85,6 +90,10 @@ __device__ void prep_row(const double *__restrict__ p, double *__restrict__ c, i
     c[C_SQK] = sqrt(kappa);
     c[C_Q] = exp2(-2.0 * kappa);
     c[C_VTSINI] = p[P_VT] * sin(inc);
+    c[C_F32A] = pack_f32x2((float)c[C_IRT], (float)(c[C_VTSINI] * inv_dvf));
+    c[C_F32B] = pack_f32x2((float)c[C_ZSPAN], 0.0f);
+    c[C_ZC0] = (p[P_VSYS] - vf0) * inv_dvf;
+    c[C_IR0L] = kLog2e * c[C_IR0];
     // fine pixel (gx, gy) of the halo-extended grid sits at x = gx/u + base
     const double invu = 1.0 / u, base = (0.5 - hp) * invu - 0.5;
     const double sp = c[C_SPA], cp = c[C_CPA], se = c[C_SECI];
@@ -98,10 +107,12 @@ __device__ void prep_row(const double *__restrict__ p, double *__restrict__ c, i
 }
 
 __global__ void k_prep(const double *__restrict__ params, int B, int rc, double dvf, int hp,
-                       int u, double *__restrict__ consts)
+                       int u, double vf0, double inv_dvf, double *__restrict__ consts)
 {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b < B) prep_row(params + (size_t)b * NPAR, consts + (size_t)b * NCONST, rc, dvf, hp, u);
+    if (b < B)
+        prep_row(params + (size_t)b * NPAR, consts + (size_t)b * NCONST, rc, dvf, hp, u, vf0,
+                 inv_dvf);
 }
 
 // Row -> model lookup of the ragged multi-model launches: the largest k with
@@ -124,7 +135,8 @@ __global__ void k_prep_multi(const double *__restrict__ params, int B,
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= B) return;
     const ModelDev &m = md[row_model[b]];
-    prep_row(params + (size_t)b * NPAR, consts + (size_t)b * NCONST, m.rc, m.dvf, m.hp, m.u);
+    prep_row(params + (size_t)b * NPAR, consts + (size_t)b * NCONST, m.rc, m.dvf, m.hp, m.u,
+             m.vf0, m.inv_dvf);
 }
 
 // ---------------------------------------------------------------------------
@@ -152,14 +164,6 @@ __device__ inline void wave_min2(int a, int b, int &amin, int &bmin)
     const unsigned hi = min(min(r0 >> 16, r1 >> 16), min(r2 >> 16, r3 >> 16));
     amin = (int)lo;
     bmin = (int)hi;
-}
-
-// 1/sqrt(r2) in FP64 (r2 >= 0; ~1e15 at r2 = 0): the FP32 estimate refined
-// by one Newton step (relative error ~1e-14)
-__device__ inline double y0_refine(double r2)
-{
-    const double y0 = (double)__builtin_amdgcn_rsqf(fmaxf((float)r2, 1e-30f));
-    return y0 * fma(-0.5 * r2 * y0, y0, 1.5);
 }
 
 // 2^x for x in roughly [-1070, 1000] in FP64 with FP32 relative accuracy:
@@ -233,8 +237,10 @@ __device__ __forceinline__ void line_sums_tile(const double *__restrict__ c,
     const double xe = fma(fx, c[C_XEX], fma(fy, c[C_XEY], c[C_XE0]));
     const double ye = fma(fx, c[C_YEX], fma(fy, c[C_YEY], c[C_YE0]));
     const double r2 = fma(xe, xe, ye * ye);
-    const double yr = y0_refine(r2);  // 1/r, FP64
-    const double rd = r2 * yr;
+    // y0 ~ 1/r (FP32), t = r2 y0 ~ r, one Newton step: r = t (1 + e/2), e = 1 - r2 y0^2
+    const double y0 = (double)__builtin_amdgcn_rsqf(fmaxf((float)r2, 1e-30f));
+    const double t = r2 * y0, e = fma(-t, y0, 1.0);
+    const double rd = fma(0.5 * t, e, t);
     const float r = (float)rd;
 
     // rotation curve (eqs. 6-7 or exponential rise) and eq. 8.  The bounded
@@ -243,15 +249,20 @@ __device__ __forceinline__ void line_sums_tile(const double *__restrict__ c,
     // when g > a (Sec. 2.1.3), where FP32 would leave ~3e-7 of a velocity of
     // thousands of km/s in the line centre, and a line centred outside the
     // band then changes its in-band wing by ~1e-5; that curve runs in FP64.
-    double vlos;
+    // line centre zc in fine halo-channel units: eq. 8 divided by the fine
+    // channel width, with the line centre at zero rotation (C_ZC0) in FP64
+    double zc;
     if (rc == RC_EPINAT) {
         // shape 0 at r = 0, where a = 0 would give exp2(0 * -inf) = NaN
+        const double yr = y0 * fma(0.5, e, 1.0);  // 1/r
         const double lq = log2(rd * c[C_IRT]);
         const double shape = r2 > 0.0 ? exp2(c[C_G] * lq) / (1.0 + exp2(c[C_A] * lq)) : 0.0;
-        vlos = c[C_VSYS] + c[C_VTSINI] * shape * (r2 > 0.0 ? xe * yr : 0.0);
+        const double vlos = c[C_VSYS] + c[C_VTSINI] * shape * (r2 > 0.0 ? xe * yr : 0.0);
+        zc = (vlos - vf0) * inv_dvf;
     } else {
+        const float2 fa = __builtin_bit_cast(float2, c[C_F32A]);
         const float costh = r > 0.0f ? (float)xe * __builtin_amdgcn_rcpf(r) : 0.0f;
-        const float q = r * (float)c[C_IRT];
+        const float q = r * fa.x;
         float shape;
         if (rc == RC_ARCTAN) {
             shape = (float)(2.0 / kPi) * atanf(q);
@@ -259,12 +270,11 @@ __device__ __forceinline__ void line_sums_tile(const double *__restrict__ c,
             // 1 - e^-q; absolute error ~1e-7, i.e. ~1e-5 km/s on the velocity
             shape = 1.0f - __builtin_amdgcn_exp2f(-q * (float)kLog2e);
         }
-        vlos = c[C_VSYS] + (double)((float)c[C_VTSINI] * shape * costh);
+        zc = c[C_ZC0] + (double)(fa.y * shape * costh);
     }
 
-    // line centre in fine halo-channel units and its significant range
-    const double zc = (vlos - vf0) * inv_dvf;
-    const float zcf = (float)zc, span = (float)c[C_ZSPAN];
+    // its significant range
+    const float zcf = (float)zc, span = __builtin_bit_cast(float2, c[C_F32B]).x;
     // clamp in floating point first so that the integer conversion cannot overflow;
     // an empty range is lo = NZE, hi = -1 (packed below as NZE - hi = NZE + 1)
     const int lo0 = in ? (int)fminf(fmaxf(ceilf(zcf - span), 0.0f), (float)NZE) : NZE;
@@ -287,7 +297,7 @@ __device__ __forceinline__ void line_sums_tile(const double *__restrict__ c,
 
     // log2 of the brightness factor: I(r) / (sqrt(2 pi) sigma), eq. 5 with the
     // exp(-60) floor
-    const double lamp = c[C_LOG2AMP] - fmin(rd * c[C_IR0], 60.0) * kLog2e;
+    const double lamp = c[C_LOG2AMP] - fmin(rd * c[C_IR0L], 60.0 * kLog2e);
     const double sqk = c[C_SQK];
     const double4 *w = reinterpret_cast<const double4 *>(wz);
     const double e0 = ((double)zlo - zc) * sqk;
@@ -452,17 +462,8 @@ __device__ __forceinline__ void psf_generic_tile(const PsfArgs &a, const RowPtrs
         if (!valid) {
             m0 = m1 = m2 = __builtin_nan("");
         } else {
-            const double s0 = S[0][q] * inv_uu, s1 = S[1][q] * inv_uu, s2 = S[2][q] * inv_uu;
-            if (s0 > 0.0) {
-                const double mr = s1 / s0;
-                m0 = a.dv * s0;
-                m1 = a.vref + mr;
-                m2 = sqrt(fmax(s2 / s0 - mr * mr, 0.0));
-            } else {
-                m0 = 0.0;
-                m1 = cb[C_VSYS];
-                m2 = 0.0;
-            }
+            moment_maps(S[0][q] * inv_uu, S[1][q] * inv_uu, S[2][q] * inv_uu, a.dv, a.vref,
+                        cb[C_VSYS], m0, m1, m2);
         }
         const size_t npix = (size_t)a.nx * a.ny;
         if (r.maps) {
@@ -604,18 +605,10 @@ __device__ __forceinline__ void psf_u1_tile(const PsfArgs &a, const RowPtrs &r)
         if (xd >= a.nx || yd >= a.ny) continue;
         const size_t p = (size_t)yd * a.nx + xd;
         double m0, m1, m2;
-        if (!valid) {
+        if (!valid)
             m0 = m1 = m2 = __builtin_nan("");
-        } else if (S[0][q] > 0.0) {
-            const double mr = S[1][q] / S[0][q];
-            m0 = a.dv * S[0][q];
-            m1 = a.vref + mr;
-            m2 = sqrt(fmax(S[2][q] / S[0][q] - mr * mr, 0.0));
-        } else {
-            m0 = 0.0;
-            m1 = cb[C_VSYS];
-            m2 = 0.0;
-        }
+        else
+            moment_maps(S[0][q], S[1][q], S[2][q], a.dv, a.vref, cb[C_VSYS], m0, m1, m2);
         if (r.maps) {
             float *mb = r.maps;
             mb[p] = (float)m0;
@@ -758,19 +751,11 @@ __device__ __forceinline__ void psf_yx_tile(const PsfArgs &a, const RowPtrs &r)
         double m0[4], m1[4], m2[4];
 #pragma unroll
         for (int o = 0; o < 4; ++o) {
-            if (!valid) {
+            if (!valid)
                 m0[o] = m1[o] = m2[o] = __builtin_nan("");
-            } else if (S[0][o] > 0.0) {
-                const double inv = 1.0 / S[0][o];
-                const double mr = S[1][o] * inv;
-                m0[o] = a.dv * S[0][o];
-                m1[o] = a.vref + mr;
-                m2[o] = sqrt(fmax(S[2][o] * inv - mr * mr, 0.0));
-            } else {
-                m0[o] = 0.0;
-                m1[o] = cb[C_VSYS];
-                m2[o] = 0.0;
-            }
+            else
+                moment_maps(S[0][o], S[1][o], S[2][o], a.dv, a.vref, cb[C_VSYS], m0[o], m1[o],
+                            m2[o]);
         }
         const size_t p0 = (size_t)yd * a.nx + xd0;
         double rv[4], rs[4];
@@ -1029,9 +1014,10 @@ hipError_t launch_reduce_multi(const double *partial, const ModelDev *md, const 
     return hipGetLastError();
 }
 hipError_t launch_prep(const double *params, int B, int rc, double dvf, int hp, int u,
-                       double *consts, hipStream_t s)
+                       double vf0, double inv_dvf, double *consts, hipStream_t s)
 {
-    launch(k_prep, dim3((B + 63) / 64), dim3(64), 0, s, params, B, rc, dvf, hp, u, consts);
+    launch(k_prep, dim3((B + 63) / 64), dim3(64), 0, s, params, B, rc, dvf, hp, u, vf0, inv_dvf,
+           consts);
     return hipGetLastError();
 }
 
