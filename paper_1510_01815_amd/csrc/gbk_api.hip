@@ -337,29 +337,9 @@ gk_status enqueue_batch(gk_model *m, const double *params, PtrKind pk, int32_t B
                                     m->d.upsample, m->d.rc, m->vf0, m->inv_dvf, m->zedge_lo,
                                     m->zedge_hi, sc->T, counter, nb, s);
         }));
-        PsfArgs a{};
+        PsfArgs a = psf_args(m, resid || chi2);
         a.T = sc->T;
         a.consts = sc->consts;
-        a.kp = m->d_kp;
-        a.hp = m->hp;
-        a.u = m->d.upsample;
-        a.nx = m->d.nx;
-        a.ny = m->d.ny;
-        a.EX = m->EX;
-        a.EY = m->EY;
-        a.TXd = m->TXd;
-        a.TYd = m->TYd;
-        a.ntx = m->ntx;
-        a.ntiles = m->ntiles;
-        a.dv = m->d.dv_kms;
-        a.vref = m->vref;
-        if (resid || chi2) {
-            a.mask = m->d_mask;
-            a.vo = m->d_vo;
-            a.so = m->d_so;
-            a.iev = m->d_iev;
-            a.ies = m->d_ies;
-        }
         a.maps = maps ? maps + (size_t)b0 * 3 * npix : nullptr;
         a.resid = resid ? resid + (size_t)b0 * 2 * npix : nullptr;
         a.partial = chi2 ? sc->partial : nullptr;
@@ -444,6 +424,34 @@ hipError_t noalloc_scratch(int dev, unsigned char **out)
 }
 
 }  // namespace
+
+// PSF/moment-pass arguments of a model (row pointers and outputs unset); the
+// observation's pointers when with_obs.
+PsfArgs gbk::psf_args(const gk_model *m, bool with_obs)
+{
+    PsfArgs a{};
+    a.kp = m->d_kp;
+    a.hp = m->hp;
+    a.u = m->d.upsample;
+    a.nx = m->d.nx;
+    a.ny = m->d.ny;
+    a.EX = m->EX;
+    a.EY = m->EY;
+    a.TXd = m->TXd;
+    a.TYd = m->TYd;
+    a.ntx = m->ntx;
+    a.ntiles = m->ntiles;
+    a.dv = m->d.dv_kms;
+    a.vref = m->vref;
+    if (with_obs) {
+        a.mask = m->d_mask;
+        a.vo = m->d_vo;
+        a.so = m->d_so;
+        a.iev = m->d_iev;
+        a.ies = m->d_ies;
+    }
+    return a;
+}
 
 // The launch chain of B device rows on s, with the model's scratch and no
 // graph bookkeeping (the caller may be recording a graph of its own).

@@ -12,8 +12,10 @@
 
 #include <cfloat>
 #include <cmath>
+#include <array>
 #include <cstring>
 #include <new>
+#include <utility>
 #include <vector>
 
 #include "gbk_model.h"
@@ -242,10 +244,10 @@ constexpr int kLMGraphIters = 8;  // iterations recorded per graph replay
 // Rows of the trial point pt and its central-difference Jacobian rows, and
 // the columns' scales 1 / (p+ - p-) (the header's rule).  After the fit has
 // ended the rows are made invalid, so the evaluation kernels skip them.
-__global__ void k_lm_rows(const LMDev *__restrict__ st, double *__restrict__ rows,
-                          double *__restrict__ scale)
+__device__ void lm_rows(const LMDev *__restrict__ st, double *__restrict__ rows,
+                        double *__restrict__ scale, int t)
 {
-    const int t = threadIdx.x, nf = st->nf;
+    const int nf = st->nf;
     if (t < 1 + 2 * nf) {
         double *r = rows + (size_t)t * NPAR;
         for (int k = 0; k < NPAR; ++k) r[k] = st->pt[k];
@@ -263,9 +265,24 @@ __global__ void k_lm_rows(const LMDev *__restrict__ st, double *__restrict__ row
     }
 }
 
+__global__ void k_lm_rows(const LMDev *__restrict__ st, double *__restrict__ rows,
+                          double *__restrict__ scale)
+{
+    lm_rows(st, rows, scale, threadIdx.x);
+}
+
 #pragma clang fp contract(off)
+// Work arrays of the step rule, kept in LDS by the kernels that run it (one
+// thread's private arrays would live in scratch memory, where each dependent
+// access of the serial solve waits on memory).
+struct LMWork {
+    double A[kMaxFree * kMaxFree], g[kMaxFree], M[kMaxFree * kMaxFree];
+    double rhs[kMaxFree], x[kMaxFree], y[kMaxFree], d[kMaxFree];
+    int act[kMaxFree];
+};
+
 // Cholesky solve of M x = b (n <= kMaxFree), as cholesky_solve on the host.
-__device__ bool lm_chol(double *M, int n, const double *b, double *x)
+__device__ bool lm_chol(double *M, int n, const double *b, double *x, double *y)
 {
     for (int i = 0; i < n; ++i)
         for (int j = 0; j <= i; ++j) {
@@ -278,7 +295,6 @@ __device__ bool lm_chol(double *M, int n, const double *b, double *x)
                 M[i * n + j] = v / M[j * n + j];
             }
         }
-    double y[kMaxFree];
     for (int i = 0; i < n; ++i) {
         double v = b[i];
         for (int k = 0; k < i; ++k) v -= M[i * n + k] * y[k];
@@ -295,12 +311,12 @@ __device__ bool lm_chol(double *M, int n, const double *b, double *x)
 // One step of the rule: take the trial's normal equations `norm` (pairs a <= b
 // in row order, then J^T r, then chi2), accept or reject the trial, test the
 // stopping rules, and form the next trial point (one thread).
-__global__ void k_lm_update(LMDev *__restrict__ st, const double *__restrict__ norm)
+__device__ void lm_rule(LMDev *__restrict__ st, const double *__restrict__ norm, LMWork *__restrict__ w)
 {
-    if (threadIdx.x != 0 || st->done) return;
+    if (st->done) return;
     const int nf = st->nf, npairs = nf * (nf + 1) / 2;
     st->n_evals += 1 + 2 * nf;
-    double A[kMaxFree * kMaxFree], g[kMaxFree];
+    double *A = w->A, *g = w->g;
     bool fin = true;
     for (int a = 0, k = 0; a < nf; ++a)
         for (int b = a; b < nf; ++b, ++k) {
@@ -361,19 +377,19 @@ __global__ void k_lm_update(LMDev *__restrict__ st, const double *__restrict__ n
     }
     st->it += 1;
     // (A + lam diag A) d = -g over the slots with a non-zero Jacobian column
-    int act[kMaxFree], na = 0;
+    int *act = w->act, na = 0;
     for (int a = 0; a < nf; ++a)
         if (st->A[a * nf + a] > 0.0) act[na++] = a;
-    double d[kMaxFree];
+    double *d = w->d;
     for (int a = 0; a < nf; ++a) d[a] = 0.0;
     if (na) {
-        double M[kMaxFree * kMaxFree], rhs[kMaxFree], x[kMaxFree];
+        double *M = w->M, *rhs = w->rhs, *x = w->x;
         for (int i = 0; i < na; ++i) {
             for (int j = 0; j < na; ++j) M[i * na + j] = st->A[act[i] * nf + act[j]];
             M[i * na + i] *= 1.0 + st->lam;
             rhs[i] = -st->g[act[i]];
         }
-        if (lm_chol(M, na, rhs, x))
+        if (lm_chol(M, na, rhs, x, w->y))
             for (int i = 0; i < na; ++i) d[act[i]] = x[i];
     }
     for (int k = 0; k < NPAR; ++k) st->pt[k] = st->p[k];
@@ -382,7 +398,229 @@ __global__ void k_lm_update(LMDev *__restrict__ st, const double *__restrict__ n
         st->pt[k] = fmin(fmax(st->p[k] + d[a], st->lo[k]), st->hi[k]);
     }
 }
+
+// lm_rule for a compile-time number of free slots, with the damped system in
+// registers: every index is static, so the serial solve keeps its operands in
+// registers instead of waiting on memory.  A slot whose Jacobian column is
+// zero gets an identity row and a zero right-hand side instead of being
+// dropped from the system; the terms this adds are exact zeros, so the other
+// slots' steps are those of the compressed solve bit for bit.
+template <int NF>
+__device__ void lm_rule_t(LMDev *__restrict__ st, const double *__restrict__ norm)
+{
+    constexpr int NPr = NF * (NF + 1) / 2;
+    if (st->done) return;
+    st->n_evals += 1 + 2 * NF;
+    bool fin = true;
+#pragma unroll
+    for (int k = 0; k < NPr + NF; ++k) fin = fin && isfinite(norm[k]);
+    double chi2 = norm[NPr + NF];
+    if (!isfinite(chi2)) chi2 = INFINITY;
+    fin = fin && isfinite(chi2);
+    bool take = false;
+    if (!st->started) {
+        st->started = 1;
+        if (!fin) {
+            st->done = 1;
+            st->reason = kLMBadStart;
+            return;
+        }
+        take = true;
+    } else if (fin && chi2 < st->chi2) {
+        double step = 0.0;
+#pragma unroll
+        for (int a = 0; a < NF; ++a) {
+            const int k = st->fr[a];
+            step = fmax(step, fabs(st->pt[k] - st->p[k]) / (fabs(st->p[k]) + 1e-10));
+        }
+        const double dec = st->chi2 > 0.0 ? (st->chi2 - chi2) / st->chi2 : 0.0;
+        take = true;
+        st->lam /= 10.0;
+        if (chi2 == 0.0 || dec <= st->ftol) {
+            st->reason = GK_LM_FTOL;
+            st->done = 1;
+        } else if (step <= st->xtol) {
+            st->reason = GK_LM_XTOL;
+            st->done = 1;
+        }
+    } else {
+        st->lam *= 10.0;
+        if (st->lam > 1e10) {
+            st->reason = GK_LM_LAMBDA;
+            st->done = 1;
+        }
+    }
+    if (take) {
+        for (int k = 0; k < NPAR; ++k) st->p[k] = st->pt[k];
+#pragma unroll
+        for (int a = 0, k = 0; a < NF; ++a)
+#pragma unroll
+            for (int b = a; b < NF; ++b, ++k) st->A[a * NF + b] = st->A[b * NF + a] = norm[k];
+#pragma unroll
+        for (int a = 0; a < NF; ++a) st->g[a] = norm[NPr + a];
+        st->chi2 = chi2;
+    }
+    if (st->done) return;
+    if (st->it >= st->max_iter) {
+        st->reason = GK_LM_MAXITER;
+        st->done = 1;
+        return;
+    }
+    st->it += 1;
+    // (A + lam diag A) d = -g; lower triangle L(i, j) at i (i + 1) / 2 + j
+    double L[NPr], y[NF], x[NF];
+    bool act[NF];
+    const double damp = 1.0 + st->lam;
+#pragma unroll
+    for (int i = 0; i < NF; ++i) act[i] = st->A[i * NF + i] > 0.0;
+#pragma unroll
+    for (int i = 0; i < NF; ++i)
+#pragma unroll
+        for (int j = 0; j <= i; ++j) {
+            double v = (act[i] && act[j]) ? st->A[i * NF + j] : (i == j ? 1.0 : 0.0);
+            if (i == j && act[i]) v *= damp;
+            L[i * (i + 1) / 2 + j] = v;
+        }
+    bool ok = true;
+#pragma unroll
+    for (int i = 0; i < NF; ++i)
+#pragma unroll
+        for (int j = 0; j <= i; ++j) {
+            double v = L[i * (i + 1) / 2 + j];
+#pragma unroll
+            for (int k = 0; k < j; ++k) v -= L[i * (i + 1) / 2 + k] * L[j * (j + 1) / 2 + k];
+            if (i == j) {
+                ok = ok && v > 0.0;
+                L[i * (i + 1) / 2 + i] = sqrt(v);
+            } else {
+                L[i * (i + 1) / 2 + j] = v / L[j * (j + 1) / 2 + j];
+            }
+        }
+#pragma unroll
+    for (int i = 0; i < NF; ++i) {
+        double v = act[i] ? -st->g[i] : 0.0;
+#pragma unroll
+        for (int k = 0; k < i; ++k) v -= L[i * (i + 1) / 2 + k] * y[k];
+        y[i] = v / L[i * (i + 1) / 2 + i];
+    }
+#pragma unroll
+    for (int i = NF - 1; i >= 0; --i) {
+        double v = y[i];
+#pragma unroll
+        for (int k = i + 1; k < NF; ++k) v -= L[k * (k + 1) / 2 + i] * x[k];
+        x[i] = v / L[i * (i + 1) / 2 + i];
+    }
+    for (int k = 0; k < NPAR; ++k) st->pt[k] = st->p[k];
+#pragma unroll
+    for (int a = 0; a < NF; ++a) {
+        const int k = st->fr[a];
+        const double d = ok && act[a] ? x[a] : 0.0;
+        st->pt[k] = fmin(fmax(st->p[k] + d, st->lo[k]), st->hi[k]);
+    }
+}
+
+// Copies of the fit state between global memory and LDS (all threads of the block).
+__device__ void lm_copy(LMDev *__restrict__ dst, const LMDev *__restrict__ src)
+{
+    static_assert(sizeof(LMDev) % 4 == 0, "state copied as 32-bit words");
+    const uint32_t *s = reinterpret_cast<const uint32_t *>(src);
+    uint32_t *d = reinterpret_cast<uint32_t *>(dst);
+    for (int i = threadIdx.x; i < (int)(sizeof(LMDev) / 4); i += blockDim.x) d[i] = s[i];
+}
+
+__global__ void k_lm_update(LMDev *__restrict__ st, const double *__restrict__ norm)
+{
+    __shared__ LMDev ls;
+    __shared__ LMWork lw;
+    lm_copy(&ls, st);
+    __syncthreads();
+    if (threadIdx.x == 0) lm_rule(&ls, norm, &lw);
+    __syncthreads();
+    lm_copy(st, &ls);
+}
 #pragma clang fp contract(on)
+
+// One fused step of the Levenberg-Marquardt iteration for residual rows of a
+// single chunk (n <= 16384 weighted entries): the trial's normal equations in
+// the summation order of k_lm_normal_rows (thread t sums entries t, t + 256,
+// ... in order, then the lanes by butterfly and the waves in order, so the
+// sums are the same bit for bit), the step rule, and the next trial's rows and
+// column scales.  first: only the rows (the start of a fit).
+template <int NF>
+__global__ __launch_bounds__(256) void k_lm_step(LMDev *__restrict__ st,
+                                                 const double *__restrict__ R, int64_t stride,
+                                                 int64_t n, double *__restrict__ rows,
+                                                 double *__restrict__ scale, int first)
+{
+    constexpr int NP = NF * (NF + 1) / 2, NB = NP + NF + 1;
+    __shared__ double norm[NB];
+    __shared__ double ws[4][NB];
+    __shared__ LMDev ls;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    lm_copy(&ls, st);
+    if (!first) {
+        double sc[NF], acc[NB];
+#pragma unroll
+        for (int a = 0; a < NF; ++a) sc[a] = scale[a];
+#pragma unroll
+        for (int k = 0; k < NB; ++k) acc[k] = 0.0;
+        // entries t, t + 256, ... in order, U of them loaded before their sums
+        constexpr int U = NF <= 8 ? 2 : 1;
+        for (int64_t i0 = tid; i0 < n; i0 += 256 * U) {
+            double r0[U], j[U][NF];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t i = i0 + 256 * u < n ? i0 + 256 * u : i0;
+                r0[u] = R[i];
+#pragma unroll
+                for (int a = 0; a < NF; ++a)
+                    j[u][a] = (R[(size_t)(1 + 2 * a) * stride + i] - R[(size_t)(2 + 2 * a) * stride + i]) * sc[a];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (i0 + 256 * u >= n) break;
+                int k = 0;
+#pragma unroll
+                for (int a = 0; a < NF; ++a)
+#pragma unroll
+                    for (int b = a; b < NF; ++b) acc[k++] += j[u][a] * j[u][b];
+#pragma unroll
+                for (int a = 0; a < NF; ++a) acc[NP + a] += j[u][a] * r0[u];
+                acc[NB - 1] += r0[u] * r0[u];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+            double v = acc[k];
+            for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+            if (lane == 0) ws[wave][k] = v;
+        }
+        __syncthreads();
+        if (tid < NB) norm[tid] = 0.0 + (((ws[0][tid] + ws[1][tid]) + ws[2][tid]) + ws[3][tid]);
+        __syncthreads();
+        if (tid == 0) lm_rule_t<NF>(&ls, norm);
+        __syncthreads();
+        lm_copy(st, &ls);
+    } else {
+        __syncthreads();
+    }
+    lm_rows(&ls, rows, scale, tid);
+}
+
+template <int NF>
+void launch_lm_step(LMDev *st, const double *R, int64_t stride, int64_t n, double *rows,
+                    double *scale, int first, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_lm_step<NF>, dim3(1), dim3(256), 0, s, st, R, stride, n, rows, scale,
+                       first);
+}
+using LMStepFn = void (*)(LMDev *, const double *, int64_t, int64_t, double *, double *, int,
+                          hipStream_t);
+template <int... F> constexpr auto make_lm_step_table(std::integer_sequence<int, F...>)
+{
+    return std::array<LMStepFn, sizeof...(F)>{&launch_lm_step<F + 1>...};
+}
+const auto kLMStepTable = make_lm_step_table(std::make_integer_sequence<int, kMaxFree>{});
 
 // Grows the fitter workspace to `rows` parameter rows (and `resid_rows`
 // residual rows when > 0).
@@ -553,8 +791,28 @@ extern "C" gk_status gk_fit_lm(gk_model *m, double *p_io, const uint8_t *free_ma
     HIP_TRY(m->reserve(std::min(rows, m->chunk_rows())));
     LMDev *d_st = (LMDev *)w->d_lm;
     double *d_scale = (double *)(w->d_aux + 4 * sizeof(int64_t));
+    // Small u = 1 models whose residual rows form one chunk take two launches
+    // per iteration: every row's whole evaluation in one workgroup
+    // (k_eval_small), then the normal equations, the step rule and the next
+    // rows in one workgroup (k_lm_step); the results are those of the general
+    // chain below bit for bit.
+    PsfArgs pa = psf_args(m, true);
+    pa.resid = w->d_resid;
+    const bool fused = nf >= 1 && used <= 16384 && !m->prof_flags &&
+                       eval_small_ok(pa, m->d.upsample, m->use_fft, kMaxLds);
+    if (fused) {
+        kLMStepTable[nf - 1](d_st, w->d_resid, n, used, w->d_params, d_scale, 1, w->stream);
+        HIP_TRY(hipGetLastError());
+    }
     // one iteration: trial rows -> residuals -> J^T J, J^T r, chi2 -> step rule
     auto iteration = [&]() -> gk_status {
+        if (fused) {
+            HIP_TRY(launch_eval_small(w->d_params, m->d_wz, m->NZE, m->d.rc, m->dvf, m->vf0,
+                                      m->inv_dvf, m->zedge_lo, m->zedge_hi, pa, rows, w->stream));
+            kLMStepTable[nf - 1](d_st, w->d_resid, n, used, w->d_params, d_scale, 0, w->stream);
+            HIP_TRY(hipGetLastError());
+            return GK_OK;
+        }
         hipLaunchKernelGGL(k_lm_rows, dim3(1), dim3(64), 0, w->stream, d_st, w->d_params, d_scale);
         HIP_TRY(hipGetLastError());
         GK_TRY(enqueue_device_rows(m, w->d_params, rows, nullptr, w->d_resid, nullptr, nullptr,

@@ -167,6 +167,15 @@ hipError_t launch_line_sums(const double *consts, const double *wz, int NZE, int
                             float zedge_hi, double *T, unsigned long long *support_count, int B,
                             hipStream_t s);
 hipError_t launch_psf_moments(const PsfArgs &a, int B, size_t lds_bytes, hipStream_t s);
+// One workgroup per parameter row of a small u = 1 model (32 x 32 data
+// tiles, T planes in LDS): constants, line sums, PSF passes, moments, maps and
+// residuals in one launch, equal to k_prep -> k_line_sums -> the 32 x 32 PSF
+// pass; a.consts and a.partial are not used.
+size_t eval_small_lds_bytes(int EX, int EY, int ny);
+bool eval_small_ok(const PsfArgs &a, int u, bool fft, size_t max_lds);
+hipError_t launch_eval_small(const double *params, const double *wz, int NZE, int rc, double dvf,
+                             double vf0, double inv_dvf, float zedge_lo, float zedge_hi,
+                             const PsfArgs &a, int B, hipStream_t s);
 
 // FFT path of the spatial convolution (gbk_fft.hip): k_fft_x convolves every
 // line of the T planes along x into U [B][3][EY][NXF]; k_fft_y_moments

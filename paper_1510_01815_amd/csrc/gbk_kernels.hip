@@ -223,7 +223,9 @@ __device__ __forceinline__ void line_sums_tile(const double *__restrict__ c,
                                                unsigned long long *__restrict__ count)
 {
     if (c[C_VALID] == 0.0) return;  // uniform over the block
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    // a group of four waves covers the tile (workgroups of 256 threads hold
+    // one group, k_eval_small's four)
+    const int wave = (threadIdx.x >> 6) & 3, lane = threadIdx.x & 63;
     const int gx = (tile_x << 4) + ((wave & 1) << 3) + (lane & 7);
     const int gy = (tile_y << 4) + ((wave >> 1) << 3) + (lane >> 3);
     const bool in = gx < EX && gy < EY;
@@ -873,6 +875,116 @@ __global__ __launch_bounds__(256) void k_psf_moments_u1(PsfArgs a)
         psf_yx_tile<HP>(a, single_row(a));
     else
         psf_u1_tile<HP, TX>(a, single_row(a));
+}
+
+// ---------------------------------------------------------------------------
+// k_eval_small: the whole evaluation of one row of a small u = 1 model in one
+// workgroup of 1024 threads, for latency-bound callers (the Levenberg-Marquardt
+// iteration evaluates 1 + 2 n_free rows at a time): the row's constants (one
+// thread, into LDS), the line sums, the PSF passes, moments and residuals, in
+// one launch.  The T planes stay in LDS
+// ([3][EY][EX]); each plane's y pass goes to LDS ([ny][EX]) and its x pass to
+// registers (pixel tid + 1024 q, q < kSmallPix); then moments, maps and the
+// residuals of eq. 11.  The passes take the taps in the order of
+// psf_yx_tile (y first, each output an FMA chain from k = 0 to 2 HP), so the
+// maps and residuals equal, bit for bit, those of the 32 x 32 register-blocked
+// path.
+// ---------------------------------------------------------------------------
+constexpr int kSmallPix = 2;  // pixels per thread: nx * ny <= 2048
+
+__global__ __launch_bounds__(1024) void k_eval_small(const double *__restrict__ params,
+                                                     const double *__restrict__ wz, int NZE,
+                                                     int rc, double dvf, double vf0,
+                                                     double inv_dvf, float zedge_lo,
+                                                     float zedge_hi, PsfArgs a)
+{
+    extern __shared__ double lds[];
+    __shared__ double c[NCONST];  // the row's constants (k_prep's)
+    const int b = blockIdx.x, tid = threadIdx.x, hp = a.hp, K = 2 * a.hp + 1;
+    const int EX = a.EX, EY = a.EY, nx = a.nx, ny = a.ny, npix = nx * ny;
+    if (tid == 0) prep_row(params + (size_t)b * NPAR, c, rc, dvf, hp, 1, vf0, inv_dvf);
+    __syncthreads();
+    const bool valid = c[C_VALID] != 0.0;
+    double *T = lds, *Y = lds + (size_t)3 * EX * EY;
+    if (valid) {  // uniform: line sums of the 16 x 16 tiles, four at a time
+        const int ntx = (EX + 15) >> 4, nt = ntx * ((EY + 15) >> 4);
+        for (int t = tid >> 8; t < nt; t += 4)
+            line_sums_tile(c, wz, NZE, EX, EY, hp, 1, rc, vf0, inv_dvf, zedge_lo, zedge_hi, T,
+                           t % ntx, t / ntx, nullptr);
+    }
+    __syncthreads();
+    double S[3][kSmallPix];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+#pragma unroll
+        for (int q = 0; q < kSmallPix; ++q) S[j][q] = 0.0;
+        if (!valid) continue;
+        const double *Tj = T + (size_t)j * EX * EY;
+        for (int e = tid; e < ny * EX; e += 1024) {
+            const int y = e / EX, x = e - y * EX;
+            const double *col = Tj + (size_t)(y + 2 * hp) * EX + x;
+            double acc = 0.0;
+            for (int k = 0; k < K; ++k) acc = fma(a.kp[k], col[-(ptrdiff_t)k * EX], acc);
+            Y[e] = acc;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < kSmallPix; ++q) {
+            const int p = tid + 1024 * q;
+            if (p >= npix) continue;
+            const int y = p / nx, x = p - y * nx;
+            const double *row = Y + (size_t)y * EX + x + 2 * hp;
+            double acc = 0.0;
+            for (int k = 0; k < K; ++k) acc = fma(a.kp[k], row[-k], acc);
+            S[j][q] = acc;
+        }
+        __syncthreads();
+    }
+    float *maps = a.maps ? a.maps + (size_t)b * 3 * npix : nullptr;
+    double *resid = a.resid ? a.resid + (size_t)b * 2 * npix : nullptr;
+#pragma unroll
+    for (int q = 0; q < kSmallPix; ++q) {
+        const int p = tid + 1024 * q;
+        if (p >= npix) continue;
+        double m0, m1, m2;
+        if (!valid)
+            m0 = m1 = m2 = __builtin_nan("");
+        else
+            moment_maps(S[0][q], S[1][q], S[2][q], a.dv, a.vref, c[C_VSYS], m0, m1, m2);
+        if (maps) {
+            maps[p] = (float)m0;
+            maps[npix + p] = (float)m1;
+            maps[2 * npix + p] = (float)m2;
+        }
+        if (resid && a.mask) {
+            const bool use = a.mask[p] != 0;
+            const double rv = use ? (m1 - (double)a.vo[p]) * a.iev[p] : 0.0;
+            const double rs = use ? (m2 - (double)a.so[p]) * a.ies[p] : 0.0;
+            resid[p] = valid ? rv : __builtin_nan("");
+            resid[npix + p] = valid ? rs : __builtin_nan("");
+        }
+    }
+}
+
+size_t eval_small_lds_bytes(int EX, int EY, int ny)
+{
+    return sizeof(double) * ((size_t)3 * EX * EY + (size_t)ny * EX);
+}
+
+bool eval_small_ok(const PsfArgs &a, int u, bool fft, size_t max_lds)
+{
+    return !fft && u == 1 && a.TXd == 32 && a.TYd == 32 && a.hp <= kMaxFastHalo &&
+           (int64_t)a.nx * a.ny <= 1024 * kSmallPix &&
+           eval_small_lds_bytes(a.EX, a.EY, a.ny) <= max_lds;
+}
+
+hipError_t launch_eval_small(const double *params, const double *wz, int NZE, int rc, double dvf,
+                             double vf0, double inv_dvf, float zedge_lo, float zedge_hi,
+                             const PsfArgs &a, int B, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_eval_small, dim3(B), dim3(1024), eval_small_lds_bytes(a.EX, a.EY, a.ny),
+                       s, params, wz, NZE, rc, dvf, vf0, inv_dvf, zedge_lo, zedge_hi, a);
+    return hipGetLastError();
 }
 
 // Row pointers of a ragged multi-model launch over one bucket of rows.

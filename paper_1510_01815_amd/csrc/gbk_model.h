@@ -252,6 +252,10 @@ gk_status run_batch(gk_model *m, const double *params, int32_t B, float *maps, d
 gk_status enqueue_device_rows(gk_model *m, const double *d_params, int32_t B, float *maps,
                               double *resid, double *chi2, int64_t *nvalid, hipStream_t s);
 
+// PSF/moment-pass arguments of a model (row pointers and outputs unset); the
+// observation's pointers when with_obs.
+PsfArgs psf_args(const gk_model *m, bool with_obs);
+
 // Data tile of a model inside a survey: the model's own, except that the
 // 64 x 32 register-blocked tile (which the survey kernels do not run) becomes
 // the 32 x 32 one, or a generic tile where that does not apply.
