@@ -549,9 +549,13 @@ gk_status gk_surrogate_chi2(gk_surrogate *s, gk_model *model, const double *para
 /* Nested sampling as gk_fit_nested, with every round's candidates screened by
  * the surrogate.  With chi2_floor the plain chi2 of the lowest live point at
  * the start of the round and `shift` the largest surrogate-minus-plain chi2
- * among the latest max(n_live, batch) plainly evaluated candidates (0 before
- * the first), a candidate whose surrogate chi2 exceeds chi2_floor + shift +
- * margin is discarded, except that a Philox draw (counter: candidate, round)
+ * among the latest 4 max(n_live, batch, batch_max) plainly evaluated
+ * candidates whose plain chi2 was within 4 max(margin, 1) of the floor of
+ * their round (the errors the screen must bound are those of acceptable
+ * candidates; until 64 such candidates exist: among the latest
+ * max(n_live, batch) plainly evaluated candidates, 0 before the first), a
+ * candidate whose surrogate chi2 exceeds chi2_floor + shift + margin is
+ * discarded, except that a Philox draw (counter: candidate, round)
  * keeps it with probability audit (the audit sample measures the screen);
  * every other candidate gets the plain chi2, which alone decides acceptance,
  * posterior and evidence.

@@ -558,6 +558,13 @@ class Worker {
 // res, best[] in unit-cube coordinates, the posterior samples post_u [M][d]
 // with normalised weights post_w [M] and their modes post_mode [M], and the
 // final modes (split ones included, with n = 0 live points after the split).
+// Screened sampling: the surrogate's error bound (`shift`) is the largest
+// surrogate-minus-plain chi2 among the latest plain evaluations whose plain
+// chi2 lay within kShiftBand margins of the floor, once kShiftMinNear of them
+// exist (before that, among all the latest plain evaluations).
+constexpr double kShiftBand = 4.0;
+constexpr size_t kShiftMinNear = 64;
+
 gk_status ns_run(int d, const DrawEval &draw_eval, const gk_ns_opts &o, gk_ns_result *res,
                  std::vector<double> &post_u, std::vector<double> &post_w,
                  std::vector<int> &post_mode, std::vector<Mode> &modes, bool &capped)
@@ -1209,6 +1216,12 @@ gk_status fit_nested(gk_model *m, gk_surrogate *sur, const double *lo, const dou
     const uint32_t audit_key[2] = {(uint32_t)o.seed, (uint32_t)(o.seed >> 32) ^ 0x61756474u};
     std::vector<double> recent;  // surrogate-minus-plain chi2 of the latest plain evaluations
     size_t recent_pos = 0;
+    // the same for the latest plain evaluations within kShiftBand of the floor
+    // (the acceptable candidates' errors are what the screen must bound)
+    std::vector<double> near;
+    size_t near_pos = 0;
+    const size_t near_window = (size_t)4 * std::max({o.n_live, o.batch, o.batch_max});
+    const double band = kShiftBand * std::max(margin, 1.0);
     double shift = 0.0;
     std::vector<int> keep;
     std::vector<char> audited;
@@ -1314,10 +1327,18 @@ gk_status fit_nested(gk_model *m, gk_surrogate *sur, const double *lo, const dou
                     recent[recent_pos] = delta;
                     recent_pos = (recent_pos + 1) % window;
                 }
+                if (c < chi2_floor + band) {
+                    if (near.size() < near_window) {
+                        near.push_back(delta);
+                    } else {
+                        near[near_pos] = delta;
+                        near_pos = (near_pos + 1) % near_window;
+                    }
+                }
             }
         }
         shift = 0.0;
-        for (double v : recent) shift = std::max(shift, v);
+        for (double v : near.size() >= kShiftMinNear ? near : recent) shift = std::max(shift, v);
         return GK_OK;
     };
     std::vector<double> pu, pw;
