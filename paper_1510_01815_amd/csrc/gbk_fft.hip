@@ -170,7 +170,7 @@ __global__ __launch_bounds__(256) void k_fft_y_moments(FftArgs f, PsfArgs a)
             const bool use = a.mask[p] != 0;
             const double rv = use ? (m1 - (double)a.vo[p]) * a.iev[p] : 0.0;
             const double rs = use ? (m2 - (double)a.so[p]) * a.ies[p] : 0.0;
-            if (use) acc += rv * rv + rs * rs;
+            if (use) acc += chi2_term(rv, rs);
             if (a.resid) {
                 double *rb = a.resid + (size_t)b * 2 * npix;
                 rb[p] = valid ? rv : __builtin_nan("");

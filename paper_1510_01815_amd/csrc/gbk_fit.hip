@@ -82,6 +82,46 @@ void fit_release(FitWork *w)
     delete w;
 }
 
+// The value that v += __shfl_xor(v, o, 64) for o = 32, 16, ..., 1 leaves in
+// every lane of the wave, bit for bit, with cheaper exchanges: a permlane32
+// swap, a swizzle and four DPP moves per 32-bit half instead of six LDS
+// permutes.  The swap hands each lane the pair (v[l mod 32], v[l mod 32 + 32])
+// in some order, and IEEE addition commutes.  After the steps over 32, 16 and
+// 8 lanes a lane's value depends only on its index mod 8, so the steps over 4,
+// 2 and 1 lanes may rotate the 16 lanes of a row instead of exchanging them.
+template <int CTRL> __device__ __forceinline__ double dpp_f64(double v)
+{
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = __builtin_amdgcn_mov_dpp((int)(uint32_t)u, CTRL, 0xF, 0xF, false);
+    const uint32_t hi = __builtin_amdgcn_mov_dpp((int)(uint32_t)(u >> 32), CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, (uint64_t)lo | ((uint64_t)hi << 32));
+}
+
+__device__ __forceinline__ double wave_butterfly_sum(double v)
+{
+    {
+        const uint64_t u = __builtin_bit_cast(uint64_t, v);
+        const auto lo = __builtin_amdgcn_permlane32_swap((uint32_t)u, (uint32_t)u, false, false);
+        const auto hi = __builtin_amdgcn_permlane32_swap((uint32_t)(u >> 32), (uint32_t)(u >> 32),
+                                                         false, false);
+        const double a = __builtin_bit_cast(double, (uint64_t)lo[0] | ((uint64_t)hi[0] << 32));
+        const double b = __builtin_bit_cast(double, (uint64_t)lo[1] | ((uint64_t)hi[1] << 32));
+        v = a + b;  // xor 32
+    }
+    {
+        const uint64_t u = __builtin_bit_cast(uint64_t, v);
+        constexpr int kSwap16 = 0x401F;  // bitmask mode: and 0x1F, xor 0x10
+        const uint32_t lo = __builtin_amdgcn_ds_swizzle((int)(uint32_t)u, kSwap16);
+        const uint32_t hi = __builtin_amdgcn_ds_swizzle((int)(uint32_t)(u >> 32), kSwap16);
+        v = v + __builtin_bit_cast(double, (uint64_t)lo | ((uint64_t)hi << 32));  // xor 16
+    }
+    v = v + dpp_f64<0x128>(v);  // row_ror 8: xor 8
+    v = v + dpp_f64<0x124>(v);  // row_ror 4
+    v = v + dpp_f64<0x122>(v);  // row_ror 2
+    v = v + dpp_f64<0x121>(v);  // row_ror 1
+    return v;
+}
+
 template <int NF>
 __global__ __launch_bounds__(256) void k_lm_normal_chunks(const double *__restrict__ R,
                                                           const int64_t *__restrict__ goff,
@@ -121,12 +161,12 @@ __global__ __launch_bounds__(256) void k_lm_normal_chunks(const double *__restri
     }
     __shared__ double ws[4][NB];
     const int wave = tid >> 6, lane = tid & 63;
+    // butterfly over the lanes
 #pragma unroll
-    for (int k = 0; k < NB; ++k) {
-        double v = acc[k];
-        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-        if (lane == 0) ws[wave][k] = v;
-    }
+    for (int k = 0; k < NB; ++k) acc[k] = wave_butterfly_sum(acc[k]);
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < NB; ++k) ws[wave][k] = acc[k];
     __syncthreads();
     if (tid < NB)
         partial[((size_t)g * nchunk + ch) * NB + tid] = ((ws[0][tid] + ws[1][tid]) + ws[2][tid]) + ws[3][tid];
@@ -528,6 +568,43 @@ __device__ void lm_copy(LMDev *__restrict__ dst, const LMDev *__restrict__ src)
     for (int i = threadIdx.x; i < (int)(sizeof(LMDev) / 4); i += blockDim.x) d[i] = s[i];
 }
 
+// The fit state in the registers of a block of BS threads (word t + BS q of
+// the state in thread t), so that its fetch can be issued early and its store
+// to LDS made later.
+constexpr int kLMWords = (int)(sizeof(LMDev) / 4);
+template <int BS> struct LMRegs {
+    uint32_t w[(kLMWords + BS - 1) / BS];
+};
+template <int BS> __device__ __forceinline__ LMRegs<BS> lm_fetch(const LMDev *__restrict__ src)
+{
+    const uint32_t *s = reinterpret_cast<const uint32_t *>(src);
+    LMRegs<BS> r;
+#pragma unroll
+    for (int q = 0; q < (kLMWords + BS - 1) / BS; ++q) {
+        const int i = threadIdx.x + BS * q;
+        r.w[q] = i < kLMWords ? s[i] : 0u;
+    }
+    return r;
+}
+template <int BS>
+__device__ __forceinline__ void lm_put(LMDev *__restrict__ dst, const LMRegs<BS> &r)
+{
+    uint32_t *d = reinterpret_cast<uint32_t *>(dst);
+#pragma unroll
+    for (int q = 0; q < (kLMWords + BS - 1) / BS; ++q) {
+        const int i = threadIdx.x + BS * q;
+        if (i < kLMWords) d[i] = r.w[q];
+    }
+}
+
+// Cross-workgroup staging of k_lm_step: the four waves' sums and the count of
+// waves that have stored theirs (zero between launches: the last wave of a
+// launch resets it).
+struct LMRed {
+    double ws[4][kNormSlots];
+    unsigned int arrived, pad;
+};
+
 __global__ void k_lm_update(LMDev *__restrict__ st, const double *__restrict__ norm)
 {
     __shared__ LMDev ls;
@@ -542,80 +619,109 @@ __global__ void k_lm_update(LMDev *__restrict__ st, const double *__restrict__ n
 
 // One fused step of the Levenberg-Marquardt iteration for residual rows of a
 // single chunk (n <= 16384 weighted entries): the trial's normal equations in
-// the summation order of k_lm_normal_rows (thread t sums entries t, t + 256,
-// ... in order, then the lanes by butterfly and the waves in order, so the
-// sums are the same bit for bit), the step rule, and the next trial's rows and
-// column scales.  first: only the rows (the start of a fit).
+// the summation order of k_lm_normal_rows (thread t of 256 sums entries t,
+// t + 256, ... in order, then the lanes of each wave by butterfly and the four
+// waves in order, so the sums are the same bit for bit), the step rule, and
+// the next trial's rows and column scales.  The four waves of that order run
+// as four workgroups of 64 threads on four CUs, each fetching a quarter of the
+// residual rows; a wave's lane sums go through LDS and are added in the
+// butterfly's pairing order (lanes l and l + 32, then l and l + 16, ...,
+// which is the value the exchanges leave in lane 0); the last workgroup to
+// store its sums adds the four in order and runs the step rule and the rows.
+// first: only the rows (the start of a fit; one workgroup), and the arrival
+// count set to zero.
 template <int NF>
-__global__ __launch_bounds__(256) void k_lm_step(LMDev *__restrict__ st,
-                                                 const double *__restrict__ R, int64_t stride,
-                                                 int64_t n, double *__restrict__ rows,
-                                                 double *__restrict__ scale, int first)
+__global__ __launch_bounds__(64) void k_lm_step(LMDev *__restrict__ st,
+                                                const double *__restrict__ R, int64_t stride,
+                                                int64_t n, double *__restrict__ rows,
+                                                double *__restrict__ scale, int first,
+                                                LMRed *__restrict__ red)
 {
-    constexpr int NP = NF * (NF + 1) / 2, NB = NP + NF + 1;
-    __shared__ double norm[NB];
-    __shared__ double ws[4][NB];
+    constexpr int NP = NF * (NF + 1) / 2, NB = NP + NF + 1, SP = 65;
+    __shared__ double tr[NB * SP];  // lane sums [output][lane], then the sums
     __shared__ LMDev ls;
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    lm_copy(&ls, st);
-    if (!first) {
-        double sc[NF], acc[NB];
-#pragma unroll
-        for (int a = 0; a < NF; ++a) sc[a] = scale[a];
-#pragma unroll
-        for (int k = 0; k < NB; ++k) acc[k] = 0.0;
-        // entries t, t + 256, ... in order, U of them loaded before their sums
-        constexpr int U = NF <= 8 ? 2 : 1;
-        for (int64_t i0 = tid; i0 < n; i0 += 256 * U) {
-            double r0[U], j[U][NF];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int64_t i = i0 + 256 * u < n ? i0 + 256 * u : i0;
-                r0[u] = R[i];
-#pragma unroll
-                for (int a = 0; a < NF; ++a)
-                    j[u][a] = (R[(size_t)(1 + 2 * a) * stride + i] - R[(size_t)(2 + 2 * a) * stride + i]) * sc[a];
-            }
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                if (i0 + 256 * u >= n) break;
-                int k = 0;
-#pragma unroll
-                for (int a = 0; a < NF; ++a)
-#pragma unroll
-                    for (int b = a; b < NF; ++b) acc[k++] += j[u][a] * j[u][b];
-#pragma unroll
-                for (int a = 0; a < NF; ++a) acc[NP + a] += j[u][a] * r0[u];
-                acc[NB - 1] += r0[u] * r0[u];
-            }
-        }
-#pragma unroll
-        for (int k = 0; k < NB; ++k) {
-            double v = acc[k];
-            for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-            if (lane == 0) ws[wave][k] = v;
-        }
+    __shared__ int last;
+    const int wave = blockIdx.x, lane = threadIdx.x, tid = 64 * wave + lane;
+    const LMRegs<64> sreg = lm_fetch<64>(st);  // in flight with the residual rows
+    if (first) {
+        lm_put<64>(&ls, sreg);
+        if (lane == 0) red->arrived = 0u;
         __syncthreads();
-        if (tid < NB) norm[tid] = 0.0 + (((ws[0][tid] + ws[1][tid]) + ws[2][tid]) + ws[3][tid]);
-        __syncthreads();
-        if (tid == 0) lm_rule_t<NF>(&ls, norm);
-        __syncthreads();
-        lm_copy(st, &ls);
-    } else {
-        __syncthreads();
+        lm_rows(&ls, rows, scale, lane);
+        return;
     }
-    lm_rows(&ls, rows, scale, tid);
+    double sc[NF], acc[NB];
+#pragma unroll
+    for (int a = 0; a < NF; ++a) sc[a] = scale[a];
+#pragma unroll
+    for (int k = 0; k < NB; ++k) acc[k] = 0.0;
+    // entries t, t + 256, ... in order, U of them loaded before their sums
+    // (the whole of a thread's entries for n <= 256 U: one wait for memory)
+    constexpr int U = NF <= 6 ? 12 : NF <= 9 ? 8 : 4;
+    for (int64_t i0 = tid; i0 < n; i0 += 256 * U) {
+        double r0[U], j[U][NF];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t i = i0 + 256 * u < n ? i0 + 256 * u : i0;
+            r0[u] = R[i];
+#pragma unroll
+            for (int a = 0; a < NF; ++a)
+                j[u][a] = (R[(size_t)(1 + 2 * a) * stride + i] - R[(size_t)(2 + 2 * a) * stride + i]) * sc[a];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (i0 + 256 * u >= n) break;
+            int k = 0;
+#pragma unroll
+            for (int a = 0; a < NF; ++a)
+#pragma unroll
+                for (int b = a; b < NF; ++b) acc[k++] += j[u][a] * j[u][b];
+#pragma unroll
+            for (int a = 0; a < NF; ++a) acc[NP + a] += j[u][a] * r0[u];
+            acc[NB - 1] += r0[u] * r0[u];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < NB; ++k) tr[k * SP + lane] = acc[k];
+    __syncthreads();
+    for (int k = lane; k < NB; k += 64) {
+        const double *v = tr + k * SP;
+        double t[32];
+#pragma unroll
+        for (int i = 0; i < 32; ++i) t[i] = v[i] + v[i + 32];
+#pragma unroll
+        for (int h = 16; h > 0; h >>= 1)
+#pragma unroll
+            for (int i = 0; i < h; ++i) t[i] = t[i] + t[i + h];
+        red->ws[wave][k] = t[0];
+    }
+    __threadfence();
+    __syncthreads();
+    if (lane == 0) last = atomicAdd(&red->arrived, 1u) == 3u;
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    lm_put<64>(&ls, sreg);
+    double *norm = tr;
+    for (int k = lane; k < NB; k += 64)
+        norm[k] = 0.0 + (((red->ws[0][k] + red->ws[1][k]) + red->ws[2][k]) + red->ws[3][k]);
+    if (lane == 0) red->arrived = 0u;
+    __syncthreads();
+    if (lane == 0) lm_rule_t<NF>(&ls, norm);
+    __syncthreads();
+    lm_copy(st, &ls);
+    lm_rows(&ls, rows, scale, lane);
 }
 
 template <int NF>
 void launch_lm_step(LMDev *st, const double *R, int64_t stride, int64_t n, double *rows,
-                    double *scale, int first, hipStream_t s)
+                    double *scale, int first, LMRed *red, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_lm_step<NF>, dim3(1), dim3(256), 0, s, st, R, stride, n, rows, scale,
-                       first);
+    hipLaunchKernelGGL(k_lm_step<NF>, dim3(first ? 1 : 4), dim3(64), 0, s, st, R, stride, n, rows,
+                       scale, first, red);
 }
 using LMStepFn = void (*)(LMDev *, const double *, int64_t, int64_t, double *, double *, int,
-                          hipStream_t);
+                          LMRed *, hipStream_t);
 template <int... F> constexpr auto make_lm_step_table(std::integer_sequence<int, F...>)
 {
     return std::array<LMStepFn, sizeof...(F)>{&launch_lm_step<F + 1>...};
@@ -636,7 +742,8 @@ gk_status fit_reserve(gk_model *m, int rows, int resid_rows)
         HIP_TRY(hipMalloc((void **)&m->fit->d_part, sizeof(double) * kNormSlots * nchunk));
         HIP_TRY(hipMalloc((void **)&m->fit->d_aux, kAuxBytes));
         HIP_TRY(hipHostMalloc((void **)&m->fit->h_aux, kAuxBytes, 0));
-        HIP_TRY(hipMalloc(&m->fit->d_lm, sizeof(LMDev)));
+        HIP_TRY(hipMalloc(&m->fit->d_lm, sizeof(LMDev) + sizeof(LMRed)));
+        HIP_TRY(hipMemset((char *)m->fit->d_lm + sizeof(LMDev), 0, sizeof(LMRed)));
         HIP_TRY(hipHostMalloc(&m->fit->h_lm, sizeof(LMDev), 0));
     }
     FitWork *w = m->fit;
@@ -790,6 +897,7 @@ extern "C" gk_status gk_fit_lm(gk_model *m, double *p_io, const uint8_t *free_ma
     HIP_TRY(hipMemcpyAsync(w->d_lm, w->h_lm, sizeof(LMDev), hipMemcpyHostToDevice, w->stream));
     HIP_TRY(m->reserve(std::min(rows, m->chunk_rows())));
     LMDev *d_st = (LMDev *)w->d_lm;
+    LMRed *d_red = (LMRed *)((char *)w->d_lm + sizeof(LMDev));
     double *d_scale = (double *)(w->d_aux + 4 * sizeof(int64_t));
     // Small u = 1 models whose residual rows form one chunk take two launches
     // per iteration: every row's whole evaluation in one workgroup
@@ -801,7 +909,8 @@ extern "C" gk_status gk_fit_lm(gk_model *m, double *p_io, const uint8_t *free_ma
     const bool fused = nf >= 1 && used <= 16384 && !m->prof_flags &&
                        eval_small_ok(pa, m->d.upsample, m->use_fft, kMaxLds);
     if (fused) {
-        kLMStepTable[nf - 1](d_st, w->d_resid, n, used, w->d_params, d_scale, 1, w->stream);
+        kLMStepTable[nf - 1](d_st, w->d_resid, n, used, w->d_params, d_scale, 1, d_red,
+                             w->stream);
         HIP_TRY(hipGetLastError());
     }
     // one iteration: trial rows -> residuals -> J^T J, J^T r, chi2 -> step rule
@@ -809,7 +918,8 @@ extern "C" gk_status gk_fit_lm(gk_model *m, double *p_io, const uint8_t *free_ma
         if (fused) {
             HIP_TRY(launch_eval_small(w->d_params, m->d_wz, m->NZE, m->d.rc, m->dvf, m->vf0,
                                       m->inv_dvf, m->zedge_lo, m->zedge_hi, pa, rows, w->stream));
-            kLMStepTable[nf - 1](d_st, w->d_resid, n, used, w->d_params, d_scale, 0, w->stream);
+            kLMStepTable[nf - 1](d_st, w->d_resid, n, used, w->d_params, d_scale, 0, d_red,
+                                 w->stream);
             HIP_TRY(hipGetLastError());
             return GK_OK;
         }

@@ -65,6 +65,12 @@ constexpr int kMaxFastHalo = 16;
 // packs a wave's channel range into two 16-bit fields of values up to NZE + 1.
 constexpr int kMaxFineChannels = 65534;
 
+// One pixel's chi-square term of eq. 11 from its weighted residuals,
+// rounded as fma(rv, rv, rs^2) in every kernel: the compiler's own
+// contraction of rv^2 + rs^2 can differ between inlined copies, and paths
+// that share a tile order must agree bit for bit.
+__device__ inline double chi2_term(double rv, double rs) { return __builtin_fma(rv, rv, rs * rs); }
+
 // Moment maps of one pixel (Sec. 2.2.5) from its sums s0 = sum C, s1 =
 // sum C vrel, s2 = sum C vrel^2 (vrel: channel velocity minus vref):
 // m0 = dv s0, m1 = vref + s1/s0, m2 = sqrt(max(s2/s0 - (s1/s0)^2, 0)); a pixel

@@ -279,8 +279,9 @@ __device__ __forceinline__ void line_sums_tile(const double *__restrict__ c,
     const float zcf = (float)zc, span = __builtin_bit_cast(float2, c[C_F32B]).x;
     // clamp in floating point first so that the integer conversion cannot overflow;
     // an empty range is lo = NZE, hi = -1 (packed below as NZE - hi = NZE + 1)
-    const int lo0 = in ? (int)fminf(fmaxf(ceilf(zcf - span), 0.0f), (float)NZE) : NZE;
-    const int hi0 = in ? (int)fmaxf(fminf(floorf(zcf + span), (float)(NZE - 1)), -1.0f) : -1;
+    const int lo_in = (int)fminf(fmaxf(ceilf(zcf - span), 0.0f), (float)NZE);
+    const int hi_in = (int)fmaxf(fminf(floorf(zcf + span), (float)(NZE - 1)), -1.0f);
+    const int lo0 = in ? lo_in : NZE, hi0 = in ? hi_in : -1;
     // a line centred where the spectral weight tapers off (or beyond the band)
     // sums over the whole band: the channels it would drop can carry more
     // weighted flux than the ones it keeps
@@ -304,7 +305,7 @@ __device__ __forceinline__ void line_sums_tile(const double *__restrict__ c,
     const double4 *w = reinterpret_cast<const double4 *>(wz);
     const double e0 = ((double)zlo - zc) * sqk;
     double t0 = 0.0, t1 = 0.0, t2 = 0.0;
-    if (!__any(in && e0 * e0 - lamp > 1020.0)) {
+    if (__builtin_expect(!__any(in && e0 * e0 - lamp > 1020.0), 1)) {
         double g = exp2_wide(lamp - e0 * e0);
         // the ratio's rounding grows linearly along the range: beyond 48
         // channels it is formed to ~1e-11 instead of FP32's ~6e-8
@@ -478,7 +479,7 @@ __device__ __forceinline__ void psf_generic_tile(const PsfArgs &a, const RowPtrs
             const bool use = a.mask[p] != 0;
             const double rv = use ? (m1 - (double)a.vo[p]) * a.iev[p] : 0.0;
             const double rs = use ? (m2 - (double)a.so[p]) * a.ies[p] : 0.0;
-            if (use) acc += rv * rv + rs * rs;
+            if (use) acc += chi2_term(rv, rs);
             if (r.resid) {
                 double *rb = r.resid;
                 rb[p] = valid ? rv : __builtin_nan("");
@@ -621,7 +622,7 @@ __device__ __forceinline__ void psf_u1_tile(const PsfArgs &a, const RowPtrs &r)
             const bool use = a.mask[p] != 0;
             const double rv = use ? (m1 - (double)a.vo[p]) * a.iev[p] : 0.0;
             const double rs = use ? (m2 - (double)a.so[p]) * a.ies[p] : 0.0;
-            if (use) acc += rv * rv + rs * rs;
+            if (use) acc += chi2_term(rv, rs);
             if (r.resid) {
                 double *rb = r.resid;
                 rb[p] = valid ? rv : __builtin_nan("");
@@ -787,7 +788,7 @@ __device__ __forceinline__ void psf_yx_tile(const PsfArgs &a, const RowPtrs &r)
                 for (int o = 0; o < 4; ++o) {
                     rv[o] = use[o] ? (m1[o] - (double)vof[o]) * iev[o] : 0.0;
                     rs[o] = use[o] ? (m2[o] - (double)sof[o]) * ies[o] : 0.0;
-                    if (use[o]) acc += rv[o] * rv[o] + rs[o] * rs[o];
+                    if (use[o]) acc += chi2_term(rv[o], rs[o]);
                 }
                 if (r.resid) {
                     double *rb = r.resid + p0;
@@ -815,7 +816,7 @@ __device__ __forceinline__ void psf_yx_tile(const PsfArgs &a, const RowPtrs &r)
                     const bool use = a.mask[p] != 0;
                     rv[o] = use ? (m1[o] - (double)a.vo[p]) * a.iev[p] : 0.0;
                     rs[o] = use ? (m2[o] - (double)a.so[p]) * a.ies[p] : 0.0;
-                    if (use) acc += rv[o] * rv[o] + rs[o] * rs[o];
+                    if (use) acc += chi2_term(rv[o], rs[o]);
                     if (r.resid) {
                         double *rb = r.resid;
                         rb[p] = valid ? rv[o] : __builtin_nan("");

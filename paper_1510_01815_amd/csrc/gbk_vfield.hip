@@ -122,7 +122,7 @@ __global__ __launch_bounds__(256) void k_vfield(VfArgs a)
                 if (MAPS) inten = prow[P_I0] * exp(-fmin(r * c[C_IR0], 60.0));  // eq. 5
                 rv = use[q] ? (v - vo[q]) * iev[q] : 0.0;
                 rs = use[q] ? (s - so[q]) * ies[q] : 0.0;
-                if (use[q]) acc += rv * rv + rs * rs;
+                if (use[q]) acc += chi2_term(rv, rs);
             }
             if (MAPS) {
                 float *mb = a.maps + (size_t)b * 3 * npix;
@@ -197,7 +197,7 @@ __global__ __launch_bounds__(256) void k_vfield_multi(const ModelDev *__restrict
             const double s = params[(size_t)b * NPAR + P_SIG];
             rv = use ? (v - (double)a.vo[p]) * a.iev[p] : 0.0;
             rs = use && sig_term ? (s - (double)a.so[p]) * a.ies[p] : 0.0;
-            if (use) acc += rv * rv + rs * rs;
+            if (use) acc += chi2_term(rv, rs);
         }
         if (resid) {  // the fitters do not read the dispersion map unless it is weighted
             double *rb = resid + rm.resid_off[b];
