@@ -106,10 +106,9 @@ size_t psf_lds_bytes(int TXd, int TYd, int u, int hp)
 // x-pass rows
 size_t psf_u1_lds_bytes(int TX, int hp)
 {
-    auto pad = [](int n) { return n + ((1 - n) % 4 + 4) % 4; };
-    if (TX == 32) return sizeof(double) * 32 * pad(32 + 2 * hp);
+    if (TX == 32) return yx_lds_bytes(hp);
     const size_t LY = 32 + 2 * hp;
-    return sizeof(double) * (LY * pad(TX + 2 * hp) + LY * pad(TX));
+    return sizeof(double) * (LY * pad_stride(TX + 2 * hp) + LY * pad_stride(TX));
 }
 
 // The 32 x 32 register-blocked kernel addresses a T plane with 32-bit byte
@@ -636,9 +635,11 @@ gk_status gk_create_model(const gk_model_desc *desc, int device, gk_model **out)
     m->EX = m->NX + 2 * m->hp;
     m->EY = m->NY + 2 * m->hp;
     m->NZE = m->NZ + 2 * m->hl;
-    if ((double)m->EX * m->EY >= 2.0e9) {
+    // the kernels address a T plane (FP64 per fine spaxel with halo) with
+    // 32-bit byte offsets
+    if ((double)m->EX * m->EY * sizeof(double) >= 2147483648.0) {
         delete m;
-        return fail(GK_EINVAL, "model grid too large");
+        return fail(GK_EINVAL, "model grid too large (%d x %d fine spaxels with halo)", m->EX, m->EY);
     }
     // the line-sum kernel packs a wave's channel range into two 16-bit fields
     // holding values up to NZE + 1
@@ -655,7 +656,8 @@ gk_status gk_create_model(const gk_model_desc *desc, int device, gk_model **out)
     m->vref = d.v0_kms + (0.5 * (d.nz - 1) - d.crpix) * d.dv_kms;
 
     // W_j(z') = (1/u) sum_{m in [0, NZ)} vrel(m/u)^j K_z[m + 2 hl - z']
-    std::vector<double> wz((size_t)4 * m->NZE, 0.0);  // [NZE][4] = {W0, W1, W2, 0}
+    // [NZE][4] = {W0, W1, W2, 0}, then kWzPad rows of zeros
+    std::vector<double> wz((size_t)4 * (m->NZE + kWzPad), 0.0);
     for (int zp = 0; zp < m->NZE; ++zp) {
         double w0 = 0, w1 = 0, w2 = 0;
         for (int t = 0; t <= 2 * m->hl; ++t) {

@@ -29,6 +29,7 @@
 //                  (eqs. 1-4), rotation curve (eqs. 6-7), velocity (eq. 8),
 //                  brightness (eq. 5), then T_j over the channels; the weight
 //                  table wz is [NZE][4] = {W0, W1, W2, 0} per fine channel
+//                  (plus kWzPad zero rows)
 //   k_psf_moments  per (evaluation, tile): PSF x and y passes on T_j (LDS
 //                  staged, or y first from HBM for 32 x 32 tiles at u = 1),
 //                  u x u block sum, moments, masked chi-square terms (eq. 11)
@@ -154,10 +155,11 @@ __device__ inline void wave_min2(int a, int b, int &amin, int &bmin)
         return __builtin_bit_cast(unsigned, r);
     };
     unsigned v = (unsigned)a | ((unsigned)b << 16);
-    v = pmin(v, __builtin_amdgcn_update_dpp(v, v, 0xB1, 0xF, 0xF, false));   // quad_perm 1,0,3,2
-    v = pmin(v, __builtin_amdgcn_update_dpp(v, v, 0x4E, 0xF, 0xF, false));   // quad_perm 2,3,0,1
-    v = pmin(v, __builtin_amdgcn_update_dpp(v, v, 0x124, 0xF, 0xF, false));  // row_ror 4
-    v = pmin(v, __builtin_amdgcn_update_dpp(v, v, 0x128, 0xF, 0xF, false));  // row_ror 8
+    // every lane of every row is written, so no old value is needed
+    v = pmin(v, __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false));   // quad_perm 1,0,3,2
+    v = pmin(v, __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false));   // quad_perm 2,3,0,1
+    v = pmin(v, __builtin_amdgcn_mov_dpp(v, 0x124, 0xF, 0xF, false));  // row_ror 4
+    v = pmin(v, __builtin_amdgcn_mov_dpp(v, 0x128, 0xF, 0xF, false));  // row_ror 8
     const unsigned r0 = __builtin_amdgcn_readlane(v, 0), r1 = __builtin_amdgcn_readlane(v, 16);
     const unsigned r2 = __builtin_amdgcn_readlane(v, 32), r3 = __builtin_amdgcn_readlane(v, 48);
     const unsigned lo = min(min(r0 & 0xffff, r1 & 0xffff), min(r2 & 0xffff, r3 & 0xffff));
@@ -165,6 +167,12 @@ __device__ inline void wave_min2(int a, int b, int &amin, int &bmin)
     amin = (int)lo;
     bmin = (int)hi;
 }
+
+// Word 3 of a raw buffer descriptor on gfx9-family chips (32-bit data format;
+// no swizzle, no index stride).
+constexpr int kBufferDword3 = 0x00020000;
+// the 64-bit payload type of the raw buffer load/store builtins
+typedef unsigned int u32x2v __attribute__((__vector_size__(2 * sizeof(unsigned int))));
 
 // 2^x for x in roughly [-1070, 1000] in FP64 with FP32 relative accuracy:
 // x = n + f, f in [0, 1), 2^x = ldexp(2^f, n).
@@ -213,8 +221,9 @@ __device__ inline double exp2_precise(double x)
 // gradient across the wave's square), the wave evaluates exp2 per channel.
 // ---------------------------------------------------------------------------
 // One 16 x 16 tile (tile_x, tile_y) of one row: c = the row's constants,
-// T = the row's three planes, count = this block's 4 support-count slots
-// (measurement only, may be NULL).
+// T = the row's three planes (in global memory, or in LDS when T_IN_LDS),
+// count = this block's 4 support-count slots (measurement only, may be NULL).
+template <bool T_IN_LDS = false>
 __device__ __forceinline__ void line_sums_tile(const double *__restrict__ c,
                                                const double *__restrict__ wz, int NZE, int EX,
                                                int EY, int hp, int u, int rc, double vf0,
@@ -279,8 +288,8 @@ __device__ __forceinline__ void line_sums_tile(const double *__restrict__ c,
     const float zcf = (float)zc, span = __builtin_bit_cast(float2, c[C_F32B]).x;
     // clamp in floating point first so that the integer conversion cannot overflow;
     // an empty range is lo = NZE, hi = -1 (packed below as NZE - hi = NZE + 1)
-    const int lo_in = (int)fminf(fmaxf(ceilf(zcf - span), 0.0f), (float)NZE);
-    const int hi_in = (int)fmaxf(fminf(floorf(zcf + span), (float)(NZE - 1)), -1.0f);
+    const int lo_in = (int)__builtin_amdgcn_fmed3f(ceilf(zcf - span), 0.0f, (float)NZE);
+    const int hi_in = (int)__builtin_amdgcn_fmed3f(floorf(zcf + span), -1.0f, (float)(NZE - 1));
     const int lo0 = in ? lo_in : NZE, hi0 = in ? hi_in : -1;
     // a line centred where the spectral weight tapers off (or beyond the band)
     // sums over the whole band: the channels it would drop can carry more
@@ -305,27 +314,38 @@ __device__ __forceinline__ void line_sums_tile(const double *__restrict__ c,
     const double4 *w = reinterpret_cast<const double4 *>(wz);
     const double e0 = ((double)zlo - zc) * sqk;
     double t0 = 0.0, t1 = 0.0, t2 = 0.0;
+    // a line below 2^-40 of its peak at every channel of the band has no flux
+    // (the wave's channel range may still be run for the other lanes): its
+    // lane sums g = 0
+    const bool empty = lo > hi;
     if (__builtin_expect(!__any(in && e0 * e0 - lamp > 1020.0), 1)) {
-        double g = exp2_wide(lamp - e0 * e0);
+        double g = empty ? 0.0 : exp2_wide(lamp - e0 * e0);
         // the ratio's rounding grows linearly along the range: beyond 48
         // channels it is formed to ~1e-11 instead of FP32's ~6e-8
         const double ra = -(2.0 * e0 + sqk) * sqk;
         double rt = zhi - zlo >= 48 ? exp2_precise(ra) : exp2_wide(ra);
         const double qq = c[C_Q];
-        // the next channel's weights are requested one step ahead, which
-        // lets the scalar loads of two channels merge into one
+        auto step = [&](const double4 &wk) {
+            t0 = fma(g, wk.x, t0);
+            t1 = fma(g, wk.y, t1);
+            t2 = fma(g, wk.z, t2);
+            g *= rt;
+            rt *= qq;
+        };
+        // channels in pairs, the next pair's weights requested while the
+        // current pair is summed (the table has kWzPad zero rows after its
+        // NZE channels, so a pair may read past zhi)
+        int z = zlo;
         if (zlo <= zhi) {
-            double4 wk = w[zlo];
-#pragma unroll 2
-            for (int z = zlo; z <= zhi; ++z) {
-                const double4 wn = w[z < zhi ? z + 1 : z];
-                t0 = fma(g, wk.x, t0);
-                t1 = fma(g, wk.y, t1);
-                t2 = fma(g, wk.z, t2);
-                g *= rt;
-                rt *= qq;
-                wk = wn;
+            double4 c0 = w[z], c1 = w[z + 1];
+            for (; z + 1 <= zhi; z += 2) {
+                const double4 n0 = w[z + 2], n1 = w[z + 3];
+                step(c0);
+                step(c1);
+                c0 = n0;
+                c1 = n1;
             }
+            if (z == zhi) step(c0);  // one channel left, uniform
         }
     } else {
         double e = e0;
@@ -338,20 +358,28 @@ __device__ __forceinline__ void line_sums_tile(const double *__restrict__ c,
             t2 = fma(g, wk.z, t2);
             e += sqk;
         }
-        const double amp = exp2_wide(lamp);
+        const double amp = empty ? 0.0 : exp2_wide(lamp);
         t0 *= amp;
         t1 *= amp;
         t2 *= amp;
     }
-    // a line below 2^-40 of its peak at every channel of the band has no flux
-    // (the wave's channel range may still have been run for the other lanes)
-    if (lo > hi) t0 = t1 = t2 = 0.0;
-    if (in) {
+    if (in && T_IN_LDS) {
+        const int plane = EX * EY, off = gy * EX + gx;
+        T[off] = t0;
+        T[plane + off] = t1;
+        T[2 * plane + off] = t2;
+    } else if (in) {
+        // buffer stores: one 32-bit byte offset from each plane's uniform base
+        // (a model's plane is under 2^31 bytes)
         const size_t plane = (size_t)EX * EY;
-        double *Tb = T + (size_t)gy * EX + gx;
-        Tb[0] = t0;
-        Tb[plane] = t1;
-        Tb[2 * plane] = t2;
+        const int pb = (int)(sizeof(double) * plane);
+        const uint32_t off = (uint32_t)(gy * EX + gx) * (uint32_t)sizeof(double);
+        __builtin_amdgcn_raw_buffer_store_b64(
+            __builtin_bit_cast(u32x2v, t0), __builtin_amdgcn_make_buffer_rsrc(T, 0, pb, kBufferDword3), off, 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b64(
+            __builtin_bit_cast(u32x2v, t1), __builtin_amdgcn_make_buffer_rsrc(T + plane, 0, pb, kBufferDword3), off, 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b64(
+            __builtin_bit_cast(u32x2v, t2), __builtin_amdgcn_make_buffer_rsrc(T + 2 * plane, 0, pb, kBufferDword3), off, 0, 0);
     }
 }
 
@@ -527,7 +555,6 @@ __device__ inline void window(const double *src, int stride, const double *kp, d
     }
 }
 
-constexpr int pad_stride(int n) { return n + ((1 - n) % 4 + 4) % 4; }
 
 template <int HP, int TX>
 __device__ __forceinline__ void psf_u1_tile(const PsfArgs &a, const RowPtrs &r)
@@ -641,6 +668,126 @@ __device__ __forceinline__ void psf_u1_tile(const PsfArgs &a, const RowPtrs &r)
     }
 }
 
+// Observation of the four pixels xd0 .. xd0 + 3 of row yd (nx = 0 mod 4 and
+// a mask present; otherwise nothing is read and the epilogue reads the
+// observation per pixel).
+struct ObsQuad {
+    uint32_t mk;  // the four mask bytes, unpacked where they are used
+    float4 vo, so;
+    double2 ev0, ev1, es0, es1;
+};
+
+__device__ __forceinline__ ObsQuad load_obs_quad(const PsfArgs &a, int yd, int xd0)
+{
+    ObsQuad q{};
+    if (a.mask && (a.nx & 3) == 0 && yd < a.ny && xd0 < a.nx) {
+        const size_t p0 = (size_t)yd * a.nx + xd0;
+        q.mk = *reinterpret_cast<const uint32_t *>(a.mask + p0);
+        q.vo = *reinterpret_cast<const float4 *>(a.vo + p0);
+        q.so = *reinterpret_cast<const float4 *>(a.so + p0);
+        q.ev0 = *reinterpret_cast<const double2 *>(a.iev + p0);
+        q.ev1 = *reinterpret_cast<const double2 *>(a.iev + p0 + 2);
+        q.es0 = *reinterpret_cast<const double2 *>(a.ies + p0);
+        q.es1 = *reinterpret_cast<const double2 *>(a.ies + p0 + 2);
+    }
+    return q;
+}
+
+// Moments, maps, residuals and the tile's chi-square partial of the 32 x 32
+// u = 1 kernels: thread tid holds the sums S of the pixels xd0 .. xd0 + 3 of
+// data row yd; ob is their observation (load_obs_quad).  With nx = 0 (mod 4)
+// the pixels are inside the image and 16-byte aligned, and the outputs are
+// written as vectors.
+__device__ __forceinline__ void yx_epilogue(const PsfArgs &a, const RowPtrs &r,
+                                            const double (&S)[3][4], bool valid, int yd, int xd0,
+                                            int tid, const ObsQuad &ob)
+{
+    const int wave = tid >> 6, lane = tid & 63;
+    const double *cb = r.c;
+    double acc = 0.0;
+    const size_t npix = (size_t)a.nx * a.ny;
+    if (yd < a.ny && xd0 < a.nx) {
+        double m0[4], m1[4], m2[4];
+#pragma unroll
+        for (int o = 0; o < 4; ++o) {
+            if (!valid)
+                m0[o] = m1[o] = m2[o] = __builtin_nan("");
+            else
+                moment_maps(S[0][o], S[1][o], S[2][o], a.dv, a.vref, cb[C_VSYS], m0[o], m1[o],
+                            m2[o]);
+        }
+        const size_t p0 = (size_t)yd * a.nx + xd0;
+        double rv[4], rs[4];
+        if ((a.nx & 3) == 0) {
+            if (r.maps) {
+                float *mb = r.maps + p0;
+                *reinterpret_cast<float4 *>(mb) =
+                    make_float4((float)m0[0], (float)m0[1], (float)m0[2], (float)m0[3]);
+                *reinterpret_cast<float4 *>(mb + npix) =
+                    make_float4((float)m1[0], (float)m1[1], (float)m1[2], (float)m1[3]);
+                *reinterpret_cast<float4 *>(mb + 2 * npix) =
+                    make_float4((float)m2[0], (float)m2[1], (float)m2[2], (float)m2[3]);
+            }
+            if (a.mask) {
+                const uchar4 mk = __builtin_bit_cast(uchar4, ob.mk);
+                const float4 vo = ob.vo, so = ob.so;
+                const double2 ev0 = ob.ev0, ev1 = ob.ev1, es0 = ob.es0, es1 = ob.es1;
+                const bool use[4] = {mk.x != 0, mk.y != 0, mk.z != 0, mk.w != 0};
+                const float vof[4] = {vo.x, vo.y, vo.z, vo.w}, sof[4] = {so.x, so.y, so.z, so.w};
+                const double iev[4] = {ev0.x, ev0.y, ev1.x, ev1.y};
+                const double ies[4] = {es0.x, es0.y, es1.x, es1.y};
+#pragma unroll
+                for (int o = 0; o < 4; ++o) {
+                    rv[o] = use[o] ? (m1[o] - (double)vof[o]) * iev[o] : 0.0;
+                    rs[o] = use[o] ? (m2[o] - (double)sof[o]) * ies[o] : 0.0;
+                    if (use[o]) acc += chi2_term(rv[o], rs[o]);
+                }
+                if (r.resid) {
+                    double *rb = r.resid + p0;
+                    if (!valid)
+#pragma unroll
+                        for (int o = 0; o < 4; ++o) rv[o] = rs[o] = __builtin_nan("");
+                    *reinterpret_cast<double2 *>(rb) = make_double2(rv[0], rv[1]);
+                    *reinterpret_cast<double2 *>(rb + 2) = make_double2(rv[2], rv[3]);
+                    *reinterpret_cast<double2 *>(rb + npix) = make_double2(rs[0], rs[1]);
+                    *reinterpret_cast<double2 *>(rb + npix + 2) = make_double2(rs[2], rs[3]);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int o = 0; o < 4; ++o) {
+                if (xd0 + o >= a.nx) break;
+                const size_t p = p0 + o;
+                if (r.maps) {
+                    float *mb = r.maps;
+                    mb[p] = (float)m0[o];
+                    mb[npix + p] = (float)m1[o];
+                    mb[2 * npix + p] = (float)m2[o];
+                }
+                if (a.mask) {
+                    const bool use = a.mask[p] != 0;
+                    rv[o] = use ? (m1[o] - (double)a.vo[p]) * a.iev[p] : 0.0;
+                    rs[o] = use ? (m2[o] - (double)a.so[p]) * a.ies[p] : 0.0;
+                    if (use) acc += chi2_term(rv[o], rs[o]);
+                    if (r.resid) {
+                        double *rb = r.resid;
+                        rb[p] = valid ? rv[o] : __builtin_nan("");
+                        rb[npix + p] = valid ? rs[o] : __builtin_nan("");
+                    }
+                }
+            }
+        }
+    }
+    if (r.partial) {
+        for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+        __shared__ double wsum[4];
+        if (lane == 0) wsum[wave] = acc;
+        __syncthreads();
+        if (tid == 0)
+            *r.partial = ((wsum[0] + wsum[1]) + wsum[2]) + wsum[3];
+    }
+}
+
 // ---------------------------------------------------------------------------
 // psf_yx_tile<HP>: the u = 1 case with 32 x 32 data-pixel tiles, y pass first.
 // Wave w owns output rows 8w..8w+7 of the tile and lane l the T column
@@ -655,9 +802,6 @@ __device__ __forceinline__ void psf_u1_tile(const PsfArgs &a, const RowPtrs &r)
 // Row stride of sY = 1 (mod 4) doubles, which spreads the x-pass lanes of a
 // wave (8 rows x 8 windows) over all LDS banks.
 // ---------------------------------------------------------------------------
-// Word 3 of a raw buffer descriptor on gfx9-family chips (32-bit data format;
-// no swizzle, no index stride).
-constexpr int kBufferDword3 = 0x00020000;
 
 // Orders a wave's LDS accesses before and after this point (the hardware runs
 // one wave's LDS instructions in order; this keeps the compiler from moving
@@ -744,96 +888,9 @@ __device__ __forceinline__ void psf_yx_tile(const PsfArgs &a, const RowPtrs &r)
         }
     }
 
-    // moments and chi-square terms of the lane's 4 pixels (xd0 .. xd0 + 3, yd);
-    // with nx = 0 (mod 4) they are inside the image and 16-byte aligned, and
-    // the observation is read and the outputs written as vectors
-    double acc = 0.0;
+    // moments and chi-square terms of the lane's 4 pixels (xd0 .. xd0 + 3, yd)
     const int yd = ty0 + ry, xd0 = tx0 + x0;
-    const size_t npix = (size_t)a.nx * a.ny;
-    if (yd < a.ny && xd0 < a.nx) {
-        double m0[4], m1[4], m2[4];
-#pragma unroll
-        for (int o = 0; o < 4; ++o) {
-            if (!valid)
-                m0[o] = m1[o] = m2[o] = __builtin_nan("");
-            else
-                moment_maps(S[0][o], S[1][o], S[2][o], a.dv, a.vref, cb[C_VSYS], m0[o], m1[o],
-                            m2[o]);
-        }
-        const size_t p0 = (size_t)yd * a.nx + xd0;
-        double rv[4], rs[4];
-        if ((a.nx & 3) == 0) {
-            if (r.maps) {
-                float *mb = r.maps + p0;
-                *reinterpret_cast<float4 *>(mb) =
-                    make_float4((float)m0[0], (float)m0[1], (float)m0[2], (float)m0[3]);
-                *reinterpret_cast<float4 *>(mb + npix) =
-                    make_float4((float)m1[0], (float)m1[1], (float)m1[2], (float)m1[3]);
-                *reinterpret_cast<float4 *>(mb + 2 * npix) =
-                    make_float4((float)m2[0], (float)m2[1], (float)m2[2], (float)m2[3]);
-            }
-            if (a.mask) {
-                const uchar4 mk = *reinterpret_cast<const uchar4 *>(a.mask + p0);
-                const float4 vo = *reinterpret_cast<const float4 *>(a.vo + p0);
-                const float4 so = *reinterpret_cast<const float4 *>(a.so + p0);
-                const double2 ev0 = *reinterpret_cast<const double2 *>(a.iev + p0);
-                const double2 ev1 = *reinterpret_cast<const double2 *>(a.iev + p0 + 2);
-                const double2 es0 = *reinterpret_cast<const double2 *>(a.ies + p0);
-                const double2 es1 = *reinterpret_cast<const double2 *>(a.ies + p0 + 2);
-                const bool use[4] = {mk.x != 0, mk.y != 0, mk.z != 0, mk.w != 0};
-                const float vof[4] = {vo.x, vo.y, vo.z, vo.w}, sof[4] = {so.x, so.y, so.z, so.w};
-                const double iev[4] = {ev0.x, ev0.y, ev1.x, ev1.y};
-                const double ies[4] = {es0.x, es0.y, es1.x, es1.y};
-#pragma unroll
-                for (int o = 0; o < 4; ++o) {
-                    rv[o] = use[o] ? (m1[o] - (double)vof[o]) * iev[o] : 0.0;
-                    rs[o] = use[o] ? (m2[o] - (double)sof[o]) * ies[o] : 0.0;
-                    if (use[o]) acc += chi2_term(rv[o], rs[o]);
-                }
-                if (r.resid) {
-                    double *rb = r.resid + p0;
-                    if (!valid)
-#pragma unroll
-                        for (int o = 0; o < 4; ++o) rv[o] = rs[o] = __builtin_nan("");
-                    *reinterpret_cast<double2 *>(rb) = make_double2(rv[0], rv[1]);
-                    *reinterpret_cast<double2 *>(rb + 2) = make_double2(rv[2], rv[3]);
-                    *reinterpret_cast<double2 *>(rb + npix) = make_double2(rs[0], rs[1]);
-                    *reinterpret_cast<double2 *>(rb + npix + 2) = make_double2(rs[2], rs[3]);
-                }
-            }
-        } else {
-#pragma unroll
-            for (int o = 0; o < 4; ++o) {
-                if (xd0 + o >= a.nx) break;
-                const size_t p = p0 + o;
-                if (r.maps) {
-                    float *mb = r.maps;
-                    mb[p] = (float)m0[o];
-                    mb[npix + p] = (float)m1[o];
-                    mb[2 * npix + p] = (float)m2[o];
-                }
-                if (a.mask) {
-                    const bool use = a.mask[p] != 0;
-                    rv[o] = use ? (m1[o] - (double)a.vo[p]) * a.iev[p] : 0.0;
-                    rs[o] = use ? (m2[o] - (double)a.so[p]) * a.ies[p] : 0.0;
-                    if (use) acc += chi2_term(rv[o], rs[o]);
-                    if (r.resid) {
-                        double *rb = r.resid;
-                        rb[p] = valid ? rv[o] : __builtin_nan("");
-                        rb[npix + p] = valid ? rs[o] : __builtin_nan("");
-                    }
-                }
-            }
-        }
-    }
-    if (r.partial) {
-        for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
-        __shared__ double wsum[4];
-        if (lane == 0) wsum[wave] = acc;
-        __syncthreads();
-        if (tid == 0)
-            *r.partial = ((wsum[0] + wsum[1]) + wsum[2]) + wsum[3];
-    }
+    yx_epilogue(a, r, S, valid, yd, xd0, tid, load_obs_quad(a, yd, xd0));
 }
 
 // Row pointers of a single-model launch, grid (ntiles, B).  Workgroups go to
@@ -910,7 +967,7 @@ __global__ __launch_bounds__(1024) void k_eval_small(const double *__restrict__ 
     if (valid) {  // uniform: line sums of the 16 x 16 tiles, four at a time
         const int ntx = (EX + 15) >> 4, nt = ntx * ((EY + 15) >> 4);
         for (int t = tid >> 8; t < nt; t += 4)
-            line_sums_tile(c, wz, NZE, EX, EY, hp, 1, rc, vf0, inv_dvf, zedge_lo, zedge_hi, T,
+            line_sums_tile<true>(c, wz, NZE, EX, EY, hp, 1, rc, vf0, inv_dvf, zedge_lo, zedge_hi, T,
                            t % ntx, t / ntx, nullptr);
     }
     __syncthreads();
