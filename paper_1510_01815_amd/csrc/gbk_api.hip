@@ -656,8 +656,7 @@ gk_status gk_create_model(const gk_model_desc *desc, int device, gk_model **out)
     m->vref = d.v0_kms + (0.5 * (d.nz - 1) - d.crpix) * d.dv_kms;
 
     // W_j(z') = (1/u) sum_{m in [0, NZ)} vrel(m/u)^j K_z[m + 2 hl - z']
-    // [NZE][4] = {W0, W1, W2, 0}, then kWzPad rows of zeros
-    std::vector<double> wz((size_t)4 * (m->NZE + kWzPad), 0.0);
+    std::vector<double> wz((size_t)4 * m->NZE, 0.0);  // [NZE][4] = {W0, W1, W2, 0}
     for (int zp = 0; zp < m->NZE; ++zp) {
         double w0 = 0, w1 = 0, w2 = 0;
         for (int t = 0; t <= 2 * m->hl; ++t) {

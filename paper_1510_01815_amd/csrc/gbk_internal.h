@@ -67,10 +67,6 @@ constexpr int pad_stride(int n) { return n + ((1 - n) % 4 + 4) % 4; }
 // dynamic LDS (bytes) of the 32 x 32 u = 1 kernel at PSF half-width hp: the
 // y-pass rows of one plane
 constexpr size_t yx_lds_bytes(int hp) { return sizeof(double) * 32 * (size_t)pad_stride(32 + 2 * hp); }
-// Zero rows after the NZE channel rows of the weight table [NZE][4]: the
-// line-sum loop reads channels in groups of four and may read up to four
-// rows past the last channel of a range.
-constexpr int kWzPad = 4;
 // Fine channels with the LSF halo (NZE) a model may have: the line-sum kernel
 // packs a wave's channel range into two 16-bit fields of values up to NZE + 1.
 constexpr int kMaxFineChannels = 65534;

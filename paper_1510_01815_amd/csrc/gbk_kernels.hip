@@ -29,7 +29,6 @@
 //                  (eqs. 1-4), rotation curve (eqs. 6-7), velocity (eq. 8),
 //                  brightness (eq. 5), then T_j over the channels; the weight
 //                  table wz is [NZE][4] = {W0, W1, W2, 0} per fine channel
-//                  (plus kWzPad zero rows)
 //   k_psf_moments  per (evaluation, tile): PSF x and y passes on T_j (LDS
 //                  staged, or y first from HBM for 32 x 32 tiles at u = 1),
 //                  u x u block sum, moments, masked chi-square terms (eq. 11)
@@ -332,20 +331,16 @@ __device__ __forceinline__ void line_sums_tile(const double *__restrict__ c,
             g *= rt;
             rt *= qq;
         };
-        // channels in pairs, the next pair's weights requested while the
-        // current pair is summed (the table has kWzPad zero rows after its
-        // NZE channels, so a pair may read past zhi)
-        int z = zlo;
+        // the next channel's weights are requested one step ahead, which
+        // lets the scalar loads of two channels merge into one
         if (zlo <= zhi) {
-            double4 c0 = w[z], c1 = w[z + 1];
-            for (; z + 1 <= zhi; z += 2) {
-                const double4 n0 = w[z + 2], n1 = w[z + 3];
-                step(c0);
-                step(c1);
-                c0 = n0;
-                c1 = n1;
+            double4 wk = w[zlo];
+#pragma unroll 2
+            for (int z = zlo; z <= zhi; ++z) {
+                const double4 wn = w[z < zhi ? z + 1 : z];
+                step(wk);
+                wk = wn;
             }
-            if (z == zhi) step(c0);  // one channel left, uniform
         }
     } else {
         double e = e0;

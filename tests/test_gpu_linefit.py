@@ -57,7 +57,11 @@ def check_against_oracle(gmaps, gst, cube, v, dv, picks):
             agree += 1
             continue
         agree += gs[p] == f.status
-        if f.status != 1 or gs[p] != 1:
+        # converged (1) or stopped at the damping limit (2, the step no longer
+        # lowers chi2 at ftol = xtol = 1e-12): both at the optimum, so the
+        # parameters are compared whichever of the two each side reports;
+        # fits stopped by the iteration cap (3) are not at an optimum
+        if f.status not in (1, 2) or gs[p] not in (1, 2):
             continue
         err = line_errors(flat[:, p].astype(np.float64), v, f.amp, f.vel, f.disp)
         for k, (got, want) in enumerate(((gm[1, p], f.vel), (gm[2, p], f.disp))):
