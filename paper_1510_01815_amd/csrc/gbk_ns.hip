@@ -1244,8 +1244,17 @@ gk_status fit_nested(gk_model *m, gk_surrogate *sur, const double *lo, const dou
         g.mode = nb.d_mode;
         hipLaunchKernelGGL(k_ns_draw, dim3((n + 3) / 4), dim3(256), 0, stream, g);
         HIP_TRY(hipGetLastError());
-        HIP_TRY(hipMemcpyAsync(nb.h_u, nb.d_u, sizeof(double) * n * d, hipMemcpyDeviceToHost, stream));
-        HIP_TRY(hipMemcpyAsync(nb.h_mode, nb.d_mode, sizeof(int) * n, hipMemcpyDeviceToHost, stream));
+        // the candidates' unit-cube coordinates and modes go to the host after
+        // the round's evaluation launches, so that the evaluation starts right
+        // after the draw (the host reads them only after the wait)
+        auto copy_draws = [&]() -> hipError_t {
+            hipError_t e = hipMemcpyAsync(nb.h_u, nb.d_u, sizeof(double) * n * d,
+                                          hipMemcpyDeviceToHost, stream);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(nb.h_mode, nb.d_mode, sizeof(int) * n, hipMemcpyDeviceToHost,
+                                   stream);
+            return e;
+        };
         for (int i = 0; i < n; ++i) logl[i] = -INFINITY;
         // screen this round only where the plain evaluations it saves (at the
         // last screened round's pass fraction) outweigh its own cost
@@ -1255,6 +1264,7 @@ gk_status fit_nested(gk_model *m, gk_surrogate *sur, const double *lo, const dou
         if (!screen) {
             ++since_screen;
             GK_TRY(run_batch(m, d_params, n, nullptr, nullptr, d_chi2, nullptr, stream));
+            HIP_TRY(copy_draws());
             HIP_TRY(hipMemcpyAsync(h_chi2, d_chi2, sizeof(double) * n, hipMemcpyDeviceToHost, stream));
             HIP_TRY(wait(stream));
             std::memcpy(u, nb.h_u, sizeof(double) * n * d);
@@ -1265,6 +1275,7 @@ gk_status fit_nested(gk_model *m, gk_surrogate *sur, const double *lo, const dou
         }
         // surrogate chi2 of every candidate, then the plain chi2 of the survivors
         GK_TRY(surrogate_chi2(sur, m, d_params, n, d_chi2s, stream));
+        HIP_TRY(copy_draws());
         HIP_TRY(hipMemcpyAsync(h_chi2s, d_chi2s, sizeof(double) * n, hipMemcpyDeviceToHost, stream));
         HIP_TRY(wait(stream));
         std::memcpy(u, nb.h_u, sizeof(double) * n * d);
