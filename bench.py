@@ -52,6 +52,7 @@ PEAK_TFLOPS = 2 * LANE_OPS_PER_S / 1e12
 SPAXEL_FLOP, SPAXEL_SLOTS = 32, 52
 FLOP_PER_VOXEL, VOXEL_SLOTS = 8, 5
 PEAK_HBM_GBS = 8000.0
+PEAK_BF16_TFLOPS = 2500.0  # dense BF16 MFMA, published (no 2:1 sparsity)
 
 # HBM traffic per launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
 # passes; reported only while the kernel sources still hash to the profiled ones
@@ -131,6 +132,8 @@ def parse():
     ap.add_argument("--fit-galaxies", type=int, default=6,
                     help="galaxies of the surrogate workload fitted both ways (0: skip)")
     ap.add_argument("--train-rows", type=int, default=2_000_000)
+    ap.add_argument("--surrogate-kernels-only", action="store_true",
+                    help="time only the surrogate's GEMM and screening pass (for counter runs)")
     ap.add_argument("--survey-galaxies", type=int, default=2000,
                     help="galaxies of the uneven-survey LM workload (0: skip)")
     ap.add_argument("--grid-galaxies", type=int, default=10,
@@ -540,6 +543,50 @@ def fits_per_hour(gbk, I, torch, n_gal, train_rows):
     return out
 
 
+def surrogate_kernels(gbk, I, torch, reps=10):
+    """The surrogate's kernels at the screening shape: the BF16 GEMM on an
+    8192 x 8192 x 1024 product (the output layer's shape with every pixel
+    kept) and the screening pass, i.e. the surrogate chi-square of 8192 rows of
+    the 64x64x64 instrument (encoding, 4 x 1024 GELU layers, output layer with
+    the fused chi-square), against the dense BF16 MFMA peak."""
+    dev = "cuda:0"
+    g = torch.Generator(device=dev).manual_seed(1)
+    A = torch.randn(8192, 1024, device=dev, generator=g).to(torch.bfloat16)
+    Bm = torch.randn(8192, 1024, device=dev, generator=g).to(torch.bfloat16)
+    C = torch.empty(8192, 8192, device=dev, dtype=torch.float32)
+
+    def timed(fn):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    t_gemm = timed(lambda: gbk.gemm_bf16(A, Bm, C=C))
+    gemm_tflops = 2 * 8192 * 8192 * 1024 / t_gemm / 1e12
+    del A, Bm, C
+    grid = I.c5_grid()
+    m = gbk.Model.from_grid(grid)
+    lo, hi = I.c5_box()
+    truth = I.c5_galaxy(1)
+    maps = m.evaluate(torch.tensor(truth[None], device=dev)).cpu().numpy()[0]
+    m.set_obs(I.make_observation(maps, 5.0, I.rng_for(5, 1, 1)))
+    S = gbk.Surrogate(m, lo, hi, hidden=1024, layers=4, batch=512, seed=1)
+    rows = torch.tensor(lo + I.rng_for(5, 0, 9).random((8192, I.NPAR)) * (hi - lo), device=dev)
+    t_scr = timed(lambda: S.chi2(m, rows))
+    t_plain = timed(lambda: m.chi2(rows))
+    S.close()
+    m.close()
+    return {"gemm_8192x8192x1024": {"us": round(t_gemm * 1e6, 1), "tflops": round(gemm_tflops, 1),
+                                   "frac_of_bf16_peak": round(gemm_tflops / PEAK_BF16_TFLOPS, 4)},
+            "screen_8192_rows": {"us": round(t_scr * 1e6, 1), "ns_per_row": round(t_scr / 8192 * 1e9, 2)},
+            "plain_8192_rows": {"us": round(t_plain * 1e6, 1), "ns_per_row": round(t_plain / 8192 * 1e9, 2)},
+            "peak_bf16_tflops": PEAK_BF16_TFLOPS}
+
+
 def host_threads() -> int:
     """Host threads for the oracle legs: the CPUs this process may run on,
     at most 16 (the host share of one GPU)."""
@@ -788,7 +835,10 @@ def main():
            "kernel_timing": f"HIP events carried by the dispatches of every {TIME_EVERY}th "
                             f"timed step ({prof['launches']['k_line_sums']} launches per kernel)"}
     log(f"{value:.0f} evals/s on the 128x128x48 workload")
-    if args.fit_galaxies > 0:
+    if args.fit_galaxies > 0 or args.surrogate_kernels_only:
+        out["surrogate_kernels"] = surrogate_kernels(gbk, I, torch)
+        log(f"surrogate kernels: {out['surrogate_kernels']}")
+    if args.fit_galaxies > 0 and not args.surrogate_kernels_only:
         out["fits_per_hour"] = fits_per_hour(gbk, I, torch, args.fit_galaxies, args.train_rows)
     precision_samples = []
     if args.survey_galaxies > 0 or args.grid_galaxies > 0 or args.ns_fits > 0:
