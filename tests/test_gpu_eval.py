@@ -324,3 +324,19 @@ def test_lines_outside_the_band(O, gbk):
     np.testing.assert_array_equal(n, rn)
     for b in range(5):
         assert_chi2_close(c[b], rc[b], rn[b], f"outside-band row {b}", obs=obs)
+
+
+def test_model_grid_limit(gbk):
+    """A T plane (FP64 per fine spaxel, with the PSF halo) is addressed with
+    32-bit byte offsets, so it must stay under 2^31 bytes: a 16384 x 16384
+    grid with a PSF halo is refused before anything is allocated, and so is a
+    4096 x 4096 grid at u = 4; a 2048 x 2048 grid at u = 4 (8192^2 fine
+    spaxels plus halo, 0.54 GB per plane) is accepted."""
+    for grid in (I.Grid(16384, 16384, 8, 30.0, psf_fwhm=2.0, lsf_sigma=0.0),
+                 I.Grid(4096, 4096, 4, 30.0, psf_fwhm=2.0, lsf_sigma=0.0, u=4)):
+        with pytest.raises(gbk.GkError) as e:
+            gbk.Model.from_grid(grid)
+        assert e.value.status == gbk.GK_EINVAL
+        assert "too large" in str(e.value)
+    m = gbk.Model.from_grid(I.Grid(2048, 2048, 4, 30.0, psf_fwhm=2.0, lsf_sigma=0.0, u=4))
+    m.close()
