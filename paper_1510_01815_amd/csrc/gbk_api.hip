@@ -463,7 +463,8 @@ gk_status gbk::enqueue_device_rows(gk_model *m, const double *d_params, int32_t 
 
 
 gk_status gbk::run_batch(gk_model *m, const double *params, int32_t B, float *maps,
-                          double *resid, double *chi2, int64_t *nvalid, void *stream)
+                          double *resid, double *chi2, int64_t *nvalid, void *stream,
+                          bool mapped_chi2)
 {
     if (!m) return fail(GK_EINVAL, "model is NULL");
     if (B < 0) return fail(GK_EINVAL, "negative batch size %d", B);
@@ -476,7 +477,7 @@ gk_status gbk::run_batch(gk_model *m, const double *params, int32_t B, float *ma
 
     for (const void *out : {(const void *)maps, (const void *)resid, (const void *)chi2,
                             (const void *)nvalid}) {
-        if (out && pointer_kind(out) != PTR_DEVICE)
+        if (out && pointer_kind(out) != PTR_DEVICE && !(mapped_chi2 && out == chi2))
             return fail(GK_EINVAL, "output arrays must be device memory");
     }
     PtrKind pk = pointer_kind(params);

@@ -242,9 +242,11 @@ struct gk_model {
 namespace gbk {
 
 // Evaluates B rows (host or device) on `stream`: any of maps [B][3][ny][nx]
-// float, resid [B][2][ny][nx] double, chi2 [B] / nvalid [B] (device).
+// float, resid [B][2][ny][nx] double, chi2 [B] / nvalid [B] (device; with
+// mapped_chi2, chi2 may also be the device address of pinned, device-mapped
+// host memory, which the chi-square reduction then writes directly).
 gk_status run_batch(gk_model *m, const double *params, int32_t B, float *maps, double *resid,
-                    double *chi2, int64_t *nvalid, void *stream);
+                    double *chi2, int64_t *nvalid, void *stream, bool mapped_chi2 = false);
 
 // The launch chain of B rows in device memory on stream s, using the model's
 // row scratch (already reserved for min(B, chunk_rows()) rows when the caller

@@ -1133,19 +1133,23 @@ __global__ void k_gather_rows(const double *__restrict__ src, const int *__restr
 }
 
 // Device buffers of one fit, freed on scope exit.
+// A round's candidates (unit-cube coordinates, modes) and plain chi-squares
+// go straight to pinned, device-mapped, coherent host buffers: the draw
+// kernel and the chi-square reduction write them there, and no copy is queued
+// behind the round's launches (h_*: host addresses, dv_*: the device's).
 struct NsBuffers {
-    double *d_u = nullptr, *d_rows2 = nullptr, *h_u = nullptr;
-    int *d_idx = nullptr, *h_idx = nullptr, *d_mode = nullptr, *h_mode = nullptr;
+    double *d_rows2 = nullptr, *h_u = nullptr, *h_chi2 = nullptr;
+    double *dv_u = nullptr, *dv_chi2 = nullptr;
+    int *d_idx = nullptr, *h_idx = nullptr, *h_mode = nullptr, *dv_mode = nullptr;
     Bound *d_bnd = nullptr, *h_bnd = nullptr;
     ~NsBuffers()
     {
         (void)hipFree(d_bnd);
         if (h_bnd) (void)hipHostFree(h_bnd);
-        (void)hipFree(d_u);
         (void)hipFree(d_rows2);
         (void)hipFree(d_idx);
-        (void)hipFree(d_mode);
         if (h_u) (void)hipHostFree(h_u);
+        if (h_chi2) (void)hipHostFree(h_chi2);
         if (h_idx) (void)hipHostFree(h_idx);
         if (h_mode) (void)hipHostFree(h_mode);
     }
@@ -1200,12 +1204,15 @@ gk_status fit_nested(gk_model *m, gk_surrogate *sur, const double *lo, const dou
     GK_TRY(fit_reserve_rows(m, 2 * rows, &h_params, &d_params, &d_chi2, &h_chi2, &stream));
     double *d_chi2s = d_chi2 + rows, *h_chi2s = h_chi2 + rows;
     NsBuffers nb;
-    HIP_TRY(hipMalloc((void **)&nb.d_u, sizeof(double) * rows * d));
     HIP_TRY(hipMalloc((void **)&nb.d_bnd, sizeof(Bound)));
     HIP_TRY(hipHostMalloc((void **)&nb.h_bnd, sizeof(Bound), 0));
-    HIP_TRY(hipHostMalloc((void **)&nb.h_u, sizeof(double) * rows * d, 0));
-    HIP_TRY(hipMalloc((void **)&nb.d_mode, sizeof(int) * rows));
-    HIP_TRY(hipHostMalloc((void **)&nb.h_mode, sizeof(int) * rows, 0));
+    const unsigned mapped = hipHostMallocMapped | hipHostMallocCoherent;
+    HIP_TRY(hipHostMalloc((void **)&nb.h_u, sizeof(double) * rows * d, mapped));
+    HIP_TRY(hipHostMalloc((void **)&nb.h_mode, sizeof(int) * rows, mapped));
+    HIP_TRY(hipHostMalloc((void **)&nb.h_chi2, sizeof(double) * rows, mapped));
+    HIP_TRY(hipHostGetDevicePointer((void **)&nb.dv_u, nb.h_u, 0));
+    HIP_TRY(hipHostGetDevicePointer((void **)&nb.dv_mode, nb.h_mode, 0));
+    HIP_TRY(hipHostGetDevicePointer((void **)&nb.dv_chi2, nb.h_chi2, 0));
     if (sur) {
         HIP_TRY(hipMalloc((void **)&nb.d_rows2, sizeof(double) * rows * NPAR));
         HIP_TRY(hipMalloc((void **)&nb.d_idx, sizeof(int) * rows));
@@ -1239,22 +1246,11 @@ gk_status fit_nested(gk_model *m, gk_surrogate *sur, const double *lo, const dou
             HIP_TRY(hipMemcpyAsync(nb.d_bnd, nb.h_bnd, sizeof(Bound), hipMemcpyHostToDevice, stream));
         }
         g.bnd = nb.d_bnd;
-        g.u = nb.d_u;
+        g.u = nb.dv_u;
         g.rows = d_params;
-        g.mode = nb.d_mode;
+        g.mode = nb.dv_mode;
         hipLaunchKernelGGL(k_ns_draw, dim3((n + 3) / 4), dim3(256), 0, stream, g);
         HIP_TRY(hipGetLastError());
-        // the candidates' unit-cube coordinates and modes go to the host after
-        // the round's evaluation launches, so that the evaluation starts right
-        // after the draw (the host reads them only after the wait)
-        auto copy_draws = [&]() -> hipError_t {
-            hipError_t e = hipMemcpyAsync(nb.h_u, nb.d_u, sizeof(double) * n * d,
-                                          hipMemcpyDeviceToHost, stream);
-            if (e == hipSuccess)
-                e = hipMemcpyAsync(nb.h_mode, nb.d_mode, sizeof(int) * n, hipMemcpyDeviceToHost,
-                                   stream);
-            return e;
-        };
         for (int i = 0; i < n; ++i) logl[i] = -INFINITY;
         // screen this round only where the plain evaluations it saves (at the
         // last screened round's pass fraction) outweigh its own cost
@@ -1263,19 +1259,16 @@ gk_status fit_nested(gk_model *m, gk_surrogate *sur, const double *lo, const dou
                                     (1.0 - pass_frac) * n > o.screen_cost * n + o.screen_rows);
         if (!screen) {
             ++since_screen;
-            GK_TRY(run_batch(m, d_params, n, nullptr, nullptr, d_chi2, nullptr, stream));
-            HIP_TRY(copy_draws());
-            HIP_TRY(hipMemcpyAsync(h_chi2, d_chi2, sizeof(double) * n, hipMemcpyDeviceToHost, stream));
+            GK_TRY(run_batch(m, d_params, n, nullptr, nullptr, nb.dv_chi2, nullptr, stream, true));
             HIP_TRY(wait(stream));
             std::memcpy(u, nb.h_u, sizeof(double) * n * d);
             std::memcpy(mode, nb.h_mode, sizeof(int) * n);
             n_plain += n;
-            for (int i = 0; i < n; ++i) logl[i] = -0.5 * h_chi2[i];
+            for (int i = 0; i < n; ++i) logl[i] = -0.5 * nb.h_chi2[i];
             return GK_OK;
         }
         // surrogate chi2 of every candidate, then the plain chi2 of the survivors
         GK_TRY(surrogate_chi2(sur, m, d_params, n, d_chi2s, stream));
-        HIP_TRY(copy_draws());
         HIP_TRY(hipMemcpyAsync(h_chi2s, d_chi2s, sizeof(double) * n, hipMemcpyDeviceToHost, stream));
         HIP_TRY(wait(stream));
         std::memcpy(u, nb.h_u, sizeof(double) * n * d);
@@ -1316,15 +1309,14 @@ gk_status fit_nested(gk_model *m, gk_surrogate *sur, const double *lo, const dou
             hipLaunchKernelGGL(k_gather_rows, dim3((nk * NPAR + 255) / 256), dim3(256), 0, stream,
                                d_params, nb.d_idx, nk, nb.d_rows2);
             HIP_TRY(hipGetLastError());
-            GK_TRY(run_batch(m, nb.d_rows2, nk, nullptr, nullptr, d_chi2, nullptr, stream));
-            HIP_TRY(hipMemcpyAsync(h_chi2, d_chi2, sizeof(double) * nk, hipMemcpyDeviceToHost, stream));
+            GK_TRY(run_batch(m, nb.d_rows2, nk, nullptr, nullptr, nb.dv_chi2, nullptr, stream, true));
             HIP_TRY(wait(stream));
         }
         n_plain += nk;
         const size_t window = (size_t)std::max(o.n_live, o.batch);  // recent plain evaluations
         for (int j = 0; j < nk; ++j) {
             const int i = keep[j];
-            const double c = h_chi2[j];
+            const double c = nb.h_chi2[j];
             logl[i] = -0.5 * c;
             if (audited[i]) {
                 res->n_audited += 1;
