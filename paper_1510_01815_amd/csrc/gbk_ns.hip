@@ -1133,13 +1133,14 @@ __global__ void k_gather_rows(const double *__restrict__ src, const int *__restr
 }
 
 // Device buffers of one fit, freed on scope exit.
-// A round's candidates (unit-cube coordinates, modes) and plain chi-squares
-// go straight to pinned, device-mapped, coherent host buffers: the draw
-// kernel and the chi-square reduction write them there, and no copy is queued
-// behind the round's launches (h_*: host addresses, dv_*: the device's).
+// A round's candidates (unit-cube coordinates, modes), plain chi-squares and
+// surrogate chi-squares go straight to pinned, device-mapped, coherent host
+// buffers: the draw kernel and the chi-square reductions write them there, and
+// no copy is queued behind the round's launches (h_*: host addresses, dv_*:
+// the device's).
 struct NsBuffers {
-    double *d_rows2 = nullptr, *h_u = nullptr, *h_chi2 = nullptr;
-    double *dv_u = nullptr, *dv_chi2 = nullptr;
+    double *d_rows2 = nullptr, *h_u = nullptr, *h_chi2 = nullptr, *h_chi2s = nullptr;
+    double *dv_u = nullptr, *dv_chi2 = nullptr, *dv_chi2s = nullptr;
     int *d_idx = nullptr, *h_idx = nullptr, *h_mode = nullptr, *dv_mode = nullptr;
     Bound *d_bnd = nullptr, *h_bnd = nullptr;
     ~NsBuffers()
@@ -1150,6 +1151,7 @@ struct NsBuffers {
         (void)hipFree(d_idx);
         if (h_u) (void)hipHostFree(h_u);
         if (h_chi2) (void)hipHostFree(h_chi2);
+        if (h_chi2s) (void)hipHostFree(h_chi2s);
         if (h_idx) (void)hipHostFree(h_idx);
         if (h_mode) (void)hipHostFree(h_mode);
     }
@@ -1200,9 +1202,7 @@ gk_status fit_nested(gk_model *m, gk_surrogate *sur, const double *lo, const dou
     double *h_params, *d_params, *d_chi2, *h_chi2;
     hipStream_t stream;
     const int rows = std::max({o.n_live, o.batch, o.batch_max});
-    // chi2 rows, then (screened) surrogate chi2 rows
-    GK_TRY(fit_reserve_rows(m, 2 * rows, &h_params, &d_params, &d_chi2, &h_chi2, &stream));
-    double *d_chi2s = d_chi2 + rows, *h_chi2s = h_chi2 + rows;
+    GK_TRY(fit_reserve_rows(m, rows, &h_params, &d_params, &d_chi2, &h_chi2, &stream));
     NsBuffers nb;
     HIP_TRY(hipMalloc((void **)&nb.d_bnd, sizeof(Bound)));
     HIP_TRY(hipHostMalloc((void **)&nb.h_bnd, sizeof(Bound), 0));
@@ -1213,6 +1213,10 @@ gk_status fit_nested(gk_model *m, gk_surrogate *sur, const double *lo, const dou
     HIP_TRY(hipHostGetDevicePointer((void **)&nb.dv_u, nb.h_u, 0));
     HIP_TRY(hipHostGetDevicePointer((void **)&nb.dv_mode, nb.h_mode, 0));
     HIP_TRY(hipHostGetDevicePointer((void **)&nb.dv_chi2, nb.h_chi2, 0));
+    if (sur) {
+        HIP_TRY(hipHostMalloc((void **)&nb.h_chi2s, sizeof(double) * rows, mapped));
+        HIP_TRY(hipHostGetDevicePointer((void **)&nb.dv_chi2s, nb.h_chi2s, 0));
+    }
     if (sur) {
         HIP_TRY(hipMalloc((void **)&nb.d_rows2, sizeof(double) * rows * NPAR));
         HIP_TRY(hipMalloc((void **)&nb.d_idx, sizeof(int) * rows));
@@ -1268,8 +1272,7 @@ gk_status fit_nested(gk_model *m, gk_surrogate *sur, const double *lo, const dou
             return GK_OK;
         }
         // surrogate chi2 of every candidate, then the plain chi2 of the survivors
-        GK_TRY(surrogate_chi2(sur, m, d_params, n, d_chi2s, stream));
-        HIP_TRY(hipMemcpyAsync(h_chi2s, d_chi2s, sizeof(double) * n, hipMemcpyDeviceToHost, stream));
+        GK_TRY(surrogate_chi2(sur, m, d_params, n, nb.dv_chi2s, stream));
         HIP_TRY(wait(stream));
         std::memcpy(u, nb.h_u, sizeof(double) * n * d);
         std::memcpy(mode, nb.h_mode, sizeof(int) * n);
@@ -1283,7 +1286,7 @@ gk_status fit_nested(gk_model *m, gk_surrogate *sur, const double *lo, const dou
         uint32_t blk[4];
         int blk_id = -1;
         for (int i = 0; i < n; ++i) {
-            if (!(h_chi2s[i] > cut)) {
+            if (!(nb.h_chi2s[i] > cut)) {
                 keep.push_back(i);
                 continue;
             }
@@ -1322,7 +1325,7 @@ gk_status fit_nested(gk_model *m, gk_surrogate *sur, const double *lo, const dou
                 res->n_audited += 1;
                 res->n_audit_miss += c < chi2_floor;
             }
-            const double delta = h_chi2s[i] - c;
+            const double delta = nb.h_chi2s[i] - c;
             if (std::isfinite(delta)) {
                 if (recent.size() < window) {
                     recent.push_back(delta);

@@ -7,7 +7,8 @@
 namespace gbk {
 
 // Surrogate chi2 of B device rows against the observation of `obs` into
-// d_chi2 (device), enqueued on st.  Calls on one surrogate must be ordered.
+// d_chi2 (device memory, or the device address of pinned, device-mapped host
+// memory), enqueued on st.  Calls on one surrogate must be ordered.
 gk_status surrogate_chi2(gk_surrogate *s, gk_model *obs, const double *d_params, int B,
                          double *d_chi2, hipStream_t st);
 
