@@ -119,7 +119,12 @@ enum { GK_CONV_AUTO = 0, GK_CONV_DIRECT = 1, GK_CONV_FFT = 2 };
 enum { GK_STRATEGY_CUBE = 0, GK_STRATEGY_VFIELD = 1 };
 
 /* Creates a model for one instrument grid on HIP device `device`.
- * Errors: GK_EINVAL (bad descriptor), GK_ENOMEM, GK_EDEVICE. */
+ * Limits of the cube strategy: upsample 1..8; at most 65534 fine channels with
+ * the LSF halo (nz * upsample + 2 h_lsf); the fine grid with the PSF halo
+ * (nx * upsample + 2 h_psf by ny * upsample + 2 h_psf) under 2^28 spaxels,
+ * i.e. one FP64 plane of it under 2^31 bytes (the kernels address a plane
+ * with 32-bit byte offsets).
+ * Errors: GK_EINVAL (bad descriptor or a limit exceeded), GK_ENOMEM, GK_EDEVICE. */
 gk_status gk_create_model(const gk_model_desc *desc, int device, gk_model **out);
 
 /* Frees the model and its device memory; waits for its pending work.  NULL is a no-op. */
