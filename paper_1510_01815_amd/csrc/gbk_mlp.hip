@@ -11,11 +11,13 @@
 //   y = h_L W_o^T + b_o                velocity map / 300, dispersion map / 100
 //   loss = sum mask (y - t)^2 / sum mask, mask: truth flux >= 1% of its peak
 //
-// GEMM: C[M][N] = sum_k A(m, k) B(n, k) on 128 x 128 tiles, K steps of 32;
-// four waves own a 64 x 64 quarter each as 4 x 4 tiles of the 16x16x32 BF16
-// MFMA.  Operands are staged through LDS as [row][k], so each operand may be
-// stored k-contiguous or k-strided: the forward product and the two backward
-// products (data and weight gradients) need all of those patterns.
+// GEMM: C[M][N] = sum_k A(m, k) B(n, k) on the 16x16x32 BF16 MFMA, each wave
+// owning a grid of 16 x 16 products.  Operands are staged through LDS as
+// [row][k], so each operand may be stored k-contiguous or k-strided: the
+// forward product and the two backward products (data and weight gradients)
+// need all of those patterns.  k-contiguous operands (the forward product)
+// take a pipelined kernel with two LDS stages and 128 x 128 or 256 x 256
+// tiles; the others, and narrow products, a register-staged one.
 #include <hip/hip_runtime.h>
 
 #include <cfloat>
@@ -41,6 +43,11 @@ constexpr int kInPad = 32;
 constexpr float kVelScale = 300.0f, kSigScale = 100.0f;
 constexpr int kRedBlocks = 256;
 // LDS rows of a stage are padded by 16 bytes (8 bf16) beyond its K depth
+
+// Word 3 of a raw buffer descriptor on gfx9-family chips (32-bit data format;
+// no swizzle, no index stride), and a byte offset past every range used here.
+constexpr int kBufferDword3 = 0x00020000;
+constexpr uint32_t kOutOfRange = 0x80000000u;
 
 enum Epi {
     EPI_F32 = 0,    // C (f32) = acc + bias
@@ -82,14 +89,15 @@ __device__ inline float gelu_grad(float z)
 
 // Global -> registers for one stage: the R x BK block (rows r0.., k0..) of
 // X(row, k), X(row, k) = X[row * ldx + k] (TR false) or X[k * ldx + row] (TR
-// true), as uint4 chunks of 8 bf16; out-of-range elements are zero.
-template <int R, int BK, bool TR>
+// true), as uint4 chunks of 8 bf16 dealt over NT threads; out-of-range
+// elements are zero.
+template <int R, int BK, bool TR, int NT = 256>
 __device__ inline void load_stage(const uint16_t *__restrict__ X, int ldx, int rows, int K, int r0,
-                                  int k0, uint4 (&reg)[R * BK / 2048], int tid)
+                                  int k0, uint4 (&reg)[R * BK / (8 * NT)], int tid)
 {
 #pragma unroll
-    for (int i = 0; i < R * BK / 2048; ++i) {
-        const int c = tid + i * 256;
+    for (int i = 0; i < R * BK / (8 * NT); ++i) {
+        const int c = tid + i * NT;
         if (!TR) {  // chunk = 8 consecutive k of one row
             const int row = c / (BK / 8), kc = (c % (BK / 8)) * 8;
             const bool ok = r0 + row < rows && k0 + kc < K;
@@ -113,13 +121,13 @@ __device__ inline void load_stage(const uint16_t *__restrict__ X, int ldx, int r
 }
 
 // registers -> LDS S[row][k] (row stride BK + 8)
-template <int R, int BK, bool TR>
-__device__ inline void store_stage(const uint4 (&reg)[R * BK / 2048], uint16_t *__restrict__ S, int tid)
+template <int R, int BK, bool TR, int NT = 256>
+__device__ inline void store_stage(const uint4 (&reg)[R * BK / (8 * NT)], uint16_t *__restrict__ S, int tid)
 {
     constexpr int LDK = BK + 8;
 #pragma unroll
-    for (int i = 0; i < R * BK / 2048; ++i) {
-        const int c = tid + i * 256;
+    for (int i = 0; i < R * BK / (8 * NT); ++i) {
+        const int c = tid + i * NT;
         if (!TR) {
             const int row = c / (BK / 8), kc = (c % (BK / 8)) * 8;
             *reinterpret_cast<uint4 *>(S + row * LDK + kc) = reg[i];
@@ -132,83 +140,23 @@ __device__ inline void store_stage(const uint4 (&reg)[R * BK / 2048], uint16_t *
     }
 }
 
-// C[M][N] = sum_k A(m, k) B(n, k) on BM x BN tiles, 4 waves of (BM/2) x (BN/2).
-// The MFMA takes the B fragment as its row operand, so a lane's four results
-// are four consecutive columns n of one row m (vector stores in the epilogue).
-template <int BM, int BN, int BK, bool TA, bool TB, int EPI>
-__global__ __launch_bounds__(256) void k_gemm(GemmArgs g)
+// Epilogue of one wave's TM x TN grid of 16 x 16 products whose first row is
+// mw and first column nw.  Lane: row m = mw + 16 i + lane % 16, columns
+// n = nw + 16 j + 4 (lane / 16) + r.  part: the wave's chi-square partial
+// column (EPI_CHI2).
+template <int TM, int TN, int EPI>
+__device__ __forceinline__ void gemm_epilogue(const GemmArgs &g, const f32x4 (&acc)[TM][TN], int mw, int nw,
+                                              int lane, int part)
 {
-    constexpr int WM = BM / 2, WN = BN / 2, TM = WM / 16, TN = WN / 16, LDK = BK + 8;
-    __shared__ __attribute__((aligned(16))) uint16_t As[BM * LDK];
-    __shared__ __attribute__((aligned(16))) uint16_t Bs[BN * LDK];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = wave & 1, wn = wave >> 1;
-    const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
-    const uint16_t *A = reinterpret_cast<const uint16_t *>(g.A);
-    const uint16_t *B = reinterpret_cast<const uint16_t *>(g.B);
-    f32x4 acc[TM][TN];
-#pragma unroll
-    for (int i = 0; i < TM; ++i)
-#pragma unroll
-        for (int j = 0; j < TN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-
-    // two register sets: stage s + 2 is loaded while stage s is multiplied
-    constexpr int RA = BM * BK / 2048, RB = BN * BK / 2048;
-    uint4 ra0[RA], rb0[RB], ra1[RA], rb1[RB];
-    auto load = [&](int k0, uint4(&ra)[RA], uint4(&rb)[RB]) {
-        if (k0 < g.K) {
-            load_stage<BM, BK, TA>(A, g.lda, g.M, g.K, m0, k0, ra, tid);
-            load_stage<BN, BK, TB>(B, g.ldb, g.N, g.K, n0, k0, rb, tid);
-        }
-    };
-    auto multiply = [&]() {
-#pragma unroll
-        for (int kk = 0; kk < BK; kk += 32) {
-            bf16x8 af[TM], bfr[TN];
-#pragma unroll
-            for (int i = 0; i < TM; ++i)
-                af[i] = *reinterpret_cast<const bf16x8 *>(
-                    As + (wm * WM + i * 16 + (lane & 15)) * LDK + kk + (lane >> 4) * 8);
-#pragma unroll
-            for (int j = 0; j < TN; ++j)
-                bfr[j] = *reinterpret_cast<const bf16x8 *>(
-                    Bs + (wn * WN + j * 16 + (lane & 15)) * LDK + kk + (lane >> 4) * 8);
-#pragma unroll
-            for (int i = 0; i < TM; ++i)
-#pragma unroll
-                for (int j = 0; j < TN; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bfr[j], af[i], acc[i][j], 0, 0, 0);
-        }
-    };
-    load(0, ra0, rb0);
-    load(BK, ra1, rb1);
-    for (int k0 = 0; k0 < g.K; k0 += 2 * BK) {
-        store_stage<BM, BK, TA>(ra0, As, tid);
-        store_stage<BN, BK, TB>(rb0, Bs, tid);
-        __syncthreads();
-        load(k0 + 2 * BK, ra0, rb0);
-        multiply();
-        __syncthreads();
-        if (k0 + BK < g.K) {  // uniform
-            store_stage<BM, BK, TA>(ra1, As, tid);
-            store_stage<BN, BK, TB>(rb1, Bs, tid);
-            __syncthreads();
-            load(k0 + 3 * BK, ra1, rb1);
-            multiply();
-            __syncthreads();
-        }
-    }
-
-    // lane: row m = ... + lane % 16, columns n = ... + 4 (lane / 16) + r
     double row_chi2[TM];
 #pragma unroll
     for (int i = 0; i < TM; ++i) row_chi2[i] = 0.0;
 #pragma unroll
     for (int i = 0; i < TM; ++i) {
-        const int m = m0 + wm * WM + i * 16 + (lane & 15);
+        const int m = mw + i * 16 + (lane & 15);
 #pragma unroll
         for (int j = 0; j < TN; ++j) {
-            const int nb = n0 + wn * WN + j * 16 + 4 * (lane >> 4);
+            const int nb = nw + j * 16 + 4 * (lane >> 4);
             if (m >= g.M || nb >= g.N) continue;
             float v[4];
 #pragma unroll
@@ -280,16 +228,194 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g)
     if (EPI == EPI_CHI2) {
         // lanes l, l ^ 16, l ^ 32, l ^ 48 hold the same row: sum them, then one
         // partial per (row, block column, wave column), no atomics
-        const int part = blockIdx.x * 2 + wn;
 #pragma unroll
         for (int i = 0; i < TM; ++i) {
             double c = row_chi2[i];
             c += __shfl_xor(c, 16, 64);
             c += __shfl_xor(c, 32, 64);
-            const int m = m0 + wm * WM + i * 16 + (lane & 15);
+            const int m = mw + i * 16 + (lane & 15);
             if (lane < 16 && m < g.M) g.obs.partial[(size_t)m * g.obs.nparts + part] = c;
         }
     }
+}
+
+// C[M][N] = sum_k A(m, k) B(n, k) on BM x BN tiles, 4 waves of (BM/2) x (BN/2).
+// The MFMA takes the B fragment as its row operand, so a lane's four results
+// are four consecutive columns n of one row m (vector stores in the epilogue).
+template <int BM, int BN, int BK, bool TA, bool TB, int EPI>
+__global__ __launch_bounds__(256) void k_gemm(GemmArgs g)
+{
+    constexpr int WM = BM / 2, WN = BN / 2, TM = WM / 16, TN = WN / 16, LDK = BK + 8;
+    __shared__ __attribute__((aligned(16))) uint16_t As[BM * LDK];
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[BN * LDK];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave & 1, wn = wave >> 1;
+    const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+    const uint16_t *A = reinterpret_cast<const uint16_t *>(g.A);
+    const uint16_t *B = reinterpret_cast<const uint16_t *>(g.B);
+    f32x4 acc[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    // two register sets: stage s + 2 is loaded while stage s is multiplied
+    constexpr int RA = BM * BK / 2048, RB = BN * BK / 2048;
+    uint4 ra0[RA], rb0[RB], ra1[RA], rb1[RB];
+    auto load = [&](int k0, uint4(&ra)[RA], uint4(&rb)[RB]) {
+        if (k0 < g.K) {
+            load_stage<BM, BK, TA>(A, g.lda, g.M, g.K, m0, k0, ra, tid);
+            load_stage<BN, BK, TB>(B, g.ldb, g.N, g.K, n0, k0, rb, tid);
+        }
+    };
+    auto multiply = [&]() {
+#pragma unroll
+        for (int kk = 0; kk < BK; kk += 32) {
+            bf16x8 af[TM], bfr[TN];
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+                af[i] = *reinterpret_cast<const bf16x8 *>(
+                    As + (wm * WM + i * 16 + (lane & 15)) * LDK + kk + (lane >> 4) * 8);
+#pragma unroll
+            for (int j = 0; j < TN; ++j)
+                bfr[j] = *reinterpret_cast<const bf16x8 *>(
+                    Bs + (wn * WN + j * 16 + (lane & 15)) * LDK + kk + (lane >> 4) * 8);
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int j = 0; j < TN; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bfr[j], af[i], acc[i][j], 0, 0, 0);
+        }
+    };
+    load(0, ra0, rb0);
+    load(BK, ra1, rb1);
+    for (int k0 = 0; k0 < g.K; k0 += 2 * BK) {
+        store_stage<BM, BK, TA>(ra0, As, tid);
+        store_stage<BN, BK, TB>(rb0, Bs, tid);
+        __syncthreads();
+        load(k0 + 2 * BK, ra0, rb0);
+        multiply();
+        __syncthreads();
+        if (k0 + BK < g.K) {  // uniform
+            store_stage<BM, BK, TA>(ra1, As, tid);
+            store_stage<BN, BK, TB>(rb1, Bs, tid);
+            __syncthreads();
+            load(k0 + 3 * BK, ra1, rb1);
+            multiply();
+            __syncthreads();
+        }
+    }
+
+    gemm_epilogue<TM, TN, EPI>(g, acc, m0 + wm * WM, n0 + wn * WN, lane, blockIdx.x * 2 + wn);
+}
+
+// C[M][N] = sum_k A(m, k) B(n, k) for k-contiguous operands: BM x BN tiles,
+// 2 x NWN waves of (BM / 2) x (BN / NWN); 256 x 256 tiles (8 waves of
+// 128 x 64) for products of at least four such tiles per compute unit, where a
+// wave reads 3/4 of the LDS bytes per product that a 64 x 64 wave does, else
+// 128 x 128 (4 waves of 64 x 64).  Two LDS stages (131,072 or 65,536 bytes)
+// take one barrier per 64-deep K stage: stage s is multiplied from one buffer
+// while stage s + 1 goes from registers into the other, after the first half
+// of stage s's products.  Stage s + 1 was fetched into its register set during
+// stage s - 1 and stage s + 2 is fetched into the other set during stage s.
+// LDS rows are 64 k (128 bytes, unpadded) with the 16-byte chunk c of row r
+// stored at c ^ f(r), f(r) = (r & 7) ^ ((r >> 3) & 1): the 16 rows that 16
+// lanes read at one chunk then fall in 16 distinct 16-byte bank groups (and
+// any 8 consecutive of them in 8), and a row's 8 chunks stay in one 128-byte
+// line for the stores.
+template <int BM, int BN, int NWN, int EPI>
+__global__ __launch_bounds__(128 * NWN, NWN == 2 ? 2 : 1) void k_gemm_db(GemmArgs g)
+{
+    constexpr int BK = 64, NT = 128 * NWN, WM = BM / 2, WN = BN / NWN, RS = NT / 8;
+    constexpr int TM = WM / 16, TN = WN / 16;
+    static_assert(RS % 16 == 0 && BM % RS == 0 && BN % RS == 0, "tile rows per store pass");
+    __shared__ __attribute__((aligned(16))) uint16_t S[2][(BM + BN) * BK];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave & 1, wn = wave >> 1;
+    const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+    f32x4 acc[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    constexpr int RA = BM / RS, RB = BN / RS;
+    uint4 ra0[RA], rb0[RB], ra1[RA], rb1[RB];
+    // The thread's chunks: rows (tid >> 3) + RS i, k = 8 (tid & 7) of the
+    // stage.  Fetched by range-checked buffer loads with no branch, so that
+    // the compiler can wait for the older of two register sets alone: rows
+    // at or past M (N) lie past the descriptor's range (M lda elements) and
+    // read as zero, and k past K gets an offset past that range.
+    const int sr = tid >> 3;
+    const __amdgpu_buffer_rsrc_t rsA =
+        __builtin_amdgcn_make_buffer_rsrc((void *)g.A, 0, (int)((size_t)g.M * g.lda * 2), kBufferDword3);
+    const __amdgpu_buffer_rsrc_t rsB =
+        __builtin_amdgcn_make_buffer_rsrc((void *)g.B, 0, (int)((size_t)g.N * g.ldb * 2), kBufferDword3);
+    const uint32_t oA = (uint32_t)(m0 + sr) * (uint32_t)g.lda * 2u + 16u * (tid & 7);
+    const uint32_t oB = (uint32_t)(n0 + sr) * (uint32_t)g.ldb * 2u + 16u * (tid & 7);
+    auto load = [&](int k0, uint4(&ra)[RA], uint4(&rb)[RB]) {
+        const bool kin = k0 + 8 * (tid & 7) < g.K;
+#pragma unroll
+        for (int i = 0; i < RA; ++i)
+            ra[i] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(
+                                                  rsA, kin ? oA + (uint32_t)(RS * i * g.lda + k0) * 2u : kOutOfRange, 0, 0));
+#pragma unroll
+        for (int i = 0; i < RB; ++i)
+            rb[i] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(
+                                                  rsB, kin ? oB + (uint32_t)(RS * i * g.ldb + k0) * 2u : kOutOfRange, 0, 0));
+    };
+    // the thread's stores: a row's f depends on row & 15 only, the same for every i
+    const int st_off = sr * BK + 8 * ((tid & 7) ^ (sr & 7) ^ ((sr >> 3) & 1));
+    auto store = [&](const uint4(&ra)[RA], const uint4(&rb)[RB], int buf) {
+        uint16_t *As = S[buf], *Bs = S[buf] + BM * BK;
+#pragma unroll
+        for (int i = 0; i < RA; ++i) *reinterpret_cast<uint4 *>(As + st_off + i * RS * BK) = ra[i];
+#pragma unroll
+        for (int i = 0; i < RB; ++i) *reinterpret_cast<uint4 *>(Bs + st_off + i * RS * BK) = rb[i];
+    };
+    // the lane's reads: row lane & 15 of each 16-row tile, chunk kk / 8 + lane / 16
+    const int lr = lane & 15, gq = (lane >> 4) ^ (lr & 7) ^ ((lr >> 3) & 1);
+    const int ld_off0 = lr * BK + 8 * gq, ld_off1 = lr * BK + (8 * gq ^ 32);
+    auto multiply = [&](int buf, int half) {
+        const uint16_t *As = S[buf] + (half ? ld_off1 : ld_off0);
+        const uint16_t *Bs = S[buf] + BM * BK + (half ? ld_off1 : ld_off0);
+        bf16x8 af[TM], bfr[TN];
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+            af[i] = *reinterpret_cast<const bf16x8 *>(As + (wm * WM + i * 16) * BK);
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+            bfr[j] = *reinterpret_cast<const bf16x8 *>(Bs + (wn * WN + j * 16) * BK);
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bfr[j], af[i], acc[i][j], 0, 0, 0);
+    };
+    // Stage s: fetched into register set s & 1 during stage s - 2, stored
+    // into LDS buffer s & 1 during stage s - 1, multiplied in stage s.  Fetches
+    // and stores of stages past K are not skipped (they read nothing and fill
+    // a buffer that is not read again): with no branch around them the
+    // compiler's wait for the older register set leaves the newer in flight.
+    load(0, ra0, rb0);
+    load(BK, ra1, rb1);
+    store(ra0, rb0, 0);
+    load(2 * BK, ra0, rb0);
+    __syncthreads();
+    for (int k0 = 0; k0 < g.K; k0 += 2 * BK) {
+        multiply(0, 0);
+        store(ra1, rb1, 1);
+        load(k0 + 3 * BK, ra1, rb1);
+        multiply(0, 1);
+        __syncthreads();
+        if (k0 + BK >= g.K) break;  // uniform
+        multiply(1, 0);
+        store(ra0, rb0, 0);
+        load(k0 + 4 * BK, ra0, rb0);
+        multiply(1, 1);
+        __syncthreads();
+    }
+    gemm_epilogue<TM, TN, EPI>(g, acc, m0 + wm * WM, n0 + wn * WN, lane, blockIdx.x * NWN + wn);
 }
 
 // uniform draws of parameter rows in the box: slot s = lo_s + u (hi_s - lo_s)
@@ -531,6 +657,15 @@ int gemm_tile(int M, int N)
     return t >= 512 ? 128 : 64;
 }
 
+// k_gemm_db for k-contiguous operands when every operand offset of a tile,
+// rows past the end included, stays below 2^31 bytes; its 256 x 256 tiles
+// when they give at least four per compute unit
+bool buffer_offsets_fit(int M, int N, int lda, int ldb)
+{
+    return ((double)M + 256) * lda * 2 < 2147483648.0 && ((double)N + 256) * ldb * 2 < 2147483648.0;
+}
+bool wide_tiles(int M, int N) { return (long)((M + 255) / 256) * ((N + 255) / 256) >= 1024; }
+
 template <bool TA, bool TB, int EPI> gk_status gemm(const GemmArgs &g, hipStream_t s)
 {
     if (g.M <= 0 || g.N <= 0 || g.K <= 0 || g.K % 32 || g.lda % 8 || g.ldb % 8 ||
@@ -546,6 +681,19 @@ template <bool TA, bool TB, int EPI> gk_status gemm(const GemmArgs &g, hipStream
     dim3 grid((g.N + T - 1) / T, gy);
     if (EPI == EPI_CHI2 && g.obs.nparts != 2 * (int)grid.x)
         return fail(GK_EINVAL, "chi2 partial count mismatch");
+    if constexpr (!TA && !TB && EPI != EPI_DGELU) {
+        if (T == 128 && buffer_offsets_fit(g.M, g.N, g.lda, g.ldb)) {
+            bool wide = false;
+            if constexpr (EPI == EPI_F32) {
+                if ((wide = wide_tiles(g.M, g.N)))
+                    hipLaunchKernelGGL((k_gemm_db<256, 256, 4, EPI>),
+                                       dim3((g.N + 255) / 256, (g.M + 255) / 256), dim3(512), 0, s, g);
+            }
+            if (!wide) hipLaunchKernelGGL((k_gemm_db<128, 128, 2, EPI>), grid, dim3(256), 0, s, g);
+            HIP_TRY(hipGetLastError());
+            return GK_OK;
+        }
+    }
     if (T == 128)
         hipLaunchKernelGGL((k_gemm<128, 128, 64, TA, TB, EPI>), grid, dim3(256), 0, s, g);
     else

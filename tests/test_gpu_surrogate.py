@@ -50,6 +50,32 @@ def test_gemm_bf16_all_layouts(gbk, ta, tb, M, N, K):
     assert err <= 1e-5 * scale * max(1.0, np.max(np.abs(ref)) / scale), err
 
 
+@pytest.mark.parametrize("M,N,K,rows", [(8000, 8300, 96, None), (8192, 8192, 1024, 96)])
+def test_gemm_bf16_wide_tiles(gbk, M, N, K, rows):
+    """Products of at least 1024 tiles of 256 x 256 (k-contiguous operands)
+    take the 256 x 256, two-LDS-stage kernel: against an FP64 product of the
+    same BF16 values, ragged in M, N and in the last 64-deep K stage (K = 96),
+    and at 8192 x 8192 x 1024 on sampled rows of every row tile, the first and
+    the last."""
+    import torch
+    g = torch.Generator().manual_seed(M + N + K)
+    A = torch.randn((M, K), generator=g).to(torch.bfloat16)
+    B = torch.randn((N, K), generator=g).to(torch.bfloat16)
+    C = gbk.gemm_bf16(A.cuda(), B.cuda(), M=M, N=N, K=K)
+    torch.cuda.synchronize()
+    if rows is None:
+        idx = np.arange(M)
+    else:
+        rng = np.random.default_rng(7)
+        idx = np.unique(np.concatenate([[0, M - 1], rng.integers(0, M, rows),
+                                        np.arange(0, M, 256) + rng.integers(0, 256, M // 256)]))
+        idx = idx[idx < M]
+    got = C[torch.as_tensor(idx, device=C.device)].cpu().numpy().astype(np.float64)
+    ref = A.to(torch.float64).numpy()[idx] @ B.to(torch.float64).numpy().T
+    err = np.max(np.abs(got - ref))
+    assert err <= 1e-5 * np.sqrt(K) * max(1.0, np.max(np.abs(ref)) / np.sqrt(K)), err
+
+
 def test_gemm_rejects_bad_shapes(gbk):
     import torch
     A = torch.zeros((64, 40), dtype=torch.bfloat16, device="cuda")
