@@ -332,7 +332,21 @@ __global__ __launch_bounds__(128 * NWN, NWN == 2 ? 2 : 1) void k_gemm_db(GemmArg
     __shared__ __attribute__((aligned(16))) uint16_t S[2][(BM + BN) * BK];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave & 1, wn = wave >> 1;
-    const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+    // Workgroups reach the 8 XCDs in turn (workgroup b on XCD b % 8).  With
+    // 128 x 128 tiles, XCD x takes the x-th eighth of the tiles in row-major
+    // order, so the row and column panels that its L2 serves are those of a
+    // compact block of tiles, not of every eighth column.  256 x 256 tiles
+    // keep the launch order (every eighth column: 4 row panels by 8 column
+    // panels in flight per XCD, against 1 by 32 for the eighth in row order).
+    int bx = blockIdx.x, by = blockIdx.y;
+    if (NWN == 2) {
+        const int T = gridDim.x * gridDim.y, b = blockIdx.y * gridDim.x + blockIdx.x;
+        const int q = T >> 3, r = T & 7, x = b & 7;
+        const int t = x * q + min(x, r) + (b >> 3);
+        bx = t % gridDim.x;
+        by = t / gridDim.x;
+    }
+    const int m0 = by * BM, n0 = bx * BN;
     f32x4 acc[TM][TN];
 #pragma unroll
     for (int i = 0; i < TM; ++i)
@@ -415,7 +429,7 @@ __global__ __launch_bounds__(128 * NWN, NWN == 2 ? 2 : 1) void k_gemm_db(GemmArg
         multiply(1, 1);
         __syncthreads();
     }
-    gemm_epilogue<TM, TN, EPI>(g, acc, m0 + wm * WM, n0 + wn * WN, lane, blockIdx.x * NWN + wn);
+    gemm_epilogue<TM, TN, EPI>(g, acc, m0 + wm * WM, n0 + wn * WN, lane, bx * NWN + wn);
 }
 
 // uniform draws of parameter rows in the box: slot s = lo_s + u (hi_s - lo_s)

@@ -50,13 +50,14 @@ def test_gemm_bf16_all_layouts(gbk, ta, tb, M, N, K):
     assert err <= 1e-5 * scale * max(1.0, np.max(np.abs(ref)) / scale), err
 
 
-@pytest.mark.parametrize("M,N,K,rows", [(8000, 8300, 96, None), (8192, 8192, 1024, 96)])
-def test_gemm_bf16_wide_tiles(gbk, M, N, K, rows):
-    """Products of at least 1024 tiles of 256 x 256 (k-contiguous operands)
-    take the 256 x 256, two-LDS-stage kernel: against an FP64 product of the
-    same BF16 values, ragged in M, N and in the last 64-deep K stage (K = 96),
-    and at 8192 x 8192 x 1024 on sampled rows of every row tile, the first and
-    the last."""
+@pytest.mark.parametrize("M,N,K,rows", [(4000, 2100, 96, None), (8000, 8300, 96, None),
+                                        (8192, 8192, 1024, 96)])
+def test_gemm_bf16_pipelined_tiles(gbk, M, N, K, rows):
+    """k-contiguous products of at least 512 tiles of 128 x 128 take the
+    two-LDS-stage kernel, with 256 x 256 tiles from 1024 such tiles on: against
+    an FP64 product of the same BF16 values, ragged in M, N and in the last
+    64-deep K stage (K = 96), and at 8192 x 8192 x 1024 on sampled rows of every
+    row tile, the first and the last."""
     import torch
     g = torch.Generator().manual_seed(M + N + K)
     A = torch.randn((M, K), generator=g).to(torch.bfloat16)
@@ -74,6 +75,35 @@ def test_gemm_bf16_wide_tiles(gbk, M, N, K, rows):
     ref = A.to(torch.float64).numpy()[idx] @ B.to(torch.float64).numpy().T
     err = np.max(np.abs(got - ref))
     assert err <= 1e-5 * np.sqrt(K) * max(1.0, np.max(np.abs(ref)) / np.sqrt(K)), err
+
+
+def test_surrogate_large_batch_equals_small_batches(gbk):
+    """8192 rows of the benchmark's network (4 x 1024 GELU, 8192 outputs on
+    the 64 x 64 x 64 instrument) run the pipelined kernels (hidden layers with
+    the GELU epilogue and the fused chi-square output layer on 128 x 128 tiles,
+    the predicted maps on 256 x 256 tiles); 256-row batches run the
+    register-staged kernel, whose layers are tested against the FP64
+    reference.  Both accumulate every output over K in the same order: maps
+    equal bit for bit, chi-squares (per-row partials split over other column
+    blocks) to 1e-12."""
+    import torch
+    grid, (lo, hi) = I.c5_grid(), I.c5_box()
+    m = gbk.Model.from_grid(grid)
+    truth = I.c5_galaxy(1)
+    maps = m.evaluate(torch.tensor(truth[None], device="cuda:0")).cpu().numpy()[0]
+    m.set_obs(I.make_observation(maps, 5.0, I.rng_for(5, 1, 1)))
+    S = gbk.Surrogate(m, lo, hi, hidden=1024, layers=4, batch=256, seed=5)
+    rows = lo + I.rng_for(5, 0, 11).random((8192, I.NPAR)) * (hi - lo)
+    c_all = S.chi2(m, rows).cpu().numpy()
+    c_parts = np.concatenate([S.chi2(m, rows[i:i + 256]).cpu().numpy() for i in range(0, 8192, 256)])
+    fin = np.isfinite(c_parts)
+    assert np.array_equal(np.isfinite(c_all), fin) and fin.sum() > 8000
+    assert np.all(np.abs(c_all[fin] - c_parts[fin]) <= 1e-12 * np.abs(c_parts[fin]))
+    y_all = S.predict(rows).cpu().numpy()
+    for i in (0, 4096, 7936):
+        assert np.array_equal(y_all[i:i + 256], S.predict(rows[i:i + 256]).cpu().numpy())
+    S.close()
+    m.close()
 
 
 def test_gemm_rejects_bad_shapes(gbk):
