@@ -309,11 +309,12 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g)
     gemm_epilogue<TM, TN, EPI>(g, acc, m0 + wm * WM, n0 + wn * WN, lane, blockIdx.x * 2 + wn);
 }
 
-// C[M][N] = sum_k A(m, k) B(n, k) for k-contiguous operands: BM x BN tiles,
-// 2 x NWN waves of (BM / 2) x (BN / NWN); 256 x 256 tiles (8 waves of
-// 128 x 64) for products of at least four such tiles per compute unit, where a
-// wave reads 3/4 of the LDS bytes per product that a 64 x 64 wave does, else
-// 128 x 128 (4 waves of 64 x 64).  Two LDS stages (131,072 or 65,536 bytes)
+// C[M][N] = sum_k A(m, k) B(n, k) for k-contiguous operands of products with
+// at least two 128 x 128 tiles per compute unit: BM x BN tiles, 2 x NWN waves
+// of (BM / 2) x (BN / NWN); 256 x 256 tiles (8 waves of 128 x 64) for f32
+// products of at least four such tiles per compute unit, where a wave reads
+// 3/4 of the LDS bytes per product that a 64 x 64 wave does, else 128 x 128
+// (4 waves of 64 x 64).  Two LDS stages (131,072 or 65,536 bytes)
 // take one barrier per 64-deep K stage: stage s is multiplied from one buffer
 // while stage s + 1 goes from registers into the other, after the first half
 // of stage s's products.  Stage s + 1 was fetched into its register set during
